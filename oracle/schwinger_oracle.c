@@ -1,0 +1,697 @@
+/*
+ * Plain FP64 CPU oracle for the HMC of the two-flavour lattice Schwinger model with
+ * the (adapted) nested force-gradient integrators of Shcherbakov, Ehrhardt,
+ * Finkenrath, Guenther, Knechtli and Peardon, "Adapted nested force-gradient
+ * integrators: the Schwinger model case" (arXiv:1512.03812).
+ *
+ * THIS IS TEST INFRASTRUCTURE.  It exists only to check the GPU library.  Only the
+ * test suite, the package smoke check and the benchmark's CPU-baseline leg may load
+ * it.  It shares no code, header, table or helper with the GPU path.  Everything is
+ * written for clarity: plain loops, lexicographic layout, double precision,
+ * `double complex`, no blocking, no fusion, no reordering beyond what the paper's
+ * definitions state.
+ *
+ * Conventions
+ *   lattice Lx x Lt, site n = x + Lx*t, direction mu = 0 is x (the paper's "1"),
+ *   mu = 1 is t (the paper's "2").  Link angles q[2*n + mu]; U_mu(n) = exp(i q_mu(n))
+ *   (Sec. 3).  Momenta p[2*n + mu] (real, the Lie algebra of U(1), Sec. 3).
+ *   Spinors psi[2*n + s], s = 0, 1, complex (two-component, Sec. 3).
+ *   Gauge field periodic in both directions.  Fermions periodic in x and
+ *   antiperiodic in t: the sign is carried by the t-links leaving the last time
+ *   slice (the paper does not state the boundary conditions; this is the reading
+ *   used throughout).
+ *
+ * Parity pins for every function here live in the test suite (free-field spectrum,
+ * adjointness and gamma5-hermiticity, gauge invariance, finite differences,
+ * reversibility, order slopes, Philox known-answer vectors, exact quenched
+ * plaquette, stage sequences typed from the paper's equations).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------------- */
+/* Lattice geometry                                                          */
+/* ------------------------------------------------------------------------- */
+
+static int wrap(int a, int L) { return ((a % L) + L) % L; }
+
+/* site index of (x, t) with periodic wrap */
+static int site(int x, int t, int Lx, int Lt) { return wrap(x, Lx) + Lx * wrap(t, Lt); }
+
+/* neighbour of n displaced by d (= +1 or -1) in direction mu */
+static int hop(int n, int mu, int d, int Lx, int Lt)
+{
+    int x = n % Lx, t = n / Lx;
+    if (mu == 0) x += d; else t += d;
+    return site(x, t, Lx, Lt);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Counter-based random numbers: Philox4x32-10                               */
+/* Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", */
+/* SC'11.  Round function: two 32x32->64 multiplies by the Philox            */
+/* multipliers, a xor with the round key and the other counter words, and a   */
+/* permutation; the key is bumped by the Weyl constants between rounds.       */
+/* ------------------------------------------------------------------------- */
+
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        if (round < 9) { k0 += PHILOX_W0; k1 += PHILOX_W1; }
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/*
+ * Stream definition shared (by specification, not by code) with the GPU path:
+ *   key     = (seed low word, seed high word)
+ *   counter = (index, stream, trajectory, chain)
+ *   streams: 0 initial links, 1 momenta, 2 pseudofermion, 3 Metropolis
+ *   index   : lexicographic link index 2n+mu (streams 0, 1), spinor index 2n+s
+ *             (stream 2), 0 (stream 3)
+ *   uniform : 64-bit word (w0 | w1 << 32) >> 11, times 2^-53, in [0, 1)
+ *   gaussian pair (Box-Muller): r = sqrt(-2 log(1 - ua)), (r cos(2 pi ub), r sin(2 pi ub))
+ */
+enum { STREAM_LINKS = 0, STREAM_MOMENTA = 1, STREAM_PSEUDOFERMION = 2, STREAM_METROPOLIS = 3 };
+
+static void draw(uint64_t seed, uint32_t chain, uint32_t traj, uint32_t stream, uint32_t index,
+                 uint32_t w[4])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {index, stream, traj, chain};
+    orc_philox4x32_10(ctr, key, w);
+}
+
+static double u01(uint32_t lo, uint32_t hi)
+{
+    uint64_t v = (uint64_t)lo | ((uint64_t)hi << 32);
+    return (double)(v >> 11) * 0x1.0p-53;
+}
+
+void orc_uniform_pair(uint64_t seed, uint32_t chain, uint32_t traj, uint32_t stream,
+                      uint32_t index, double out[2])
+{
+    uint32_t w[4];
+    draw(seed, chain, traj, stream, index, w);
+    out[0] = u01(w[0], w[1]);
+    out[1] = u01(w[2], w[3]);
+}
+
+void orc_gaussian_pair(uint64_t seed, uint32_t chain, uint32_t traj, uint32_t stream,
+                       uint32_t index, double out[2])
+{
+    double u[2];
+    orc_uniform_pair(seed, chain, traj, stream, index, u);
+    double r = sqrt(-2.0 * log(1.0 - u[0]));
+    double a = 6.283185307179586 * u[1];
+    out[0] = r * cos(a);
+    out[1] = r * sin(a);
+}
+
+/* uniform hot start q in [-pi, pi) */
+void orc_random_links(int Lx, int Lt, uint64_t seed, uint32_t chain, double *q)
+{
+    int nl = 2 * Lx * Lt;
+    for (int l = 0; l < nl; ++l) {
+        double u[2];
+        orc_uniform_pair(seed, chain, 0, STREAM_LINKS, (uint32_t)l, u);
+        q[l] = 3.141592653589793 * (2.0 * u[0] - 1.0);
+    }
+}
+
+/* momenta p ~ N(0, 1), one per link (density exp(-p^2/2) from the kinetic term of Eq. (12)) */
+void orc_random_momenta(int Lx, int Lt, uint64_t seed, uint32_t chain, uint32_t traj, double *p)
+{
+    int nl = 2 * Lx * Lt;
+    for (int l = 0; l < nl; ++l) {
+        double g[2];
+        orc_gaussian_pair(seed, chain, traj, STREAM_MOMENTA, (uint32_t)l, g);
+        p[l] = g[0];
+    }
+}
+
+/* complex Gaussian zeta with density exp(-zeta^dagger zeta): Re, Im ~ N(0, 1/2) */
+void orc_random_zeta(int Lx, int Lt, uint64_t seed, uint32_t chain, uint32_t traj, cplx *zeta)
+{
+    int ns = 2 * Lx * Lt;
+    for (int k = 0; k < ns; ++k) {
+        double g[2];
+        orc_gaussian_pair(seed, chain, traj, STREAM_PSEUDOFERMION, (uint32_t)k, g);
+        zeta[k] = g[0] * 0.70710678118654752440 + I * (g[1] * 0.70710678118654752440);
+    }
+}
+
+double orc_metropolis_uniform(uint64_t seed, uint32_t chain, uint32_t traj)
+{
+    double u[2];
+    orc_uniform_pair(seed, chain, traj, STREAM_METROPOLIS, 0, u);
+    return u[0];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Compensated summation (Neumaier) for energies and their differences       */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { double s, c; } ksum;
+
+static void kadd(ksum *k, double v)
+{
+    double t = k->s + v;
+    if (fabs(k->s) >= fabs(v)) k->c += (k->s - t) + v;
+    else k->c += (v - t) + k->s;
+    k->s = t;
+}
+
+static double kval(const ksum *k) { return k->s + k->c; }
+
+/* ------------------------------------------------------------------------- */
+/* Gauge part: plaquette, Wilson action (Eq. (13)), gauge force (Eq. (16))   */
+/* ------------------------------------------------------------------------- */
+
+static cplx link(const double *q, int n, int mu) { return cexp(I * q[2 * n + mu]); }
+
+/*
+ * Oriented plaquette P_{mu nu}(n) = U_mu(n) U_nu(n+mu) U_mu^dagger(n+nu) U_nu^dagger(n).
+ * P_{01}(n) is the plaquette P(n) of Sec. 3; P_{10}(n) is its complex conjugate.
+ */
+static cplx plaquette(const double *q, int n, int mu, int nu, int Lx, int Lt)
+{
+    int n_mu = hop(n, mu, +1, Lx, Lt), n_nu = hop(n, nu, +1, Lx, Lt);
+    return link(q, n, mu) * link(q, n_mu, nu) * conj(link(q, n_nu, mu)) * conj(link(q, n, nu));
+}
+
+/* S_G = beta * sum_n (1 - Re P(n)), Eq. (13) */
+double orc_gauge_action(int Lx, int Lt, double beta, const double *q)
+{
+    ksum k = {0, 0};
+    for (int n = 0; n < Lx * Lt; ++n) kadd(&k, 1.0 - creal(plaquette(q, n, 0, 1, Lx, Lt)));
+    return beta * kval(&k);
+}
+
+/* average Re P(n) */
+double orc_mean_plaquette(int Lx, int Lt, const double *q)
+{
+    ksum k = {0, 0};
+    for (int n = 0; n < Lx * Lt; ++n) kadd(&k, creal(plaquette(q, n, 0, 1, Lx, Lt)));
+    return kval(&k) / (double)(Lx * Lt);
+}
+
+/*
+ * beta g(n, mu) = dS_G/dq_mu(n) = beta Im(P_{mu nu}(n) - P_{mu nu}(n - nu)), nu != mu,
+ * Eq. (16), reading P in the mu-first orientation of the plaquettes P_1, P_2 that
+ * the paper lists for the force-gradient term C_GG.
+ */
+void orc_gauge_force(int Lx, int Lt, double beta, const double *q, double *F)
+{
+    for (int n = 0; n < Lx * Lt; ++n)
+        for (int mu = 0; mu < 2; ++mu) {
+            int nu = 1 - mu;
+            int n_mnu = hop(n, nu, -1, Lx, Lt);
+            F[2 * n + mu] = beta * cimag(plaquette(q, n, mu, nu, Lx, Lt) -
+                                         plaquette(q, n_mnu, mu, nu, Lx, Lt));
+        }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Wilson-Dirac operator (Sec. 3)                                            */
+/* ------------------------------------------------------------------------- */
+
+/* Pauli matrices sigma_1, sigma_2 of Sec. 3, row-major */
+static const cplx SIGMA[2][2][2] = {
+    {{0, 1}, {1, 0}},
+    {{0, -I}, {I, 0}},
+};
+
+/* out = (1 + sgn * sigma_mu) v */
+static void proj(int mu, int sgn, const cplx v[2], cplx out[2])
+{
+    for (int a = 0; a < 2; ++a) {
+        cplx acc = v[a];
+        for (int b = 0; b < 2; ++b) acc += (double)sgn * SIGMA[mu][a][b] * v[b];
+        out[a] = acc;
+    }
+}
+
+/* fermion link: U_mu(n) with the antiperiodic sign on t-links leaving t = Lt-1 */
+static cplx flink(const double *q, int n, int mu, int Lx, int Lt)
+{
+    cplx u = link(q, n, mu);
+    if (mu == 1 && n / Lx == Lt - 1) u = -u;
+    return u;
+}
+
+/*
+ * (D psi)(n) = (2 + m0) psi(n)
+ *   - 1/2 sum_mu [ (1 - sigma_mu) U_mu(n) psi(n + mu) + (1 + sigma_mu) U_mu^dagger(n - mu) psi(n - mu) ]
+ * Sec. 3 (the Wilson-Dirac matrix D_{n,m}).
+ */
+void orc_dirac(int Lx, int Lt, double m0, const double *q, const cplx *in, cplx *out)
+{
+    for (int n = 0; n < Lx * Lt; ++n) {
+        cplx acc[2] = {(2.0 + m0) * in[2 * n], (2.0 + m0) * in[2 * n + 1]};
+        for (int mu = 0; mu < 2; ++mu) {
+            int nf = hop(n, mu, +1, Lx, Lt), nb = hop(n, mu, -1, Lx, Lt);
+            cplx uf = flink(q, n, mu, Lx, Lt), ub = conj(flink(q, nb, mu, Lx, Lt));
+            cplx vf[2] = {uf * in[2 * nf], uf * in[2 * nf + 1]};
+            cplx vb[2] = {ub * in[2 * nb], ub * in[2 * nb + 1]};
+            cplx pf[2], pb[2];
+            proj(mu, -1, vf, pf);
+            proj(mu, +1, vb, pb);
+            for (int a = 0; a < 2; ++a) acc[a] -= 0.5 * (pf[a] + pb[a]);
+        }
+        out[2 * n] = acc[0];
+        out[2 * n + 1] = acc[1];
+    }
+}
+
+/*
+ * D^dagger as the literal conjugate transpose of D_{n,m}: the forward hop carries
+ * (1 + sigma_mu) U_mu(n), the backward hop (1 - sigma_mu) U_mu^dagger(n - mu)
+ * (sigma_mu is hermitian).  gamma5-hermiticity D^dagger = sigma_3 D sigma_3 is
+ * checked by test, not used here.
+ */
+void orc_dirac_dagger(int Lx, int Lt, double m0, const double *q, const cplx *in, cplx *out)
+{
+    for (int n = 0; n < Lx * Lt; ++n) {
+        cplx acc[2] = {(2.0 + m0) * in[2 * n], (2.0 + m0) * in[2 * n + 1]};
+        for (int mu = 0; mu < 2; ++mu) {
+            int nf = hop(n, mu, +1, Lx, Lt), nb = hop(n, mu, -1, Lx, Lt);
+            cplx uf = flink(q, n, mu, Lx, Lt), ub = conj(flink(q, nb, mu, Lx, Lt));
+            cplx vf[2] = {uf * in[2 * nf], uf * in[2 * nf + 1]};
+            cplx vb[2] = {ub * in[2 * nb], ub * in[2 * nb + 1]};
+            cplx pf[2], pb[2];
+            proj(mu, +1, vf, pf);
+            proj(mu, -1, vb, pb);
+            for (int a = 0; a < 2; ++a) acc[a] -= 0.5 * (pf[a] + pb[a]);
+        }
+        out[2 * n] = acc[0];
+        out[2 * n + 1] = acc[1];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Conjugate gradient on the normal equations D^dagger D x = phi             */
+/* (the solver behind "D^{-1}" in Sec. 3; x0 = 0; relative 2-norm residual)  */
+/* ------------------------------------------------------------------------- */
+
+static double dot_re(int ns, const cplx *a, const cplx *b)
+{
+    ksum k = {0, 0};
+    for (int i = 0; i < ns; ++i) kadd(&k, creal(conj(a[i]) * b[i]));
+    return kval(&k);
+}
+
+static void normal_op(int Lx, int Lt, double m0, const double *q, const cplx *in, cplx *tmp, cplx *out)
+{
+    orc_dirac(Lx, Lt, m0, q, in, tmp);
+    orc_dirac_dagger(Lx, Lt, m0, q, tmp, out);
+}
+
+/*
+ * Returns the number of iterations, or -1 if max_iter was reached without
+ * convergence (x then holds the last iterate).  Stops when ||r_k|| <= tol ||phi||
+ * on the recursively updated residual; *true_rel_resid receives
+ * ||phi - D^dagger D x|| / ||phi|| recomputed at the end.
+ */
+int orc_cg(int Lx, int Lt, double m0, const double *q, const cplx *phi, cplx *x, double tol,
+           int max_iter, double *true_rel_resid)
+{
+    int ns = 2 * Lx * Lt;
+    cplx *r = malloc(sizeof(cplx) * ns), *p = malloc(sizeof(cplx) * ns);
+    cplx *Ap = malloc(sizeof(cplx) * ns), *tmp = malloc(sizeof(cplx) * ns);
+    for (int i = 0; i < ns; ++i) { x[i] = 0; r[i] = phi[i]; p[i] = phi[i]; }
+    double phi2 = dot_re(ns, phi, phi);
+    double rho = phi2;
+    int it = 0, converged = (rho <= tol * tol * phi2);
+    while (!converged && it < max_iter) {
+        normal_op(Lx, Lt, m0, q, p, tmp, Ap);
+        double alpha = rho / dot_re(ns, p, Ap);
+        for (int i = 0; i < ns; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * Ap[i]; }
+        double rho_new = dot_re(ns, r, r);
+        ++it;
+        if (rho_new <= tol * tol * phi2) { converged = 1; break; }
+        double beta = rho_new / rho;
+        for (int i = 0; i < ns; ++i) p[i] = r[i] + beta * p[i];
+        rho = rho_new;
+    }
+    if (true_rel_resid) {
+        normal_op(Lx, Lt, m0, q, x, tmp, Ap);
+        for (int i = 0; i < ns; ++i) r[i] = phi[i] - Ap[i];
+        *true_rel_resid = phi2 > 0 ? sqrt(dot_re(ns, r, r) / phi2) : 0.0;
+    }
+    free(r); free(p); free(Ap); free(tmp);
+    return converged ? it : -1;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Fermion action (Eq. (14)) and fermion force (Eqs. (17), (18))             */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * f(n, mu) = -Im[ chi^dagger(n) (1 - sigma_mu) U_mu(n) xi(n + mu)
+ *                 - chi^dagger(n + mu) (1 + sigma_mu) U_mu^dagger(n) xi(n) ]
+ * with chi = D^{dagger -1} eta and xi = D^{-1} D^{dagger -1} eta, Eqs. (17)-(18).
+ * The fermion link (with the boundary sign) enters; its derivative in q is i times itself.
+ */
+void orc_fermion_force_chixi(int Lx, int Lt, const double *q, const cplx *chi, const cplx *xi,
+                             double *f)
+{
+    for (int n = 0; n < Lx * Lt; ++n)
+        for (int mu = 0; mu < 2; ++mu) {
+            int nf = hop(n, mu, +1, Lx, Lt);
+            cplx u = flink(q, n, mu, Lx, Lt);
+            cplx a[2] = {u * xi[2 * nf], u * xi[2 * nf + 1]};
+            cplx b[2] = {conj(u) * xi[2 * n], conj(u) * xi[2 * n + 1]};
+            cplx pa[2], pb[2];
+            proj(mu, -1, a, pa);
+            proj(mu, +1, b, pb);
+            cplx term1 = conj(chi[2 * n]) * pa[0] + conj(chi[2 * n + 1]) * pa[1];
+            cplx term2 = conj(chi[2 * nf]) * pb[0] + conj(chi[2 * nf + 1]) * pb[1];
+            f[2 * n + mu] = -cimag(term1 - term2);
+        }
+}
+
+/*
+ * Solves xi = (D^dagger D)^{-1} phi, forms chi = D xi (= D^{dagger -1} phi) and the
+ * force f = dS_F/dq.  Optional outputs: chi, xi, S_F = Re phi^dagger xi.
+ * Returns CG iterations or -1 on non-convergence.
+ */
+int orc_fermion_force(int Lx, int Lt, double m0, const double *q, const cplx *phi, double tol,
+                      int max_iter, double *f, cplx *chi_out, cplx *xi_out, double *sf_out)
+{
+    int ns = 2 * Lx * Lt;
+    cplx *xi = malloc(sizeof(cplx) * ns), *chi = malloc(sizeof(cplx) * ns);
+    int it = orc_cg(Lx, Lt, m0, q, phi, xi, tol, max_iter, NULL);
+    orc_dirac(Lx, Lt, m0, q, xi, chi);
+    if (f) orc_fermion_force_chixi(Lx, Lt, q, chi, xi, f);
+    if (sf_out) *sf_out = dot_re(ns, phi, xi);
+    if (chi_out) memcpy(chi_out, chi, sizeof(cplx) * ns);
+    if (xi_out) memcpy(xi_out, xi, sizeof(cplx) * ns);
+    free(xi); free(chi);
+    return it;
+}
+
+/* S_F = phi^dagger (D^dagger D)^{-1} phi, Eq. (14) */
+double orc_fermion_action(int Lx, int Lt, double m0, const double *q, const cplx *phi, double tol,
+                          int max_iter)
+{
+    double sf = 0;
+    orc_fermion_force(Lx, Lt, m0, q, phi, tol, max_iter, NULL, NULL, NULL, &sf);
+    return sf;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Molecular dynamics (Sec. 2.1, 2.2)                                        */
+/* ------------------------------------------------------------------------- */
+
+enum {
+    SCHEME_LEAPFROG = 0,          /* Eq. (3)  */
+    SCHEME_OMELYAN_5STAGE = 1,    /* Eq. (4)  */
+    SCHEME_FORCE_GRADIENT = 2,    /* Eq. (5), force-gradient term via the shifted force */
+    SCHEME_NESTED_FG = 3,         /* Eq. (10) */
+    SCHEME_ADAPTED_NESTED_FG = 4, /* Eq. (11) */
+};
+
+/* stage kinds recorded in the trace */
+enum {
+    ST_A = 0,      /* e^{eps A}: q += eps p */
+    ST_B = 1,      /* kick with the full force F_G + F_F */
+    ST_BG = 2,     /* kick with the gauge force only (fast part B_1) */
+    ST_BF = 3,     /* kick with the fermion force only (slow part B_2) */
+    ST_BT = 4,     /* force-gradient kick with the full force */
+    ST_BTG = 5,    /* force-gradient kick with the gauge force */
+    ST_BTF = 6,    /* force-gradient kick with the fermion force */
+};
+
+#define FLAG_QUENCHED 1 /* drop S_F entirely (pure gauge HMC, used for exact-plaquette tests) */
+
+typedef struct {
+    int Lx, Lt, flags;
+    double beta, m0, tol;
+    int max_iter;
+    double *q, *p;
+    const cplx *phi;
+    double *F, *F2, *qs; /* scratch: force, shifted force, saved links */
+    /* counters */
+    long n_solves, n_cg_iters;
+    int failed;
+    /* optional stage trace */
+    int *trace_kind;
+    double *trace_eps;
+    int trace_cap, trace_len;
+} md_state;
+
+static void trace(md_state *s, int kind, double eps)
+{
+    if (s->trace_kind && s->trace_len < s->trace_cap) {
+        s->trace_kind[s->trace_len] = kind;
+        s->trace_eps[s->trace_len] = eps;
+    }
+    s->trace_len++;
+}
+
+/* F = dS_G/dq (+ dS_F/dq); which: 0 gauge, 1 fermion, 2 total */
+static void force(md_state *s, int which, const double *q, double *F)
+{
+    int nl = 2 * s->Lx * s->Lt;
+    int use_f = !(s->flags & FLAG_QUENCHED);
+    if (which == 0 || which == 2) orc_gauge_force(s->Lx, s->Lt, s->beta, q, F);
+    else for (int l = 0; l < nl; ++l) F[l] = 0;
+    if ((which == 1 || which == 2) && use_f) {
+        double *ff = malloc(sizeof(double) * nl);
+        int it = orc_fermion_force(s->Lx, s->Lt, s->m0, q, s->phi, s->tol, s->max_iter, ff, NULL,
+                                   NULL, NULL);
+        s->n_solves++;
+        if (it < 0) { s->failed = 1; it = s->max_iter; }
+        s->n_cg_iters += it;
+        for (int l = 0; l < nl; ++l) F[l] += ff[l];
+        free(ff);
+    }
+}
+
+/* e^{eps A}: U' = exp(i P eps) U, i.e. q' = q + eps p (Sec. 2.1) */
+static void stage_A(md_state *s, double eps)
+{
+    int nl = 2 * s->Lx * s->Lt;
+    for (int l = 0; l < nl; ++l) s->q[l] += eps * s->p[l];
+    trace(s, ST_A, eps);
+}
+
+/* e^{eps B}: p' = p - eps F (Sec. 2.1; the momenta are real for U(1)) */
+static void stage_B(md_state *s, int which, double eps)
+{
+    int nl = 2 * s->Lx * s->Lt;
+    force(s, which, s->q, s->F);
+    for (int l = 0; l < nl; ++l) s->p[l] -= eps * s->F[l];
+    trace(s, which == 0 ? ST_BG : which == 1 ? ST_BF : ST_B, eps);
+}
+
+/*
+ * Force-gradient kick e^{eps B + c h^3 C} with eps = 2h/3 and the force-gradient
+ * term approximated through a force evaluated at shifted links (Sec. 2.2, the
+ * Taylor-expansion variant): the kick is p' = p - eps F(q - (h^2/24) F(q)), which
+ * equals p - eps F + (h^3/72) C + O(h^5) with C = grad |F|^2 of Eq. (19).  The
+ * links are restored afterwards.  `h` is the step of the level the kick belongs to.
+ */
+static void stage_B_fg(md_state *s, int which, double eps, double h)
+{
+    int nl = 2 * s->Lx * s->Lt;
+    force(s, which, s->q, s->F);
+    for (int l = 0; l < nl; ++l) s->qs[l] = s->q[l] - (h * h / 24.0) * s->F[l];
+    force(s, which, s->qs, s->F2);
+    for (int l = 0; l < nl; ++l) s->p[l] -= eps * s->F2[l];
+    trace(s, which == 0 ? ST_BTG : which == 1 ? ST_BTF : ST_BT, eps);
+}
+
+/* Delta_1(s)_M = (e^{s/(2M) B_1} e^{s/M A} e^{s/(2M) B_1})^M, the inner leapfrog of Eq. (8) */
+static void inner_leapfrog(md_state *st, double s, int M)
+{
+    for (int k = 0; k < M; ++k) {
+        stage_B(st, 0, s / (2.0 * M));
+        stage_A(st, s / M);
+        stage_B(st, 0, s / (2.0 * M));
+    }
+}
+
+/* Delta_2(s)_M of Eq. (10): M inner 5-stage force-gradient steps of size s/M on A + B_1 */
+static void inner_fg(md_state *st, double s, int M)
+{
+    double hm = s / M;
+    for (int k = 0; k < M; ++k) {
+        stage_B(st, 0, hm / 6.0);
+        stage_A(st, hm / 2.0);
+        stage_B_fg(st, 0, 2.0 * hm / 3.0, hm);
+        stage_A(st, hm / 2.0);
+        stage_B(st, 0, hm / 6.0);
+    }
+}
+
+/* one outer step of size h */
+static void md_step(md_state *s, int scheme, double h, int M)
+{
+    switch (scheme) {
+    case SCHEME_LEAPFROG: /* Eq. (3) */
+        stage_B(s, 2, h / 2.0);
+        stage_A(s, h);
+        stage_B(s, 2, h / 2.0);
+        break;
+    case SCHEME_OMELYAN_5STAGE: /* Eq. (4) */
+        stage_B(s, 2, h / 6.0);
+        stage_A(s, h / 2.0);
+        stage_B(s, 2, 2.0 * h / 3.0);
+        stage_A(s, h / 2.0);
+        stage_B(s, 2, h / 6.0);
+        break;
+    case SCHEME_FORCE_GRADIENT: /* Eq. (5) */
+        stage_B(s, 2, h / 6.0);
+        stage_A(s, h / 2.0);
+        stage_B_fg(s, 2, 2.0 * h / 3.0, h);
+        stage_A(s, h / 2.0);
+        stage_B(s, 2, h / 6.0);
+        break;
+    case SCHEME_NESTED_FG: /* Eq. (10) */
+        stage_B(s, 1, h / 6.0);
+        inner_fg(s, h / 2.0, M);
+        stage_B_fg(s, 1, 2.0 * h / 3.0, h);
+        inner_fg(s, h / 2.0, M);
+        stage_B(s, 1, h / 6.0);
+        break;
+    case SCHEME_ADAPTED_NESTED_FG: /* Eq. (11) */
+        stage_B(s, 1, h / 6.0);
+        inner_leapfrog(s, h / 2.0, M);
+        stage_B_fg(s, 1, 2.0 * h / 3.0, h);
+        inner_leapfrog(s, h / 2.0, M);
+        stage_B(s, 1, h / 6.0);
+        break;
+    }
+}
+
+/*
+ * Integrates Hamilton's equations (Eq. (2)) for a trajectory of length tau with
+ * n_outer steps h = tau / n_outer; n_inner = M is the number of inner steps in
+ * each inner call of the nested schemes.  q and p are updated in place.
+ * counters[0] = fermion solves, counters[1] = total CG iterations,
+ * counters[2] = stages recorded.  Returns 0, or -3 if a solve did not converge.
+ */
+int orc_md_integrate(int Lx, int Lt, double beta, double m0, int scheme, double tau, int n_outer,
+                     int n_inner, double tol, int max_iter, int flags, double *q, double *p,
+                     const cplx *phi, long *counters, int *trace_kind, double *trace_eps,
+                     int trace_cap)
+{
+    int nl = 2 * Lx * Lt;
+    md_state s;
+    memset(&s, 0, sizeof(s));
+    s.Lx = Lx; s.Lt = Lt; s.flags = flags; s.beta = beta; s.m0 = m0; s.tol = tol;
+    s.max_iter = max_iter; s.q = q; s.p = p; s.phi = phi;
+    s.F = malloc(sizeof(double) * nl);
+    s.F2 = malloc(sizeof(double) * nl);
+    s.qs = malloc(sizeof(double) * nl);
+    s.trace_kind = trace_kind; s.trace_eps = trace_eps; s.trace_cap = trace_cap;
+    double h = tau / n_outer;
+    for (int k = 0; k < n_outer; ++k) md_step(&s, scheme, h, n_inner);
+    free(s.F); free(s.F2); free(s.qs);
+    if (counters) {
+        counters[0] = s.n_solves;
+        counters[1] = s.n_cg_iters;
+        counters[2] = s.trace_len;
+    }
+    return s.failed ? -3 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* HMC update (Sec. 2.1)                                                     */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * One HMC trajectory from links q (updated in place on acceptance):
+ *   p ~ N(0,1) (stream 1), zeta complex Gaussian (stream 2), phi = D^dagger zeta, so that
+ *   phi is distributed as exp(-S_F) of Eq. (14) and S_F(U0) = zeta^dagger zeta exactly;
+ *   molecular dynamics to (q', p'); Delta H = H(q', p') - H(q, p) summed as a sum of
+ *   per-term differences; accept iff Delta H <= 0 or u < exp(-Delta H) with u from stream 3.
+ * info[0] = Delta H, info[1] = accepted (0/1), info[2] = mean plaquette after the update,
+ * info[3] = fermion solves, info[4] = total CG iterations, info[5] = H0, info[6] = H1,
+ * info[7] = Metropolis uniform.
+ * Returns 0, -3 (CG failure: trajectory rejected) or -5 (non-finite Delta H: rejected).
+ */
+int orc_hmc_trajectory(int Lx, int Lt, double beta, double m0, uint64_t seed, uint32_t chain,
+                       uint32_t traj, int scheme, double tau, int n_outer, int n_inner, double tol,
+                       int max_iter, int flags, double *q, double *info)
+{
+    int V = Lx * Lt, nl = 2 * V, ns = 2 * V;
+    double *q0 = malloc(sizeof(double) * nl), *p = malloc(sizeof(double) * nl);
+    double *p0 = malloc(sizeof(double) * nl);
+    cplx *zeta = malloc(sizeof(cplx) * ns), *phi = malloc(sizeof(cplx) * ns);
+    cplx *xi = malloc(sizeof(cplx) * ns);
+    memcpy(q0, q, sizeof(double) * nl);
+    orc_random_momenta(Lx, Lt, seed, chain, traj, p);
+    memcpy(p0, p, sizeof(double) * nl);
+    int quenched = flags & FLAG_QUENCHED;
+    if (!quenched) {
+        orc_random_zeta(Lx, Lt, seed, chain, traj, zeta);
+        orc_dirac_dagger(Lx, Lt, m0, q, zeta, phi);
+    } else {
+        for (int k = 0; k < ns; ++k) phi[k] = 0;
+    }
+    long counters[3] = {0, 0, 0};
+    int rc = orc_md_integrate(Lx, Lt, beta, m0, scheme, tau, n_outer, n_inner, tol, max_iter,
+                              flags, q, p, phi, counters, NULL, NULL, 0);
+    double sf1 = 0, sf0 = 0;
+    if (!quenched) {
+        int it = orc_cg(Lx, Lt, m0, q, phi, xi, tol, max_iter, NULL);
+        counters[0]++;
+        if (it < 0) { rc = -3; it = max_iter; }
+        counters[1] += it;
+        sf1 = dot_re(ns, phi, xi);
+        sf0 = dot_re(ns, zeta, zeta);
+    }
+    /* Delta H as a sum of differences (Eq. (12)) */
+    ksum dk = {0, 0}, dg = {0, 0};
+    ksum h0 = {0, 0}, h1 = {0, 0};
+    for (int l = 0; l < nl; ++l) {
+        kadd(&dk, 0.5 * (p[l] - p0[l]) * (p[l] + p0[l]));
+        kadd(&h0, 0.5 * p0[l] * p0[l]);
+        kadd(&h1, 0.5 * p[l] * p[l]);
+    }
+    for (int n = 0; n < V; ++n) {
+        double c0 = creal(plaquette(q0, n, 0, 1, Lx, Lt)), c1 = creal(plaquette(q, n, 0, 1, Lx, Lt));
+        kadd(&dg, c0 - c1);
+        kadd(&h0, beta * (1.0 - c0));
+        kadd(&h1, beta * (1.0 - c1));
+    }
+    double dH = kval(&dk) + beta * kval(&dg) + (sf1 - sf0);
+    kadd(&h0, sf0);
+    kadd(&h1, sf1);
+    double u = orc_metropolis_uniform(seed, chain, traj);
+    int accept = 0;
+    if (rc == 0 && !isfinite(dH)) rc = -5;
+    if (rc == 0) accept = (dH <= 0.0) || (u < exp(-dH));
+    if (!accept) memcpy(q, q0, sizeof(double) * nl);
+    if (info) {
+        info[0] = dH; info[1] = accept; info[2] = orc_mean_plaquette(Lx, Lt, q);
+        info[3] = (double)counters[0]; info[4] = (double)counters[1];
+        info[5] = kval(&h0); info[6] = kval(&h1); info[7] = u;
+    }
+    free(q0); free(p); free(p0); free(zeta); free(phi); free(xi);
+    return rc;
+}
