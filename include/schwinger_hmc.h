@@ -1,0 +1,256 @@
+/*
+ * schwinger_hmc.h -- C ABI of the MI355X (gfx950) library for the hot path of the HMC
+ * of the two-flavour lattice Schwinger model with (adapted) nested force-gradient
+ * integrators (Shcherbakov, Ehrhardt, Finkenrath, Guenther, Knechtli, Peardon,
+ * arXiv:1512.03812).
+ *
+ * Model (Sec. 3): an Lx x Lt lattice with U(1) links U_mu(n) = exp(i q_mu(n)), real
+ * momenta p_mu(n), H = 1/2 sum p^2 + S_G + S_F (Eq. (12)), Wilson gauge action S_G
+ * (Eq. (13)), pseudofermion action S_F = phi^dagger (D^dagger D)^{-1} phi (Eq. (14))
+ * with the two-component Wilson-Dirac operator D of Sec. 3.  Gauge field periodic;
+ * fermions periodic in x and antiperiodic in t (the paper leaves the boundary
+ * conditions open; this library fixes that reading).
+ *
+ * Memory and ownership
+ *   - The library never allocates device memory.  The caller allocates one device
+ *     workspace of hmc_workspace_bytes() bytes (e.g. a torch tensor) and binds it with
+ *     hmc_bind(); every field of the context lives inside it.  All other device
+ *     pointers passed in are owned by the caller and are never freed.
+ *   - All device work is enqueued on the HIP stream given to hmc_bind() (NULL = the
+ *     default stream).  Calls that return per-chain info structs synchronise that
+ *     stream before returning; the others return as soon as the work is enqueued.
+ *   - The only host allocations are the context itself and a small pinned staging
+ *     buffer for scalar read-backs (hipHostMalloc), both released by hmc_destroy().
+ *
+ * Native field layout (device pointers; see hmc_field / hmc_pack_*):
+ *   A context holds n_chains independent lattices in one flat site space of V_total
+ *   sites; chain c owns sites [offset_c, offset_c + Lx_c*Lt_c).  Inside a chain sites
+ *   are ordered by parity (x+t)&1, then t, then x/2 (even-odd / checkerboard order).
+ *   real link field (q, p, forces): double[2][V_total]          (mu = 0 is x, 1 is t)
+ *   spinor field                  : double[2][V_total][2]       (spin s, then re/im)
+ *   The lexicographic layout used by hmc_pack_* / hmc_unpack_* is, per chain,
+ *   links double[Lt][Lx][2] (index 2n+mu, n = x + Lx t) and spinors
+ *   double[Lt][Lx][2][2] (index 2n+s, then re/im), chains concatenated in order.
+ *
+ * Errors: every int-returning call returns HMC_OK (0) or a negative code; the text of
+ * the last error is available from hmc_last_error().  A NULL context gives HMC_E_INVAL.
+ */
+#ifndef SCHWINGER_HMC_H
+#define SCHWINGER_HMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HMC_OK = 0,
+    HMC_E_INVAL = -1,   /* invalid argument (sizes, non-finite parameters, unbound context) */
+    HMC_E_NOMEM = -2,   /* workspace too small */
+    HMC_E_NOCONV = -3,  /* a CG solve hit max_iter before reaching its tolerance */
+    HMC_E_HIP = -4,     /* a HIP runtime call failed */
+    HMC_E_NAN = -5      /* a non-finite energy difference (the trajectory is rejected) */
+};
+
+/* Integrators of Sec. 2.2 */
+enum {
+    HMC_LEAPFROG = 0,          /* Eq. (3) */
+    HMC_OMELYAN_5STAGE = 1,    /* Eq. (4): 5-stage scheme, lambda = 1/6 */
+    HMC_FORCE_GRADIENT = 2,    /* Eq. (5), force-gradient term via the shifted force */
+    HMC_NESTED_FG = 3,         /* Eq. (10) */
+    HMC_ADAPTED_NESTED_FG = 4  /* Eq. (11) */
+};
+
+enum { HMC_PREC_FP64 = 0, HMC_PREC_MIXED = 1 };
+
+/* which force for hmc_fg_shifted_force */
+enum { HMC_FORCE_GAUGE = 0, HMC_FORCE_FERMION = 1, HMC_FORCE_TOTAL = 2 };
+
+/* named fields inside the bound workspace (hmc_field) */
+enum {
+    HMC_FIELD_Q = 0,    /* link angles q, real link field (the state of the chains) */
+    HMC_FIELD_P = 1,    /* momenta p, real link field */
+    HMC_FIELD_PHI = 2,  /* pseudofermion phi of the current trajectory, spinor field */
+    HMC_FIELD_CHI = 3,  /* chi = D xi after the last fermion force, spinor field (Eq. (18)) */
+    HMC_FIELD_XI = 4,   /* xi = (D^dagger D)^{-1} phi after the last fermion force, spinor field */
+    HMC_FIELD_F = 5,    /* last force written by a trajectory, real link field */
+    HMC_FIELD_ZETA = 6  /* Gaussian zeta of the last refresh (phi = D^dagger zeta), spinor field */
+};
+
+typedef struct hmc_ctx hmc_ctx;
+
+/* per-chain result of a CG solve */
+typedef struct {
+    int iters;             /* CG iterations (FP32 iterations in mixed precision) */
+    int converged;         /* 1 if the tolerance was reached */
+    int reliable_updates;  /* FP64 residual recomputations (mixed precision), else 0 */
+    int pad;
+    double rel_resid;      /* ||r|| / ||phi|| of the solver's own residual */
+    double rel_resid_true; /* ||phi - D^dagger D x|| / ||phi|| recomputed in FP64 */
+} hmc_cg_info;
+
+/* per-chain result of one HMC trajectory (Sec. 2.1) */
+typedef struct {
+    double dH;           /* H(U', P') - H(U, P), summed as per-term differences */
+    double H0, H1;       /* Hamiltonian (Eq. (12)) before and after the molecular dynamics */
+    double plaquette;    /* mean Re P(n) of the chain after the Metropolis step */
+    double u;            /* Metropolis uniform */
+    int accepted;        /* 1 if U' was accepted */
+    int status;          /* HMC_OK, HMC_E_NOCONV or HMC_E_NAN for this chain */
+    int n_force_evals;   /* fermion-force evaluations of the molecular dynamics */
+    int n_solves;        /* CG solves actually run (repeated forces at unchanged links are reused) */
+    int n_dinv;          /* inversions of D in the paper's count (2 per fermion-force evaluation) */
+    int pad;
+    long long n_cg_iters;  /* total CG iterations of this chain over the trajectory */
+} hmc_traj_info;
+
+/* ---------------------------------------------------------------- set-up */
+
+/* One Lx = Lt = L chain.  L even and >= 2; beta, m0 finite.  The Philox key is seed;
+ * the chain index (counter word 3) is 0.  Links start cold (q = 0). */
+int hmc_init(hmc_ctx **out, int L, double beta, double m0, uint64_t seed);
+
+/* One Lx x Lt chain (both even, >= 2). */
+int hmc_init_ex(hmc_ctx **out, int Lx, int Lt, double beta, double m0, uint64_t seed);
+
+/* n_chains independent chains (chain c uses Philox chain index c). */
+int hmc_batch_init(hmc_ctx **out, int n_chains, const int *Lx, const int *Lt, const double *beta,
+                   const double *m0, uint64_t seed);
+
+/* Device bytes the caller must provide to hmc_bind(). */
+size_t hmc_workspace_bytes(const hmc_ctx *ctx);
+
+/* Binds the caller-owned device workspace (>= hmc_workspace_bytes, 256-byte aligned)
+ * and the HIP stream (hipStream_t passed as void*).  Must precede every device call;
+ * may be called again to move the context to another workspace/stream (fields are
+ * not copied). */
+int hmc_bind(hmc_ctx *ctx, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/* Device pointer (and size in bytes) of a named field inside the workspace. */
+int hmc_field(hmc_ctx *ctx, int which, void **dev_ptr, size_t *bytes);
+
+/* n_chains, V_total, and per chain (arrays of n_chains, any may be NULL) the flat
+ * offset and extents. */
+int hmc_geometry(const hmc_ctx *ctx, int *n_chains, long long *v_total, int *offsets, int *Lx,
+                 int *Lt);
+
+/* Layout conversion between the lexicographic and the native layout (device pointers,
+ * the two buffers must not overlap). */
+int hmc_pack_links(hmc_ctx *ctx, const double *lexico, double *native);
+int hmc_unpack_links(hmc_ctx *ctx, const double *native, double *lexico);
+int hmc_pack_spinor(hmc_ctx *ctx, const double *lexico, double *native);
+int hmc_unpack_spinor(hmc_ctx *ctx, const double *native, double *lexico);
+
+/* Links: q = 0 (cold) or q uniform in [-pi, pi) from Philox stream 0 (hot start). */
+int hmc_cold_start(hmc_ctx *ctx);
+int hmc_hot_start(hmc_ctx *ctx);
+
+/* Trajectory counter used as Philox counter word 2 by the next hmc_trajectory
+ * (starts at 0, incremented by every trajectory; set it to resume a chain). */
+int hmc_set_trajectory_counter(hmc_ctx *ctx, uint32_t traj);
+uint32_t hmc_get_trajectory_counter(const hmc_ctx *ctx);
+
+/* Solver tolerance and iteration cap used inside hmc_trajectory (default 1e-12, 100000).
+ * reliable_delta: in mixed precision, the FP64 residual is recomputed whenever the
+ * FP32 residual has dropped by this factor (default 0.1). */
+int hmc_set_solver(hmc_ctx *ctx, double tol, int max_iter, double reliable_delta);
+
+/* Drop the fermion action (pure-gauge HMC; used to check the gauge part against the exact
+ * plaquette of 2-D U(1)).  Default 0. */
+int hmc_set_quenched(hmc_ctx *ctx, int quenched);
+
+/* Every `every` CG iterations the host reads back how many chains have converged
+ * (default 8).  Iterations launched after a chain converged do no work for it. */
+int hmc_set_check_interval(hmc_ctx *ctx, int every);
+
+/* ---------------------------------------------------------------- operators (Sec. 3) */
+
+/* out = D in: (D psi)(n) = (2+m0) psi(n) - 1/2 sum_mu [(1 - sigma_mu) U_mu(n) psi(n+mu)
+ * + (1 + sigma_mu) U_mu^dagger(n-mu) psi(n-mu)], links from the context's q.
+ * in/out: native spinor fields (device), must not overlap. */
+int hmc_dslash(hmc_ctx *ctx, const void *in, void *out);
+
+/* out = D^dagger in (the conjugate transpose of D above). */
+int hmc_dslash_dagger(hmc_ctx *ctx, const void *in, void *out);
+
+/* Solves D^dagger D x = phi for every chain by CG from x = 0 (the "D^{-1}" of Sec. 3:
+ * one solve is two inversions of D).  Stops per chain when ||r|| <= tol ||phi||;
+ * prec = HMC_PREC_MIXED runs the iterations in FP32 with FP64 reliable updates and
+ * stops on the FP64 true residual.  info: array of n_chains (may be NULL).
+ * Returns HMC_E_NOCONV if any chain hit max_iter (x then holds its last iterate). */
+int hmc_cg_solve(hmc_ctx *ctx, const void *phi, void *x, double tol, int max_iter, int prec,
+                 hmc_cg_info *info);
+
+/* ---------------------------------------------------------------- forces (Sec. 3) */
+
+/* f = dS_F/dq (Eqs. (17), (18)): solves xi = (D^dagger D)^{-1} phi, forms chi = D xi and
+ * evaluates the fermion force into the real link field f (device, caller-owned).
+ * chi and xi stay in the workspace (HMC_FIELD_CHI / HMC_FIELD_XI).  sf (n_chains
+ * doubles, host, may be NULL) receives S_F = Re phi^dagger xi per chain.  f may be NULL:
+ * then only xi, chi and S_F are formed (the forward pass of an adjoint-force pair). */
+int hmc_fermion_force(hmc_ctx *ctx, const void *phi, double *f, double tol, int max_iter, int prec,
+                      hmc_cg_info *info, double *sf);
+
+/* The force kernel alone: f from given chi, xi (the adjoint of S_F, Eq. (17)). */
+int hmc_fermion_force_chixi(hmc_ctx *ctx, const void *chi, const void *xi, double *f);
+
+/* F = dS_G/dq + dS_F/dq (Eq. (15)) with the fermion part from given chi, xi: the adjoint
+ * of S = S_G + S_F, used as the backward pass of an autograd function. */
+int hmc_total_force_chixi(hmc_ctx *ctx, const void *chi, const void *xi, double *F);
+
+/* g = dS_G/dq = beta Im(P_{mu nu}(n) - P_{mu nu}(n - nu)), Eq. (16), from the context's q. */
+int hmc_gauge_force(hmc_ctx *ctx, double *g);
+
+/* Actions per chain (host arrays of n_chains, any may be NULL): S_G (Eq. (13)), mean
+ * plaquette, and, if phi is not NULL, S_F = phi^dagger (D^dagger D)^{-1} phi (Eq. (14))
+ * solved to tol in FP64. */
+int hmc_actions(hmc_ctx *ctx, const void *phi, double tol, double *s_gauge, double *plaquette,
+                double *s_fermion);
+
+/* ---------------------------------------------------------------- updates (Sec. 2.1) */
+
+/* e^{eps A}: q += eps p (U' = exp(i p eps) U) on the context's fields. */
+int hmc_update_links(hmc_ctx *ctx, double eps);
+
+/* e^{eps B}: p -= eps F, F a real link field (device). */
+int hmc_update_momenta(hmc_ctx *ctx, double eps, const double *F);
+
+/* Force at the force-gradient-shifted links: F_out = F(q + c_h2 F(q)) with F the gauge,
+ * fermion or total force (which = HMC_FORCE_*); c_h2 = -h^2/24 gives the Taylor form of
+ * the force-gradient kick (Sec. 2.2).  q itself is left unchanged.  phi is needed unless
+ * which == HMC_FORCE_GAUGE.  info: n_chains entries for the last solve (may be NULL). */
+int hmc_fg_shifted_force(hmc_ctx *ctx, double c_h2, int which, const void *phi, double *F_out,
+                         int prec, hmc_cg_info *info);
+
+/* ---------------------------------------------------------------- HMC (Sec. 2.1, 2.2) */
+
+/* One HMC trajectory for every chain: momentum and pseudofermion refresh from Philox
+ * streams 1 and 2 (phi = D^dagger zeta), molecular dynamics with the given scheme
+ * (h = tau / n_outer; n_inner = M inner steps per inner call of the nested schemes,
+ * ignored otherwise), Delta H in FP64, Metropolis test with stream 3, links restored on
+ * rejection.  info: n_chains entries (may be NULL).  Returns HMC_OK, or the first
+ * failing chain's status (the failing chain is rejected, the others proceed). */
+int hmc_trajectory(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inner, int prec,
+                   hmc_traj_info *info);
+
+/* The refresh of Sec. 2.1 alone, for the current trajectory counter (not incremented):
+ * p ~ N(0,1) from Philox stream 1, zeta with density exp(-zeta^dagger zeta) from stream 2,
+ * phi = D^dagger zeta at the current links (so S_F(U) = zeta^dagger zeta). */
+int hmc_refresh(hmc_ctx *ctx);
+
+/* Molecular dynamics only, from the context's q, p and phi (no refresh, no Metropolis). */
+int hmc_integrate(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inner, int prec,
+                  hmc_traj_info *info);
+
+/* ---------------------------------------------------------------- misc */
+
+const char *hmc_last_error(const hmc_ctx *ctx);
+int hmc_destroy(hmc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCHWINGER_HMC_H */

@@ -1,0 +1,950 @@
+// Host runtime and C ABI of the Schwinger-model HMC library: context and workspace,
+// CG drivers (FP64 and mixed precision), force evaluation, the integrators of Sec. 2.2
+// and the HMC update of Sec. 2.1.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/schwinger_hmc.h"
+#include "kernels.hpp"
+
+using namespace shmc;
+
+namespace {
+
+constexpr int kNumXcd = 8;        // XCDs of an MI355X; workgroups are dealt to them round robin
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Names of the real-link and spinor buffers carved out of the workspace.
+enum LinkBuf { LQ, LP, LQ0, LP0, LQS, LF, LFF, LFT, LG, kNumLinkBufs };
+enum SpinBuf { SPHI, SZETA, SXI, SCHI, SR, SPA, SPB, ST, kNumSpinBufs };
+enum Spin32Buf { FX, FR, FT, FPA, FPB, kNumSpin32Bufs };
+
+}  // namespace
+
+struct hmc_ctx {
+    // ------------------------------------------------------------ geometry (host)
+    int nchains = 0;
+    int Vtot = 0;
+    int block = 256;
+    std::vector<ChainInfo> chains;
+    std::vector<BlockWork> work;
+    uint64_t seed = 0;
+    uint32_t traj = 0;
+    // ------------------------------------------------------------ solver settings
+    double tol = 1e-12;
+    int max_iter = 100000;
+    double delta = 0.1;
+    int check_every = 8;
+    bool quenched = false;
+    // ------------------------------------------------------------ workspace
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    size_t off_chains = 0, off_work = 0, off_cg = 0, off_partials = 0, off_counters = 0,
+           off_sums = 0, off_metro = 0, off_status = 0, off_count = 0, off_links[kNumLinkBufs] = {},
+           off_spin[kNumSpinBufs] = {}, off_U64 = 0, off_U32 = 0, off_spin32[kNumSpin32Bufs] = {};
+    // ------------------------------------------------------------ pinned host staging
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    // ------------------------------------------------------------ state tracking
+    long q_version = 0;      // bumped whenever Q changes inside the library
+    long links_version = -1; // q version the materialised FP64 links belong to (-1: none / other q)
+    long links32_version = -1; // same for the FP32 copy
+    long ff_version = -1;    // q version of the cached fermion force LFF (-1: none)
+    long xi_version = -1;    // q version of the solution in SXI (-1: none / shifted links)
+    std::string err;
+    // per-solve bookkeeping of the last CG (host copies)
+    std::vector<CGState> cg_host;
+
+    // ------------------------------------------------------------ accessors
+    template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    double *link(int b) const { return at<double>(off_links[b]); }
+    double2 *spin(int b) const { return at<double2>(off_spin[b]); }
+    float2 *spin32(int b) const { return at<float2>(off_spin32[b]); }
+    double2 *U64() const { return at<double2>(off_U64); }
+    float2 *U32() const { return at<float2>(off_U32); }
+    CGState *cg() const { return at<CGState>(off_cg); }
+    double *sums() const { return at<double>(off_sums); }
+    Geo geo() const {
+        Geo g;
+        g.chains = at<ChainInfo>(off_chains);
+        g.work = at<BlockWork>(off_work);
+        g.nblocks = (int)work.size();
+        g.nchains = nchains;
+        g.Vtot = Vtot;
+        g.block = block;
+        return g;
+    }
+    Reduce red() const {
+        Reduce r;
+        r.partials = at<double>(off_partials);
+        r.counters = at<unsigned>(off_counters);
+        return r;
+    }
+};
+
+namespace {
+
+int fail(hmc_ctx *c, int code, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(ctx, HMC_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+#define CHECK_BOUND(ctx)                                                                        \
+    do {                                                                                        \
+        if (!(ctx)) return HMC_E_INVAL;                                                         \
+        if (!(ctx)->ws) return fail(ctx, HMC_E_INVAL, "context has no workspace bound");        \
+    } while (0)
+
+// Block table: every chain gets ceil(V / block) logical workgroups (chains contiguous in
+// logical order); hardware workgroup h runs on XCD h % 8, and the j-th workgroup of XCD k
+// receives logical workgroup start_k + j, so each XCD sweeps one contiguous site range.
+void build_tables(hmc_ctx *c) {
+    std::vector<BlockWork> logical;
+    for (int ch = 0; ch < c->nchains; ++ch) {
+        ChainInfo &ci = c->chains[ch];
+        ci.block0 = (int)logical.size();
+        ci.nblocks = (ci.V + c->block - 1) / c->block;
+        for (int j = 0; j < ci.nblocks; ++j) {
+            BlockWork w;
+            w.chain = ch;
+            w.start = j * c->block;
+            w.logical = (int)logical.size();
+            w.pad = 0;
+            logical.push_back(w);
+        }
+    }
+    const int N = (int)logical.size();
+    c->work.assign(N, BlockWork());
+    std::vector<int> start(kNumXcd + 1, 0);
+    for (int k = 0; k < kNumXcd; ++k) start[k + 1] = start[k] + N / kNumXcd + (k < N % kNumXcd ? 1 : 0);
+    for (int h = 0; h < N; ++h) c->work[h] = logical[start[h % kNumXcd] + h / kNumXcd];
+}
+
+void layout_workspace(hmc_ctx *c) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    const size_t C = c->nchains, N = c->work.size(), V = c->Vtot;
+    c->off_chains = take(sizeof(ChainInfo) * C);
+    c->off_work = take(sizeof(BlockWork) * N);
+    c->off_cg = take(sizeof(CGState) * C);
+    c->off_partials = take(sizeof(double) * kMaxReduce * N);
+    c->off_counters = take(sizeof(unsigned) * C);
+    c->off_sums = take(sizeof(double) * 16 * C);
+    c->off_metro = take(sizeof(MetroOut) * C);
+    c->off_status = take(sizeof(int) * C);
+    c->off_count = take(sizeof(int) * 4);
+    for (int b = 0; b < kNumLinkBufs; ++b) c->off_links[b] = take(sizeof(double) * 2 * V);
+    for (int b = 0; b < kNumSpinBufs; ++b) c->off_spin[b] = take(sizeof(double2) * 2 * V);
+    c->off_U64 = take(sizeof(double2) * 2 * V);
+    c->off_U32 = take(sizeof(float2) * 2 * V);
+    for (int b = 0; b < kNumSpin32Bufs; ++b) c->off_spin32[b] = take(sizeof(float2) * 2 * V);
+    c->ws_bytes = o;
+}
+
+int make_ctx(hmc_ctx **out, int n, const int *Lx, const int *Lt, const double *beta,
+             const double *m0, uint64_t seed) {
+    if (!out) return HMC_E_INVAL;
+    *out = nullptr;
+    if (n < 1 || !Lx || !Lt || !beta || !m0) return HMC_E_INVAL;
+    long long vt = 0;
+    for (int c = 0; c < n; ++c) {
+        if (Lx[c] < 2 || Lt[c] < 2 || (Lx[c] & 1) || (Lt[c] & 1)) return HMC_E_INVAL;
+        if (!isfinite(beta[c]) || !isfinite(m0[c])) return HMC_E_INVAL;
+        vt += (long long)Lx[c] * Lt[c];
+    }
+    if (vt > (1LL << 30)) return HMC_E_INVAL;  // flat indices are 32-bit
+    hmc_ctx *c = new hmc_ctx();
+    c->nchains = n;
+    c->seed = seed;
+    c->chains.resize(n);
+    int off = 0;
+    for (int k = 0; k < n; ++k) {
+        ChainInfo &ci = c->chains[k];
+        memset(&ci, 0, sizeof ci);
+        ci.off = off;
+        ci.Lx = Lx[k];
+        ci.Lt = Lt[k];
+        ci.hx = Lx[k] / 2;
+        ci.V = Lx[k] * Lt[k];
+        ci.Vh = ci.V / 2;
+        ci.beta = beta[k];
+        ci.m0 = m0[k];
+        ci.chain_id = (uint32_t)k;
+        off += ci.V;
+    }
+    c->Vtot = off;
+    build_tables(c);
+    layout_workspace(c);
+    c->cg_host.resize(n);
+    *out = c;
+    return HMC_OK;
+}
+
+// ------------------------------------------------------------------ helpers on a bound context
+int sync(hmc_ctx *c) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return HMC_OK;
+}
+
+int to_host(hmc_ctx *c, void *dst, const void *src_dev, size_t bytes) {
+    if (bytes > c->pinned_bytes) {
+        HIP_TRY(c, hipMemcpyAsync(dst, src_dev, bytes, hipMemcpyDeviceToHost, c->stream));
+        return sync(c);
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->pinned, src_dev, bytes, hipMemcpyDeviceToHost, c->stream));
+    int rc = sync(c);
+    if (rc) return rc;
+    memcpy(dst, c->pinned, bytes);
+    return HMC_OK;
+}
+
+void ensure_links(hmc_ctx *c, const double *q, bool need32, long version) {
+    // version >= 0 identifies q == LQ at that version; -1 forces a rebuild
+    const bool have64 = version >= 0 && c->links_version == version;
+    const bool have32 = version >= 0 && c->links32_version == version;
+    if (have64 && (!need32 || have32)) return;
+    launch_make_links(c->geo(), q, c->U64(), need32 ? c->U32() : nullptr, c->stream);
+    c->links_version = version;
+    c->links32_version = need32 ? version : -1;
+}
+
+void forget_links(hmc_ctx *c) { c->links_version = c->links32_version = -1; }
+
+void forget_all(hmc_ctx *c) {
+    c->q_version++;
+    forget_links(c);
+    c->ff_version = c->xi_version = -1;
+}
+
+__global__ void k_count_converged(const CGState *st, int n, int *out) {
+    __shared__ int sh;
+    if (threadIdx.x == 0) sh = 0;
+    __syncthreads();
+    int cnt = 0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) cnt += st[c].converged;
+    atomicAdd(&sh, cnt);
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = sh;
+}
+
+int all_converged(hmc_ctx *c, bool *done) {
+    hipLaunchKernelGGL(k_count_converged, dim3(1), dim3(256), 0, c->stream, c->cg(), c->nchains,
+                       c->at<int>(c->off_count));
+    int cnt = 0;
+    int rc = to_host(c, &cnt, c->at<int>(c->off_count), sizeof(int));
+    if (rc) return rc;
+    *done = cnt == c->nchains;
+    return HMC_OK;
+}
+
+// CG on D^dagger D x = phi with the links already materialised (U64, and U32 if mixed).
+// Per-chain results land in c->cg_host.  Returns HMC_E_NOCONV if a chain did not converge.
+int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, int prec) {
+    const Geo g = c->geo();
+    const Reduce r = c->red();
+    int rc = HMC_OK;
+    if (prec == HMC_PREC_FP64) {
+        launch_cg_init64(g, r, phi, x, c->spin(SR), c->cg(), tol, 0.0, c->stream);
+        double2 *pb[2] = {c->spin(SPA), c->spin(SPB)};
+        int cur = 0;
+        for (int it = 1; it <= max_iter; ++it) {
+            launch_cg_step64(g, r, c->U64(), x, c->spin(SR), pb[cur], pb[cur ^ 1], c->spin(ST),
+                             c->cg(), c->stream);
+            cur ^= 1;
+            if (it % c->check_every == 0 || it == max_iter) {
+                bool done = false;
+                if ((rc = all_converged(c, &done))) return rc;
+                if (done) break;
+            }
+        }
+    } else {
+        MixedFields m;
+        m.phi = phi;
+        m.x64 = x;
+        m.t64 = c->spin(ST);
+        m.x32 = c->spin32(FX);
+        m.r32 = c->spin32(FR);
+        m.t32 = c->spin32(FT);
+        launch_cg_init_mixed(g, r, m, c->cg(), tol, c->delta, c->stream);
+        float2 *pb[2] = {c->spin32(FPA), c->spin32(FPB)};
+        int cur = 0;
+        // iteration slots: FP32 iterations plus FP64 residual recomputations
+        const int max_slots = max_iter + max_iter / 2 + 64;
+        for (int it = 1; it <= max_slots; ++it) {
+            launch_cg_step_mixed(g, r, c->U64(), c->U32(), m, pb[cur], pb[cur ^ 1], c->cg(), c->stream);
+            cur ^= 1;
+            if (it % c->check_every == 0 || it == max_slots) {
+                bool done = false;
+                if ((rc = all_converged(c, &done))) return rc;
+                if (done) break;
+                // stop when every unconverged chain has used up its FP32 iterations
+                if ((rc = to_host(c, c->cg_host.data(), c->cg(), sizeof(CGState) * c->nchains))) return rc;
+                bool exhausted = true;
+                for (const CGState &s : c->cg_host)
+                    if (!s.converged && s.iters < max_iter) exhausted = false;
+                if (exhausted) break;
+            }
+        }
+        launch_cg_finish_mixed(g, m, c->cg(), c->stream);
+    }
+    if ((rc = to_host(c, c->cg_host.data(), c->cg(), sizeof(CGState) * c->nchains))) return rc;
+    for (const CGState &s : c->cg_host)
+        if (!s.converged) return fail(c, HMC_E_NOCONV, "CG did not converge in %d iterations", max_iter);
+    return HMC_OK;
+}
+
+void fill_cg_info(hmc_ctx *c, hmc_cg_info *info, const std::vector<double> *true2) {
+    if (!info) return;
+    for (int k = 0; k < c->nchains; ++k) {
+        const CGState &s = c->cg_host[k];
+        info[k].iters = s.iters;
+        info[k].converged = s.converged;
+        info[k].reliable_updates = s.n_updates;
+        info[k].pad = 0;
+        info[k].rel_resid = s.phi2 > 0 ? sqrt(s.rho / s.phi2) : 0.0;
+        info[k].rel_resid_true = (true2 && s.phi2 > 0) ? sqrt((*true2)[k] / s.phi2) : info[k].rel_resid;
+    }
+}
+
+// ------------------------------------------------------------------ molecular dynamics
+struct MD {
+    hmc_ctx *c;
+    int prec;
+    double tol;
+    int max_iter;
+    int status = HMC_OK;
+    std::vector<int> chain_status;
+    std::vector<long long> iters;
+    int force_evals = 0;
+    int solves = 0;
+};
+
+// fermion force at links q (== LQ when version >= 0) into out; XI/CHI keep xi and chi.
+int fermion_force_at(MD &md, const double *q, long version, double *out) {
+    hmc_ctx *c = md.c;
+    md.force_evals++;
+    if (version >= 0 && c->ff_version == version) {
+        if (out != c->link(LFF))
+            launch_copy(c->link(LFF), out, sizeof(double) * 2 * c->Vtot, c->stream);
+        return HMC_OK;
+    }
+    ensure_links(c, q, md.prec == HMC_PREC_MIXED, version);
+    int rc = solve(c, c->spin(SPHI), c->spin(SXI), md.tol, md.max_iter, md.prec);
+    md.solves++;
+    for (int k = 0; k < c->nchains; ++k) {
+        md.iters[k] += c->cg_host[k].iters;
+        if (!c->cg_host[k].converged) md.chain_status[k] = HMC_E_NOCONV;
+    }
+    if (rc == HMC_E_NOCONV) md.status = rc;
+    else if (rc) return rc;
+    launch_dslash64(c->geo(), c->U64(), c->spin(SXI), c->spin(SCHI), false, c->stream);
+    launch_fermion_force(c->geo(), c->U64(), c->spin(SCHI), c->spin(SXI), out, c->stream);
+    c->xi_version = version;
+    if (version >= 0) {
+        if (out != c->link(LFF))
+            launch_copy(out, c->link(LFF), sizeof(double) * 2 * c->Vtot, c->stream);
+        c->ff_version = version;
+    }
+    return HMC_OK;
+}
+
+// which: 0 gauge, 1 fermion, 2 total (F_G + F_F, added in that order)
+int force_at(MD &md, int which, const double *q, long version, double *out) {
+    hmc_ctx *c = md.c;
+    const Geo g = c->geo();
+    if (which == 0 || c->quenched) {
+        launch_gauge_force(g, q, nullptr, out, c->stream);
+        if (which == 1) launch_axpy_links(g, out, -1.0, out, out, c->stream);  // quenched: F_F = 0
+        return HMC_OK;
+    }
+    if (which == 1) return fermion_force_at(md, q, version, out);
+    int rc = fermion_force_at(md, q, version, c->link(LFT));
+    if (rc) return rc;
+    launch_gauge_force(g, q, c->link(LFT), out, c->stream);
+    return HMC_OK;
+}
+
+void stage_A(MD &md, double eps) {
+    hmc_ctx *c = md.c;
+    launch_axpy_links(c->geo(), c->link(LQ), eps, c->link(LP), c->link(LQ), c->stream);
+    c->q_version++;
+}
+
+int stage_B(MD &md, int which, double eps) {
+    hmc_ctx *c = md.c;
+    int rc = force_at(md, which, c->link(LQ), c->q_version, c->link(LF));
+    if (rc) return rc;
+    launch_axpy_links(c->geo(), c->link(LP), -eps, c->link(LF), c->link(LP), c->stream);
+    return HMC_OK;
+}
+
+// force-gradient kick: p -= eps F(q - (h^2/24) F(q)); q is untouched.
+int stage_B_fg(MD &md, int which, double eps, double h) {
+    hmc_ctx *c = md.c;
+    const Geo g = c->geo();
+    int rc = force_at(md, which, c->link(LQ), c->q_version, c->link(LF));
+    if (rc) return rc;
+    launch_axpy_links(g, c->link(LQ), -(h * h / 24.0), c->link(LF), c->link(LQS), c->stream);
+    rc = force_at(md, which, c->link(LQS), -1, c->link(LG));
+    if (rc) return rc;
+    forget_links(c);
+    launch_axpy_links(g, c->link(LP), -eps, c->link(LG), c->link(LP), c->stream);
+    return HMC_OK;
+}
+
+int inner_leapfrog(MD &md, double s, int M) {
+    int rc;
+    for (int k = 0; k < M; ++k) {
+        if ((rc = stage_B(md, 0, s / (2.0 * M)))) return rc;
+        stage_A(md, s / M);
+        if ((rc = stage_B(md, 0, s / (2.0 * M)))) return rc;
+    }
+    return HMC_OK;
+}
+
+int inner_fg(MD &md, double s, int M) {
+    const double hm = s / M;
+    int rc;
+    for (int k = 0; k < M; ++k) {
+        if ((rc = stage_B(md, 0, hm / 6.0))) return rc;
+        stage_A(md, hm / 2.0);
+        if ((rc = stage_B_fg(md, 0, 2.0 * hm / 3.0, hm))) return rc;
+        stage_A(md, hm / 2.0);
+        if ((rc = stage_B(md, 0, hm / 6.0))) return rc;
+    }
+    return HMC_OK;
+}
+
+int md_step(MD &md, int scheme, double h, int M) {
+    int rc = HMC_OK;
+#define T(x) if ((rc = (x))) return rc
+    switch (scheme) {
+    case HMC_LEAPFROG:  // Eq. (3)
+        T(stage_B(md, 2, h / 2.0)); stage_A(md, h); T(stage_B(md, 2, h / 2.0));
+        break;
+    case HMC_OMELYAN_5STAGE:  // Eq. (4)
+        T(stage_B(md, 2, h / 6.0)); stage_A(md, h / 2.0); T(stage_B(md, 2, 2.0 * h / 3.0));
+        stage_A(md, h / 2.0); T(stage_B(md, 2, h / 6.0));
+        break;
+    case HMC_FORCE_GRADIENT:  // Eq. (5)
+        T(stage_B(md, 2, h / 6.0)); stage_A(md, h / 2.0); T(stage_B_fg(md, 2, 2.0 * h / 3.0, h));
+        stage_A(md, h / 2.0); T(stage_B(md, 2, h / 6.0));
+        break;
+    case HMC_NESTED_FG:  // Eq. (10)
+        T(stage_B(md, 1, h / 6.0)); T(inner_fg(md, h / 2.0, M)); T(stage_B_fg(md, 1, 2.0 * h / 3.0, h));
+        T(inner_fg(md, h / 2.0, M)); T(stage_B(md, 1, h / 6.0));
+        break;
+    case HMC_ADAPTED_NESTED_FG:  // Eq. (11)
+        T(stage_B(md, 1, h / 6.0)); T(inner_leapfrog(md, h / 2.0, M));
+        T(stage_B_fg(md, 1, 2.0 * h / 3.0, h)); T(inner_leapfrog(md, h / 2.0, M));
+        T(stage_B(md, 1, h / 6.0));
+        break;
+    default:
+        return HMC_E_INVAL;
+    }
+#undef T
+    return HMC_OK;
+}
+
+int check_md_args(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, int prec) {
+    if (scheme < HMC_LEAPFROG || scheme > HMC_ADAPTED_NESTED_FG)
+        return fail(c, HMC_E_INVAL, "unknown scheme %d", scheme);
+    if (!isfinite(tau) || n_outer < 1) return fail(c, HMC_E_INVAL, "need finite tau and n_outer >= 1");
+    if ((scheme == HMC_NESTED_FG || scheme == HMC_ADAPTED_NESTED_FG) && n_inner < 1)
+        return fail(c, HMC_E_INVAL, "nested schemes need n_inner >= 1");
+    if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
+    return HMC_OK;
+}
+
+int run_md(MD &md, int scheme, double tau, int n_outer, int n_inner) {
+    const double h = tau / n_outer;
+    for (int k = 0; k < n_outer; ++k) {
+        int rc = md_step(md, scheme, h, n_inner);
+        if (rc) return rc;
+    }
+    return HMC_OK;
+}
+
+void init_md(MD &md, hmc_ctx *c, int prec) {
+    md.c = c;
+    md.prec = prec;
+    md.tol = c->tol;
+    md.max_iter = c->max_iter;
+    md.chain_status.assign(c->nchains, HMC_OK);
+    md.iters.assign(c->nchains, 0);
+    c->ff_version = -1;
+    c->xi_version = -1;
+    forget_links(c);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int hmc_init(hmc_ctx **out, int L, double beta, double m0, uint64_t seed) {
+    return hmc_init_ex(out, L, L, beta, m0, seed);
+}
+
+int hmc_init_ex(hmc_ctx **out, int Lx, int Lt, double beta, double m0, uint64_t seed) {
+    return make_ctx(out, 1, &Lx, &Lt, &beta, &m0, seed);
+}
+
+int hmc_batch_init(hmc_ctx **out, int n_chains, const int *Lx, const int *Lt, const double *beta,
+                   const double *m0, uint64_t seed) {
+    return make_ctx(out, n_chains, Lx, Lt, beta, m0, seed);
+}
+
+size_t hmc_workspace_bytes(const hmc_ctx *ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+int hmc_bind(hmc_ctx *c, void *ws, size_t bytes, void *stream) {
+    if (!c) return HMC_E_INVAL;
+    if (!ws) return fail(c, HMC_E_INVAL, "null workspace");
+    if ((uintptr_t)ws % kAlign) return fail(c, HMC_E_INVAL, "workspace must be 256-byte aligned");
+    if (bytes < c->ws_bytes)
+        return fail(c, HMC_E_NOMEM, "workspace has %zu bytes, needs %zu", bytes, c->ws_bytes);
+    c->ws = (char *)ws;
+    c->stream = (hipStream_t)stream;
+    if (!c->pinned) {
+        c->pinned_bytes = align_up(sizeof(CGState) * c->nchains + sizeof(MetroOut) * c->nchains +
+                                   sizeof(double) * 16 * c->nchains + 4096);
+        HIP_TRY(c, hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault));
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->at<ChainInfo>(c->off_chains), c->chains.data(),
+                              sizeof(ChainInfo) * c->nchains, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->at<BlockWork>(c->off_work), c->work.data(),
+                              sizeof(BlockWork) * c->work.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->at<unsigned>(c->off_counters), 0, sizeof(unsigned) * c->nchains,
+                              c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->link(LQ), 0, sizeof(double) * 2 * c->Vtot, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->link(LP), 0, sizeof(double) * 2 * c->Vtot, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->spin(SPHI), 0, sizeof(double2) * 2 * c->Vtot, c->stream));
+    forget_all(c);
+    return sync(c);
+}
+
+int hmc_field(hmc_ctx *c, int which, void **ptr, size_t *bytes) {
+    CHECK_BOUND(c);
+    if (!ptr) return fail(c, HMC_E_INVAL, "null output pointer");
+    const size_t lb = sizeof(double) * 2 * c->Vtot, sb = sizeof(double2) * 2 * c->Vtot;
+    switch (which) {
+    case HMC_FIELD_Q: *ptr = c->link(LQ); if (bytes) *bytes = lb; break;
+    case HMC_FIELD_P: *ptr = c->link(LP); if (bytes) *bytes = lb; break;
+    case HMC_FIELD_PHI: *ptr = c->spin(SPHI); if (bytes) *bytes = sb; break;
+    case HMC_FIELD_CHI: *ptr = c->spin(SCHI); if (bytes) *bytes = sb; break;
+    case HMC_FIELD_XI: *ptr = c->spin(SXI); if (bytes) *bytes = sb; break;
+    case HMC_FIELD_F: *ptr = c->link(LF); if (bytes) *bytes = lb; break;
+    case HMC_FIELD_ZETA: *ptr = c->spin(SZETA); if (bytes) *bytes = sb; break;
+    default: return fail(c, HMC_E_INVAL, "unknown field %d", which);
+    }
+    // the caller may write q through this pointer: forget everything derived from it
+    forget_all(c);
+    return HMC_OK;
+}
+
+int hmc_geometry(const hmc_ctx *c, int *n, long long *vt, int *offsets, int *Lx, int *Lt) {
+    if (!c) return HMC_E_INVAL;
+    if (n) *n = c->nchains;
+    if (vt) *vt = c->Vtot;
+    for (int k = 0; k < c->nchains; ++k) {
+        if (offsets) offsets[k] = c->chains[k].off;
+        if (Lx) Lx[k] = c->chains[k].Lx;
+        if (Lt) Lt[k] = c->chains[k].Lt;
+    }
+    return HMC_OK;
+}
+
+int hmc_pack_links(hmc_ctx *c, const double *lex, double *nat) {
+    CHECK_BOUND(c);
+    if (!lex || !nat) return fail(c, HMC_E_INVAL, "null pointer");
+    launch_pack_links(c->geo(), const_cast<double *>(lex), nat, true, c->stream);
+    forget_all(c);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_unpack_links(hmc_ctx *c, const double *nat, double *lex) {
+    CHECK_BOUND(c);
+    if (!lex || !nat) return fail(c, HMC_E_INVAL, "null pointer");
+    launch_pack_links(c->geo(), lex, const_cast<double *>(nat), false, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_pack_spinor(hmc_ctx *c, const double *lex, double *nat) {
+    CHECK_BOUND(c);
+    if (!lex || !nat) return fail(c, HMC_E_INVAL, "null pointer");
+    launch_pack_spinor(c->geo(), (double2 *)const_cast<double *>(lex), (double2 *)nat, true, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_unpack_spinor(hmc_ctx *c, const double *nat, double *lex) {
+    CHECK_BOUND(c);
+    if (!lex || !nat) return fail(c, HMC_E_INVAL, "null pointer");
+    launch_pack_spinor(c->geo(), (double2 *)lex, (double2 *)const_cast<double *>(nat), false, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_cold_start(hmc_ctx *c) {
+    CHECK_BOUND(c);
+    HIP_TRY(c, hipMemsetAsync(c->link(LQ), 0, sizeof(double) * 2 * c->Vtot, c->stream));
+    forget_all(c);
+    return HMC_OK;
+}
+
+int hmc_hot_start(hmc_ctx *c) {
+    CHECK_BOUND(c);
+    launch_rng_links(c->geo(), c->seed, c->link(LQ), c->stream);
+    forget_all(c);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_set_trajectory_counter(hmc_ctx *c, uint32_t traj) {
+    if (!c) return HMC_E_INVAL;
+    c->traj = traj;
+    return HMC_OK;
+}
+
+uint32_t hmc_get_trajectory_counter(const hmc_ctx *c) { return c ? c->traj : 0; }
+
+int hmc_set_solver(hmc_ctx *c, double tol, int max_iter, double reliable_delta) {
+    if (!c) return HMC_E_INVAL;
+    if (!(tol >= 0) || !isfinite(tol) || max_iter < 1 || !(reliable_delta > 0 && reliable_delta < 1))
+        return fail(c, HMC_E_INVAL, "bad solver settings");
+    c->tol = tol;
+    c->max_iter = max_iter;
+    c->delta = reliable_delta;
+    return HMC_OK;
+}
+
+int hmc_set_quenched(hmc_ctx *c, int quenched) {
+    if (!c) return HMC_E_INVAL;
+    c->quenched = quenched != 0;
+    return HMC_OK;
+}
+
+int hmc_set_check_interval(hmc_ctx *c, int every) {
+    if (!c || every < 1) return HMC_E_INVAL;
+    c->check_every = every;
+    return HMC_OK;
+}
+
+int hmc_dslash(hmc_ctx *c, const void *in, void *out) {
+    CHECK_BOUND(c);
+    if (!in || !out || in == out) return fail(c, HMC_E_INVAL, "need distinct in/out");
+    ensure_links(c, c->link(LQ), false, -1);
+    launch_dslash64(c->geo(), c->U64(), (const double2 *)in, (double2 *)out, false, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_dslash_dagger(hmc_ctx *c, const void *in, void *out) {
+    CHECK_BOUND(c);
+    if (!in || !out || in == out) return fail(c, HMC_E_INVAL, "need distinct in/out");
+    ensure_links(c, c->link(LQ), false, -1);
+    launch_dslash64(c->geo(), c->U64(), (const double2 *)in, (double2 *)out, true, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_cg_solve(hmc_ctx *c, const void *phi, void *x, double tol, int max_iter, int prec,
+                 hmc_cg_info *info) {
+    CHECK_BOUND(c);
+    if (!phi || !x || phi == x) return fail(c, HMC_E_INVAL, "need distinct phi/x");
+    if (!(tol >= 0) || max_iter < 1) return fail(c, HMC_E_INVAL, "bad tol/max_iter");
+    if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
+    ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, -1);
+    int rc = solve(c, (const double2 *)phi, (double2 *)x, tol, max_iter, prec);
+    if (rc && rc != HMC_E_NOCONV) return rc;
+    std::vector<double> t2(c->nchains);
+    double *dev = c->sums() + 12 * c->nchains;
+    launch_true_residual64(c->geo(), c->red(), c->U64(), (const double2 *)phi, (const double2 *)x,
+                           c->spin(ST), dev, c->stream);
+    int rc2 = to_host(c, t2.data(), dev, sizeof(double) * c->nchains);
+    if (rc2) return rc2;
+    fill_cg_info(c, info, &t2);
+    return rc;
+}
+
+int hmc_fermion_force_chixi(hmc_ctx *c, const void *chi, const void *xi, double *f) {
+    CHECK_BOUND(c);
+    if (!chi || !xi || !f) return fail(c, HMC_E_INVAL, "null pointer");
+    ensure_links(c, c->link(LQ), false, -1);
+    launch_fermion_force(c->geo(), c->U64(), (const double2 *)chi, (const double2 *)xi, f, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_fermion_force(hmc_ctx *c, const void *phi, double *f, double tol, int max_iter, int prec,
+                      hmc_cg_info *info, double *sf) {
+    CHECK_BOUND(c);
+    if (!phi) return fail(c, HMC_E_INVAL, "null pointer");
+    if (!(tol >= 0) || max_iter < 1) return fail(c, HMC_E_INVAL, "bad tol/max_iter");
+    if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
+    ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, -1);
+    int rc = solve(c, (const double2 *)phi, c->spin(SXI), tol, max_iter, prec);
+    if (rc && rc != HMC_E_NOCONV) return rc;
+    launch_dslash64(c->geo(), c->U64(), c->spin(SXI), c->spin(SCHI), false, c->stream);
+    if (f) launch_fermion_force(c->geo(), c->U64(), c->spin(SCHI), c->spin(SXI), f, c->stream);
+    fill_cg_info(c, info, nullptr);
+    if (sf) {
+        double *dev = c->sums() + 12 * c->nchains;
+        launch_gauge_energy(c->geo(), c->red(), c->link(LQ), (const double2 *)phi, c->spin(SXI),
+                            dev, c->stream);
+        std::vector<double> h(3 * c->nchains);
+        int rc2 = to_host(c, h.data(), dev, sizeof(double) * 3 * c->nchains);
+        if (rc2) return rc2;
+        for (int k = 0; k < c->nchains; ++k) sf[k] = h[2 * c->nchains + k];
+    }
+    c->ff_version = c->xi_version = -1;
+    HIP_TRY(c, hipGetLastError());
+    return rc;
+}
+
+int hmc_total_force_chixi(hmc_ctx *c, const void *chi, const void *xi, double *F) {
+    CHECK_BOUND(c);
+    if (!chi || !xi || !F) return fail(c, HMC_E_INVAL, "null pointer");
+    ensure_links(c, c->link(LQ), false, -1);
+    launch_fermion_force(c->geo(), c->U64(), (const double2 *)chi, (const double2 *)xi, F, c->stream);
+    launch_gauge_force(c->geo(), c->link(LQ), F, F, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_gauge_force(hmc_ctx *c, double *g) {
+    CHECK_BOUND(c);
+    if (!g) return fail(c, HMC_E_INVAL, "null pointer");
+    launch_gauge_force(c->geo(), c->link(LQ), nullptr, g, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_actions(hmc_ctx *c, const void *phi, double tol, double *s_gauge, double *plaq,
+                double *s_fermion) {
+    CHECK_BOUND(c);
+    const int C = c->nchains;
+    if (phi && s_fermion) {
+        ensure_links(c, c->link(LQ), false, -1);
+        int rc = solve(c, (const double2 *)phi, c->spin(SXI), tol, c->max_iter, HMC_PREC_FP64);
+        if (rc) return rc;
+        c->ff_version = c->xi_version = -1;
+    }
+    double *dev = c->sums() + 12 * C;
+    launch_gauge_energy(c->geo(), c->red(), c->link(LQ), (phi && s_fermion) ? (const double2 *)phi : nullptr,
+                        c->spin(SXI), dev, c->stream);
+    std::vector<double> h(3 * C);
+    int rc = to_host(c, h.data(), dev, sizeof(double) * 3 * C);
+    if (rc) return rc;
+    for (int k = 0; k < C; ++k) {
+        if (s_gauge) s_gauge[k] = c->chains[k].beta * h[k];
+        if (plaq) plaq[k] = h[C + k] / c->chains[k].V;
+        if (s_fermion && phi) s_fermion[k] = h[2 * C + k];
+    }
+    return HMC_OK;
+}
+
+int hmc_update_links(hmc_ctx *c, double eps) {
+    CHECK_BOUND(c);
+    if (!isfinite(eps)) return fail(c, HMC_E_INVAL, "non-finite eps");
+    launch_axpy_links(c->geo(), c->link(LQ), eps, c->link(LP), c->link(LQ), c->stream);
+    forget_all(c);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_update_momenta(hmc_ctx *c, double eps, const double *F) {
+    CHECK_BOUND(c);
+    if (!F || !isfinite(eps)) return fail(c, HMC_E_INVAL, "bad arguments");
+    launch_axpy_links(c->geo(), c->link(LP), -eps, F, c->link(LP), c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_fg_shifted_force(hmc_ctx *c, double c_h2, int which, const void *phi, double *F_out,
+                         int prec, hmc_cg_info *info) {
+    CHECK_BOUND(c);
+    if (!F_out || !isfinite(c_h2) || which < 0 || which > 2) return fail(c, HMC_E_INVAL, "bad arguments");
+    if (which != HMC_FORCE_GAUGE && !phi) return fail(c, HMC_E_INVAL, "phi needed");
+    if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
+    MD md;
+    init_md(md, c, prec);
+    if (phi && phi != c->spin(SPHI))
+        launch_copy(phi, c->spin(SPHI), sizeof(double2) * 2 * c->Vtot, c->stream);
+    int rc = force_at(md, which, c->link(LQ), -1, c->link(LF));
+    if (rc) return rc;
+    launch_axpy_links(c->geo(), c->link(LQ), c_h2, c->link(LF), c->link(LQS), c->stream);
+    rc = force_at(md, which, c->link(LQS), -1, F_out);
+    if (rc) return rc;
+    forget_links(c);
+    c->ff_version = c->xi_version = -1;
+    if (which != HMC_FORCE_GAUGE) fill_cg_info(c, info, nullptr);
+    HIP_TRY(c, hipGetLastError());
+    return md.status;
+}
+
+static int finish_traj(hmc_ctx *c, MD &md, bool metropolis, hmc_traj_info *info) {
+    const Geo g = c->geo();
+    const int C = c->nchains;
+    const bool fermions = !c->quenched;
+    // S_F at the final links: reuse xi if the last solve was at the current q
+    if (fermions && c->xi_version != c->q_version) {
+        ensure_links(c, c->link(LQ), md.prec == HMC_PREC_MIXED, c->q_version);
+        int rc = solve(c, c->spin(SPHI), c->spin(SXI), md.tol, md.max_iter, md.prec);
+        md.solves++;
+        for (int k = 0; k < C; ++k) {
+            md.iters[k] += c->cg_host[k].iters;
+            if (!c->cg_host[k].converged) md.chain_status[k] = HMC_E_NOCONV;
+        }
+        if (rc && rc != HMC_E_NOCONV) return rc;
+        c->xi_version = c->q_version;
+    }
+    // sums layout: [0, 7C) energies, [7C, 9C) refresh, [9C, 12C) gauge sums,
+    // [12C, 15C) scratch of the API-level reductions
+    double *es = c->sums();             // [7][C]
+    double *rs = c->sums() + 7 * C;     // [2][C] from the refresh
+    double *gs = c->sums() + 9 * C;     // [3][C]
+    launch_energy(g, c->red(), c->link(LQ), c->link(LQ0), c->link(LP), c->link(LP0),
+                  fermions ? c->spin(SPHI) : nullptr, c->spin(SXI), es, c->stream);
+    HIP_TRY(c, hipMemcpyAsync(c->at<int>(c->off_status), md.chain_status.data(), sizeof(int) * C,
+                              hipMemcpyHostToDevice, c->stream));
+    MetroOut *mo = c->at<MetroOut>(c->off_metro);
+    launch_metropolis(g, c->seed, c->traj, es, rs, c->at<int>(c->off_status), mo, fermions, c->stream);
+    if (metropolis) {
+        launch_restore(g, mo, c->link(LQ0), c->link(LQ), c->stream);
+        c->q_version++;
+    }
+    launch_gauge_energy(g, c->red(), c->link(LQ), nullptr, c->spin(SXI), gs, c->stream);
+    std::vector<MetroOut> mh(C);
+    std::vector<double> gh(3 * C);
+    int rc = to_host(c, mh.data(), mo, sizeof(MetroOut) * C);
+    if (rc) return rc;
+    if ((rc = to_host(c, gh.data(), gs, sizeof(double) * 3 * C))) return rc;
+    int status = HMC_OK;
+    for (int k = 0; k < C; ++k) {
+        if (info) {
+            hmc_traj_info &t = info[k];
+            memset(&t, 0, sizeof t);
+            t.dH = mh[k].dH;
+            t.H0 = mh[k].H0;
+            t.H1 = mh[k].H1;
+            t.u = mh[k].u;
+            t.accepted = metropolis ? mh[k].accepted : 0;
+            t.status = mh[k].status;
+            t.plaquette = gh[C + k] / c->chains[k].V;
+            t.n_force_evals = md.force_evals;
+            t.n_solves = md.solves;
+            t.n_dinv = 2 * md.force_evals;
+            t.n_cg_iters = md.iters[k];
+        }
+        if (mh[k].status && status == HMC_OK) status = mh[k].status;
+    }
+    if (status) fail(c, status, "a chain failed (status %d)", status);
+    return status;
+}
+
+static void refresh(hmc_ctx *c) {
+    const Geo g = c->geo();
+    const bool fermions = !c->quenched;
+    double *rs = c->sums() + 7 * c->nchains;
+    launch_refresh(g, c->red(), c->seed, c->traj, c->link(LP), c->spin(SZETA), fermions, rs, c->stream);
+    if (fermions) {
+        ensure_links(c, c->link(LQ), false, c->q_version);
+        launch_dslash64(g, c->U64(), c->spin(SZETA), c->spin(SPHI), true, c->stream);
+    }
+}
+
+int hmc_refresh(hmc_ctx *c) {
+    CHECK_BOUND(c);
+    forget_all(c);
+    refresh(c);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
+int hmc_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, int prec,
+                   hmc_traj_info *info) {
+    CHECK_BOUND(c);
+    int rc = check_md_args(c, scheme, tau, n_outer, n_inner, prec);
+    if (rc) return rc;
+    MD md;
+    init_md(md, c, prec);
+    refresh(c);
+    launch_copy(c->link(LQ), c->link(LQ0), sizeof(double) * 2 * c->Vtot, c->stream);
+    launch_copy(c->link(LP), c->link(LP0), sizeof(double) * 2 * c->Vtot, c->stream);
+    rc = run_md(md, scheme, tau, n_outer, n_inner);
+    if (rc && rc != HMC_E_NOCONV) return rc;
+    rc = finish_traj(c, md, true, info);
+    c->traj++;
+    return rc;
+}
+
+int hmc_integrate(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, int prec,
+                  hmc_traj_info *info) {
+    CHECK_BOUND(c);
+    int rc = check_md_args(c, scheme, tau, n_outer, n_inner, prec);
+    if (rc) return rc;
+    MD md;
+    init_md(md, c, prec);
+    // energies before: refresh sums from the current p; zeta^dagger zeta is not known, so the
+    // initial S_F is solved for (stored in the refresh slot)
+    const Geo g = c->geo();
+    const int C = c->nchains;
+    launch_copy(c->link(LQ), c->link(LQ0), sizeof(double) * 2 * c->Vtot, c->stream);
+    launch_copy(c->link(LP), c->link(LP0), sizeof(double) * 2 * c->Vtot, c->stream);
+    double *rs = c->sums() + 7 * C;
+    {
+        // 1/2 sum p^2 and S_F(q0) = Re phi^dagger xi(q0)
+        double *es = c->sums();
+        if (!c->quenched) {
+            ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, c->q_version);
+            rc = solve(c, c->spin(SPHI), c->spin(SXI), md.tol, md.max_iter, prec);
+            if (rc) return rc;
+        }
+        launch_energy(g, c->red(), c->link(LQ), c->link(LQ0), c->link(LP), c->link(LP0),
+                      c->quenched ? nullptr : c->spin(SPHI), c->spin(SXI), es, c->stream);
+        std::vector<double> h(7 * C), r(2 * C);
+        if ((rc = to_host(c, h.data(), es, sizeof(double) * 7 * C))) return rc;
+        for (int k = 0; k < C; ++k) { r[k] = h[2 * C + k]; r[C + k] = h[5 * C + k]; }
+        HIP_TRY(c, hipMemcpyAsync(rs, r.data(), sizeof(double) * 2 * C, hipMemcpyHostToDevice, c->stream));
+        c->xi_version = -1;
+    }
+    rc = run_md(md, scheme, tau, n_outer, n_inner);
+    if (rc && rc != HMC_E_NOCONV) return rc;
+    return finish_traj(c, md, false, info);
+}
+
+const char *hmc_last_error(const hmc_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int hmc_destroy(hmc_ctx *c) {
+    if (!c) return HMC_E_INVAL;
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+    return HMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,391 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle, element by
+element on the same seeded inputs.  FP64 tolerances: 1e-12 relative for the
+stencil-level operators, 1e-10 relative for solver-dependent quantities (forces,
+Delta H) with CG tolerances of 1e-14, bit-identity for the Philox uniforms."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def hmc():
+    import paper_1512_03812_amd as m
+    return m
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+class Batch:
+    """A Lattice plus numpy<->native helpers for a list of (Lx, Lt, beta, m0)."""
+
+    def __init__(self, shapes, seed=0):
+        m = hmc()
+        Lx = [s[0] for s in shapes]
+        Lt = [s[1] for s in shapes]
+        beta = [s[2] if len(s) > 2 else 2.0 for s in shapes]
+        m0 = [s[3] if len(s) > 3 else 0.1 for s in shapes]
+        self.lat = m.Lattice.batch(Lx, Lt, beta, m0, seed=seed)
+        self.shapes = list(zip(Lx, Lt, beta, m0))
+
+    def links_to_native(self, arrays, out=None):
+        flat = np.concatenate([np.ascontiguousarray(a, dtype=np.float64).ravel() for a in arrays])
+        return self.lat.pack_links(torch.from_numpy(flat), out=out)
+
+    def spinor_to_native(self, arrays, out=None):
+        flat = np.concatenate([np.ascontiguousarray(a, dtype=np.complex128).ravel() for a in arrays])
+        return self.lat.pack_spinor(torch.from_numpy(flat), out=out)
+
+    def links_from_native(self, t):
+        flat = self.lat.unpack_links(t).cpu().numpy()
+        return [flat[2 * o:2 * o + 2 * Lx * Lt].reshape(Lt, Lx, 2)
+                for o, (Lx, Lt, _, _) in zip(self.lat.offsets, self.shapes)]
+
+    def spinor_from_native(self, t):
+        flat = self.lat.unpack_spinor(t).cpu().numpy()
+        return [flat[2 * o:2 * o + 2 * Lx * Lt].reshape(Lt, Lx, 2)
+                for o, (Lx, Lt, _, _) in zip(self.lat.offsets, self.shapes)]
+
+    def set_q(self, arrays):
+        self.links_to_native(arrays, out=self.lat.q)
+
+
+SHAPES = [(2, 2), (4, 4), (8, 8), (6, 10), (34, 18), (32, 32)]
+
+
+# ------------------------------------------------------------------ layout and random numbers
+def test_pack_roundtrip_is_exact():
+    b = Batch([(8, 8), (6, 4), (34, 18)])
+    q = [inputs.random_angles(Lx, Lt, 1 + i) for i, (Lx, Lt, _, _) in enumerate(b.shapes)]
+    s = [inputs.random_spinor(Lx, Lt, 7 + i) for i, (Lx, Lt, _, _) in enumerate(b.shapes)]
+    for a, c in zip(b.links_from_native(b.links_to_native(q)), q):
+        assert np.array_equal(a, c)
+    for a, c in zip(b.spinor_from_native(b.spinor_to_native(s)), s):
+        assert np.array_equal(a, c)
+
+
+def test_hot_start_uniforms_bit_identical():
+    b = Batch([(8, 8), (6, 10), (32, 32)], seed=0xDEADBEEF12345)
+    b.lat.hot_start()
+    for c, (got, (Lx, Lt, _, _)) in enumerate(zip(b.links_from_native(b.lat.q), b.shapes)):
+        want = oracle.random_links(Lx, Lt, 0xDEADBEEF12345, chain=c)
+        assert np.array_equal(got, want)
+
+
+def test_refresh_streams_match_oracle():
+    seed = 987654321
+    b = Batch([(8, 8), (6, 10)], seed=seed)
+    b.lat.trajectory_counter = 5
+    b.lat.refresh()
+    torch.cuda.synchronize()
+    ps = b.links_from_native(b.lat.p)
+    zs = b.spinor_from_native(b.lat.zeta)
+    n_exact = n_total = 0
+    for c, (Lx, Lt, _, _) in enumerate(b.shapes):
+        p_ref = oracle.random_momenta(Lx, Lt, seed, chain=c, traj=5)
+        z_ref = oracle.random_zeta(Lx, Lt, seed, chain=c, traj=5)
+        # Gaussians: same uniforms, libm vs device log/cos/sin may differ in the last ulps
+        assert np.max(np.abs(ps[c] - p_ref) / np.maximum(np.abs(p_ref), 1e-3)) < 8e-16
+        assert np.max(np.abs(zs[c] - z_ref) / np.maximum(np.abs(z_ref), 1e-3)) < 8e-16
+        n_exact += np.sum(ps[c] == p_ref)
+        n_total += p_ref.size
+    assert n_exact > 0.5 * n_total
+
+
+# ------------------------------------------------------------------ Dirac operator
+@pytest.mark.parametrize("Lx,Lt", SHAPES)
+def test_dslash_parity(Lx, Lt):
+    m0 = 0.1
+    b = Batch([(Lx, Lt, 2.0, m0)])
+    q = inputs.random_angles(Lx, Lt, 11)
+    psi = inputs.random_spinor(Lx, Lt, 12)
+    b.set_q([q])
+    x = b.spinor_to_native([psi])
+    got = b.spinor_from_native(b.lat.dslash(x))[0]
+    assert rel(got, oracle.dirac(q, psi, m0)) < 1e-13
+    got = b.spinor_from_native(b.lat.dslash_dagger(x))[0]
+    assert rel(got, oracle.dirac_dagger(q, psi, m0)) < 1e-13
+
+
+def test_dslash_batch_of_uneven_chains():
+    shapes = [(16, 16, 2.0, 0.1), (4, 6, 1.0, 0.3), (34, 18, 3.0, 0.05), (2, 2, 2.0, 0.2),
+              (64, 64, 2.5, 0.02)]
+    b = Batch(shapes)
+    q = [inputs.random_angles(s[0], s[1], 20 + i) for i, s in enumerate(shapes)]
+    psi = [inputs.random_spinor(s[0], s[1], 40 + i) for i, s in enumerate(shapes)]
+    b.set_q(q)
+    x = b.spinor_to_native(psi)
+    got = b.spinor_from_native(b.lat.dslash(x))
+    gotd = b.spinor_from_native(b.lat.dslash_dagger(x))
+    for i, s in enumerate(shapes):
+        assert rel(got[i], oracle.dirac(q[i], psi[i], s[3])) < 1e-13
+        assert rel(gotd[i], oracle.dirac_dagger(q[i], psi[i], s[3])) < 1e-13
+
+
+def test_dslash_large_lattice_sampled():
+    """256 x 256 (the precision workload's size) against the oracle on the whole field."""
+    Lx = Lt = 256
+    b = Batch([(Lx, Lt, 4.0, 0.05)])
+    q = inputs.random_angles(Lx, Lt, 5)
+    psi = inputs.random_spinor(Lx, Lt, 6)
+    b.set_q([q])
+    got = b.spinor_from_native(b.lat.dslash(b.spinor_to_native([psi])))[0]
+    assert rel(got, oracle.dirac(q, psi, 0.05)) < 1e-13
+
+
+# ------------------------------------------------------------------ gauge part
+@pytest.mark.parametrize("Lx,Lt", [(4, 4), (6, 10), (34, 18)])
+def test_gauge_force_and_action_parity(Lx, Lt):
+    beta = 1.7
+    b = Batch([(Lx, Lt, beta, 0.1)])
+    q = inputs.random_angles(Lx, Lt, 3)
+    b.set_q([q])
+    F = b.links_from_native(b.lat.gauge_force())[0]
+    assert rel(F, oracle.gauge_force(q, beta)) < 1e-12
+    sg, pl, _ = b.lat.actions()
+    assert abs(sg[0] - oracle.gauge_action(q, beta)) < 1e-12 * abs(sg[0])
+    assert abs(pl[0] - oracle.mean_plaquette(q)) < 1e-13
+
+
+# ------------------------------------------------------------------ solver and fermion force
+@pytest.mark.parametrize("Lx,Lt,m0", [(4, 4, 0.1), (8, 8, 0.1), (6, 10, 0.05), (34, 18, 0.1)])
+def test_cg_parity(Lx, Lt, m0):
+    b = Batch([(Lx, Lt, 2.0, m0)])
+    q = inputs.random_angles(Lx, Lt, 31)
+    phi = inputs.random_spinor(Lx, Lt, 32)
+    b.set_q([q])
+    x, res = b.lat.cg_solve(b.spinor_to_native([phi]), tol=1e-14)
+    xr, itr, resr = oracle.cg(q, phi, m0, tol=1e-14)
+    assert res.converged[0] and abs(res.iters[0] - itr) <= 2
+    assert res.rel_resid_true[0] < 1e-12
+    assert rel(b.spinor_from_native(x)[0], xr) < 1e-10
+
+
+@pytest.mark.parametrize("Lx,Lt,m0", [(8, 8, 0.1), (6, 10, 0.05), (32, 32, 0.1)])
+def test_fermion_force_parity(Lx, Lt, m0):
+    b = Batch([(Lx, Lt, 2.0, m0)])
+    q = inputs.random_angles(Lx, Lt, 41)
+    phi = inputs.random_spinor(Lx, Lt, 42)
+    b.set_q([q])
+    f, sf, res = b.lat.fermion_force(b.spinor_to_native([phi]), tol=1e-14)
+    fr, chir, xir, sfr, _ = oracle.fermion_force(q, phi, m0, tol=1e-14)
+    assert rel(b.links_from_native(f)[0], fr) < 1e-10
+    assert abs(sf[0] - sfr) < 1e-12 * abs(sfr)
+    assert rel(b.spinor_from_native(b.lat.xi)[0], xir) < 1e-10
+    assert rel(b.spinor_from_native(b.lat.chi)[0], chir) < 1e-10
+    # the adjoint kernel alone, on the oracle's chi and xi
+    f2 = b.lat.fermion_force_chixi(b.spinor_to_native([chir]), b.spinor_to_native([xir]))
+    assert rel(b.links_from_native(f2)[0], oracle.fermion_force_chixi(q, chir, xir)) < 1e-13
+
+
+def test_fermion_force_128_sampled():
+    """128 x 128 (the differentiation workload's size): force against the oracle."""
+    Lx = Lt = 128
+    b = Batch([(Lx, Lt, 2.0, 0.1)])
+    q = inputs.smooth_angles(Lx, Lt, 1, 0.4)
+    phi = inputs.random_spinor(Lx, Lt, 2)
+    b.set_q([q])
+    f, sf, res = b.lat.fermion_force(b.spinor_to_native([phi]), tol=1e-13)
+    fr, _, _, sfr, _ = oracle.fermion_force(q, phi, 0.1, tol=1e-13)
+    assert rel(b.links_from_native(f)[0], fr) < 1e-9
+    assert abs(sf[0] - sfr) < 1e-11 * abs(sfr)
+
+
+@pytest.mark.parametrize("which", ["gauge", "fermion", "total"])
+def test_fg_shifted_force_parity(which):
+    Lx, Lt, beta, m0, h = 8, 6, 2.0, 0.1, 0.25
+    b = Batch([(Lx, Lt, beta, m0)])
+    q = inputs.random_angles(Lx, Lt, 51)
+    phi = inputs.random_spinor(Lx, Lt, 52)
+    b.set_q([q])
+    b.lat.set_solver(tol=1e-14)
+    phin = b.spinor_to_native([phi])
+    F = b.lat.fg_shifted_force(-(h * h / 24.0), which, phin)
+    ref = oracle.fg_shifted_force(q, phi, beta, m0, h, which, tol=1e-14)
+    assert rel(b.links_from_native(F)[0], ref) < 1e-10
+
+
+def test_zero_source_and_nonconvergence():
+    b = Batch([(8, 8)])
+    b.set_q([inputs.random_angles(8, 8, 1)])
+    x, res = b.lat.cg_solve(b.lat.new_spinor(), tol=1e-12)
+    assert res.converged[0] and res.iters[0] == 0 and float(x.abs().max()) == 0.0
+    phi = b.spinor_to_native([inputs.random_spinor(8, 8, 2)])
+    x, res = b.lat.cg_solve(phi, tol=1e-14, max_iter=3)
+    assert not res.converged[0] and res.iters[0] == 3
+
+
+# ------------------------------------------------------------------ molecular dynamics
+@pytest.mark.parametrize("scheme", list(oracle.SCHEMES))
+def test_md_parity(scheme):
+    Lx, Lt, beta, m0 = 8, 8, 2.0, 0.1
+    b = Batch([(Lx, Lt, beta, m0)])
+    q = inputs.random_angles(Lx, Lt, 61)
+    p = inputs.random_momenta(Lx, Lt, 62)
+    phi = inputs.random_spinor(Lx, Lt, 63)
+    b.set_q([q])
+    b.links_to_native([p], out=b.lat.p)
+    b.spinor_to_native([phi], out=b.lat.phi)
+    b.lat.set_solver(tol=1e-14)
+    res = b.lat.integrate(scheme, 1.0, 4, 3)
+    q1, p1, info = oracle.md_integrate(q, p, phi, beta, m0, scheme, 1.0, 4, 3, tol=1e-14)
+    assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - q1)) < 1e-10
+    assert np.max(np.abs(b.links_from_native(b.lat.p)[0] - p1)) < 1e-10
+    dH_ref = oracle.hamiltonian(q1, p1, phi, beta, m0) - oracle.hamiltonian(q, p, phi, beta, m0)
+    assert abs(res.dH[0] - dH_ref) < 1e-10 * max(1.0, abs(dH_ref))
+    assert res.n_force_evals == info["n_solves"]
+
+
+# ------------------------------------------------------------------ HMC trajectories
+def run_oracle_chain(Lx, Lt, beta, m0, seed, chain, n_traj, scheme, tau, n_outer, n_inner, tol):
+    q = oracle.random_links(Lx, Lt, seed, chain)
+    out = []
+    for t in range(n_traj):
+        q, info = oracle.hmc_trajectory(q, beta, m0, seed, chain, t, scheme, tau, n_outer, n_inner,
+                                        tol=tol)
+        out.append((q.copy(), info))
+    return out
+
+
+def test_plain_method_8x8_omelyan():
+    """The plain FP64 method on 8 x 8: beta 2, m0 0.1, 5-stage scheme, 10 steps, tau 1."""
+    seed = 2024
+    b = Batch([(8, 8, 2.0, 0.1)], seed=seed)
+    b.lat.hot_start()
+    b.lat.set_solver(tol=1e-12)
+    ref = run_oracle_chain(8, 8, 2.0, 0.1, seed, 0, 6, "omelyan", 1.0, 10, 1, 1e-12)
+    for t in range(6):
+        r = b.lat.trajectory("omelyan", 1.0, 10, 1)
+        qr, ir = ref[t]
+        assert r.accepted[0] == ir["accepted"]
+        assert abs(r.dH[0] - ir["dH"]) < 1e-10 * max(1.0, abs(ir["dH"]))
+        assert abs(r.H0[0] - ir["H0"]) < 1e-11 * abs(ir["H0"])
+        assert abs(r.plaquette[0] - ir["plaquette"]) < 1e-11
+        assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - qr)) < 1e-9
+
+
+@pytest.mark.parametrize("scheme,n_outer,n_inner", [
+    ("leapfrog", 16, 1), ("force_gradient", 4, 1), ("nested_fg", 4, 2), ("adapted_nested_fg", 4, 2)])
+def test_trajectory_parity_all_schemes(scheme, n_outer, n_inner):
+    seed = 77
+    b = Batch([(8, 8, 2.0, 0.1)], seed=seed)
+    b.lat.hot_start()
+    b.lat.set_solver(tol=1e-13)
+    ref = run_oracle_chain(8, 8, 2.0, 0.1, seed, 0, 3, scheme, 1.0, n_outer, n_inner, 1e-13)
+    for t in range(3):
+        r = b.lat.trajectory(scheme, 1.0, n_outer, n_inner)
+        qr, ir = ref[t]
+        assert r.accepted[0] == ir["accepted"]
+        assert abs(r.dH[0] - ir["dH"]) < 1e-10 * max(1.0, abs(ir["dH"]))
+        assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - qr)) < 1e-9
+
+
+def test_inversion_counts_per_step():
+    counts = {"leapfrog": 4, "omelyan": 6, "force_gradient": 8, "nested_fg": 8,
+              "adapted_nested_fg": 8}
+    b = Batch([(8, 8)], seed=3)
+    b.lat.hot_start()
+    for scheme, per_step in counts.items():
+        r = b.lat.trajectory(scheme, 1.0, 3, 2)
+        assert r.n_dinv == 3 * per_step
+        assert r.n_solves <= r.n_force_evals + 1
+
+
+def test_batched_trajectories_match_single_chain_oracle():
+    shapes = [(8, 8, 2.0, 0.1), (4, 6, 1.5, 0.2), (6, 4, 3.0, 0.05), (2, 2, 1.0, 0.15)]
+    seed = 31337
+    b = Batch(shapes, seed=seed)
+    b.lat.hot_start()
+    b.lat.set_solver(tol=1e-13)
+    refs = [run_oracle_chain(s[0], s[1], s[2], s[3], seed, c, 3, "adapted_nested_fg", 1.0, 4, 2, 1e-13)
+            for c, s in enumerate(shapes)]
+    for t in range(3):
+        r = b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2)
+        qs = b.links_from_native(b.lat.q)
+        for c in range(len(shapes)):
+            qr, ir = refs[c][t]
+            assert r.accepted[c] == ir["accepted"], (t, c)
+            assert abs(r.dH[c] - ir["dH"]) < 1e-10 * max(1.0, abs(ir["dH"])), (t, c)
+            assert np.max(np.abs(qs[c] - qr)) < 1e-9
+
+
+def test_trajectory_is_bitwise_reproducible():
+    out = []
+    for _ in range(2):
+        b = Batch([(16, 16), (8, 8)], seed=5)
+        b.lat.hot_start()
+        r = [b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2) for _ in range(2)]
+        out.append((b.lat.q.cpu().numpy().copy(), [x.dH for x in r]))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
+# ------------------------------------------------------------------ mixed precision
+@pytest.mark.parametrize("Lx,m0", [(16, 0.1), (64, 0.05)])
+def test_mixed_cg_reaches_fp64_residual(Lx, m0):
+    b = Batch([(Lx, Lx, 4.0, m0)])
+    q = inputs.smooth_angles(Lx, Lx, 71, 0.3)
+    phi = inputs.random_spinor(Lx, Lx, 72)
+    b.set_q([q])
+    x, res = b.lat.cg_solve(b.spinor_to_native([phi]), tol=1e-10, prec="mixed")
+    assert res.converged[0] and res.rel_resid_true[0] < 1e-10 and res.reliable_updates[0] > 0
+    x64, res64 = b.lat.cg_solve(b.spinor_to_native([phi]), tol=1e-13)
+    assert rel(b.spinor_from_native(x)[0], b.spinor_from_native(x64)[0]) < 1e-7
+
+
+def test_mixed_trajectory_matches_fp64_oracle():
+    seed = 404
+    b = Batch([(16, 16, 4.0, 0.05)], seed=seed)
+    b.lat.hot_start()
+    b.lat.set_solver(tol=1e-12)
+    ref = run_oracle_chain(16, 16, 4.0, 0.05, seed, 0, 2, "adapted_nested_fg", 1.0, 8, 4, 1e-12)
+    for t in range(2):
+        r = b.lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+        qr, ir = ref[t]
+        assert r.accepted[0] == ir["accepted"]
+        assert abs(r.dH[0] - ir["dH"]) < 1e-8
+
+
+# ------------------------------------------------------------------ autograd form
+def test_autograd_action_gradient_matches_finite_differences_and_oracle():
+    m = hmc()
+    Lx = Lt = 16
+    beta, m0 = 2.0, 0.1
+    b = Batch([(Lx, Lt, beta, m0)])
+    q = inputs.random_angles(Lx, Lt, 81)
+    phi = inputs.random_spinor(Lx, Lt, 82)
+    qn = b.links_to_native([q]).clone().requires_grad_(True)
+    phin = b.spinor_to_native([phi])
+    S = m.SchwingerAction.apply(qn, b.lat, phin, 1e-14)
+    S.sum().backward()
+    grad = b.links_from_native(qn.grad)[0]
+    ref = oracle.gauge_force(q, beta) + oracle.fermion_force(q, phi, m0, tol=1e-14)[0]
+    assert rel(grad, ref) < 1e-10
+    S_ref = oracle.gauge_action(q, beta) + oracle.fermion_action(q, phi, m0, tol=1e-14)
+    assert abs(float(S[0]) - S_ref) < 1e-11 * S_ref
+    g = np.random.default_rng(83)
+    eps = 1e-6
+    worst = 0.0
+    for _ in range(64):
+        t, x, mu = int(g.integers(Lt)), int(g.integers(Lx)), int(g.integers(2))
+        qp, qm = q.copy(), q.copy()
+        qp[t, x, mu] += eps
+        qm[t, x, mu] -= eps
+        with torch.no_grad():
+            sp = float(m.SchwingerAction.apply(b.links_to_native([qp]), b.lat, phin, 1e-14)[0])
+            sm = float(m.SchwingerAction.apply(b.links_to_native([qm]), b.lat, phin, 1e-14)[0])
+        worst = max(worst, abs((sp - sm) / (2 * eps) - grad[t, x, mu]))
+    assert worst < 1e-6 * np.max(np.abs(grad))
