@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the Schwinger-model HMC hot path on one MI355X.
+
+A step is one HMC trajectory (refresh, adapted nested force-gradient molecular dynamics
+of Eq. (11) with the fermion-force CG solves and force-gradient-shifted force, Delta H,
+Metropolis) for every chain of the batched workload:
+  512 independent chains, L drawn from {16, 32, 64, 128} with weights 4:3:2:1,
+  beta ~ U[1, 4], m0 ~ U[0.02, 0.2] (seeded), tau = 1, n_outer = 8, n_inner = 4,
+  CG in FP32 with FP64 reliable updates to a true relative residual of 1e-10,
+  Delta H / Metropolis / energies in FP64.
+value = chain-trajectories per second over the timed steps (inputs resident in HBM).
+Beside it: the dominant kernel's roofline figure (event-timed inside the timed region),
+the plain FP64 single-chain 32 x 32 path on the same GPU, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+METRIC = "HMC trajectories/sec at fixed acceptance; Dslash+CG achieved HBM GB/s"
+
+# Algorithmic bytes per lattice site of the CG step kernels (each distinct input read
+# once, each output written once; neighbour reads come from cache).
+#   step 1, FP32 slot : r 16 + p_old 16 + U 16 read, p_new 16 + t 16 written      =  80
+#   step 2, FP32 slot : t 16 + U 16 + x 16 + p 16 + r 16 read, x 16 + r 16 written = 112
+#   step 1, FP64 residual slot: x64 32 + x32 16 + U64 32 + p_old 16 read, t64 32 + p_new 16 = 144
+#   step 2, FP64 residual slot: t64 32 + U64 32 + phi 32 + x64 32 + x32 16 read,
+#                               x64 32 + x32 16 + r32 16 written                    = 208
+#   FP64 solver: step 1 = 160, step 2 = 224
+BYTES = {"step1": {"fp32": 80, "upd": 144, "fp64": 160},
+         "step2": {"fp32": 112, "upd": 208, "fp64": 224}}
+
+
+def workload(seed=1512, n_chains=512):
+    import numpy as np
+    g = np.random.default_rng(seed)
+    L = g.choice([16, 32, 64, 128], size=n_chains, p=[0.4, 0.3, 0.2, 0.1]).tolist()
+    beta = g.uniform(1.0, 4.0, size=n_chains).tolist()
+    m0 = g.uniform(0.02, 0.2, size=n_chains).tolist()
+    return L, beta, m0
+
+
+def algorithmic_bytes(stat, kernel):
+    b = BYTES[kernel]
+    return (stat["site_iters_fp32"] * b["fp32"] + stat["site_updates"] * b["upd"]
+            + stat["site_iters_fp64"] * b["fp64"])
+
+
+def run_batched(args):
+    import torch
+    import paper_1512_03812_amd as hmc
+    L, beta, m0 = workload(args.seed, args.chains)
+    lat = hmc.Lattice.batch(L, L, beta, m0, seed=args.seed)
+    lat.hot_start()
+    lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=0.1)
+    for _ in range(args.warmup):
+        lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+    torch.cuda.synchronize()
+    lat.set_timing(True)
+    acc, status, iters, force_evals, solves = [], [], 0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+        acc += r.accepted
+        status += r.status
+        iters += sum(r.n_cg_iters)
+        force_evals, solves = r.n_force_evals, r.n_solves
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s1, s2 = lat.kernel_stats(0), lat.kernel_stats(1)
+    lat.set_timing(False)
+    return dict(L=L, dt=dt, acc=acc, status=status, s1=s1, s2=s2, sites=lat.V_total,
+                n_chains=lat.n_chains, force_evals=force_evals, solves=solves,
+                cg_iters_per_traj=iters / max(1, args.steps))
+
+
+def run_single_fp64(args):
+    """The plain FP64 single-chain path: 32 x 32, beta 2, m0 0.1, same scheme."""
+    import torch
+    import paper_1512_03812_amd as hmc
+    lat = hmc.Lattice(32, 2.0, 0.1, seed=args.seed)
+    lat.hot_start()
+    lat.set_solver(tol=1e-12)
+    for _ in range(2):
+        lat.trajectory("adapted_nested_fg", 1.0, 8, 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc = []
+    n = args.single_steps
+    for _ in range(n):
+        acc += lat.trajectory("adapted_nested_fg", 1.0, 8, 4).accepted
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "trajectories/s", "ms_per_traj": 1e3 * dt / n,
+            "acceptance": sum(acc) / len(acc), "dtype": "f64",
+            "config": "32x32, beta 2.0, m0 0.1, adapted nested FG tau 1 n_outer 8 n_inner 4, CG tol 1e-12"}
+
+
+def cpu_baseline(args):
+    """The oracle (plain FP64 C, one thread) on a bounded, stratified sample of the workload:
+    full oracle trajectories (adapted nested FG, tau 1, 8 x 4, CG to 1e-10) from the hot
+    start of the first 3 chains with L = 16, the first 2 with L = 32 and the first with
+    L = 64; for L = 128 one fermion-force solve at its hot start, scaled by the
+    trajectory/solve time ratio measured on the L = 64 chain.  Per-size mean times are
+    weighted by the workload's count of chains of each size."""
+    import oracle
+    L, beta, m0 = workload(args.seed, args.chains)
+    t_begin = time.perf_counter()
+    per_L, solve_t = {}, {}
+
+    def first(Ls, k):
+        return [i for i, l in enumerate(L) if l == Ls][:k]
+
+    def solve_time(Ls, c):
+        q = oracle.random_links(Ls, Ls, args.seed, c)
+        phi = oracle.dirac_dagger(q, oracle.random_zeta(Ls, Ls, args.seed, c, 0), m0[c])
+        t0 = time.perf_counter()
+        oracle.fermion_force(q, phi, m0[c], tol=1e-10)
+        return time.perf_counter() - t0
+
+    for Ls, k in ((16, 3), (32, 2), (64, 1)):
+        ts = []
+        for c in first(Ls, k):
+            q = oracle.random_links(Ls, Ls, args.seed, c)
+            t0 = time.perf_counter()
+            oracle.hmc_trajectory(q, beta[c], m0[c], args.seed, c, 0, "adapted_nested_fg", 1.0, 8, 4,
+                                  tol=1e-10)
+            ts.append(time.perf_counter() - t0)
+        if ts:
+            per_L[Ls] = sum(ts) / len(ts)
+    ratio = per_L[64] / solve_time(64, first(64, 1)[0]) if 64 in per_L else 33.0
+    c128 = first(128, 1)
+    if c128:
+        per_L[128] = ratio * solve_time(128, c128[0])
+    total = sum(per_L[Ls] * L.count(Ls) for Ls in per_L)
+    sample_s = time.perf_counter() - t_begin
+    return {"value": round(len(L) / total, 4), "unit": "chain-trajectories/s", "cores": 1,
+            "kind": "oracle",
+            "sample": ("full oracle trajectories from the hot start of the first 3 L=16, 2 L=32 and "
+                       "1 L=64 chains; L=128 from one oracle solve times the trajectory/solve ratio "
+                       f"({ratio:.1f}) of the L=64 chain; weighted by the workload's L counts; "
+                       f"sample CPU time {sample_s:.1f} s"),
+            "seconds_per_chain_traj_by_L": {str(k): round(v, 3) for k, v in per_L.items()}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=1512)
+    ap.add_argument("--chains", type=int, default=512)
+    ap.add_argument("--single-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the chains of this workload are independent and "
+              "this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    b = run_batched(args)
+    n_traj = b["n_chains"] * args.steps
+    value = n_traj / b["dt"]
+    s1, s2 = b["s1"], b["s2"]
+    by1, by2 = algorithmic_bytes(s1, "step1"), algorithmic_bytes(s2, "step2")
+    ach2 = by2 / (s2["total_ms"] * 1e-3) / 1e9 if s2["total_ms"] > 0 else 0.0
+    cg_gbs = (by1 + by2) / ((s1["total_ms"] + s2["total_ms"]) * 1e-3) / 1e9 if s1["total_ms"] > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "chain-trajectories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * b["dt"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("batched: 512 chains, L in {16,32,64,128} weights 4:3:2:1, beta U[1,4], "
+                         "m0 U[0.02,0.2], hot start, adapted nested FG tau=1 n_outer=8 n_inner=4, "
+                         "mixed CG (FP32 + FP64 reliable updates) to true residual 1e-10"),
+            "n_chains": b["n_chains"], "sites": b["sites"], "scheme": "adapted_nested_fg",
+            "parallelism": "single GPU, chains batched in every launch",
+        },
+        "acceptance": round(sum(b["acc"]) / len(b["acc"]), 4),
+        "chain_failures": sum(1 for s in b["status"] if s != 0),
+        "cg_iters_per_step": b["cg_iters_per_traj"],
+        "force_evals_per_traj": b["force_evals"],
+        "solves_per_traj": b["solves"],
+        "roofline": {
+            "bound": "hbm", "kernel": "k_cg_step2_mixed",
+            "achieved": round(ach2, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach2 / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(1e3 * s2["total_ms"] / max(1, s2["launches"]), 3),
+            "launches": s2["launches"],
+        },
+        "cg_step1_step2_gbs": round(cg_gbs, 1),
+    }
+    if not args.no_single:
+        out["fp64_single_chain"] = run_single_fp64(args)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -244,6 +244,22 @@ int hmc_refresh(hmc_ctx *ctx);
 int hmc_integrate(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inner, int prec,
                   hmc_traj_info *info);
 
+/* ---------------------------------------------------------------- kernel timing */
+
+/* Event timing of the CG step kernels: while on, every CG iteration slot is bracketed by
+ * HIP events on the bound stream (which = 0: step 1, t = D p; which = 1: step 2,
+ * D^dagger t and the x, r updates).  hmc_set_timing resets the statistics. */
+typedef struct {
+    long long launches;        /* timed launches of this kernel */
+    double total_ms;           /* summed event-measured duration */
+    long long site_iters_fp64; /* sum over solves and chains of V_c * FP64 iterations */
+    long long site_iters_fp32; /* same for FP32 iterations of the mixed solver */
+    long long site_updates;    /* same for FP64 residual recomputations of the mixed solver */
+} hmc_kernel_stat;
+
+int hmc_set_timing(hmc_ctx *ctx, int on);
+int hmc_get_kernel_stats(hmc_ctx *ctx, int which, hmc_kernel_stat *out);
+
 /* ---------------------------------------------------------------- misc */
 
 const char *hmc_last_error(const hmc_ctx *ctx);

@@ -232,6 +232,16 @@ class Lattice:
     def set_check_interval(self, every: int):
         self._check(self._lib.hmc_set_check_interval(self._ctx, int(every)))
 
+    def set_timing(self, on: bool):
+        """Bracket every CG iteration slot with HIP events (resets the statistics)."""
+        self._check(self._lib.hmc_set_timing(self._ctx, int(bool(on))))
+
+    def kernel_stats(self, which: int) -> dict:
+        """Event timing of CG step 1 (which=0) or step 2 (which=1) since set_timing."""
+        st = _lib.KernelStat()
+        self._check(self._lib.hmc_get_kernel_stats(self._ctx, int(which), ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
     @property
     def trajectory_counter(self) -> int:
         return int(self._lib.hmc_get_trajectory_counter(self._ctx))

@@ -32,6 +32,12 @@ class TrajInfo(ctypes.Structure):
                 ("n_cg_iters", ctypes.c_longlong)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_longlong), ("total_ms", ctypes.c_double),
+                ("site_iters_fp64", ctypes.c_longlong), ("site_iters_fp32", ctypes.c_longlong),
+                ("site_updates", ctypes.c_longlong)]
+
+
 # name -> (restype, argtypes)
 _P, _I, _D, _U32, _U64, _SZ = (ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint32,
                                ctypes.c_uint64, ctypes.c_size_t)
@@ -68,6 +74,8 @@ SIGNATURES = {
     "hmc_trajectory": (_I, [_P, _I, _D, _I, _I, _I, _P]),
     "hmc_integrate": (_I, [_P, _I, _D, _I, _I, _I, _P]),
     "hmc_refresh": (_I, [_P]),
+    "hmc_set_timing": (_I, [_P, _I]),
+    "hmc_get_kernel_stats": (_I, [_P, _I, _P]),
     "hmc_last_error": (ctypes.c_char_p, [_P]),
     "hmc_destroy": (_I, [_P]),
 }

@@ -19,7 +19,7 @@
 
 namespace shmc {
 
-constexpr int kMaxBlock = 256;  // threads per workgroup of the site kernels
+constexpr int kMaxBlock = 1024;  // largest workgroup of the site kernels
 
 struct ChainInfo {
     int off;      // first flat site
@@ -37,11 +37,12 @@ struct ChainInfo {
 static_assert(sizeof(ChainInfo) == 64, "ChainInfo is 64 bytes");
 
 // One entry per hardware workgroup (hardware order, XCD-aware permutation applied on the host).
+// A workgroup of B threads handles the chain-local sites start + tid + j*B, j < spt.
 struct BlockWork {
     int chain;    // chain index
     int start;    // first chain-local site handled by this workgroup
     int logical;  // logical workgroup index (chains are contiguous in logical order)
-    int pad;
+    int spt;      // sites per thread
 };
 
 struct Site {

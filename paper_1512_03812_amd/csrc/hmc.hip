@@ -28,6 +28,17 @@ enum Spin32Buf { FX, FR, FT, FPA, FPB, kNumSpin32Bufs };
 
 }  // namespace
 
+// Event timing of the two CG step kernels (kernel index 0: step 1, 1: step 2).
+struct KernelTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // pool, three events per timed slot
+    size_t used = 0;
+    double ms[2] = {0.0, 0.0};
+    long long launches[2] = {0, 0};
+    long long site_iters[2] = {0, 0};  // sum over solves of V_c * iterations (FP64, mixed FP32)
+    long long site_updates = 0;        // sum of V_c * FP64 residual recomputations (mixed)
+};
+
 struct hmc_ctx {
     // ------------------------------------------------------------ geometry (host)
     int nchains = 0;
@@ -47,7 +58,7 @@ struct hmc_ctx {
     size_t ws_bytes = 0;
     char *ws = nullptr;
     hipStream_t stream = nullptr;
-    size_t off_chains = 0, off_work = 0, off_cg = 0, off_partials = 0, off_counters = 0,
+    size_t off_chains = 0, off_work = 0, off_active = 0, off_cg = 0, off_partials = 0,
            off_sums = 0, off_metro = 0, off_status = 0, off_count = 0, off_links[kNumLinkBufs] = {},
            off_spin[kNumSpinBufs] = {}, off_U64 = 0, off_U32 = 0, off_spin32[kNumSpin32Bufs] = {};
     // ------------------------------------------------------------ pinned host staging
@@ -62,6 +73,7 @@ struct hmc_ctx {
     std::string err;
     // per-solve bookkeeping of the last CG (host copies)
     std::vector<CGState> cg_host;
+    KernelTimer timer;
 
     // ------------------------------------------------------------ accessors
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -77,17 +89,13 @@ struct hmc_ctx {
         g.chains = at<ChainInfo>(off_chains);
         g.work = at<BlockWork>(off_work);
         g.nblocks = (int)work.size();
+        g.nlog = (int)work.size();
         g.nchains = nchains;
         g.Vtot = Vtot;
         g.block = block;
         return g;
     }
-    Reduce red() const {
-        Reduce r;
-        r.partials = at<double>(off_partials);
-        r.counters = at<unsigned>(off_counters);
-        return r;
-    }
+    double *partials() const { return at<double>(off_partials); }
 };
 
 namespace {
@@ -117,21 +125,27 @@ int fail(hmc_ctx *c, int code, const char *fmt, ...) {
         if (!(ctx)->ws) return fail(ctx, HMC_E_INVAL, "context has no workspace bound");        \
     } while (0)
 
-// Block table: every chain gets ceil(V / block) logical workgroups (chains contiguous in
-// logical order); hardware workgroup h runs on XCD h % 8, and the j-th workgroup of XCD k
+// Block table: every chain gets ceil(V / (block * spt)) logical workgroups (chains
+// contiguous in logical order), with spt sites per thread chosen so that no chain has
+// more than kMaxChainBlocks workgroups (a consumer workgroup re-adds all of its chain's
+// partials).  Hardware workgroup h runs on XCD h % 8, and the j-th workgroup of XCD k
 // receives logical workgroup start_k + j, so each XCD sweeps one contiguous site range.
+constexpr int kMaxChainBlocks = 2048;
+
 void build_tables(hmc_ctx *c) {
     std::vector<BlockWork> logical;
     for (int ch = 0; ch < c->nchains; ++ch) {
         ChainInfo &ci = c->chains[ch];
+        const long long per = (long long)c->block * kMaxChainBlocks;
+        const int spt = (int)((ci.V + per - 1) / per);
         ci.block0 = (int)logical.size();
-        ci.nblocks = (ci.V + c->block - 1) / c->block;
+        ci.nblocks = (ci.V + c->block * spt - 1) / (c->block * spt);
         for (int j = 0; j < ci.nblocks; ++j) {
             BlockWork w;
             w.chain = ch;
-            w.start = j * c->block;
+            w.start = j * c->block * spt;
             w.logical = (int)logical.size();
-            w.pad = 0;
+            w.spt = spt;
             logical.push_back(w);
         }
     }
@@ -148,9 +162,9 @@ void layout_workspace(hmc_ctx *c) {
     const size_t C = c->nchains, N = c->work.size(), V = c->Vtot;
     c->off_chains = take(sizeof(ChainInfo) * C);
     c->off_work = take(sizeof(BlockWork) * N);
-    c->off_cg = take(sizeof(CGState) * C);
+    c->off_active = take(sizeof(BlockWork) * N);
+    c->off_cg = take(sizeof(CGState) * 2 * C);
     c->off_partials = take(sizeof(double) * kMaxReduce * N);
-    c->off_counters = take(sizeof(unsigned) * C);
     c->off_sums = take(sizeof(double) * 16 * C);
     c->off_metro = take(sizeof(MetroOut) * C);
     c->off_status = take(sizeof(int) * C);
@@ -238,78 +252,122 @@ void forget_all(hmc_ctx *c) {
     c->ff_version = c->xi_version = -1;
 }
 
-__global__ void k_count_converged(const CGState *st, int n, int *out) {
-    __shared__ int sh;
-    if (threadIdx.x == 0) sh = 0;
-    __syncthreads();
-    int cnt = 0;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) cnt += st[c].converged;
-    atomicAdd(&sh, cnt);
-    __syncthreads();
-    if (threadIdx.x == 0) out[0] = sh;
+// Rebuilds the list of workgroups of the unconverged chains; returns its length in *active.
+int check_convergence(hmc_ctx *c, int *active) {
+    int *dev = c->at<int>(c->off_count);
+    launch_compact(c->geo(), c->cg(), c->at<BlockWork>(c->off_active), dev, c->stream);
+    int n = 0;
+    int rc = to_host(c, &n, dev, sizeof(int));
+    if (rc) return rc;
+    *active = n;
+    return HMC_OK;
 }
 
-int all_converged(hmc_ctx *c, bool *done) {
-    hipLaunchKernelGGL(k_count_converged, dim3(1), dim3(256), 0, c->stream, c->cg(), c->nchains,
-                       c->at<int>(c->off_count));
-    int cnt = 0;
-    int rc = to_host(c, &cnt, c->at<int>(c->off_count), sizeof(int));
-    if (rc) return rc;
-    *done = cnt == c->nchains;
-    return HMC_OK;
+// Timing of the CG step kernels with HIP events on the library's stream.
+void timer_flush(hmc_ctx *c) {
+    KernelTimer &T = c->timer;
+    // called only after the stream was synchronised, so every recorded event is complete
+    for (size_t k = 0; k + 3 <= T.used; k += 3) {
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, T.ev[k], T.ev[k + 1]) == hipSuccess) T.ms[0] += a;
+        if (hipEventElapsedTime(&b, T.ev[k + 1], T.ev[k + 2]) == hipSuccess) T.ms[1] += b;
+        T.launches[0]++;
+        T.launches[1]++;
+    }
+    T.used = 0;
+}
+
+hipEvent_t timer_event(hmc_ctx *c) {
+    KernelTimer &T = c->timer;
+    if (T.used == T.ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        T.ev.push_back(e);
+    }
+    return T.ev[T.used++];
+}
+
+// One CG slot (step 1 + step 2), bracketed by events when timing is on.
+template <typename L1, typename L2> void slot_launch(hmc_ctx *c, L1 step1, L2 step2) {
+    if (!c->timer.on) {
+        step1();
+        step2();
+        return;
+    }
+    hipEvent_t a = timer_event(c), b = timer_event(c), d = timer_event(c);
+    (void)hipEventRecord(a, c->stream);
+    step1();
+    (void)hipEventRecord(b, c->stream);
+    step2();
+    (void)hipEventRecord(d, c->stream);
+}
+
+void timer_account(hmc_ctx *c, bool mixed) {
+    if (!c->timer.on) return;
+    timer_flush(c);
+    for (int k = 0; k < c->nchains; ++k) {
+        const long long V = c->chains[k].V;
+        c->timer.site_iters[mixed ? 1 : 0] += V * c->cg_host[k].iters;
+        c->timer.site_updates += V * c->cg_host[k].n_updates;
+    }
 }
 
 // CG on D^dagger D x = phi with the links already materialised (U64, and U32 if mixed).
 // Per-chain results land in c->cg_host.  Returns HMC_E_NOCONV if a chain did not converge.
+// Every check_every slots the host reads back how many workgroups still belong to
+// unconverged chains and launches only those from then on.
 int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, int prec) {
-    const Geo g = c->geo();
-    const Reduce r = c->red();
-    int rc = HMC_OK;
-    if (prec == HMC_PREC_FP64) {
-        launch_cg_init64(g, r, phi, x, c->spin(SR), c->cg(), tol, 0.0, c->stream);
-        double2 *pb[2] = {c->spin(SPA), c->spin(SPB)};
-        int cur = 0;
-        for (int it = 1; it <= max_iter; ++it) {
-            launch_cg_step64(g, r, c->U64(), x, c->spin(SR), pb[cur], pb[cur ^ 1], c->spin(ST),
-                             c->cg(), c->stream);
-            cur ^= 1;
-            if (it % c->check_every == 0 || it == max_iter) {
-                bool done = false;
-                if ((rc = all_converged(c, &done))) return rc;
-                if (done) break;
-            }
-        }
-    } else {
-        MixedFields m;
-        m.phi = phi;
-        m.x64 = x;
-        m.t64 = c->spin(ST);
-        m.x32 = c->spin32(FX);
-        m.r32 = c->spin32(FR);
-        m.t32 = c->spin32(FT);
-        launch_cg_init_mixed(g, r, m, c->cg(), tol, c->delta, c->stream);
-        float2 *pb[2] = {c->spin32(FPA), c->spin32(FPB)};
-        int cur = 0;
-        // iteration slots: FP32 iterations plus FP64 residual recomputations
-        const int max_slots = max_iter + max_iter / 2 + 64;
-        for (int it = 1; it <= max_slots; ++it) {
-            launch_cg_step_mixed(g, r, c->U64(), c->U32(), m, pb[cur], pb[cur ^ 1], c->cg(), c->stream);
-            cur ^= 1;
-            if (it % c->check_every == 0 || it == max_slots) {
-                bool done = false;
-                if ((rc = all_converged(c, &done))) return rc;
-                if (done) break;
+    const bool mixed = prec == HMC_PREC_MIXED;
+    const Geo full = c->geo();
+    Geo g = full;
+    CGFields f;
+    f.phi = phi;
+    f.x64 = x;
+    f.r64 = c->spin(SR);
+    f.t64 = c->spin(ST);
+    f.x32 = c->spin32(FX);
+    f.r32 = c->spin32(FR);
+    f.t32 = c->spin32(FT);
+    f.U64 = c->U64();
+    f.U32 = c->U32();
+    f.p1 = c->partials();
+    f.p2 = c->partials() + full.nlog;
+    f.st = c->cg();
+    void *pb[2];
+    if (mixed) { pb[0] = c->spin32(FPA); pb[1] = c->spin32(FPB); }
+    else { pb[0] = c->spin(SPA); pb[1] = c->spin(SPB); }
+    launch_cg_init(full, f, mixed, c->delta, c->stream);
+    // iteration slots: CG iterations plus, in mixed precision, FP64 residual recomputations
+    const int max_slots = mixed ? max_iter + max_iter / 2 + 64 : max_iter;
+    int rc = HMC_OK, slot = 0;
+    for (; slot < max_slots; ++slot) {
+        void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
+        slot_launch(c, [&] { launch_cg_step1(g, f, mixed, slot, tol, po, pn, false, c->stream); },
+                    [&] { launch_cg_step2(g, f, mixed, slot, pn, c->stream); });
+        if ((slot + 1) % c->check_every == 0) {
+            int active = 0;
+            if ((rc = check_convergence(c, &active))) return rc;
+            if (c->timer.on) timer_flush(c);
+            if (active == 0) { ++slot; break; }
+            g.work = c->at<BlockWork>(c->off_active);
+            g.nblocks = active;
+            if (mixed) {
                 // stop when every unconverged chain has used up its FP32 iterations
-                if ((rc = to_host(c, c->cg_host.data(), c->cg(), sizeof(CGState) * c->nchains))) return rc;
+                if ((rc = to_host(c, c->cg_host.data(), c->cg() + (size_t)(slot & 1) * c->nchains,
+                                  sizeof(CGState) * c->nchains))) return rc;
                 bool exhausted = true;
                 for (const CGState &s : c->cg_host)
                     if (!s.converged && s.iters < max_iter) exhausted = false;
-                if (exhausted) break;
+                if (exhausted) { ++slot; break; }
             }
         }
-        launch_cg_finish_mixed(g, m, c->cg(), c->stream);
     }
-    if ((rc = to_host(c, c->cg_host.data(), c->cg(), sizeof(CGState) * c->nchains))) return rc;
+    // fold the last slot's residual into the state (decision only), on every chain
+    launch_cg_step1(full, f, mixed, slot, tol, pb[slot & 1], pb[(slot + 1) & 1], true, c->stream);
+    if (mixed) launch_cg_finish_mixed(full, f, c->stream);
+    if ((rc = to_host(c, c->cg_host.data(), c->cg() + (size_t)(slot & 1) * c->nchains,
+                      sizeof(CGState) * c->nchains))) return rc;
+    timer_account(c, mixed);
     for (const CGState &s : c->cg_host)
         if (!s.converged) return fail(c, HMC_E_NOCONV, "CG did not converge in %d iterations", max_iter);
     return HMC_OK;
@@ -323,7 +381,7 @@ void fill_cg_info(hmc_ctx *c, hmc_cg_info *info, const std::vector<double> *true
         info[k].converged = s.converged;
         info[k].reliable_updates = s.n_updates;
         info[k].pad = 0;
-        info[k].rel_resid = s.phi2 > 0 ? sqrt(s.rho / s.phi2) : 0.0;
+        info[k].rel_resid = s.phi2 > 0 ? sqrt(s.rho / s.phi2) : 0.0;  // last decided residual
         info[k].rel_resid_true = (true2 && s.phi2 > 0) ? sqrt((*true2)[k] / s.phi2) : info[k].rel_resid;
     }
 }
@@ -536,8 +594,6 @@ int hmc_bind(hmc_ctx *c, void *ws, size_t bytes, void *stream) {
                               sizeof(ChainInfo) * c->nchains, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->at<BlockWork>(c->off_work), c->work.data(),
                               sizeof(BlockWork) * c->work.size(), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->at<unsigned>(c->off_counters), 0, sizeof(unsigned) * c->nchains,
-                              c->stream));
     HIP_TRY(c, hipMemsetAsync(c->link(LQ), 0, sizeof(double) * 2 * c->Vtot, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->link(LP), 0, sizeof(double) * 2 * c->Vtot, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->spin(SPHI), 0, sizeof(double2) * 2 * c->Vtot, c->stream));
@@ -683,8 +739,8 @@ int hmc_cg_solve(hmc_ctx *c, const void *phi, void *x, double tol, int max_iter,
     if (rc && rc != HMC_E_NOCONV) return rc;
     std::vector<double> t2(c->nchains);
     double *dev = c->sums() + 12 * c->nchains;
-    launch_true_residual64(c->geo(), c->red(), c->U64(), (const double2 *)phi, (const double2 *)x,
-                           c->spin(ST), dev, c->stream);
+    launch_true_residual64(c->geo(), c->U64(), (const double2 *)phi, (const double2 *)x,
+                           c->spin(ST), c->partials(), dev, c->stream);
     int rc2 = to_host(c, t2.data(), dev, sizeof(double) * c->nchains);
     if (rc2) return rc2;
     fill_cg_info(c, info, &t2);
@@ -714,8 +770,8 @@ int hmc_fermion_force(hmc_ctx *c, const void *phi, double *f, double tol, int ma
     fill_cg_info(c, info, nullptr);
     if (sf) {
         double *dev = c->sums() + 12 * c->nchains;
-        launch_gauge_energy(c->geo(), c->red(), c->link(LQ), (const double2 *)phi, c->spin(SXI),
-                            dev, c->stream);
+        launch_gauge_energy(c->geo(), c->link(LQ), (const double2 *)phi, c->spin(SXI),
+                            c->partials(), dev, c->stream);
         std::vector<double> h(3 * c->nchains);
         int rc2 = to_host(c, h.data(), dev, sizeof(double) * 3 * c->nchains);
         if (rc2) return rc2;
@@ -755,8 +811,8 @@ int hmc_actions(hmc_ctx *c, const void *phi, double tol, double *s_gauge, double
         c->ff_version = c->xi_version = -1;
     }
     double *dev = c->sums() + 12 * C;
-    launch_gauge_energy(c->geo(), c->red(), c->link(LQ), (phi && s_fermion) ? (const double2 *)phi : nullptr,
-                        c->spin(SXI), dev, c->stream);
+    launch_gauge_energy(c->geo(), c->link(LQ), (phi && s_fermion) ? (const double2 *)phi : nullptr,
+                        c->spin(SXI), c->partials(), dev, c->stream);
     std::vector<double> h(3 * C);
     int rc = to_host(c, h.data(), dev, sizeof(double) * 3 * C);
     if (rc) return rc;
@@ -828,8 +884,8 @@ static int finish_traj(hmc_ctx *c, MD &md, bool metropolis, hmc_traj_info *info)
     double *es = c->sums();             // [7][C]
     double *rs = c->sums() + 7 * C;     // [2][C] from the refresh
     double *gs = c->sums() + 9 * C;     // [3][C]
-    launch_energy(g, c->red(), c->link(LQ), c->link(LQ0), c->link(LP), c->link(LP0),
-                  fermions ? c->spin(SPHI) : nullptr, c->spin(SXI), es, c->stream);
+    launch_energy(g, c->link(LQ), c->link(LQ0), c->link(LP), c->link(LP0),
+                  fermions ? c->spin(SPHI) : nullptr, c->spin(SXI), c->partials(), es, c->stream);
     HIP_TRY(c, hipMemcpyAsync(c->at<int>(c->off_status), md.chain_status.data(), sizeof(int) * C,
                               hipMemcpyHostToDevice, c->stream));
     MetroOut *mo = c->at<MetroOut>(c->off_metro);
@@ -838,7 +894,7 @@ static int finish_traj(hmc_ctx *c, MD &md, bool metropolis, hmc_traj_info *info)
         launch_restore(g, mo, c->link(LQ0), c->link(LQ), c->stream);
         c->q_version++;
     }
-    launch_gauge_energy(g, c->red(), c->link(LQ), nullptr, c->spin(SXI), gs, c->stream);
+    launch_gauge_energy(g, c->link(LQ), nullptr, c->spin(SXI), c->partials(), gs, c->stream);
     std::vector<MetroOut> mh(C);
     std::vector<double> gh(3 * C);
     int rc = to_host(c, mh.data(), mo, sizeof(MetroOut) * C);
@@ -871,7 +927,8 @@ static void refresh(hmc_ctx *c) {
     const Geo g = c->geo();
     const bool fermions = !c->quenched;
     double *rs = c->sums() + 7 * c->nchains;
-    launch_refresh(g, c->red(), c->seed, c->traj, c->link(LP), c->spin(SZETA), fermions, rs, c->stream);
+    launch_refresh(g, c->seed, c->traj, c->link(LP), c->spin(SZETA), fermions, c->partials(), rs,
+                   c->stream);
     if (fermions) {
         ensure_links(c, c->link(LQ), false, c->q_version);
         launch_dslash64(g, c->U64(), c->spin(SZETA), c->spin(SPHI), true, c->stream);
@@ -925,8 +982,9 @@ int hmc_integrate(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, 
             rc = solve(c, c->spin(SPHI), c->spin(SXI), md.tol, md.max_iter, prec);
             if (rc) return rc;
         }
-        launch_energy(g, c->red(), c->link(LQ), c->link(LQ0), c->link(LP), c->link(LP0),
-                      c->quenched ? nullptr : c->spin(SPHI), c->spin(SXI), es, c->stream);
+        launch_energy(g, c->link(LQ), c->link(LQ0), c->link(LP), c->link(LP0),
+                      c->quenched ? nullptr : c->spin(SPHI), c->spin(SXI), c->partials(), es,
+                      c->stream);
         std::vector<double> h(7 * C), r(2 * C);
         if ((rc = to_host(c, h.data(), es, sizeof(double) * 7 * C))) return rc;
         for (int k = 0; k < C; ++k) { r[k] = h[2 * C + k]; r[C + k] = h[5 * C + k]; }
@@ -940,8 +998,36 @@ int hmc_integrate(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, 
 
 const char *hmc_last_error(const hmc_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+int hmc_set_timing(hmc_ctx *c, int on) {
+    if (!c) return HMC_E_INVAL;
+    if (c->ws) {
+        int rc = sync(c);
+        if (rc) return rc;
+    }
+    KernelTimer &T = c->timer;
+    T.on = on != 0;
+    T.used = 0;
+    T.ms[0] = T.ms[1] = 0.0;
+    T.launches[0] = T.launches[1] = 0;
+    T.site_iters[0] = T.site_iters[1] = 0;
+    T.site_updates = 0;
+    return HMC_OK;
+}
+
+int hmc_get_kernel_stats(hmc_ctx *c, int which, hmc_kernel_stat *out) {
+    if (!c || !out || which < 0 || which > 1) return HMC_E_INVAL;
+    const KernelTimer &T = c->timer;
+    out->launches = T.launches[which];
+    out->total_ms = T.ms[which];
+    out->site_iters_fp64 = T.site_iters[0];
+    out->site_iters_fp32 = T.site_iters[1];
+    out->site_updates = T.site_updates;
+    return HMC_OK;
+}
+
 int hmc_destroy(hmc_ctx *c) {
     if (!c) return HMC_E_INVAL;
+    for (hipEvent_t e : c->timer.ev) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
     return HMC_OK;

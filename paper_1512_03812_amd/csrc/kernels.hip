@@ -1,31 +1,32 @@
 // HIP kernels (gfx950) of the Schwinger-model HMC hot path.
 //
-// Every site kernel runs one thread per lattice site.  Workgroup b handles the sites
-// [work[b].start, work[b].start + blockDim) of chain work[b].chain; the host permutes
-// the table so that each XCD receives a contiguous range of sites (its L2 then holds
-// the neighbouring rows of the stencil).  Per-chain sums use a deterministic two-level
-// tree: a wavefront shuffle + LDS reduction per workgroup, then the last workgroup of
-// the chain to arrive (agent-scope atomic counter) adds the chain's block partials in
-// a fixed order.  No floating-point atomics are used, so every result is bitwise
-// reproducible run to run.
+// Site kernels: workgroup b handles the sites start + tid + j*B (j < spt) of chain
+// work[b].chain; the host permutes the workgroup table so that each XCD receives a
+// contiguous range of sites (its L2 then holds the neighbouring rows of the stencil).
+//
+// Reductions use no atomics and no cross-workgroup fences: a producer kernel writes one
+// partial per workgroup (wavefront shuffle + LDS tree), and every consumer workgroup of a
+// chain re-adds that chain's partials in a fixed order, so all of them obtain the same,
+// bitwise reproducible total.  The kernel boundary provides the visibility.  Totals that
+// the host needs go through a one-workgroup-per-chain finalize kernel.
 #include <math.h>
 
 #include "kernels.hpp"
 
 namespace shmc {
 
-constexpr int kMaxWaves = 1024 / 64;
+constexpr int kMaxWaves = kMaxBlock / 64;
 
 // ================================================================ reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
+    return v;  // complete in lane 0
 }
 
-// Sums NV values over the workgroup; the result is valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (&sh)[NV][kMaxWaves]) {
+// Sums NV values over the workgroup; every thread receives the totals.
+template <int NV> __device__ __forceinline__ void block_sum_all(double (&v)[NV]) {
+    __shared__ double sh[NV][kMaxWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
@@ -34,51 +35,52 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (&sh)[NV][kMax
         for (int k = 0; k < NV; ++k) sh[k][wave] = v[k];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double a = 0.0;
-            for (int w = 0; w < nw; ++w) a += sh[k][w];
-            v[k] = a;
-        }
+    for (int k = 0; k < NV; ++k) {
+        double a = 0.0;
+        for (int w = 0; w < nw; ++w) a += sh[k][w];
+        v[k] = a;
     }
     __syncthreads();
 }
 
-// Per-chain reduction.  Returns true in the last-arriving workgroup of the chain, whose
-// thread 0 then holds the chain totals in tot[].  All workgroups of a chain must call it.
+// One partial per workgroup into row k of partials (k < NV).
 template <int NV>
-__device__ bool chain_reduce(double (&v)[NV], const ChainInfo &ci, const BlockWork &w,
-                             const Reduce &red, int nlog, double (&tot)[NV]) {
-    __shared__ double sh[NV][kMaxWaves];
-    __shared__ int is_last;
-    block_sum<NV>(v, sh);
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *partials, int nlog,
+                                               int logical) {
+    block_sum_all<NV>(v);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
-            __hip_atomic_store(&red.partials[(size_t)k * nlog + w.logical], v[k], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        unsigned prev = __hip_atomic_fetch_add(&red.counters[w.chain], 1u, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (prev == (unsigned)(ci.nblocks - 1)) ? 1 : 0;
+        for (int k = 0; k < NV; ++k) partials[(size_t)k * nlog + logical] = v[k];
     }
-    __syncthreads();
-    if (!is_last) return false;
-    double acc[NV];
+}
+
+// The chain's total of one partial row, identical in every workgroup of the chain.
+__device__ __forceinline__ double chain_total(const double *__restrict__ row, const ChainInfo &ci) {
+    double a[1] = {0.0};
+    for (int j = threadIdx.x; j < ci.nblocks; j += blockDim.x) a[0] += row[ci.block0 + j];
+    block_sum_all<1>(a);
+    return a[0];
+}
+
+template <int NV> __global__ void k_finalize(Geo g, const double *__restrict__ partials, double *out) {
+    const ChainInfo ci = g.chains[blockIdx.x];
+    double v[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        acc[k] = 0.0;
+        v[k] = 0.0;
         for (int j = threadIdx.x; j < ci.nblocks; j += blockDim.x)
-            acc[k] += __hip_atomic_load(&red.partials[(size_t)k * nlog + ci.block0 + j],
-                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            v[k] += partials[(size_t)k * g.nlog + ci.block0 + j];
     }
-    block_sum<NV>(acc, sh);
+    block_sum_all<NV>(v);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) tot[k] = acc[k];
-        __hip_atomic_store(&red.counters[w.chain], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < NV; ++k) out[(size_t)k * g.nchains + blockIdx.x] = v[k];
     }
-    return true;
+}
+
+template <int NV> void launch_finalize(const Geo &g, const double *partials, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize<NV>, dim3(g.nchains), dim3(256), 0, s, g, partials, out);
 }
 
 // ================================================================ stencil
@@ -128,45 +130,49 @@ __device__ __forceinline__ double norm2(float2 a) {
     return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
 }
 
-#define SITE_PROLOGUE                                  \
-    const BlockWork w = g.work[blockIdx.x];            \
-    const ChainInfo ci = g.chains[w.chain];            \
-    const int local = w.start + (int)threadIdx.x;      \
-    const bool valid = local < ci.V;                   \
-    const int Vtot = g.Vtot;                           \
-    (void)Vtot;
+// Loop over the sites of this workgroup; `local` is the chain-local site index.
+#define SITES_LOOP                                                                \
+    for (int j_ = 0; j_ < w.spt; ++j_) {                                          \
+        const int local = w.start + (int)threadIdx.x + j_ * (int)blockDim.x;      \
+        if (local >= ci.V) break;
+#define SITES_BEGIN                                                               \
+    const BlockWork w = g.work[blockIdx.x];                                       \
+    const ChainInfo ci = g.chains[w.chain];                                       \
+    const int Vtot = g.Vtot;                                                      \
+    (void)Vtot;                                                                   \
+    SITES_LOOP
+#define SITES_END }
 
 // ================================================================ layout
 __global__ void k_pack_links(Geo g, double *__restrict__ lex, double *__restrict__ nat,
                              int to_native) {
-    SITE_PROLOGUE
-    if (!valid) return;
+    SITES_BEGIN
     const Site s = decode_site(ci, local);
     const size_t l = 2 * ((size_t)ci.off + s.x + (size_t)ci.Lx * s.t);
     for (int mu = 0; mu < 2; ++mu) {
         if (to_native) nat[(size_t)mu * Vtot + s.flat] = lex[l + mu];
         else lex[l + mu] = nat[(size_t)mu * Vtot + s.flat];
     }
+    SITES_END
 }
 
 __global__ void k_pack_spinor(Geo g, double2 *__restrict__ lex, double2 *__restrict__ nat,
                               int to_native) {
-    SITE_PROLOGUE
-    if (!valid) return;
+    SITES_BEGIN
     const Site s = decode_site(ci, local);
     const size_t l = 2 * ((size_t)ci.off + s.x + (size_t)ci.Lx * s.t);
     for (int sp = 0; sp < 2; ++sp) {
         if (to_native) nat[(size_t)sp * Vtot + s.flat] = lex[l + sp];
         else lex[l + sp] = nat[(size_t)sp * Vtot + s.flat];
     }
+    SITES_END
 }
 
 void launch_pack_links(const Geo &g, double *lex, double *nat, bool to_native, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_links, dim3(g.nblocks), dim3(g.block), 0, s, g,
-                       lex, nat, to_native ? 1 : 0);
+    hipLaunchKernelGGL(k_pack_links, dim3(g.nblocks), dim3(g.block), 0, s, g, lex, nat,
+                       to_native ? 1 : 0);
 }
-void launch_pack_spinor(const Geo &g, double2 *lex, double2 *nat, bool to_native,
-                        hipStream_t s) {
+void launch_pack_spinor(const Geo &g, double2 *lex, double2 *nat, bool to_native, hipStream_t s) {
     hipLaunchKernelGGL(k_pack_spinor, dim3(g.nblocks), dim3(g.block), 0, s, g, lex, nat,
                        to_native ? 1 : 0);
 }
@@ -176,8 +182,7 @@ void launch_pack_spinor(const Geo &g, double2 *lex, double2 *nat, bool to_native
 // antiperiodic fermion boundary sign.
 __global__ void k_make_links(Geo g, const double *__restrict__ q, double2 *__restrict__ U64,
                              float2 *__restrict__ U32) {
-    SITE_PROLOGUE
-    if (!valid) return;
+    SITES_BEGIN
     const Site s = decode_site(ci, local);
     for (int mu = 0; mu < 2; ++mu) {
         double sn, cs;
@@ -186,6 +191,7 @@ __global__ void k_make_links(Geo g, const double *__restrict__ q, double2 *__res
         U64[(size_t)mu * Vtot + s.flat] = make_double2(cs, sn);
         if (U32) U32[(size_t)mu * Vtot + s.flat] = make_float2((float)cs, (float)sn);
     }
+    SITES_END
 }
 
 void launch_make_links(const Geo &g, const double *q, double2 *U64, float2 *U32, hipStream_t s) {
@@ -196,8 +202,7 @@ void launch_make_links(const Geo &g, const double *q, double2 *U64, float2 *U32,
 template <bool DAG>
 __global__ void k_dslash64(Geo g, const double2 *__restrict__ U, const double2 *__restrict__ in,
                            double2 *__restrict__ out) {
-    SITE_PROLOGUE
-    if (!valid) return;
+    SITES_BEGIN
     const Site s = decode_site(ci, local);
     const Nbr nb = neighbours(ci, s);
     auto load = [&](int f, double2 &b0, double2 &b1) { b0 = in[f]; b1 = in[(size_t)Vtot + f]; };
@@ -206,6 +211,7 @@ __global__ void k_dslash64(Geo g, const double2 *__restrict__ U, const double2 *
                              2.0 + ci.m0, load, o0, o1);
     out[s.flat] = o0;
     out[(size_t)Vtot + s.flat] = o1;
+    SITES_END
 }
 
 void launch_dslash64(const Geo &g, const double2 *U, const double2 *in, double2 *out, bool dagger,
@@ -214,365 +220,321 @@ void launch_dslash64(const Geo &g, const double2 *U, const double2 *in, double2 
     else hipLaunchKernelGGL(k_dslash64<false>, dim3(g.nblocks), dim3(g.block), 0, s, g, U, in, out);
 }
 
-// ================================================================ CG, FP64
-__global__ void k_cg_init64(Geo g, Reduce red, const double2 *__restrict__ phi,
-                            double2 *__restrict__ x, double2 *__restrict__ r, CGState *st,
-                            double tol, double delta) {
-    SITE_PROLOGUE
-    double v[1] = {0.0};
-    if (valid) {
-        const int f = ci.off + local;
-        for (int sp = 0; sp < 2; ++sp) {
-            const double2 a = phi[(size_t)sp * Vtot + f];
-            r[(size_t)sp * Vtot + f] = a;
-            x[(size_t)sp * Vtot + f] = make_double2(0.0, 0.0);
-            v[0] += norm2(a);
-        }
-    }
-    double tot[1];
-    if (chain_reduce<1>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) {
-        CGState &S = st[w.chain];
-        S.phi2 = tot[0];
-        S.rho = tot[0];
-        S.rho_prev = tot[0];
-        S.rmax2 = tot[0];
-        S.target = tol * tol * tot[0];
-        S.delta2 = delta * delta;
-        S.alpha = 0.0;
-        S.beta = 0.0;
-        S.pAp = 0.0;
-        S.iters = 0;
-        S.update = 0;
-        S.n_updates = 0;
-        S.converged = (tot[0] <= S.target) ? 1 : 0;
-    }
-}
-
-// p_new = r + beta p_old (p_new = r on the first iteration), t = D p_new, ||t||^2 -> alpha.
-__global__ void k_cg_step1_64(Geo g, Reduce red, const double2 *__restrict__ U,
-                              const double2 *__restrict__ r, const double2 *__restrict__ p_old,
-                              double2 *__restrict__ p_new, double2 *__restrict__ t, CGState *st) {
-    SITE_PROLOGUE
-    const CGState S = st[w.chain];
-    if (S.converged) return;
-    const bool first = S.iters == 0;
-    const double beta = S.beta;
-    double v[1] = {0.0};
-    if (valid) {
-        const Site s = decode_site(ci, local);
-        const Nbr nb = neighbours(ci, s);
-        auto load = [&](int f, double2 &b0, double2 &b1) {
-            b0 = r[f];
-            b1 = r[(size_t)Vtot + f];
-            if (!first) {
-                const double2 q0 = p_old[f], q1 = p_old[(size_t)Vtot + f];
-                b0 = make_double2(b0.x + beta * q0.x, b0.y + beta * q0.y);
-                b1 = make_double2(b1.x + beta * q1.x, b1.y + beta * q1.y);
-            }
-        };
-        double2 a0, a1, o0, o1;
-        load(s.flat, a0, a1);
-        dslash_site<double, false>(nb, s.flat, Vtot, U, a0, a1, 2.0 + ci.m0, load, o0, o1);
-        p_new[s.flat] = a0;
-        p_new[(size_t)Vtot + s.flat] = a1;
-        t[s.flat] = o0;
-        t[(size_t)Vtot + s.flat] = o1;
-        v[0] = norm2(o0) + norm2(o1);
-    }
-    double tot[1];
-    if (chain_reduce<1>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) {
-        st[w.chain].pAp = tot[0];
-        st[w.chain].alpha = S.rho / tot[0];
-    }
-}
-
-// x += alpha p; r -= alpha D^dagger t; ||r||^2 -> rho, beta, convergence.
-__global__ void k_cg_step2_64(Geo g, Reduce red, const double2 *__restrict__ U,
-                              double2 *__restrict__ x, double2 *__restrict__ r,
-                              const double2 *__restrict__ p, const double2 *__restrict__ t,
-                              CGState *st) {
-    SITE_PROLOGUE
-    const CGState S = st[w.chain];
-    if (S.converged) return;
-    const double alpha = S.alpha;
-    double v[1] = {0.0};
-    if (valid) {
-        const Site s = decode_site(ci, local);
-        const Nbr nb = neighbours(ci, s);
-        auto load = [&](int f, double2 &b0, double2 &b1) { b0 = t[f]; b1 = t[(size_t)Vtot + f]; };
-        double2 a0, a1;
-        dslash_site<double, true>(nb, s.flat, Vtot, U, t[s.flat], t[(size_t)Vtot + s.flat],
-                                  2.0 + ci.m0, load, a0, a1);
-        const double2 Ap[2] = {a0, a1};
-        for (int sp = 0; sp < 2; ++sp) {
-            const size_t f = (size_t)sp * Vtot + s.flat;
-            const double2 pp = p[f];
-            double2 xx = x[f], rr = r[f];
-            xx.x += alpha * pp.x; xx.y += alpha * pp.y;
-            rr.x -= alpha * Ap[sp].x; rr.y -= alpha * Ap[sp].y;
-            x[f] = xx;
-            r[f] = rr;
-            v[0] += norm2(rr);
-        }
-    }
-    double tot[1];
-    if (chain_reduce<1>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) {
-        CGState &T = st[w.chain];
-        T.iters = S.iters + 1;
-        T.rho_prev = S.rho;
-        T.rho = tot[0];
-        if (tot[0] <= S.target) T.converged = 1;
-        else T.beta = tot[0] / S.rho;
-    }
-}
-
-void launch_cg_init64(const Geo &g, const Reduce &red, const double2 *phi, double2 *x, double2 *r,
-                      CGState *st, double tol, double delta, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init64, dim3(g.nblocks), dim3(g.block), 0, s, g, red, phi, x, r, st,
-                       tol, delta);
-}
-
-void launch_cg_step64(const Geo &g, const Reduce &red, const double2 *U, double2 *x, double2 *r,
-                      const double2 *p_old, double2 *p_new, double2 *t, CGState *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_step1_64, dim3(g.nblocks), dim3(g.block), 0, s, g, red, U, r, p_old,
-                       p_new, t, st);
-    hipLaunchKernelGGL(k_cg_step2_64, dim3(g.nblocks), dim3(g.block), 0, s, g, red, U, x, r, p_new,
-                       t, st);
-}
-
-// ================================================================ CG, mixed precision
-// FP32 iterations; when the FP32 residual has dropped by delta since the last FP64
-// recomputation (or reached the target), the next iteration slot recomputes
+// ================================================================ CG on D^dagger D
+// FP64 solver: slots are plain CG iterations.  Mixed solver: slots are FP32 CG
+// iterations, except that whenever the FP32 residual has dropped by delta since the last
+// FP64 recomputation (or reached the target) the next slot recomputes
 // r = phi - D^dagger D (x64 + x32) in FP64, folds x32 into x64 and restarts the FP32
-// residual from it (reliable update).  Convergence is only declared on that FP64 residual.
-__global__ void k_cg_init_mixed(Geo g, Reduce red, MixedFields m, CGState *st, double tol,
-                                double delta) {
-    SITE_PROLOGUE
+// residual from it (reliable update); convergence is only declared on that FP64 residual.
+template <bool MIXED> struct Prec;
+template <> struct Prec<false> { using R = double; };
+template <> struct Prec<true> { using R = float; };
+
+template <bool MIXED>
+__global__ void k_cg_init(Geo g, CGFields f, double delta2) {
     double v[1] = {0.0};
-    if (valid) {
-        const int f = ci.off + local;
-        for (int sp = 0; sp < 2; ++sp) {
-            const size_t k = (size_t)sp * Vtot + f;
-            const double2 a = m.phi[k];
-            m.x64[k] = make_double2(0.0, 0.0);
-            m.x32[k] = make_float2(0.f, 0.f);
-            m.r32[k] = make_float2((float)a.x, (float)a.y);
-            v[0] += norm2(a);
+    SITES_BEGIN
+    const int fl = ci.off + local;
+    for (int sp = 0; sp < 2; ++sp) {
+        const size_t k = (size_t)sp * Vtot + fl;
+        const double2 a = f.phi[k];
+        f.x64[k] = make_double2(0.0, 0.0);
+        if (MIXED) {
+            f.x32[k] = make_float2(0.f, 0.f);
+            f.r32[k] = make_float2((float)a.x, (float)a.y);
+        } else {
+            f.r64[k] = a;
         }
+        v[0] += norm2(a);
     }
-    double tot[1];
-    if (chain_reduce<1>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) {
-        CGState &S = st[w.chain];
-        S.phi2 = tot[0];
-        S.rho = tot[0];
-        S.rho_prev = tot[0];
-        S.rmax2 = tot[0];
-        S.target = tol * tol * tot[0];
-        S.delta2 = delta * delta;
-        S.alpha = 0.0;
-        S.beta = 0.0;
-        S.pAp = 0.0;
-        S.iters = 0;
-        S.update = 0;
-        S.n_updates = 0;
-        S.converged = (tot[0] <= S.target) ? 1 : 0;
+    SITES_END
+    write_partials<1>(v, f.p2, g.nlog, w.logical);
+    if (w.logical == ci.block0 && threadIdx.x == 0) {
+        CGState S = {};
+        S.mode = kModeInit;
+        S.delta2 = delta2;
+        f.st[(size_t)g.nchains + w.chain] = S;  // parity 1: the state "before" slot 0
     }
 }
 
-__global__ void k_cg_step1_mixed(Geo g, Reduce red, const double2 *__restrict__ U64,
-                                 const float2 *__restrict__ U32, MixedFields m,
-                                 const float2 *__restrict__ p_old, float2 *__restrict__ p_new,
-                                 CGState *st) {
-    SITE_PROLOGUE
-    const CGState S = st[w.chain];
-    if (S.converged) return;
-    if (S.update) {
+template <bool MIXED>
+__global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void *p_old_v,
+                           void *p_new_v, int decide_only) {
+    using R = typename Prec<MIXED>::R;
+    using C = cplx_t<R>;
+    const BlockWork w = g.work[blockIdx.x];
+    const ChainInfo ci = g.chains[w.chain];
+    const int Vtot = g.Vtot;
+    const bool leader = w.logical == ci.block0 && threadIdx.x == 0;
+    CGState *out = f.st + (size_t)(slot & 1) * g.nchains + w.chain;
+    const CGState P = f.st[(size_t)((slot + 1) & 1) * g.nchains + w.chain];
+    if (P.converged) {
+        if (leader) *out = P;
+        return;
+    }
+    const double rho = chain_total(f.p2, ci);
+    CGState S = P;
+    bool update = false, first = false;
+    if (P.mode == kModeInit) {
+        S.phi2 = rho; S.target = tol2 * rho; S.rmax2 = rho; S.rho = rho; S.rho_p = rho;
+        S.iters = 0; S.n_updates = 0; S.beta = 0.0;
+        S.converged = rho <= S.target ? 1 : 0;
+        first = true;
+    } else if (P.mode == kModeUpdate) {
+        S.n_updates = P.n_updates + 1;
+        S.rmax2 = rho;
+        S.converged = rho <= S.target ? 1 : 0;
+        S.beta = rho / P.rho_p;
+        S.rho = rho;
+    } else {
+        S.iters = P.iters + 1;
+        S.rho_p = P.rho;
+        S.rho = rho;
+        S.beta = rho / P.rho;
+        if (!MIXED) S.converged = rho <= S.target ? 1 : 0;
+        else update = rho <= S.target || rho <= S.delta2 * S.rmax2;
+    }
+    S.mode = update ? kModeUpdate : kModeNormal;
+    if (leader) *out = S;
+    if (S.converged || decide_only) return;
+    const C *__restrict__ p_old = (const C *)p_old_v;
+    C *__restrict__ p_new = (C *)p_new_v;
+    if (MIXED && update) {
         // FP64 residual recomputation, first half: t64 = D (x64 + x32); p carried over.
-        if (!valid) return;
+        SITES_LOOP
         const Site s = decode_site(ci, local);
         const Nbr nb = neighbours(ci, s);
-        auto load = [&](int f, double2 &b0, double2 &b1) {
-            const double2 y0 = m.x64[f], y1 = m.x64[(size_t)Vtot + f];
-            const float2 z0 = m.x32[f], z1 = m.x32[(size_t)Vtot + f];
+        auto load = [&](int fl, double2 &b0, double2 &b1) {
+            const double2 y0 = f.x64[fl], y1 = f.x64[(size_t)Vtot + fl];
+            const float2 z0 = f.x32[fl], z1 = f.x32[(size_t)Vtot + fl];
             b0 = make_double2(y0.x + (double)z0.x, y0.y + (double)z0.y);
             b1 = make_double2(y1.x + (double)z1.x, y1.y + (double)z1.y);
         };
         double2 a0, a1, o0, o1;
         load(s.flat, a0, a1);
-        dslash_site<double, false>(nb, s.flat, Vtot, U64, a0, a1, 2.0 + ci.m0, load, o0, o1);
-        m.t64[s.flat] = o0;
-        m.t64[(size_t)Vtot + s.flat] = o1;
-        if (S.iters > 0) {
-            p_new[s.flat] = p_old[s.flat];
-            p_new[(size_t)Vtot + s.flat] = p_old[(size_t)Vtot + s.flat];
-        }
+        dslash_site<double, false>(nb, s.flat, Vtot, f.U64, a0, a1, 2.0 + ci.m0, load, o0, o1);
+        f.t64[s.flat] = o0;
+        f.t64[(size_t)Vtot + s.flat] = o1;
+        p_new[s.flat] = p_old[s.flat];
+        p_new[(size_t)Vtot + s.flat] = p_old[(size_t)Vtot + s.flat];
+        SITES_END
         return;
     }
-    const bool first = S.iters == 0;
-    const float beta = (float)S.beta;
+    const C *__restrict__ r;
+    C *__restrict__ t;
+    const C *__restrict__ U;
+    if constexpr (MIXED) { r = f.r32; t = f.t32; U = f.U32; }
+    else { r = f.r64; t = f.t64; U = f.U64; }
+    const R beta = (R)S.beta;
     double v[1] = {0.0};
-    if (valid) {
-        const Site s = decode_site(ci, local);
-        const Nbr nb = neighbours(ci, s);
-        auto load = [&](int f, float2 &b0, float2 &b1) {
-            b0 = m.r32[f];
-            b1 = m.r32[(size_t)Vtot + f];
-            if (!first) {
-                const float2 q0 = p_old[f], q1 = p_old[(size_t)Vtot + f];
-                b0 = make_float2(b0.x + beta * q0.x, b0.y + beta * q0.y);
-                b1 = make_float2(b1.x + beta * q1.x, b1.y + beta * q1.y);
-            }
-        };
-        float2 a0, a1, o0, o1;
-        load(s.flat, a0, a1);
-        dslash_site<float, false>(nb, s.flat, Vtot, U32, a0, a1, 2.0f + (float)ci.m0, load, o0, o1);
-        p_new[s.flat] = a0;
-        p_new[(size_t)Vtot + s.flat] = a1;
-        m.t32[s.flat] = o0;
-        m.t32[(size_t)Vtot + s.flat] = o1;
-        v[0] = norm2(o0) + norm2(o1);
-    }
-    double tot[1];
-    if (chain_reduce<1>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) {
-        st[w.chain].pAp = tot[0];
-        st[w.chain].alpha = S.rho / tot[0];
-    }
+    SITES_LOOP
+    const Site s = decode_site(ci, local);
+    const Nbr nb = neighbours(ci, s);
+    auto load = [&](int fl, C &b0, C &b1) {
+        b0 = r[fl];
+        b1 = r[(size_t)Vtot + fl];
+        if (!first) {
+            const C q0 = p_old[fl], q1 = p_old[(size_t)Vtot + fl];
+            b0 = cmake<C>(b0.x + beta * q0.x, b0.y + beta * q0.y);
+            b1 = cmake<C>(b1.x + beta * q1.x, b1.y + beta * q1.y);
+        }
+    };
+    C a0, a1, o0, o1;
+    load(s.flat, a0, a1);
+    dslash_site<R, false>(nb, s.flat, Vtot, U, a0, a1, (R)(2.0 + ci.m0), load, o0, o1);
+    p_new[s.flat] = a0;
+    p_new[(size_t)Vtot + s.flat] = a1;
+    t[s.flat] = o0;
+    t[(size_t)Vtot + s.flat] = o1;
+    v[0] += norm2(o0) + norm2(o1);
+    SITES_END
+    write_partials<1>(v, f.p1, g.nlog, w.logical);
 }
 
-__global__ void k_cg_step2_mixed(Geo g, Reduce red, const double2 *__restrict__ U64,
-                                 const float2 *__restrict__ U32, MixedFields m,
-                                 const float2 *__restrict__ p, CGState *st) {
-    SITE_PROLOGUE
-    const CGState S = st[w.chain];
+template <bool MIXED>
+__global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
+    using R = typename Prec<MIXED>::R;
+    using C = cplx_t<R>;
+    const BlockWork w = g.work[blockIdx.x];
+    const ChainInfo ci = g.chains[w.chain];
+    const int Vtot = g.Vtot;
+    const CGState S = f.st[(size_t)(slot & 1) * g.nchains + w.chain];
     if (S.converged) return;
     double v[1] = {0.0};
-    double tot[1];
-    if (S.update) {
+    if (MIXED && S.mode == kModeUpdate) {
         // second half: r64 = phi - D^dagger t64; x64 += x32; x32 = 0; r32 = r64.
-        if (valid) {
-            const Site s = decode_site(ci, local);
-            const Nbr nb = neighbours(ci, s);
-            auto load = [&](int f, double2 &b0, double2 &b1) {
-                b0 = m.t64[f];
-                b1 = m.t64[(size_t)Vtot + f];
-            };
-            double2 a0, a1;
-            dslash_site<double, true>(nb, s.flat, Vtot, U64, m.t64[s.flat],
-                                      m.t64[(size_t)Vtot + s.flat], 2.0 + ci.m0, load, a0, a1);
-            const double2 Ay[2] = {a0, a1};
-            for (int sp = 0; sp < 2; ++sp) {
-                const size_t f = (size_t)sp * Vtot + s.flat;
-                const double2 ph = m.phi[f];
-                const double2 rr = make_double2(ph.x - Ay[sp].x, ph.y - Ay[sp].y);
-                const double2 xx = m.x64[f];
-                const float2 zz = m.x32[f];
-                m.x64[f] = make_double2(xx.x + (double)zz.x, xx.y + (double)zz.y);
-                m.x32[f] = make_float2(0.f, 0.f);
-                m.r32[f] = make_float2((float)rr.x, (float)rr.y);
-                v[0] += norm2(rr);
-            }
-        }
-        if (chain_reduce<1>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) {
-            CGState &T = st[w.chain];
-            T.update = 0;
-            T.n_updates = S.n_updates + 1;
-            T.rmax2 = tot[0];
-            T.rho = tot[0];
-            if (tot[0] <= S.target) T.converged = 1;
-            else T.beta = tot[0] / S.rho_prev;
-        }
-        return;
-    }
-    const float alpha = (float)S.alpha;
-    if (valid) {
+        SITES_LOOP
         const Site s = decode_site(ci, local);
         const Nbr nb = neighbours(ci, s);
-        auto load = [&](int f, float2 &b0, float2 &b1) {
-            b0 = m.t32[f];
-            b1 = m.t32[(size_t)Vtot + f];
+        auto load = [&](int fl, double2 &b0, double2 &b1) {
+            b0 = f.t64[fl];
+            b1 = f.t64[(size_t)Vtot + fl];
         };
-        float2 a0, a1;
-        dslash_site<float, true>(nb, s.flat, Vtot, U32, m.t32[s.flat], m.t32[(size_t)Vtot + s.flat],
-                                 2.0f + (float)ci.m0, load, a0, a1);
-        const float2 Ap[2] = {a0, a1};
+        double2 a0, a1;
+        dslash_site<double, true>(nb, s.flat, Vtot, f.U64, f.t64[s.flat],
+                                  f.t64[(size_t)Vtot + s.flat], 2.0 + ci.m0, load, a0, a1);
+        const double2 Ay[2] = {a0, a1};
         for (int sp = 0; sp < 2; ++sp) {
-            const size_t f = (size_t)sp * Vtot + s.flat;
-            const float2 pp = p[f];
-            float2 xx = m.x32[f], rr = m.r32[f];
-            xx.x += alpha * pp.x; xx.y += alpha * pp.y;
-            rr.x -= alpha * Ap[sp].x; rr.y -= alpha * Ap[sp].y;
-            m.x32[f] = xx;
-            m.r32[f] = rr;
+            const size_t k = (size_t)sp * Vtot + s.flat;
+            const double2 ph = f.phi[k];
+            const double2 rr = make_double2(ph.x - Ay[sp].x, ph.y - Ay[sp].y);
+            const double2 xx = f.x64[k];
+            const float2 zz = f.x32[k];
+            f.x64[k] = make_double2(xx.x + (double)zz.x, xx.y + (double)zz.y);
+            f.x32[k] = make_float2(0.f, 0.f);
+            f.r32[k] = make_float2((float)rr.x, (float)rr.y);
             v[0] += norm2(rr);
         }
+        SITES_END
+        write_partials<1>(v, f.p2, g.nlog, w.logical);
+        return;
     }
-    if (chain_reduce<1>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) {
-        CGState &T = st[w.chain];
-        T.iters = S.iters + 1;
-        T.rho_prev = S.rho;
-        T.rho = tot[0];
-        T.beta = tot[0] / S.rho;
-        if (tot[0] <= S.target || tot[0] <= S.delta2 * S.rmax2) T.update = 1;
-    }
-}
-
-__global__ void k_cg_finish_mixed(Geo g, MixedFields m, const CGState *st) {
-    SITE_PROLOGUE
-    if (!valid) return;
-    const int f = ci.off + local;
+    const double pAp = chain_total(f.p1, ci);
+    const R alpha = (R)(S.rho / pAp);
+    const C *__restrict__ p = (const C *)p_new_v;
+    const C *__restrict__ t;
+    C *__restrict__ r;
+    C *__restrict__ x;
+    const C *__restrict__ U;
+    if constexpr (MIXED) { t = f.t32; r = f.r32; x = f.x32; U = f.U32; }
+    else { t = f.t64; r = f.r64; x = f.x64; U = f.U64; }
+    SITES_LOOP
+    const Site s = decode_site(ci, local);
+    const Nbr nb = neighbours(ci, s);
+    auto load = [&](int fl, C &b0, C &b1) { b0 = t[fl]; b1 = t[(size_t)Vtot + fl]; };
+    C a0, a1;
+    dslash_site<R, true>(nb, s.flat, Vtot, U, t[s.flat], t[(size_t)Vtot + s.flat],
+                         (R)(2.0 + ci.m0), load, a0, a1);
+    const C Ap[2] = {a0, a1};
     for (int sp = 0; sp < 2; ++sp) {
-        const size_t k = (size_t)sp * Vtot + f;
-        const double2 xx = m.x64[k];
-        const float2 zz = m.x32[k];
-        m.x64[k] = make_double2(xx.x + (double)zz.x, xx.y + (double)zz.y);
-        m.x32[k] = make_float2(0.f, 0.f);
+        const size_t k = (size_t)sp * Vtot + s.flat;
+        const C pp = p[k];
+        C xx = x[k], rr = r[k];
+        xx.x += alpha * pp.x; xx.y += alpha * pp.y;
+        rr.x -= alpha * Ap[sp].x; rr.y -= alpha * Ap[sp].y;
+        x[k] = xx;
+        r[k] = rr;
+        v[0] += norm2(rr);
     }
+    SITES_END
+    write_partials<1>(v, f.p2, g.nlog, w.logical);
 }
 
-void launch_cg_init_mixed(const Geo &g, const Reduce &red, const MixedFields &m, CGState *st,
-                          double tol, double delta, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_init_mixed, dim3(g.nblocks), dim3(g.block), 0, s, g, red, m, st, tol,
-                       delta);
+__global__ void k_cg_finish_mixed(Geo g, CGFields f) {
+    SITES_BEGIN
+    const int fl = ci.off + local;
+    for (int sp = 0; sp < 2; ++sp) {
+        const size_t k = (size_t)sp * Vtot + fl;
+        const double2 xx = f.x64[k];
+        const float2 zz = f.x32[k];
+        f.x64[k] = make_double2(xx.x + (double)zz.x, xx.y + (double)zz.y);
+        f.x32[k] = make_float2(0.f, 0.f);
+    }
+    SITES_END
 }
 
-void launch_cg_step_mixed(const Geo &g, const Reduce &red, const double2 *U64, const float2 *U32,
-                          const MixedFields &m, const float2 *p_old, float2 *p_new, CGState *st,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_step1_mixed, dim3(g.nblocks), dim3(g.block), 0, s, g, red, U64, U32, m,
-                       p_old, p_new, st);
-    hipLaunchKernelGGL(k_cg_step2_mixed, dim3(g.nblocks), dim3(g.block), 0, s, g, red, U64, U32, m,
-                       p_new, st);
+void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, hipStream_t s) {
+    if (mixed) hipLaunchKernelGGL(k_cg_init<true>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, delta * delta);
+    else hipLaunchKernelGGL(k_cg_init<false>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, delta * delta);
 }
 
-void launch_cg_finish_mixed(const Geo &g, const MixedFields &m, const CGState *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_finish_mixed, dim3(g.nblocks), dim3(g.block), 0, s, g, m, st);
+void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
+                     const void *p_old, void *p_new, bool decide_only, hipStream_t s) {
+    if (mixed)
+        hipLaunchKernelGGL(k_cg_step1<true>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, slot,
+                           tol * tol, p_old, p_new, decide_only ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_cg_step1<false>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, slot,
+                           tol * tol, p_old, p_new, decide_only ? 1 : 0);
+}
+
+void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
+                     hipStream_t s) {
+    if (mixed)
+        hipLaunchKernelGGL(k_cg_step2<true>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, slot, p_new);
+    else
+        hipLaunchKernelGGL(k_cg_step2<false>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, slot, p_new);
+}
+
+void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_finish_mixed, dim3(g.nblocks), dim3(g.block), 0, s, g, f);
+}
+
+// Order-preserving compaction of the workgroups of unconverged chains (one workgroup).
+// A chain is dropped once either state parity says converged (a chain leaves the grid
+// right after convergence, so its other parity may still hold the state before it).
+__global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGState *__restrict__ st,
+                          int nchains, BlockWork *__restrict__ out, int *count) {
+    __shared__ int wave_cnt[kMaxWaves];
+    __shared__ int base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    for (int chunk = 0; chunk < n; chunk += blockDim.x) {
+        const int i = chunk + threadIdx.x;
+        BlockWork wk = {};
+        bool keep = false;
+        if (i < n) {
+            wk = work[i];
+            keep = st[wk.chain].converged == 0 && st[nchains + wk.chain].converged == 0;
+        }
+        const unsigned long long m = __ballot(keep);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_cnt[wave] = __popcll(m);
+        __syncthreads();
+        int off = base;
+        for (int v = 0; v < wave; ++v) off += wave_cnt[v];
+        if (keep) out[off + before] = wk;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int v = 0; v < nw; ++v) tot += wave_cnt[v];
+            base += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base;
+}
+
+void launch_compact(const Geo &full, const CGState *st, BlockWork *out, int *count, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, full.work, full.nblocks, st,
+                       full.nchains, out, count);
+}
+
+__global__ void k_count_converged(const CGState *__restrict__ st, int n, int *out) {
+    double v[1] = {0.0};
+    for (int c = threadIdx.x; c < n; c += blockDim.x) v[0] += st[c].converged;
+    block_sum_all<1>(v);
+    if (threadIdx.x == 0) out[0] = (int)v[0];
+}
+
+void launch_count_converged(const CGState *st_par, int n, int *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_converged, dim3(1), dim3(256), 0, s, st_par, n, out);
 }
 
 // ||phi - D^dagger t||^2 per chain, t = D x computed before.
-__global__ void k_residual64(Geo g, Reduce red, const double2 *__restrict__ U,
-                             const double2 *__restrict__ phi, const double2 *__restrict__ t,
-                             double *out) {
-    SITE_PROLOGUE
+__global__ void k_residual64(Geo g, const double2 *__restrict__ U, const double2 *__restrict__ phi,
+                             const double2 *__restrict__ t, double *partials) {
     double v[1] = {0.0};
-    if (valid) {
-        const Site s = decode_site(ci, local);
-        const Nbr nb = neighbours(ci, s);
-        auto load = [&](int f, double2 &b0, double2 &b1) { b0 = t[f]; b1 = t[(size_t)Vtot + f]; };
-        double2 a0, a1;
-        dslash_site<double, true>(nb, s.flat, Vtot, U, t[s.flat], t[(size_t)Vtot + s.flat],
-                                  2.0 + ci.m0, load, a0, a1);
-        const double2 ph0 = phi[s.flat], ph1 = phi[(size_t)Vtot + s.flat];
-        v[0] = norm2(make_double2(ph0.x - a0.x, ph0.y - a0.y)) +
-               norm2(make_double2(ph1.x - a1.x, ph1.y - a1.y));
-    }
-    double tot[1];
-    if (chain_reduce<1>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) out[w.chain] = tot[0];
+    SITES_BEGIN
+    const Site s = decode_site(ci, local);
+    const Nbr nb = neighbours(ci, s);
+    auto load = [&](int fl, double2 &b0, double2 &b1) { b0 = t[fl]; b1 = t[(size_t)Vtot + fl]; };
+    double2 a0, a1;
+    dslash_site<double, true>(nb, s.flat, Vtot, U, t[s.flat], t[(size_t)Vtot + s.flat],
+                              2.0 + ci.m0, load, a0, a1);
+    const double2 ph0 = phi[s.flat], ph1 = phi[(size_t)Vtot + s.flat];
+    v[0] += norm2(make_double2(ph0.x - a0.x, ph0.y - a0.y)) +
+            norm2(make_double2(ph1.x - a1.x, ph1.y - a1.y));
+    SITES_END
+    write_partials<1>(v, partials, g.nlog, w.logical);
 }
 
-void launch_true_residual64(const Geo &g, const Reduce &red, const double2 *U, const double2 *phi,
-                            const double2 *x, double2 *t, double *out, hipStream_t s) {
+void launch_true_residual64(const Geo &g, const double2 *U, const double2 *phi, const double2 *x,
+                            double2 *t, double *partials, double *out, hipStream_t s) {
     launch_dslash64(g, U, x, t, false, s);
-    hipLaunchKernelGGL(k_residual64, dim3(g.nblocks), dim3(g.block), 0, s, g, red, U, phi, t, out);
+    hipLaunchKernelGGL(k_residual64, dim3(g.nblocks), dim3(g.block), 0, s, g, U, phi, t, partials);
+    launch_finalize<1>(g, partials, out, s);
 }
 
 // ================================================================ forces
@@ -586,8 +548,7 @@ void launch_true_residual64(const Geo &g, const Reduce &red, const double2 *U, c
 __global__ void k_fermion_force(Geo g, const double2 *__restrict__ U,
                                 const double2 *__restrict__ chi, const double2 *__restrict__ xi,
                                 double *__restrict__ f) {
-    SITE_PROLOGUE
-    if (!valid) return;
+    SITES_BEGIN
     const Site s = decode_site(ci, local);
     const int nxp = flat_of(ci, wrap_inc(s.x, ci.Lx), s.t);
     const int ntp = flat_of(ci, s.x, wrap_inc(s.t, ci.Lt));
@@ -609,6 +570,7 @@ __global__ void k_fermion_force(Geo g, const double2 *__restrict__ U,
         const double2 term2 = cmulc(csub(cn0, cmuli(cn1)), cmulc(u, csub(x0, cmuli(x1))));
         f[(size_t)Vtot + s.flat] = term2.y - term1.y;
     }
+    SITES_END
 }
 
 void launch_fermion_force(const Geo &g, const double2 *U, const double2 *chi, const double2 *xi,
@@ -627,10 +589,9 @@ __device__ __forceinline__ double plaq_angle(const ChainInfo &ci, const double *
 
 // dS_G/dq: F_x(n) = beta [sin theta(n) - sin theta(n - t)], F_t(n) = beta [sin theta(n - x)
 // - sin theta(n)] -- Eq. (16) with P read as P_{mu nu}(n), whose angle is -theta for mu = t.
-__global__ void k_gauge_force(Geo g, const double *__restrict__ q, const double *__restrict__ add,
-                              double *__restrict__ F) {
-    SITE_PROLOGUE
-    if (!valid) return;
+__global__ void k_gauge_force(Geo g, const double *__restrict__ q, const double *add,
+                              double *F) {
+    SITES_BEGIN
     const Site s = decode_site(ci, local);
     const double th = plaq_angle(ci, q, Vtot, s.x, s.t);
     const double th_mt = plaq_angle(ci, q, Vtot, s.x, wrap_dec(s.t, ci.Lt));
@@ -644,6 +605,7 @@ __global__ void k_gauge_force(Geo g, const double *__restrict__ q, const double 
     }
     F[s.flat] = fx;
     F[(size_t)Vtot + s.flat] = ft;
+    SITES_END
 }
 
 void launch_gauge_force(const Geo &g, const double *q, const double *add, double *F, hipStream_t s) {
@@ -684,8 +646,7 @@ __device__ __forceinline__ void gaussian_pair(const U32x4 &w, double &g0, double
 
 __global__ void k_rng_links(Geo g, uint32_t k0, uint32_t k1, double *__restrict__ q) {
 #pragma clang fp contract(off)
-    SITE_PROLOGUE
-    if (!valid) return;
+    SITES_BEGIN
     const Site s = decode_site(ci, local);
     const uint32_t n = (uint32_t)(s.x + ci.Lx * s.t);
     for (int mu = 0; mu < 2; ++mu) {
@@ -693,6 +654,7 @@ __global__ void k_rng_links(Geo g, uint32_t k0, uint32_t k1, double *__restrict_
         const double u = u01_from(r.v[0], r.v[1]);
         q[(size_t)mu * Vtot + s.flat] = 3.141592653589793 * (2.0 * u - 1.0);
     }
+    SITES_END
 }
 
 void launch_rng_links(const Geo &g, uint64_t seed, double *q, hipStream_t s) {
@@ -700,112 +662,99 @@ void launch_rng_links(const Geo &g, uint64_t seed, double *q, hipStream_t s) {
                        (uint32_t)(seed >> 32), q);
 }
 
-__global__ void k_refresh(Geo g, Reduce red, uint32_t k0, uint32_t k1, uint32_t traj,
-                          double *__restrict__ p, double2 *__restrict__ zeta, int fermions,
-                          double *sums) {
+__global__ void k_refresh(Geo g, uint32_t k0, uint32_t k1, uint32_t traj, double *__restrict__ p,
+                          double2 *__restrict__ zeta, int fermions, double *partials) {
 #pragma clang fp contract(off)
-    SITE_PROLOGUE
     double v[2] = {0.0, 0.0};
-    if (valid) {
-        const Site s = decode_site(ci, local);
-        const uint32_t n = (uint32_t)(s.x + ci.Lx * s.t);
-        for (int mu = 0; mu < 2; ++mu) {
+    SITES_BEGIN
+    const Site s = decode_site(ci, local);
+    const uint32_t n = (uint32_t)(s.x + ci.Lx * s.t);
+    for (int mu = 0; mu < 2; ++mu) {
+        double g0, g1;
+        gaussian_pair(philox4x32_10(2 * n + mu, kStreamMomenta, traj, ci.chain_id, k0, k1), g0, g1);
+        p[(size_t)mu * Vtot + s.flat] = g0;
+        v[0] += 0.5 * g0 * g0;
+    }
+    if (fermions) {
+        for (int sp = 0; sp < 2; ++sp) {
             double g0, g1;
-            gaussian_pair(philox4x32_10(2 * n + mu, kStreamMomenta, traj, ci.chain_id, k0, k1), g0, g1);
-            p[(size_t)mu * Vtot + s.flat] = g0;
-            v[0] += 0.5 * g0 * g0;
-        }
-        if (fermions) {
-            for (int sp = 0; sp < 2; ++sp) {
-                double g0, g1;
-                gaussian_pair(philox4x32_10(2 * n + sp, kStreamPseudofermion, traj, ci.chain_id, k0, k1),
-                              g0, g1);
-                const double2 z = make_double2(g0 * 0.70710678118654752440, g1 * 0.70710678118654752440);
-                zeta[(size_t)sp * Vtot + s.flat] = z;
-                v[1] += z.x * z.x + z.y * z.y;
-            }
+            gaussian_pair(philox4x32_10(2 * n + sp, kStreamPseudofermion, traj, ci.chain_id, k0, k1),
+                          g0, g1);
+            const double2 z = make_double2(g0 * 0.70710678118654752440, g1 * 0.70710678118654752440);
+            zeta[(size_t)sp * Vtot + s.flat] = z;
+            v[1] += z.x * z.x + z.y * z.y;
         }
     }
-    double tot[2];
-    if (chain_reduce<2>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) {
-        sums[w.chain] = tot[0];
-        sums[g.nchains + w.chain] = tot[1];
-    }
+    SITES_END
+    write_partials<2>(v, partials, g.nlog, w.logical);
 }
 
-void launch_refresh(const Geo &g, const Reduce &red, uint64_t seed, uint32_t traj, double *p,
-                    double2 *zeta, bool fermions, double *sums, hipStream_t s) {
-    hipLaunchKernelGGL(k_refresh, dim3(g.nblocks), dim3(g.block), 0, s, g, red, (uint32_t)seed,
-                       (uint32_t)(seed >> 32), traj, p, zeta, fermions ? 1 : 0, sums);
+void launch_refresh(const Geo &g, uint64_t seed, uint32_t traj, double *p, double2 *zeta,
+                    bool fermions, double *partials, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_refresh, dim3(g.nblocks), dim3(g.block), 0, s, g, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), traj, p, zeta, fermions ? 1 : 0, partials);
+    launch_finalize<2>(g, partials, out, s);
 }
 
 // ================================================================ energies
-__global__ void k_energy(Geo g, Reduce red, const double *__restrict__ q,
-                         const double *__restrict__ q0, const double *__restrict__ p,
-                         const double *__restrict__ p0, const double2 *__restrict__ phi,
-                         const double2 *__restrict__ xi, double *sums) {
-    SITE_PROLOGUE
+__global__ void k_energy(Geo g, const double *__restrict__ q, const double *__restrict__ q0,
+                         const double *__restrict__ p, const double *__restrict__ p0,
+                         const double2 *__restrict__ phi, const double2 *__restrict__ xi,
+                         double *partials) {
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (valid) {
-        const Site s = decode_site(ci, local);
-        for (int mu = 0; mu < 2; ++mu) {
-            const double a = p[(size_t)mu * Vtot + s.flat], b = p0[(size_t)mu * Vtot + s.flat];
-            v[0] += 0.5 * (a - b) * (a + b);
-            v[2] += 0.5 * a * a;
-        }
-        const double c1 = cos(plaq_angle(ci, q, Vtot, s.x, s.t));
-        const double c0 = cos(plaq_angle(ci, q0, Vtot, s.x, s.t));
-        v[1] = c0 - c1;
-        v[3] = 1.0 - c1;
-        v[4] = 1.0 - c0;
-        v[6] = c1;
-        if (phi) {
-            for (int sp = 0; sp < 2; ++sp) {
-                const double2 a = phi[(size_t)sp * Vtot + s.flat], b = xi[(size_t)sp * Vtot + s.flat];
-                v[5] += a.x * b.x + a.y * b.y;
-            }
+    SITES_BEGIN
+    const Site s = decode_site(ci, local);
+    for (int mu = 0; mu < 2; ++mu) {
+        const double a = p[(size_t)mu * Vtot + s.flat], b = p0[(size_t)mu * Vtot + s.flat];
+        v[0] += 0.5 * (a - b) * (a + b);
+        v[2] += 0.5 * a * a;
+    }
+    const double c1 = cos(plaq_angle(ci, q, Vtot, s.x, s.t));
+    const double c0 = cos(plaq_angle(ci, q0, Vtot, s.x, s.t));
+    v[1] += c0 - c1;
+    v[3] += 1.0 - c1;
+    v[4] += 1.0 - c0;
+    v[6] += c1;
+    if (phi) {
+        for (int sp = 0; sp < 2; ++sp) {
+            const double2 a = phi[(size_t)sp * Vtot + s.flat], b = xi[(size_t)sp * Vtot + s.flat];
+            v[5] += a.x * b.x + a.y * b.y;
         }
     }
-    double tot[7];
-    if (chain_reduce<7>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) {
-        for (int k = 0; k < 7; ++k) sums[k * g.nchains + w.chain] = tot[k];
-    }
+    SITES_END
+    write_partials<7>(v, partials, g.nlog, w.logical);
 }
 
-void launch_energy(const Geo &g, const Reduce &red, const double *q, const double *q0,
-                   const double *p, const double *p0, const double2 *phi, const double2 *xi,
-                   double *sums, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy, dim3(g.nblocks), dim3(g.block), 0, s, g, red, q, q0, p, p0, phi,
-                       xi, sums);
+void launch_energy(const Geo &g, const double *q, const double *q0, const double *p,
+                   const double *p0, const double2 *phi, const double2 *xi, double *partials,
+                   double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy, dim3(g.nblocks), dim3(g.block), 0, s, g, q, q0, p, p0, phi, xi,
+                       partials);
+    launch_finalize<7>(g, partials, out, s);
 }
 
-__global__ void k_gauge_energy(Geo g, Reduce red, const double *__restrict__ q,
-                               const double2 *__restrict__ phi, const double2 *__restrict__ xi,
-                               double *sums) {
-    SITE_PROLOGUE
+__global__ void k_gauge_energy(Geo g, const double *__restrict__ q, const double2 *__restrict__ phi,
+                               const double2 *__restrict__ xi, double *partials) {
     double v[3] = {0, 0, 0};
-    if (valid) {
-        const Site s = decode_site(ci, local);
-        const double c1 = cos(plaq_angle(ci, q, Vtot, s.x, s.t));
-        v[0] = 1.0 - c1;
-        v[1] = c1;
-        if (phi) {
-            for (int sp = 0; sp < 2; ++sp) {
-                const double2 a = phi[(size_t)sp * Vtot + s.flat], b = xi[(size_t)sp * Vtot + s.flat];
-                v[2] += a.x * b.x + a.y * b.y;
-            }
+    SITES_BEGIN
+    const Site s = decode_site(ci, local);
+    const double c1 = cos(plaq_angle(ci, q, Vtot, s.x, s.t));
+    v[0] += 1.0 - c1;
+    v[1] += c1;
+    if (phi) {
+        for (int sp = 0; sp < 2; ++sp) {
+            const double2 a = phi[(size_t)sp * Vtot + s.flat], b = xi[(size_t)sp * Vtot + s.flat];
+            v[2] += a.x * b.x + a.y * b.y;
         }
     }
-    double tot[3];
-    if (chain_reduce<3>(v, ci, w, red, g.nblocks, tot) && threadIdx.x == 0) {
-        for (int k = 0; k < 3; ++k) sums[k * g.nchains + w.chain] = tot[k];
-    }
+    SITES_END
+    write_partials<3>(v, partials, g.nlog, w.logical);
 }
 
-void launch_gauge_energy(const Geo &g, const Reduce &red, const double *q, const double2 *phi,
-                         const double2 *xi, double *sums, hipStream_t s) {
-    hipLaunchKernelGGL(k_gauge_energy, dim3(g.nblocks), dim3(g.block), 0, s, g, red, q, phi, xi,
-                       sums);
+void launch_gauge_energy(const Geo &g, const double *q, const double2 *phi, const double2 *xi,
+                         double *partials, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_gauge_energy, dim3(g.nblocks), dim3(g.block), 0, s, g, q, phi, xi, partials);
+    launch_finalize<3>(g, partials, out, s);
 }
 
 // Delta H = sum 1/2 (p'^2 - p^2) + beta sum (cos theta - cos theta') + (S_F' - S_F), then
@@ -843,12 +792,12 @@ void launch_metropolis(const Geo &g, uint64_t seed, uint32_t traj, const double 
 
 __global__ void k_restore(Geo g, const MetroOut *__restrict__ m, const double *__restrict__ q0,
                           double *__restrict__ q) {
-    SITE_PROLOGUE
-    if (!valid) return;
-    if (m[w.chain].accepted) return;
-    const int f = ci.off + local;
-    q[f] = q0[f];
-    q[(size_t)Vtot + f] = q0[(size_t)Vtot + f];
+    SITES_BEGIN
+    if (m[w.chain].accepted) break;
+    const int fl = ci.off + local;
+    q[fl] = q0[fl];
+    q[(size_t)Vtot + fl] = q0[(size_t)Vtot + fl];
+    SITES_END
 }
 
 void launch_restore(const Geo &g, const MetroOut *m, const double *q0, double *q, hipStream_t s) {

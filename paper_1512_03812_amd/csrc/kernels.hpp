@@ -10,36 +10,35 @@ namespace shmc {
 // Geometry of a batch as the kernels see it.
 struct Geo {
     const ChainInfo *chains;  // device, n_chains entries
-    const BlockWork *work;    // device, nblocks entries (hardware order)
-    int nblocks;              // hardware workgroups of a site kernel
+    const BlockWork *work;    // device, nblocks entries (hardware order; may be a compacted list)
+    int nblocks;              // workgroups launched
+    int nlog;                 // logical workgroups of the whole batch (size of a partials row)
     int nchains;
     int Vtot;
     int block;                // threads per workgroup
 };
 
-// Per-chain state of a (possibly mixed-precision) CG solve, device resident.
+// Per-chain CG state.  Double-buffered by the parity of the iteration slot: the first
+// kernel of slot k reads state[(k+1)&1] and its chain-leading workgroup writes
+// state[k&1]; the second kernel of slot k reads state[k&1].
 struct CGState {
-    double rho;       // ||r||^2 of the current residual
-    double rho_prev;  // ||r||^2 one iteration earlier
-    double pAp;       // ||D p||^2 = <p, D^dagger D p>
-    double alpha, beta;
-    double target;    // tol^2 ||phi||^2
-    double phi2;      // ||phi||^2
-    double rmax2;     // mixed: ||r||^2 at the last FP64 residual recomputation
-    double delta2;    // mixed: reliable-update trigger factor squared
-    int iters;        // CG iterations done
-    int converged;    // 1 once the stopping test passed
-    int update;       // mixed: 1 if the next iteration slot is an FP64 residual recomputation
-    int n_updates;    // mixed: FP64 recomputations done
+    double rho;     // ||r||^2 of the residual entering this slot
+    double rho_p;   // ||r||^2 one CG iteration earlier (beta denominator after an update)
+    double target;  // tol^2 ||phi||^2
+    double phi2;    // ||phi||^2
+    double rmax2;   // mixed: ||r||^2 at the last FP64 residual recomputation
+    double beta;    // beta of this slot's direction update
+    double delta2;  // mixed: reliable-update trigger factor squared
+    int iters;      // CG iterations completed
+    int converged;  // 1 once the stopping test passed
+    int mode;       // kModeInit, kModeNormal or kModeUpdate (this slot)
+    int n_updates;  // mixed: FP64 residual recomputations completed
     int pad[6];
 };
 static_assert(sizeof(CGState) % 16 == 0, "CGState alignment");
+enum { kModeInit = 0, kModeNormal = 1, kModeUpdate = 2 };
 
-// Scratch for per-chain reductions.
-struct Reduce {
-    double *partials;   // [kMaxReduce][nblocks] logical-ordered block partials
-    unsigned *counters; // [nchains] arrival counters (self-resetting)
-};
+// Partial sums: row k of partials holds one double per logical workgroup.
 constexpr int kMaxReduce = 8;
 
 // ---------------------------------------------------------------- layout
@@ -57,37 +56,43 @@ void launch_dslash64(const Geo &g, const double2 *U, const double2 *in, double2 
                      hipStream_t s);
 
 // ---------------------------------------------------------------- CG on D^dagger D
-// x = 0, r = phi, ||phi||^2 -> state (rho, target = tol^2 ||phi||^2, converged if phi == 0).
-void launch_cg_init64(const Geo &g, const Reduce &red, const double2 *phi, double2 *x, double2 *r,
-                      CGState *st, double tol, double delta, hipStream_t s);
-// One FP64 iteration: (p_new = r + beta p_old; t = D p_new; ||t||^2 -> alpha) then
-// (x += alpha p_new; r -= alpha D^dagger t; ||r||^2 -> beta, convergence).
-void launch_cg_step64(const Geo &g, const Reduce &red, const double2 *U, double2 *x, double2 *r,
-                      const double2 *p_old, double2 *p_new, double2 *t, CGState *st, hipStream_t s);
-// Mixed precision: FP32 iteration with FP64 reliable updates folded into the same slots.
-struct MixedFields {
-    const double2 *phi;  // FP64 right-hand side
-    double2 *x64;        // FP64 accumulated solution
-    double2 *t64;        // FP64 scratch (D y in a residual recomputation)
-    float2 *x32, *r32, *t32;
+struct CGFields {
+    const double2 *phi;       // FP64 right-hand side
+    double2 *x64;             // FP64 solution (accumulated solution in mixed precision)
+    double2 *r64, *t64;       // FP64 residual and D p (FP64 solver); t64 is also the mixed scratch
+    float2 *x32, *r32, *t32;  // mixed: FP32 partial solution, residual, D p
+    const double2 *U64;
+    const float2 *U32;
+    double *p1, *p2;          // partial rows: ||D p||^2 (step 1) and ||r||^2 (step 2)
+    CGState *st;              // [2][nchains]
 };
-void launch_cg_init_mixed(const Geo &g, const Reduce &red, const MixedFields &m, CGState *st,
-                          double tol, double delta, hipStream_t s);
-void launch_cg_step_mixed(const Geo &g, const Reduce &red, const double2 *U64, const float2 *U32,
-                          const MixedFields &m, const float2 *p_old, float2 *p_new, CGState *st,
-                          hipStream_t s);
-// x64 += x32 for chains that stopped between recomputations (none in exact arithmetic);
-// also used at the end of a mixed solve.
-void launch_cg_finish_mixed(const Geo &g, const MixedFields &m, const CGState *st, hipStream_t s);
-// True residual ||phi - D^dagger D x||^2 per chain into out[c] (uses t as scratch).
-void launch_true_residual64(const Geo &g, const Reduce &red, const double2 *U, const double2 *phi,
-                            const double2 *x, double2 *t, double *out, hipStream_t s);
+// x = 0, r = phi, partial ||phi||^2 -> p2, state[1] = initial.
+void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, hipStream_t s);
+// Slot k, first kernel: decide (converged / beta / reliable update) from the partials of
+// the previous slot, then p_new = r + beta p_old and t = D p_new with partial ||t||^2
+// (or, in a reliable-update slot, t64 = D (x64 + x32)).  decide_only: state update only.
+void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
+                     const void *p_old, void *p_new, bool decide_only, hipStream_t s);
+// Slot k, second kernel: alpha from the partials of step 1, x += alpha p, r -= alpha
+// D^dagger t with partial ||r||^2 (or the FP64 residual recomputation).
+void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
+                     hipStream_t s);
+// x64 += x32 (end of a mixed solve).
+void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s);
+// Workgroups of chains not yet converged (st: both state parities) -> out[0..*count).
+void launch_compact(const Geo &full, const CGState *st, BlockWork *out, int *count, hipStream_t s);
+// Number of converged chains in one state parity -> *out.
+void launch_count_converged(const CGState *st_par, int n, int *out, hipStream_t s);
+
+// True residual ||phi - D^dagger D x||^2 per chain into out[c] (t: FP64 spinor scratch).
+void launch_true_residual64(const Geo &g, const double2 *U, const double2 *phi, const double2 *x,
+                            double2 *t, double *partials, double *out, hipStream_t s);
 
 // ---------------------------------------------------------------- forces
 // f = dS_F/dq from chi, xi (Eq. (17)).
 void launch_fermion_force(const Geo &g, const double2 *U, const double2 *chi, const double2 *xi,
                           double *f, hipStream_t s);
-// F = dS_G/dq (Eq. (16)), plus add[] if add != null.
+// F = dS_G/dq (Eq. (16)), plus add[] if add != null (add may alias F).
 void launch_gauge_force(const Geo &g, const double *q, const double *add, double *F, hipStream_t s);
 
 // ---------------------------------------------------------------- updates
@@ -97,22 +102,22 @@ void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- random numbers
 void launch_rng_links(const Geo &g, uint64_t seed, double *q, hipStream_t s);
-// momenta (stream 1) and zeta (stream 2) for trajectory traj; partial energies
-// 1/2 sum p^2 -> sums[0][c], zeta^dagger zeta -> sums[1][c].
-void launch_refresh(const Geo &g, const Reduce &red, uint64_t seed, uint32_t traj, double *p,
-                    double2 *zeta, bool fermions, double *sums, hipStream_t s);
+// momenta (stream 1) and zeta (stream 2) for trajectory traj; per chain
+// out[0][c] = 1/2 sum p^2, out[1][c] = zeta^dagger zeta.
+void launch_refresh(const Geo &g, uint64_t seed, uint32_t traj, double *p, double2 *zeta,
+                    bool fermions, double *partials, double *out, hipStream_t s);
 
 // ---------------------------------------------------------------- energies and Metropolis
-// Per chain: sums[0] = sum 1/2 (p - p0)(p + p0), sums[1] = sum (cos theta0 - cos theta),
-// sums[2] = 1/2 sum p^2, sums[3] = sum (1 - cos theta), sums[4] = sum (1 - cos theta0),
-// sums[5] = Re phi^dagger xi (if phi != null), sums[6] = sum cos theta.
-void launch_energy(const Geo &g, const Reduce &red, const double *q, const double *q0,
-                   const double *p, const double *p0, const double2 *phi, const double2 *xi,
-                   double *sums, hipStream_t s);
-// Per chain: S_G-type sums only: sums[0] = sum (1 - cos theta), sums[1] = sum cos theta,
-// sums[2] = Re phi^dagger xi (if phi != null).
-void launch_gauge_energy(const Geo &g, const Reduce &red, const double *q, const double2 *phi,
-                         const double2 *xi, double *sums, hipStream_t s);
+// Per chain: out[0] = sum 1/2 (p - p0)(p + p0), out[1] = sum (cos theta0 - cos theta),
+// out[2] = 1/2 sum p^2, out[3] = sum (1 - cos theta), out[4] = sum (1 - cos theta0),
+// out[5] = Re phi^dagger xi (if phi != null), out[6] = sum cos theta.
+void launch_energy(const Geo &g, const double *q, const double *q0, const double *p,
+                   const double *p0, const double2 *phi, const double2 *xi, double *partials,
+                   double *out, hipStream_t s);
+// Per chain: out[0] = sum (1 - cos theta), out[1] = sum cos theta,
+// out[2] = Re phi^dagger xi (if phi != null).
+void launch_gauge_energy(const Geo &g, const double *q, const double2 *phi, const double2 *xi,
+                         double *partials, double *out, hipStream_t s);
 // One thread per chain: Delta H, Metropolis decision with stream 3.
 struct MetroOut {
     double dH, H0, H1, u;
