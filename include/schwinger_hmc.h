@@ -246,15 +246,19 @@ int hmc_integrate(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inner
 
 /* ---------------------------------------------------------------- kernel timing */
 
-/* Event timing of the CG step kernels: while on, every CG iteration slot is bracketed by
- * HIP events on the bound stream (which = 0: step 1, t = D p; which = 1: step 2,
- * D^dagger t and the x, r updates).  hmc_set_timing resets the statistics. */
+/* Sampled event timing of the CG step kernels (which = 0: step 1, t = D p; which = 1:
+ * step 2, D^dagger t and the x, r updates).  While on, every 8th CG iteration slot is
+ * bracketed by HIP events on the bound stream and the per-chain CG state of that slot is
+ * copied to pinned host memory; the algorithmic bytes of the timed launches (the sites of
+ * the chains not yet converged times the bytes per site of the slot's mode) are summed
+ * beside their durations.  hmc_set_timing resets the statistics. */
 typedef struct {
-    long long launches;        /* timed launches of this kernel */
-    double total_ms;           /* summed event-measured duration */
-    long long site_iters_fp64; /* sum over solves and chains of V_c * FP64 iterations */
-    long long site_iters_fp32; /* same for FP32 iterations of the mixed solver */
-    long long site_updates;    /* same for FP64 residual recomputations of the mixed solver */
+    long long launches;       /* CG slots launched while timing was on */
+    long long timed_launches; /* launches of this kernel bracketed by events */
+    double timed_ms;          /* their summed event-measured duration */
+    double timed_bytes;       /* their summed algorithmic bytes */
+    int sample_every;         /* sampling period in slots */
+    int pad;
 } hmc_kernel_stat;
 
 int hmc_set_timing(hmc_ctx *ctx, int on);

@@ -33,9 +33,9 @@ class TrajInfo(ctypes.Structure):
 
 
 class KernelStat(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_longlong), ("total_ms", ctypes.c_double),
-                ("site_iters_fp64", ctypes.c_longlong), ("site_iters_fp32", ctypes.c_longlong),
-                ("site_updates", ctypes.c_longlong)]
+    _fields_ = [("launches", ctypes.c_longlong), ("timed_launches", ctypes.c_longlong),
+                ("timed_ms", ctypes.c_double), ("timed_bytes", ctypes.c_double),
+                ("sample_every", ctypes.c_int), ("pad", ctypes.c_int)]
 
 
 # name -> (restype, argtypes)

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -28,16 +29,31 @@ enum Spin32Buf { FX, FR, FT, FPA, FPB, kNumSpin32Bufs };
 
 }  // namespace
 
-// Event timing of the two CG step kernels (kernel index 0: step 1, 1: step 2).
+// Sampled event timing of the two CG step kernels (kernel index 0: step 1, 1: step 2).
+// Every sample_every-th iteration slot is bracketed by HIP events, and the per-chain CG
+// state of that slot is copied to pinned host memory, so that the algorithmic bytes of
+// exactly those launches (active chains x sites x bytes per site of the slot's mode) can
+// be attributed to the measured durations.
+struct TimedSlot {
+    hipEvent_t ev[3];
+    int mixed;
+    int snap;  // index of the state snapshot in the pinned ring
+};
+
 struct KernelTimer {
     bool on = false;
-    std::vector<hipEvent_t> ev;  // pool, three events per timed slot
-    size_t used = 0;
+    int sample_every = 8;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    std::vector<TimedSlot> pending;
+    void *ring = nullptr;  // pinned: kRingSlots snapshots of the CG state (one parity)
+    int ring_used = 0;
     double ms[2] = {0.0, 0.0};
-    long long launches[2] = {0, 0};
-    long long site_iters[2] = {0, 0};  // sum over solves of V_c * iterations (FP64, mixed FP32)
-    long long site_updates = 0;        // sum of V_c * FP64 residual recomputations (mixed)
+    double bytes[2] = {0.0, 0.0};
+    long long timed[2] = {0, 0};
+    long long launches = 0;  // all slots launched while timing was on
 };
+constexpr int kRingSlots = 32;
 
 struct hmc_ctx {
     // ------------------------------------------------------------ geometry (host)
@@ -252,64 +268,95 @@ void forget_all(hmc_ctx *c) {
     c->ff_version = c->xi_version = -1;
 }
 
-// Rebuilds the list of workgroups of the unconverged chains; returns its length in *active.
-int check_convergence(hmc_ctx *c, int *active) {
+// Rebuilds the list of workgroups of the unconverged chains; returns its length in *active
+// and the number of unconverged chains with iterations left in *live.
+int check_convergence(hmc_ctx *c, int max_iter, int *active, int *live) {
     int *dev = c->at<int>(c->off_count);
-    launch_compact(c->geo(), c->cg(), c->at<BlockWork>(c->off_active), dev, c->stream);
-    int n = 0;
-    int rc = to_host(c, &n, dev, sizeof(int));
+    launch_compact(c->geo(), c->cg(), max_iter, c->at<BlockWork>(c->off_active), dev, c->stream);
+    int n[2] = {0, 0};
+    int rc = to_host(c, n, dev, sizeof(n));
     if (rc) return rc;
-    *active = n;
+    *active = n[0];
+    *live = n[1];
     return HMC_OK;
 }
 
-// Timing of the CG step kernels with HIP events on the library's stream.
-void timer_flush(hmc_ctx *c) {
-    KernelTimer &T = c->timer;
-    // called only after the stream was synchronised, so every recorded event is complete
-    for (size_t k = 0; k + 3 <= T.used; k += 3) {
-        float a = 0.f, b = 0.f;
-        if (hipEventElapsedTime(&a, T.ev[k], T.ev[k + 1]) == hipSuccess) T.ms[0] += a;
-        if (hipEventElapsedTime(&b, T.ev[k + 1], T.ev[k + 2]) == hipSuccess) T.ms[1] += b;
-        T.launches[0]++;
-        T.launches[1]++;
-    }
-    T.used = 0;
-}
+// Algorithmic bytes per lattice site of the CG step kernels (each distinct input read once,
+// each output written once; stencil neighbours come from cache).
+//   FP64 solver   step 1: r 32 + p_old 32 + U 32 read, p 32 + t 32 written      = 160
+//                 step 2: t 32 + U 32 + x 32 + p 32 + r 32 read, x 32 + r 32    = 224
+//   mixed, FP32   step 1: r 16 + p_old 16 + U 16 read, p 16 + t 16 written      =  80
+//                 step 2: t 16 + U 16 + x 16 + p 16 + r 16 read, x 16 + r 16    = 112
+//   mixed, FP64 residual recomputation
+//                 step 1: x64 32 + x32 16 + U64 32 + p_old 16 read, t64 32 + p 16 = 144
+//                 step 2: t64 32 + U64 32 + phi 32 + x64 32 + x32 16 read,
+//                         x64 32 + x32 16 + r32 16 written                      = 208
+constexpr double kBytesFp64[2] = {160.0, 224.0};
+constexpr double kBytesFp32[2] = {80.0, 112.0};
+constexpr double kBytesUpdate[2] = {144.0, 208.0};
 
 hipEvent_t timer_event(hmc_ctx *c) {
     KernelTimer &T = c->timer;
-    if (T.used == T.ev.size()) {
+    if (T.pool_used == T.pool.size()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        T.ev.push_back(e);
+        T.pool.push_back(e);
     }
-    return T.ev[T.used++];
+    return T.pool[T.pool_used++];
 }
 
-// One CG slot (step 1 + step 2), bracketed by events when timing is on.
-template <typename L1, typename L2> void slot_launch(hmc_ctx *c, L1 step1, L2 step2) {
-    if (!c->timer.on) {
+// Called only after the stream was synchronised: every recorded event and snapshot is complete.
+void timer_flush(hmc_ctx *c) {
+    KernelTimer &T = c->timer;
+    for (const TimedSlot &ts : T.pending) {
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, ts.ev[0], ts.ev[1]) != hipSuccess) continue;
+        if (hipEventElapsedTime(&b, ts.ev[1], ts.ev[2]) != hipSuccess) continue;
+        const CGState *snap = (const CGState *)((char *)T.ring + (size_t)ts.snap * sizeof(CGState) * c->nchains);
+        double by[2] = {0.0, 0.0};
+        for (int k = 0; k < c->nchains; ++k) {
+            if (snap[k].converged) continue;
+            const double V = c->chains[k].V;
+            const double *per = !ts.mixed ? kBytesFp64 : snap[k].mode == kModeUpdate ? kBytesUpdate : kBytesFp32;
+            by[0] += V * per[0];
+            by[1] += V * per[1];
+        }
+        T.ms[0] += a;
+        T.ms[1] += b;
+        T.bytes[0] += by[0];
+        T.bytes[1] += by[1];
+        T.timed[0]++;
+        T.timed[1]++;
+    }
+    T.pending.clear();
+    T.pool_used = 0;
+    T.ring_used = 0;
+}
+
+// One CG slot (step 1 + step 2); sampled slots are bracketed by events and their state
+// snapshotted.
+template <typename L1, typename L2> void slot_launch(hmc_ctx *c, int slot, bool mixed, L1 step1, L2 step2) {
+    KernelTimer &T = c->timer;
+    if (T.on) T.launches++;
+    if (!T.on || slot % T.sample_every != 0 || T.ring_used == kRingSlots || !T.ring) {
         step1();
         step2();
         return;
     }
-    hipEvent_t a = timer_event(c), b = timer_event(c), d = timer_event(c);
-    (void)hipEventRecord(a, c->stream);
+    TimedSlot ts;
+    for (int k = 0; k < 3; ++k) ts.ev[k] = timer_event(c);
+    ts.mixed = mixed ? 1 : 0;
+    ts.snap = T.ring_used++;
+    (void)hipEventRecord(ts.ev[0], c->stream);
     step1();
-    (void)hipEventRecord(b, c->stream);
+    (void)hipEventRecord(ts.ev[1], c->stream);
     step2();
-    (void)hipEventRecord(d, c->stream);
-}
-
-void timer_account(hmc_ctx *c, bool mixed) {
-    if (!c->timer.on) return;
-    timer_flush(c);
-    for (int k = 0; k < c->nchains; ++k) {
-        const long long V = c->chains[k].V;
-        c->timer.site_iters[mixed ? 1 : 0] += V * c->cg_host[k].iters;
-        c->timer.site_updates += V * c->cg_host[k].n_updates;
-    }
+    (void)hipEventRecord(ts.ev[2], c->stream);
+    // the state written by step 1 of this slot stays valid until step 1 of slot + 2
+    (void)hipMemcpyAsync((char *)T.ring + (size_t)ts.snap * sizeof(CGState) * c->nchains,
+                         c->cg() + (size_t)(slot & 1) * c->nchains, sizeof(CGState) * c->nchains,
+                         hipMemcpyDeviceToHost, c->stream);
+    T.pending.push_back(ts);
 }
 
 // CG on D^dagger D x = phi with the links already materialised (U64, and U32 if mixed).
@@ -340,26 +387,25 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     // iteration slots: CG iterations plus, in mixed precision, FP64 residual recomputations
     const int max_slots = mixed ? max_iter + max_iter / 2 + 64 : max_iter;
     int rc = HMC_OK, slot = 0;
+    // Convergence checks: the first after check_every slots; the interval doubles (up to
+    // 8x) while no chain converges and falls back when the active set shrinks.
+    int interval = c->check_every, next_check = interval, last_active = full.nblocks;
     for (; slot < max_slots; ++slot) {
         void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
-        slot_launch(c, [&] { launch_cg_step1(g, f, mixed, slot, tol, po, pn, false, c->stream); },
+        slot_launch(c, slot, mixed,
+                    [&] { launch_cg_step1(g, f, mixed, slot, tol, po, pn, false, c->stream); },
                     [&] { launch_cg_step2(g, f, mixed, slot, pn, c->stream); });
-        if ((slot + 1) % c->check_every == 0) {
-            int active = 0;
-            if ((rc = check_convergence(c, &active))) return rc;
+        if (slot + 1 == next_check) {
+            int active = 0, live = 0;
+            if ((rc = check_convergence(c, mixed ? max_iter : max_slots, &active, &live))) return rc;
             if (c->timer.on) timer_flush(c);
-            if (active == 0) { ++slot; break; }
+            if (active == 0 || (mixed && live == 0)) { ++slot; break; }
             g.work = c->at<BlockWork>(c->off_active);
             g.nblocks = active;
-            if (mixed) {
-                // stop when every unconverged chain has used up its FP32 iterations
-                if ((rc = to_host(c, c->cg_host.data(), c->cg() + (size_t)(slot & 1) * c->nchains,
-                                  sizeof(CGState) * c->nchains))) return rc;
-                bool exhausted = true;
-                for (const CGState &s : c->cg_host)
-                    if (!s.converged && s.iters < max_iter) exhausted = false;
-                if (exhausted) { ++slot; break; }
-            }
+            interval = active == last_active ? std::min(2 * interval, 8 * c->check_every)
+                                             : c->check_every;
+            last_active = active;
+            next_check = slot + 1 + interval;
         }
     }
     // fold the last slot's residual into the state (decision only), on every chain
@@ -367,7 +413,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     if (mixed) launch_cg_finish_mixed(full, f, c->stream);
     if ((rc = to_host(c, c->cg_host.data(), c->cg() + (size_t)(slot & 1) * c->nchains,
                       sizeof(CGState) * c->nchains))) return rc;
-    timer_account(c, mixed);
+    if (c->timer.on) timer_flush(c);
     for (const CGState &s : c->cg_host)
         if (!s.converged) return fail(c, HMC_E_NOCONV, "CG did not converge in %d iterations", max_iter);
     return HMC_OK;
@@ -1005,29 +1051,34 @@ int hmc_set_timing(hmc_ctx *c, int on) {
         if (rc) return rc;
     }
     KernelTimer &T = c->timer;
+    if (on && !T.ring)
+        HIP_TRY(c, hipHostMalloc(&T.ring, sizeof(CGState) * c->nchains * kRingSlots, hipHostMallocDefault));
     T.on = on != 0;
-    T.used = 0;
+    T.pending.clear();
+    T.pool_used = 0;
+    T.ring_used = 0;
     T.ms[0] = T.ms[1] = 0.0;
-    T.launches[0] = T.launches[1] = 0;
-    T.site_iters[0] = T.site_iters[1] = 0;
-    T.site_updates = 0;
+    T.bytes[0] = T.bytes[1] = 0.0;
+    T.timed[0] = T.timed[1] = 0;
+    T.launches = 0;
     return HMC_OK;
 }
 
 int hmc_get_kernel_stats(hmc_ctx *c, int which, hmc_kernel_stat *out) {
     if (!c || !out || which < 0 || which > 1) return HMC_E_INVAL;
     const KernelTimer &T = c->timer;
-    out->launches = T.launches[which];
-    out->total_ms = T.ms[which];
-    out->site_iters_fp64 = T.site_iters[0];
-    out->site_iters_fp32 = T.site_iters[1];
-    out->site_updates = T.site_updates;
+    out->launches = T.launches;
+    out->timed_launches = T.timed[which];
+    out->timed_ms = T.ms[which];
+    out->timed_bytes = T.bytes[which];
+    out->sample_every = T.sample_every;
     return HMC_OK;
 }
 
 int hmc_destroy(hmc_ctx *c) {
     if (!c) return HMC_E_INVAL;
-    for (hipEvent_t e : c->timer.ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
+    if (c->timer.ring) (void)hipHostFree(c->timer.ring);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
     return HMC_OK;

@@ -267,36 +267,46 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     const int Vtot = g.Vtot;
     const bool leader = w.logical == ci.block0 && threadIdx.x == 0;
     CGState *out = f.st + (size_t)(slot & 1) * g.nchains + w.chain;
-    const CGState P = f.st[(size_t)((slot + 1) & 1) * g.nchains + w.chain];
-    if (P.converged) {
-        if (leader) *out = P;
+    const CGState *prev = f.st + (size_t)((slot + 1) & 1) * g.nchains + w.chain;
+    // the state is handled field by field in scalars (a whole-struct copy per thread would
+    // be placed in LDS by the compiler)
+    const int p_conv = prev->converged;
+    if (p_conv) {
+        if (leader) *out = *prev;
         return;
     }
+    const int p_mode = prev->mode, p_iters = prev->iters, p_nupd = prev->n_updates;
+    const double p_rho = prev->rho, p_rho_p = prev->rho_p, p_target = prev->target;
+    const double p_phi2 = prev->phi2, p_rmax2 = prev->rmax2, delta2 = prev->delta2;
     const double rho = chain_total(f.p2, ci);
-    CGState S = P;
+    double n_rho = rho, n_rho_p = p_rho_p, n_target = p_target, n_phi2 = p_phi2, n_rmax2 = p_rmax2;
+    double n_beta = 0.0;
+    int n_iters = p_iters, n_nupd = p_nupd, n_conv = 0;
     bool update = false, first = false;
-    if (P.mode == kModeInit) {
-        S.phi2 = rho; S.target = tol2 * rho; S.rmax2 = rho; S.rho = rho; S.rho_p = rho;
-        S.iters = 0; S.n_updates = 0; S.beta = 0.0;
-        S.converged = rho <= S.target ? 1 : 0;
+    if (p_mode == kModeInit) {
+        n_phi2 = rho; n_target = tol2 * rho; n_rmax2 = rho; n_rho_p = rho;
+        n_iters = 0; n_nupd = 0;
+        n_conv = rho <= n_target ? 1 : 0;
         first = true;
-    } else if (P.mode == kModeUpdate) {
-        S.n_updates = P.n_updates + 1;
-        S.rmax2 = rho;
-        S.converged = rho <= S.target ? 1 : 0;
-        S.beta = rho / P.rho_p;
-        S.rho = rho;
+    } else if (p_mode == kModeUpdate) {
+        n_nupd = p_nupd + 1;
+        n_rmax2 = rho;
+        n_conv = rho <= n_target ? 1 : 0;
+        n_beta = rho / p_rho_p;
     } else {
-        S.iters = P.iters + 1;
-        S.rho_p = P.rho;
-        S.rho = rho;
-        S.beta = rho / P.rho;
-        if (!MIXED) S.converged = rho <= S.target ? 1 : 0;
-        else update = rho <= S.target || rho <= S.delta2 * S.rmax2;
+        n_iters = p_iters + 1;
+        n_rho_p = p_rho;
+        n_beta = rho / p_rho;
+        if (!MIXED) n_conv = rho <= n_target ? 1 : 0;
+        else update = rho <= n_target || rho <= delta2 * n_rmax2;
     }
-    S.mode = update ? kModeUpdate : kModeNormal;
-    if (leader) *out = S;
-    if (S.converged || decide_only) return;
+    if (leader) {
+        out->rho = n_rho; out->rho_p = n_rho_p; out->target = n_target; out->phi2 = n_phi2;
+        out->rmax2 = n_rmax2; out->beta = n_beta; out->delta2 = delta2; out->iters = n_iters;
+        out->converged = n_conv; out->mode = update ? kModeUpdate : kModeNormal;
+        out->n_updates = n_nupd;
+    }
+    if (n_conv || decide_only) return;
     const C *__restrict__ p_old = (const C *)p_old_v;
     C *__restrict__ p_new = (C *)p_new_v;
     if (MIXED && update) {
@@ -325,7 +335,7 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     const C *__restrict__ U;
     if constexpr (MIXED) { r = f.r32; t = f.t32; U = f.U32; }
     else { r = f.r64; t = f.t64; U = f.U64; }
-    const R beta = (R)S.beta;
+    const R beta = (R)n_beta;
     double v[1] = {0.0};
     SITES_LOOP
     const Site s = decode_site(ci, local);
@@ -358,10 +368,12 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
     const BlockWork w = g.work[blockIdx.x];
     const ChainInfo ci = g.chains[w.chain];
     const int Vtot = g.Vtot;
-    const CGState S = f.st[(size_t)(slot & 1) * g.nchains + w.chain];
-    if (S.converged) return;
+    const CGState *st = f.st + (size_t)(slot & 1) * g.nchains + w.chain;
+    if (st->converged) return;
+    const int mode = st->mode;
+    const double s_rho = st->rho;
     double v[1] = {0.0};
-    if (MIXED && S.mode == kModeUpdate) {
+    if (MIXED && mode == kModeUpdate) {
         // second half: r64 = phi - D^dagger t64; x64 += x32; x32 = 0; r32 = r64.
         SITES_LOOP
         const Site s = decode_site(ci, local);
@@ -390,7 +402,7 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
         return;
     }
     const double pAp = chain_total(f.p1, ci);
-    const R alpha = (R)(S.rho / pAp);
+    const R alpha = (R)(s_rho / pAp);
     const C *__restrict__ p = (const C *)p_new_v;
     const C *__restrict__ t;
     C *__restrict__ r;
@@ -463,8 +475,10 @@ void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s) {
 // Order-preserving compaction of the workgroups of unconverged chains (one workgroup).
 // A chain is dropped once either state parity says converged (a chain leaves the grid
 // right after convergence, so its other parity may still hold the state before it).
+// count[1] receives the number of unconverged chains that still have iterations left
+// (iters < max_iter).
 __global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGState *__restrict__ st,
-                          int nchains, BlockWork *__restrict__ out, int *count) {
+                          int nchains, int max_iter, BlockWork *__restrict__ out, int *count) {
     __shared__ int wave_cnt[kMaxWaves];
     __shared__ int base;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -472,11 +486,14 @@ __global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGSta
     __syncthreads();
     for (int chunk = 0; chunk < n; chunk += blockDim.x) {
         const int i = chunk + threadIdx.x;
-        BlockWork wk = {};
+        int ch = 0, start = 0, logical = 0, spt = 0;
         bool keep = false;
         if (i < n) {
-            wk = work[i];
-            keep = st[wk.chain].converged == 0 && st[nchains + wk.chain].converged == 0;
+            ch = work[i].chain;
+            start = work[i].start;
+            logical = work[i].logical;
+            spt = work[i].spt;
+            keep = st[ch].converged == 0 && st[nchains + ch].converged == 0;
         }
         const unsigned long long m = __ballot(keep);
         const int before = __popcll(m & ((1ull << lane) - 1ull));
@@ -484,7 +501,13 @@ __global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGSta
         __syncthreads();
         int off = base;
         for (int v = 0; v < wave; ++v) off += wave_cnt[v];
-        if (keep) out[off + before] = wk;
+        if (keep) {
+            BlockWork *o = out + off + before;
+            o->chain = ch;
+            o->start = start;
+            o->logical = logical;
+            o->spt = spt;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             int tot = 0;
@@ -493,12 +516,23 @@ __global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGSta
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *count = base;
+    double live[1] = {0.0};
+    for (int c = threadIdx.x; c < nchains; c += blockDim.x) {
+        if (!st[c].converged && !st[nchains + c].converged &&
+            (st[c].iters < max_iter || st[nchains + c].iters < max_iter))
+            live[0] += 1.0;
+    }
+    block_sum_all<1>(live);
+    if (threadIdx.x == 0) {
+        count[0] = base;
+        count[1] = (int)live[0];
+    }
 }
 
-void launch_compact(const Geo &full, const CGState *st, BlockWork *out, int *count, hipStream_t s) {
+void launch_compact(const Geo &full, const CGState *st, int max_iter, BlockWork *out, int *count,
+                    hipStream_t s) {
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, full.work, full.nblocks, st,
-                       full.nchains, out, count);
+                       full.nchains, max_iter, out, count);
 }
 
 __global__ void k_count_converged(const CGState *__restrict__ st, int n, int *out) {

@@ -79,8 +79,10 @@ void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, cons
                      hipStream_t s);
 // x64 += x32 (end of a mixed solve).
 void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s);
-// Workgroups of chains not yet converged (st: both state parities) -> out[0..*count).
-void launch_compact(const Geo &full, const CGState *st, BlockWork *out, int *count, hipStream_t s);
+// Workgroups of chains not yet converged (st: both state parities) -> out[0..count[0]);
+// count[1] = unconverged chains with iterations left (< max_iter).
+void launch_compact(const Geo &full, const CGState *st, int max_iter, BlockWork *out, int *count,
+                    hipStream_t s);
 // Number of converged chains in one state parity -> *out.
 void launch_count_converged(const CGState *st_par, int n, int *out, hipStream_t s);
 
