@@ -165,6 +165,11 @@ int hmc_set_quenched(hmc_ctx *ctx, int quenched);
  * (default 8).  Iterations launched after a chain converged do no work for it. */
 int hmc_set_check_interval(hmc_ctx *ctx, int every);
 
+/* Chains with at most vmax sites solve their CG inside one persistent workgroup (the
+ * search direction and D p held in LDS), concurrently with the multi-workgroup kernels that
+ * handle the larger chains; 0 disables it.  Default and maximum 2048. */
+int hmc_set_persistent_limit(hmc_ctx *ctx, int vmax);
+
 /* ---------------------------------------------------------------- operators (Sec. 3) */
 
 /* out = D in: (D psi)(n) = (2+m0) psi(n) - 1/2 sum_mu [(1 - sigma_mu) U_mu(n) psi(n+mu)

@@ -229,6 +229,10 @@ class Lattice:
     def set_quenched(self, quenched: bool):
         self._check(self._lib.hmc_set_quenched(self._ctx, int(bool(quenched))))
 
+    def set_persistent_limit(self, vmax: int):
+        """Chains of at most vmax sites solve inside one persistent workgroup (0: never)."""
+        self._check(self._lib.hmc_set_persistent_limit(self._ctx, int(vmax)))
+
     def set_check_interval(self, every: int):
         self._check(self._lib.hmc_set_check_interval(self._ctx, int(every)))
 

@@ -60,6 +60,7 @@ SIGNATURES = {
     "hmc_set_solver": (_I, [_P, _D, _I, _D]),
     "hmc_set_quenched": (_I, [_P, _I]),
     "hmc_set_check_interval": (_I, [_P, _I]),
+    "hmc_set_persistent_limit": (_I, [_P, _I]),
     "hmc_dslash": (_I, [_P, _P, _P]),
     "hmc_dslash_dagger": (_I, [_P, _P, _P]),
     "hmc_cg_solve": (_I, [_P, _P, _P, _D, _I, _I, _P]),

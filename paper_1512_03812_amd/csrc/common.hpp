@@ -32,7 +32,8 @@ struct ChainInfo {
     double beta;  // Wilson gauge coupling
     double m0;    // bare mass
     uint32_t chain_id;  // chain index used as the fourth Philox counter word
-    int pad[3];
+    int small;          // 1: its CG runs in the one-workgroup persistent solver
+    int pad[2];
 };
 static_assert(sizeof(ChainInfo) == 64, "ChainInfo is 64 bytes");
 

@@ -70,13 +70,21 @@ struct hmc_ctx {
     double delta = 0.1;
     int check_every = 8;
     bool quenched = false;
+    int persist_vmax = 2048;  // chains with at most this many sites use the persistent solver
     // ------------------------------------------------------------ workspace
     size_t ws_bytes = 0;
     char *ws = nullptr;
     hipStream_t stream = nullptr;
-    size_t off_chains = 0, off_work = 0, off_active = 0, off_cg = 0, off_partials = 0,
+    size_t off_chains = 0, off_work = 0, off_active = 0, off_big = 0, off_small = 0, off_cg = 0,
+           off_partials = 0,
            off_sums = 0, off_metro = 0, off_status = 0, off_count = 0, off_links[kNumLinkBufs] = {},
            off_spin[kNumSpinBufs] = {}, off_U64 = 0, off_U32 = 0, off_spin32[kNumSpin32Bufs] = {};
+    // ------------------------------------------------------------ solver partition
+    hipStream_t side = nullptr;           // second stream for the persistent solver
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    int part_vmax = -1;                   // vmax the device partition tables were built for
+    int n_big_blocks = 0, n_small = 0, small_vmax = 0;
+    size_t lds_max = 64 * 1024;           // dynamic LDS a workgroup may opt in to
     // ------------------------------------------------------------ pinned host staging
     void *pinned = nullptr;
     size_t pinned_bytes = 0;
@@ -179,6 +187,8 @@ void layout_workspace(hmc_ctx *c) {
     c->off_chains = take(sizeof(ChainInfo) * C);
     c->off_work = take(sizeof(BlockWork) * N);
     c->off_active = take(sizeof(BlockWork) * N);
+    c->off_big = take(sizeof(BlockWork) * N);
+    c->off_small = take(sizeof(int) * C);
     c->off_cg = take(sizeof(CGState) * 2 * C);
     c->off_partials = take(sizeof(double) * kMaxReduce * N);
     c->off_sums = take(sizeof(double) * 16 * C);
@@ -270,9 +280,9 @@ void forget_all(hmc_ctx *c) {
 
 // Rebuilds the list of workgroups of the unconverged chains; returns its length in *active
 // and the number of unconverged chains with iterations left in *live.
-int check_convergence(hmc_ctx *c, int max_iter, int *active, int *live) {
+int check_convergence(hmc_ctx *c, const Geo &big, int max_iter, int *active, int *live) {
     int *dev = c->at<int>(c->off_count);
-    launch_compact(c->geo(), c->cg(), max_iter, c->at<BlockWork>(c->off_active), dev, c->stream);
+    launch_compact(big, c->cg(), max_iter, c->at<BlockWork>(c->off_active), dev, c->stream);
     int n[2] = {0, 0};
     int rc = to_host(c, n, dev, sizeof(n));
     if (rc) return rc;
@@ -359,10 +369,50 @@ template <typename L1, typename L2> void slot_launch(hmc_ctx *c, int slot, bool 
     T.pending.push_back(ts);
 }
 
+// Splits the chains between the persistent one-workgroup solver (V <= vmax) and the
+// multi-workgroup slot kernels, and uploads the workgroup list of the latter and the chain
+// list of the former.
+int build_partition(hmc_ctx *c, int vmax) {
+    if (c->part_vmax == vmax) return HMC_OK;
+    std::vector<BlockWork> big;
+    std::vector<int> small;
+    int svmax = 0;
+    for (int k = 0; k < c->nchains; ++k) {
+        if (c->chains[k].V <= vmax) {
+            small.push_back(k);
+            svmax = std::max(svmax, c->chains[k].V);
+        }
+    }
+    for (const BlockWork &w : c->work)
+        if (c->chains[w.chain].V > vmax) big.push_back(w);
+    if (!big.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->at<BlockWork>(c->off_big), big.data(), sizeof(BlockWork) * big.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    if (!small.empty())
+        HIP_TRY(c, hipMemcpyAsync(c->at<int>(c->off_small), small.data(), sizeof(int) * small.size(),
+                                  hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->n_big_blocks = (int)big.size();
+    c->n_small = (int)small.size();
+    c->small_vmax = svmax;
+    c->part_vmax = vmax;
+    return HMC_OK;
+}
+
+// Largest chain the persistent solver takes for a precision (LDS holds 4V complex; at most
+// 2 sites per thread of a 1024-thread workgroup; the device's opt-in LDS limit, less the
+// kernel's static LDS).
+int persistent_limit(hmc_ctx *c, bool mixed) {
+    int v = std::min(c->persist_vmax, 2048);
+    while (v > 0 && cg_wg_lds_bytes(v, mixed) + 1024 > c->lds_max) v /= 2;
+    return v;
+}
+
 // CG on D^dagger D x = phi with the links already materialised (U64, and U32 if mixed).
 // Per-chain results land in c->cg_host.  Returns HMC_E_NOCONV if a chain did not converge.
 // Every check_every slots the host reads back how many workgroups still belong to
 // unconverged chains and launches only those from then on.
+int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, int prec);
 int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, int prec) {
     const bool mixed = prec == HMC_PREC_MIXED;
     const Geo full = c->geo();
@@ -383,13 +433,34 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     void *pb[2];
     if (mixed) { pb[0] = c->spin32(FPA); pb[1] = c->spin32(FPB); }
     else { pb[0] = c->spin(SPA); pb[1] = c->spin(SPB); }
-    launch_cg_init(full, f, mixed, c->delta, c->stream);
+    int rc = build_partition(c, persistent_limit(c, mixed));
+    if (rc) return rc;
+    // small chains: one persistent workgroup each, on the side stream
+    if (c->n_small > 0) {
+        HIP_TRY(c, hipEventRecord(c->fork_ev, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
+        if (launch_cg_wg(full, f, mixed, c->at<int>(c->off_small), c->n_small, c->small_vmax, tol,
+                         c->delta, max_iter, c->side)) {
+            // the device refused the LDS request: solve every chain with the slot kernels
+            c->lds_max = cg_wg_lds_bytes(c->small_vmax, mixed) - 1;
+            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->fork_ev, 0));
+            return solve(c, phi, x, tol, max_iter, prec);
+        }
+        HIP_TRY(c, hipEventRecord(c->join_ev, c->side));
+    }
+    // large chains: multi-workgroup slot kernels on the bound stream
+    Geo big = full;
+    big.work = c->at<BlockWork>(c->off_big);
+    big.nblocks = c->n_big_blocks;
+    g = big;
+    int slot = 0;
+    if (big.nblocks > 0) {
+    launch_cg_init(big, f, mixed, c->delta, c->stream);
     // iteration slots: CG iterations plus, in mixed precision, FP64 residual recomputations
     const int max_slots = mixed ? max_iter + max_iter / 2 + 64 : max_iter;
-    int rc = HMC_OK, slot = 0;
     // Convergence checks: the first after check_every slots; the interval doubles (up to
     // 8x) while no chain converges and falls back when the active set shrinks.
-    int interval = c->check_every, next_check = interval, last_active = full.nblocks;
+    int interval = c->check_every, next_check = interval, last_active = big.nblocks;
     for (; slot < max_slots; ++slot) {
         void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
         slot_launch(c, slot, mixed,
@@ -397,7 +468,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
                     [&] { launch_cg_step2(g, f, mixed, slot, pn, c->stream); });
         if (slot + 1 == next_check) {
             int active = 0, live = 0;
-            if ((rc = check_convergence(c, mixed ? max_iter : max_slots, &active, &live))) return rc;
+            if ((rc = check_convergence(c, big, mixed ? max_iter : max_slots, &active, &live))) return rc;
             if (c->timer.on) timer_flush(c);
             if (active == 0 || (mixed && live == 0)) { ++slot; break; }
             g.work = c->at<BlockWork>(c->off_active);
@@ -408,9 +479,11 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
             next_check = slot + 1 + interval;
         }
     }
-    // fold the last slot's residual into the state (decision only), on every chain
-    launch_cg_step1(full, f, mixed, slot, tol, pb[slot & 1], pb[(slot + 1) & 1], true, c->stream);
-    if (mixed) launch_cg_finish_mixed(full, f, c->stream);
+    // fold the last slot's residual into the state (decision only), on every large chain
+    launch_cg_step1(big, f, mixed, slot, tol, pb[slot & 1], pb[(slot + 1) & 1], true, c->stream);
+    if (mixed) launch_cg_finish_mixed(big, f, c->stream);
+    }
+    if (c->n_small > 0) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->join_ev, 0));
     if ((rc = to_host(c, c->cg_host.data(), c->cg() + (size_t)(slot & 1) * c->nchains,
                       sizeof(CGState) * c->nchains))) return rc;
     if (c->timer.on) timer_flush(c);
@@ -636,6 +709,22 @@ int hmc_bind(hmc_ctx *c, void *ws, size_t bytes, void *stream) {
                                    sizeof(double) * 16 * c->nchains + 4096);
         HIP_TRY(c, hipHostMalloc(&c->pinned, c->pinned_bytes, hipHostMallocDefault));
     }
+    {
+        int dev = 0, optin = 0, plain = 0;
+        HIP_TRY(c, hipGetDevice(&dev));
+        if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess)
+            optin = 0;
+        if (hipDeviceGetAttribute(&plain, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            plain = 0;
+        (void)hipGetLastError();
+        c->lds_max = (size_t)std::max(std::max(optin, plain), 0);
+    }
+    if (!c->side) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    }
+    c->part_vmax = -1;
     HIP_TRY(c, hipMemcpyAsync(c->at<ChainInfo>(c->off_chains), c->chains.data(),
                               sizeof(ChainInfo) * c->nchains, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->at<BlockWork>(c->off_work), c->work.data(),
@@ -747,6 +836,12 @@ int hmc_set_solver(hmc_ctx *c, double tol, int max_iter, double reliable_delta) 
 int hmc_set_quenched(hmc_ctx *c, int quenched) {
     if (!c) return HMC_E_INVAL;
     c->quenched = quenched != 0;
+    return HMC_OK;
+}
+
+int hmc_set_persistent_limit(hmc_ctx *c, int vmax) {
+    if (!c || vmax < 0) return HMC_E_INVAL;
+    c->persist_vmax = vmax;
     return HMC_OK;
 }
 
@@ -1079,6 +1174,9 @@ int hmc_destroy(hmc_ctx *c) {
     if (!c) return HMC_E_INVAL;
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
     if (c->timer.ring) (void)hipHostFree(c->timer.ring);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
     return HMC_OK;

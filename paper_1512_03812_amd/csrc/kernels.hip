@@ -472,13 +472,255 @@ void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_finish_mixed, dim3(g.nblocks), dim3(g.block), 0, s, g, f);
 }
 
+// ---------------------------------------------------------------- persistent small-chain CG
+// One workgroup runs a whole solve for one small chain.  The search direction p and
+// t = D p live in LDS (dynamic shared memory, 2 x 2V complex); r, x, the site geometry and
+// the chain's links live in registers; the reductions are workgroup-local.  Mixed precision
+// recomputes the residual in FP64 through global memory (x64, t64, r32) whenever the FP32
+// residual has dropped by delta, exactly as the slot kernels do; that rare step is kept out
+// of line so that its FP64 operands do not occupy registers in the iteration loop.  Each
+// thread owns the chain-local sites tid + k * blockDim, k < SPT.  The final state is
+// written to both state parities.
+
+// t64 = D x64 on this thread's sites.
+__device__ __noinline__ void wg_dx64(ChainInfo ci, CGFields f, int Vtot, int spt) {
+    for (int k = 0; k < spt; ++k) {
+        const int local = threadIdx.x + k * blockDim.x;
+        if (local >= ci.V) break;
+        const Site s = decode_site(ci, local);
+        const Nbr nb = neighbours(ci, s);
+        auto load = [&](int q, double2 &b0, double2 &b1) { b0 = f.x64[q]; b1 = f.x64[(size_t)Vtot + q]; };
+        double2 o0, o1;
+        dslash_site<double, false>(nb, s.flat, Vtot, f.U64, f.x64[s.flat],
+                                   f.x64[(size_t)Vtot + s.flat], 2.0 + ci.m0, load, o0, o1);
+        f.t64[s.flat] = o0;
+        f.t64[(size_t)Vtot + s.flat] = o1;
+    }
+}
+
+// r = phi - D^dagger t64 on this thread's sites, stored as r32; returns the local ||r||^2.
+__device__ __noinline__ double wg_res64(ChainInfo ci, CGFields f, int Vtot, int spt) {
+    double acc = 0.0;
+    for (int k = 0; k < spt; ++k) {
+        const int local = threadIdx.x + k * blockDim.x;
+        if (local >= ci.V) break;
+        const Site s = decode_site(ci, local);
+        const Nbr nb = neighbours(ci, s);
+        auto load = [&](int q, double2 &b0, double2 &b1) { b0 = f.t64[q]; b1 = f.t64[(size_t)Vtot + q]; };
+        double2 a0, a1;
+        dslash_site<double, true>(nb, s.flat, Vtot, f.U64, f.t64[s.flat],
+                                  f.t64[(size_t)Vtot + s.flat], 2.0 + ci.m0, load, a0, a1);
+        const double2 Ay[2] = {a0, a1};
+        for (int sp = 0; sp < 2; ++sp) {
+            const size_t q = (size_t)sp * Vtot + s.flat;
+            const double2 ph = f.phi[q];
+            const double2 rr = make_double2(ph.x - Ay[sp].x, ph.y - Ay[sp].y);
+            f.r32[q] = make_float2((float)rr.x, (float)rr.y);
+            acc += norm2(rr);
+        }
+    }
+    return acc;
+}
+
+template <bool MIXED, int SPT>
+__global__ void __launch_bounds__(1024)
+k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, double delta2,
+        int max_iter) {
+    using R = typename Prec<MIXED>::R;
+    using C = cplx_t<R>;
+    extern __shared__ double smem_d[];
+    const int c = chain_list[blockIdx.x];
+    const ChainInfo ci = g.chains[c];
+    const int V = ci.V, Vtot = g.Vtot, off = ci.off;
+    C *ps = (C *)smem_d;  // [2][V]
+    C *ts = ps + 2 * V;   // [2][V]
+    const C *__restrict__ U;
+    if constexpr (MIXED) U = f.U32; else U = f.U64;
+    const R mass = (R)(2.0 + ci.m0);
+
+    Nbr nb[SPT];
+    int fl[SPT];
+    bool ok[SPT];
+    C r[SPT][2], x[SPT][2], p[SPT][2];
+    double v[1] = {0.0};
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        const int local = threadIdx.x + k * blockDim.x;
+        ok[k] = local < V;
+        fl[k] = off + (ok[k] ? local : 0);
+        const Site s = decode_site(ci, ok[k] ? local : 0);
+        nb[k] = neighbours(ci, s);
+        for (int sp = 0; sp < 2; ++sp) {
+            const double2 a = ok[k] ? f.phi[(size_t)sp * Vtot + fl[k]] : make_double2(0.0, 0.0);
+            r[k][sp] = cmake<C>((R)a.x, (R)a.y);
+            x[k][sp] = cmake<C>((R)0, (R)0);
+            p[k][sp] = r[k][sp];
+            v[0] += norm2(a);
+            if (ok[k]) {
+                if (MIXED) f.x64[(size_t)sp * Vtot + fl[k]] = make_double2(0.0, 0.0);
+                ps[sp * V + (fl[k] - off)] = p[k][sp];
+            }
+        }
+    }
+    block_sum_all<1>(v);  // also makes ps visible
+    const double phi2 = v[0], target = tol2 * v[0];
+    double rho = v[0], rho_prev = v[0], rmax2 = v[0];
+    int iters = 0, nupd = 0;
+    bool conv = rho <= target;
+    auto loadP = [&](int q, C &b0, C &b1) { b0 = ps[q - off]; b1 = ps[V + q - off]; };
+    auto loadT = [&](int q, C &b0, C &b1) { b0 = ts[q - off]; b1 = ts[V + q - off]; };
+    while (!conv && iters < max_iter) {
+        // t = D p
+        v[0] = 0.0;
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            if (!ok[k]) continue;
+            C o0, o1;
+            dslash_site<R, false>(nb[k], fl[k], Vtot, U, p[k][0], p[k][1], mass, loadP, o0, o1);
+            ts[fl[k] - off] = o0;
+            ts[V + fl[k] - off] = o1;
+            v[0] += norm2(o0) + norm2(o1);
+        }
+        block_sum_all<1>(v);
+        const R alpha = (R)(rho / v[0]);
+        // x += alpha p, r -= alpha D^dagger t
+        v[0] = 0.0;
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            if (!ok[k]) continue;
+            C a0, a1;
+            dslash_site<R, true>(nb[k], fl[k], Vtot, U, ts[fl[k] - off], ts[V + fl[k] - off], mass,
+                                 loadT, a0, a1);
+            const C Ap[2] = {a0, a1};
+            for (int sp = 0; sp < 2; ++sp) {
+                x[k][sp].x += alpha * p[k][sp].x; x[k][sp].y += alpha * p[k][sp].y;
+                r[k][sp].x -= alpha * Ap[sp].x; r[k][sp].y -= alpha * Ap[sp].y;
+                v[0] += norm2(r[k][sp]);
+            }
+        }
+        block_sum_all<1>(v);
+        const double rho_new = v[0];
+        ++iters;
+        double beta = rho_new / rho;
+        rho_prev = rho;
+        rho = rho_new;
+        if (!MIXED) {
+            if (rho_new <= target) { conv = true; break; }
+        } else if (rho_new <= target || rho_new <= delta2 * rmax2) {
+            // FP64 residual recomputation: x64 += x32; t64 = D x64; r = phi - D^dagger t64.
+#pragma unroll
+            for (int k = 0; k < SPT; ++k) {
+                if (!ok[k]) continue;
+                for (int sp = 0; sp < 2; ++sp) {
+                    const size_t q = (size_t)sp * Vtot + fl[k];
+                    const double2 xx = f.x64[q];
+                    f.x64[q] = make_double2(xx.x + (double)x[k][sp].x, xx.y + (double)x[k][sp].y);
+                    x[k][sp] = cmake<C>((R)0, (R)0);
+                }
+            }
+            __syncthreads();
+            wg_dx64(ci, f, Vtot, SPT);
+            __syncthreads();
+            v[0] = wg_res64(ci, f, Vtot, SPT);
+            block_sum_all<1>(v);
+#pragma unroll
+            for (int k = 0; k < SPT; ++k) {
+                if (!ok[k]) continue;
+                for (int sp = 0; sp < 2; ++sp) {
+                    const float2 rr = f.r32[(size_t)sp * Vtot + fl[k]];
+                    r[k][sp] = cmake<C>((R)rr.x, (R)rr.y);
+                }
+            }
+            ++nupd;
+            rmax2 = v[0];
+            if (v[0] <= target) { rho = v[0]; conv = true; break; }
+            beta = v[0] / rho_prev;
+            rho = v[0];
+        }
+        // p = r + beta p
+        const R b = (R)beta;
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            if (!ok[k]) continue;
+            for (int sp = 0; sp < 2; ++sp) {
+                p[k][sp].x = r[k][sp].x + b * p[k][sp].x;
+                p[k][sp].y = r[k][sp].y + b * p[k][sp].y;
+                ps[sp * V + (fl[k] - off)] = p[k][sp];
+            }
+        }
+        __syncthreads();
+    }
+    // solution out
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+        if (!ok[k]) continue;
+        for (int sp = 0; sp < 2; ++sp) {
+            const size_t q = (size_t)sp * Vtot + fl[k];
+            if (MIXED) {
+                const double2 xx = f.x64[q];
+                f.x64[q] = make_double2(xx.x + (double)x[k][sp].x, xx.y + (double)x[k][sp].y);
+            } else {
+                f.x64[q] = make_double2((double)x[k][sp].x, (double)x[k][sp].y);
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int par = 0; par < 2; ++par) {
+            CGState *o = f.st + (size_t)par * g.nchains + c;
+            o->rho = rho; o->rho_p = rho_prev; o->target = target; o->phi2 = phi2; o->rmax2 = rmax2;
+            o->beta = 0.0; o->delta2 = delta2; o->iters = iters; o->converged = conv ? 1 : 0;
+            o->mode = kModeNormal; o->n_updates = nupd;
+        }
+    }
+}
+
+template <bool MIXED, int SPT>
+static int launch_wg_inst(const Geo &g, const CGFields &f, const int *chains, int n, int block,
+                          double tol, double delta, int max_iter, size_t lds, hipStream_t s) {
+    static size_t granted = 64 * 1024;  // dynamic LDS available without opting in
+    if (lds > granted) {
+        if (hipFuncSetAttribute((const void *)k_cg_wg<MIXED, SPT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+            (void)hipGetLastError();  // clear the error state: the caller falls back
+            return -1;
+        }
+        granted = lds;
+    }
+    hipLaunchKernelGGL((k_cg_wg<MIXED, SPT>), dim3(n), dim3(block), lds, s, g, f, chains, tol * tol,
+                       delta * delta, max_iter);
+    return 0;
+}
+
+size_t cg_wg_lds_bytes(int vmax, bool mixed) {
+    return (size_t)4 * vmax * (mixed ? sizeof(float2) : sizeof(double2));
+}
+
+int launch_cg_wg(const Geo &g, const CGFields &f, bool mixed, const int *chains, int n, int vmax,
+                 double tol, double delta, int max_iter, hipStream_t s) {
+    if (n <= 0) return 0;
+    const size_t lds = cg_wg_lds_bytes(vmax, mixed);
+    // threads: the chain's sites over at most 4 per thread, in whole wavefronts
+    int spt = 1;
+    while ((vmax + spt - 1) / spt > 1024) spt *= 2;
+    if (spt > 2) return -1;
+    int block = (vmax + spt - 1) / spt;
+    block = (block + 63) / 64 * 64;
+    if (mixed) {
+        if (spt == 1) return launch_wg_inst<true, 1>(g, f, chains, n, block, tol, delta, max_iter, lds, s);
+        return launch_wg_inst<true, 2>(g, f, chains, n, block, tol, delta, max_iter, lds, s);
+    }
+    if (spt == 1) return launch_wg_inst<false, 1>(g, f, chains, n, block, tol, delta, max_iter, lds, s);
+    return launch_wg_inst<false, 2>(g, f, chains, n, block, tol, delta, max_iter, lds, s);
+}
+
 // Order-preserving compaction of the workgroups of unconverged chains (one workgroup).
 // A chain is dropped once either state parity says converged (a chain leaves the grid
 // right after convergence, so its other parity may still hold the state before it).
 // count[1] receives the number of unconverged chains that still have iterations left
 // (iters < max_iter).
 __global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGState *__restrict__ st,
-                          int nchains, int max_iter, BlockWork *__restrict__ out, int *count) {
+                          const ChainInfo *__restrict__ chains, int nchains, int max_iter,
+                          BlockWork *__restrict__ out, int *count) {
     __shared__ int wave_cnt[kMaxWaves];
     __shared__ int base;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -517,7 +759,9 @@ __global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGSta
         __syncthreads();
     }
     double live[1] = {0.0};
-    for (int c = threadIdx.x; c < nchains; c += blockDim.x) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int c = work[i].chain;
+        if (work[i].logical != chains[c].block0) continue;  // count each chain once
         if (!st[c].converged && !st[nchains + c].converged &&
             (st[c].iters < max_iter || st[nchains + c].iters < max_iter))
             live[0] += 1.0;
@@ -532,7 +776,7 @@ __global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGSta
 void launch_compact(const Geo &full, const CGState *st, int max_iter, BlockWork *out, int *count,
                     hipStream_t s) {
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, full.work, full.nblocks, st,
-                       full.nchains, max_iter, out, count);
+                       full.chains, full.nchains, max_iter, out, count);
 }
 
 __global__ void k_count_converged(const CGState *__restrict__ st, int n, int *out) {

@@ -83,6 +83,11 @@ void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s);
 // count[1] = unconverged chains with iterations left (< max_iter).
 void launch_compact(const Geo &full, const CGState *st, int max_iter, BlockWork *out, int *count,
                     hipStream_t s);
+// Persistent solver: one workgroup per chain of chains[0..n), each with at most vmax sites
+// (LDS holds p and t: 4 * vmax complex).  Returns -1 if vmax does not fit.
+size_t cg_wg_lds_bytes(int vmax, bool mixed);
+int launch_cg_wg(const Geo &g, const CGFields &f, bool mixed, const int *chains, int n, int vmax,
+                 double tol, double delta, int max_iter, hipStream_t s);
 // Number of converged chains in one state parity -> *out.
 void launch_count_converged(const CGState *st_par, int n, int *out, hipStream_t s);
 

@@ -33,13 +33,15 @@ def rel(a, b):
 class Batch:
     """A Lattice plus numpy<->native helpers for a list of (Lx, Lt, beta, m0)."""
 
-    def __init__(self, shapes, seed=0):
+    def __init__(self, shapes, seed=0, persistent=None):
         m = hmc()
         Lx = [s[0] for s in shapes]
         Lt = [s[1] for s in shapes]
         beta = [s[2] if len(s) > 2 else 2.0 for s in shapes]
         m0 = [s[3] if len(s) > 3 else 0.1 for s in shapes]
         self.lat = m.Lattice.batch(Lx, Lt, beta, m0, seed=seed)
+        if persistent is not None:
+            self.lat.set_persistent_limit(persistent)
         self.shapes = list(zip(Lx, Lt, beta, m0))
 
     def links_to_native(self, arrays, out=None):
@@ -162,9 +164,14 @@ def test_gauge_force_and_action_parity(Lx, Lt):
 
 
 # ------------------------------------------------------------------ solver and fermion force
-@pytest.mark.parametrize("Lx,Lt,m0", [(4, 4, 0.1), (8, 8, 0.1), (6, 10, 0.05), (34, 18, 0.1)])
-def test_cg_parity(Lx, Lt, m0):
-    b = Batch([(Lx, Lt, 2.0, m0)])
+SOLVERS = [0, 2048]  # persistent limit: 0 = multi-workgroup slot kernels only
+
+
+@pytest.mark.parametrize("persistent", SOLVERS)
+@pytest.mark.parametrize("Lx,Lt,m0", [(4, 4, 0.1), (8, 8, 0.1), (6, 10, 0.05), (34, 18, 0.1),
+                                      (32, 32, 0.1), (64, 32, 0.1)])
+def test_cg_parity(Lx, Lt, m0, persistent):
+    b = Batch([(Lx, Lt, 2.0, m0)], persistent=persistent)
     q = inputs.random_angles(Lx, Lt, 31)
     phi = inputs.random_spinor(Lx, Lt, 32)
     b.set_q([q])
@@ -175,9 +182,10 @@ def test_cg_parity(Lx, Lt, m0):
     assert rel(b.spinor_from_native(x)[0], xr) < 1e-10
 
 
+@pytest.mark.parametrize("persistent", SOLVERS)
 @pytest.mark.parametrize("Lx,Lt,m0", [(8, 8, 0.1), (6, 10, 0.05), (32, 32, 0.1)])
-def test_fermion_force_parity(Lx, Lt, m0):
-    b = Batch([(Lx, Lt, 2.0, m0)])
+def test_fermion_force_parity(Lx, Lt, m0, persistent):
+    b = Batch([(Lx, Lt, 2.0, m0)], persistent=persistent)
     q = inputs.random_angles(Lx, Lt, 41)
     phi = inputs.random_spinor(Lx, Lt, 42)
     b.set_q([q])
@@ -219,8 +227,9 @@ def test_fg_shifted_force_parity(which):
     assert rel(b.links_from_native(F)[0], ref) < 1e-10
 
 
-def test_zero_source_and_nonconvergence():
-    b = Batch([(8, 8)])
+@pytest.mark.parametrize("persistent", SOLVERS)
+def test_zero_source_and_nonconvergence(persistent):
+    b = Batch([(8, 8)], persistent=persistent)
     b.set_q([inputs.random_angles(8, 8, 1)])
     x, res = b.lat.cg_solve(b.lat.new_spinor(), tol=1e-12)
     assert res.converged[0] and res.iters[0] == 0 and float(x.abs().max()) == 0.0
@@ -278,11 +287,12 @@ def test_plain_method_8x8_omelyan():
         assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - qr)) < 1e-9
 
 
+@pytest.mark.parametrize("persistent", SOLVERS)
 @pytest.mark.parametrize("scheme,n_outer,n_inner", [
     ("leapfrog", 16, 1), ("force_gradient", 4, 1), ("nested_fg", 4, 2), ("adapted_nested_fg", 4, 2)])
-def test_trajectory_parity_all_schemes(scheme, n_outer, n_inner):
+def test_trajectory_parity_all_schemes(scheme, n_outer, n_inner, persistent):
     seed = 77
-    b = Batch([(8, 8, 2.0, 0.1)], seed=seed)
+    b = Batch([(8, 8, 2.0, 0.1)], seed=seed, persistent=persistent)
     b.lat.hot_start()
     b.lat.set_solver(tol=1e-13)
     ref = run_oracle_chain(8, 8, 2.0, 0.1, seed, 0, 3, scheme, 1.0, n_outer, n_inner, 1e-13)
@@ -305,10 +315,12 @@ def test_inversion_counts_per_step():
         assert r.n_solves <= r.n_force_evals + 1
 
 
-def test_batched_trajectories_match_single_chain_oracle():
+@pytest.mark.parametrize("persistent", [0, 64, 2048])
+def test_batched_trajectories_match_single_chain_oracle(persistent):
+    # with limit 64 the 8x8 chain runs in the slot kernels while the others run persistent
     shapes = [(8, 8, 2.0, 0.1), (4, 6, 1.5, 0.2), (6, 4, 3.0, 0.05), (2, 2, 1.0, 0.15)]
     seed = 31337
-    b = Batch(shapes, seed=seed)
+    b = Batch(shapes, seed=seed, persistent=persistent)
     b.lat.hot_start()
     b.lat.set_solver(tol=1e-13)
     refs = [run_oracle_chain(s[0], s[1], s[2], s[3], seed, c, 3, "adapted_nested_fg", 1.0, 4, 2, 1e-13)
@@ -334,9 +346,10 @@ def test_trajectory_is_bitwise_reproducible():
 
 
 # ------------------------------------------------------------------ mixed precision
-@pytest.mark.parametrize("Lx,m0", [(16, 0.1), (64, 0.05)])
-def test_mixed_cg_reaches_fp64_residual(Lx, m0):
-    b = Batch([(Lx, Lx, 4.0, m0)])
+@pytest.mark.parametrize("persistent", SOLVERS)
+@pytest.mark.parametrize("Lx,m0", [(16, 0.1), (32, 0.05), (64, 0.05)])
+def test_mixed_cg_reaches_fp64_residual(Lx, m0, persistent):
+    b = Batch([(Lx, Lx, 4.0, m0)], persistent=persistent)
     q = inputs.smooth_angles(Lx, Lx, 71, 0.3)
     phi = inputs.random_spinor(Lx, Lx, 72)
     b.set_q([q])
@@ -346,9 +359,10 @@ def test_mixed_cg_reaches_fp64_residual(Lx, m0):
     assert rel(b.spinor_from_native(x)[0], b.spinor_from_native(x64)[0]) < 1e-7
 
 
-def test_mixed_trajectory_matches_fp64_oracle():
+@pytest.mark.parametrize("persistent", SOLVERS)
+def test_mixed_trajectory_matches_fp64_oracle(persistent):
     seed = 404
-    b = Batch([(16, 16, 4.0, 0.05)], seed=seed)
+    b = Batch([(16, 16, 4.0, 0.05)], seed=seed, persistent=persistent)
     b.lat.hot_start()
     b.lat.set_solver(tol=1e-12)
     ref = run_oracle_chain(16, 16, 4.0, 0.05, seed, 0, 2, "adapted_nested_fg", 1.0, 8, 4, 1e-12)
