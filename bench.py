@@ -47,8 +47,11 @@ def run_batched(args):
     lat = hmc.Lattice.batch(L, L, beta, m0, seed=args.seed)
     lat.hot_start()
     lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=0.1)
-    for _ in range(args.warmup):
+    tune = None
+    for w in range(args.warmup):
         lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+        if w == 0 and not args.no_tune:
+            tune = lat.autotune("mixed", 1e-10)
     torch.cuda.synchronize()
     lat.set_timing(not args.no_timing)
     acc, status, iters, force_evals, solves = [], [], 0, 0, 0
@@ -64,7 +67,7 @@ def run_batched(args):
     dt = time.perf_counter() - t0
     s1, s2 = lat.kernel_stats(0), lat.kernel_stats(1)
     lat.set_timing(False)
-    return dict(L=L, dt=dt, acc=acc, status=status, s1=s1, s2=s2, sites=lat.V_total,
+    return dict(L=L, dt=dt, acc=acc, status=status, s1=s1, s2=s2, sites=lat.V_total, tune=tune,
                 n_chains=lat.n_chains, force_evals=force_evals, solves=solves,
                 cg_iters_per_traj=iters / max(1, args.steps))
 
@@ -76,8 +79,10 @@ def run_single_fp64(args):
     lat = hmc.Lattice(32, 2.0, 0.1, seed=args.seed)
     lat.hot_start()
     lat.set_solver(tol=1e-12)
-    for _ in range(2):
+    for w in range(2):
         lat.trajectory("adapted_nested_fg", 1.0, 8, 4)
+        if w == 0 and not args.no_tune:
+            lat.autotune("fp64", 1e-12)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     acc = []
@@ -148,6 +153,7 @@ def main():
     ap.add_argument("--single-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket the CG kernels with events (roofline figure omitted)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -197,6 +203,7 @@ def main():
             "n_chains": b["n_chains"], "sites": b["sites"], "scheme": "adapted_nested_fg",
             "parallelism": "single GPU, chains batched in every launch",
         },
+        "autotune": b["tune"],
         "acceptance": round(sum(b["acc"]) / len(b["acc"]), 4),
         "chain_failures": sum(1 for s in b["status"] if s != 0),
         "cg_iters_per_step": b["cg_iters_per_traj"],

@@ -170,6 +170,21 @@ int hmc_set_check_interval(hmc_ctx *ctx, int every);
  * handle the larger chains; 0 disables it.  Default and maximum 2048. */
 int hmc_set_persistent_limit(hmc_ctx *ctx, int vmax);
 
+/* Threads per workgroup of the site kernels (128..1024, multiple of 64; default 256). */
+int hmc_set_block_size(hmc_ctx *ctx, int block);
+
+/* Autotuner: times CG solves of this context's own chains at its current links (with a
+ * fresh pseudofermion; p and phi are overwritten) for workgroup sizes {128, 256, 512} and
+ * each applicable persistent-solver limit {0, 1024, 2048}, and keeps the fastest. */
+typedef struct {
+    int block;             /* chosen workgroup size */
+    int persistent_limit;  /* chosen persistent-solver limit (sites) */
+    double solve_ms;       /* mean time of one solve with that choice */
+    int candidates;        /* configurations timed */
+    int pad;
+} hmc_tune_info;
+int hmc_autotune(hmc_ctx *ctx, int prec, double tol, hmc_tune_info *out);
+
 /* ---------------------------------------------------------------- operators (Sec. 3) */
 
 /* out = D in: (D psi)(n) = (2+m0) psi(n) - 1/2 sum_mu [(1 - sigma_mu) U_mu(n) psi(n+mu)

@@ -233,6 +233,17 @@ class Lattice:
         """Chains of at most vmax sites solve inside one persistent workgroup (0: never)."""
         self._check(self._lib.hmc_set_persistent_limit(self._ctx, int(vmax)))
 
+    def set_block_size(self, block: int):
+        self._check(self._lib.hmc_set_block_size(self._ctx, int(block)))
+
+    def autotune(self, prec="fp64", tol=1e-10) -> dict:
+        """Times solves over workgroup sizes and persistent-solver limits; keeps the fastest.
+        Overwrites p and phi (not q)."""
+        t = _lib.TuneInfo()
+        self._check(self._lib.hmc_autotune(self._ctx, _prec(prec), tol, ctypes.byref(t)))
+        return {"block": t.block, "persistent_limit": t.persistent_limit, "solve_ms": t.solve_ms,
+                "candidates": t.candidates}
+
     def set_check_interval(self, every: int):
         self._check(self._lib.hmc_set_check_interval(self._ctx, int(every)))
 

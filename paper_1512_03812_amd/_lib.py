@@ -32,6 +32,11 @@ class TrajInfo(ctypes.Structure):
                 ("n_cg_iters", ctypes.c_longlong)]
 
 
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("persistent_limit", ctypes.c_int),
+                ("solve_ms", ctypes.c_double), ("candidates", ctypes.c_int), ("pad", ctypes.c_int)]
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_longlong), ("timed_launches", ctypes.c_longlong),
                 ("timed_ms", ctypes.c_double), ("timed_bytes", ctypes.c_double),
@@ -61,6 +66,8 @@ SIGNATURES = {
     "hmc_set_quenched": (_I, [_P, _I]),
     "hmc_set_check_interval": (_I, [_P, _I]),
     "hmc_set_persistent_limit": (_I, [_P, _I]),
+    "hmc_set_block_size": (_I, [_P, _I]),
+    "hmc_autotune": (_I, [_P, _I, _D, _P]),
     "hmc_dslash": (_I, [_P, _P, _P]),
     "hmc_dslash_dagger": (_I, [_P, _P, _P]),
     "hmc_cg_solve": (_I, [_P, _P, _P, _D, _I, _I, _P]),

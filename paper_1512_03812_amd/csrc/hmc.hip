@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -60,6 +61,7 @@ struct hmc_ctx {
     int nchains = 0;
     int Vtot = 0;
     int block = 256;
+    int nlog_max = 0;  // workgroups of the table at the smallest workgroup size
     std::vector<ChainInfo> chains;
     std::vector<BlockWork> work;
     uint64_t seed = 0;
@@ -180,10 +182,13 @@ void build_tables(hmc_ctx *c) {
     for (int h = 0; h < N; ++h) c->work[h] = logical[start[h % kNumXcd] + h / kNumXcd];
 }
 
-void layout_workspace(hmc_ctx *c) {
+// Per-workgroup arrays are sized for the smallest workgroup the tuner may choose.
+constexpr int kMinBlock = 128;
+
+void layout_workspace(hmc_ctx *c, size_t N) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
-    const size_t C = c->nchains, N = c->work.size(), V = c->Vtot;
+    const size_t C = c->nchains, V = c->Vtot;
     c->off_chains = take(sizeof(ChainInfo) * C);
     c->off_work = take(sizeof(BlockWork) * N);
     c->off_active = take(sizeof(BlockWork) * N);
@@ -235,8 +240,12 @@ int make_ctx(hmc_ctx **out, int n, const int *Lx, const int *Lt, const double *b
         off += ci.V;
     }
     c->Vtot = off;
+    c->block = kMinBlock;
     build_tables(c);
-    layout_workspace(c);
+    c->nlog_max = (int)c->work.size();
+    c->block = 256;
+    build_tables(c);
+    layout_workspace(c, (size_t)c->nlog_max);
     c->cg_host.resize(n);
     *out = c;
     return HMC_OK;
@@ -676,9 +685,26 @@ void init_md(MD &md, hmc_ctx *c, int prec) {
     forget_links(c);
 }
 
+// Rebuilds the workgroup tables for another workgroup size and uploads them.
+int set_block(hmc_ctx *c, int block) {
+    if (block < kMinBlock || block > 1024 || block % 64) return fail(c, HMC_E_INVAL, "bad workgroup size");
+    if (block == c->block) return HMC_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->block = block;
+    build_tables(c);
+    HIP_TRY(c, hipMemcpyAsync(c->at<ChainInfo>(c->off_chains), c->chains.data(),
+                              sizeof(ChainInfo) * c->nchains, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->at<BlockWork>(c->off_work), c->work.data(),
+                              sizeof(BlockWork) * c->work.size(), hipMemcpyHostToDevice, c->stream));
+    c->part_vmax = -1;
+    return sync(c);
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
+static void refresh(hmc_ctx *c);
+
 extern "C" {
 
 int hmc_init(hmc_ctx **out, int L, double beta, double m0, uint64_t seed) {
@@ -842,6 +868,68 @@ int hmc_set_quenched(hmc_ctx *c, int quenched) {
 int hmc_set_persistent_limit(hmc_ctx *c, int vmax) {
     if (!c || vmax < 0) return HMC_E_INVAL;
     c->persist_vmax = vmax;
+    return HMC_OK;
+}
+
+int hmc_set_block_size(hmc_ctx *c, int block) {
+    CHECK_BOUND(c);
+    return set_block(c, block);
+}
+
+int hmc_autotune(hmc_ctx *c, int prec, double tol, hmc_tune_info *out) {
+    CHECK_BOUND(c);
+    if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
+    if (!(tol > 0)) return fail(c, HMC_E_INVAL, "bad tolerance");
+    // a realistic right-hand side at the current links: phi = D^dagger zeta
+    forget_all(c);
+    refresh(c);
+    std::vector<int> persist = {0};
+    int vmin = 1 << 30;
+    for (const ChainInfo &ci : c->chains) vmin = std::min(vmin, ci.V);
+    if (vmin <= 1024) persist.push_back(1024);
+    for (const ChainInfo &ci : c->chains)
+        if (ci.V > 1024 && ci.V <= 2048) { persist.push_back(2048); break; }
+    const int blocks[3] = {128, 256, 512};
+    const int saved_block = c->block, saved_persist = c->persist_vmax;
+    double best = 1e300;
+    int best_block = saved_block, best_persist = saved_persist, n = 0;
+    for (int b : blocks) {
+        int rc = set_block(c, b);
+        if (rc) return rc;
+        for (int pv : persist) {
+            c->persist_vmax = pv;
+            ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, -1);
+            rc = solve(c, c->spin(SPHI), c->spin(SXI), tol, c->max_iter, prec);  // warm-up
+            if (rc && rc != HMC_E_NOCONV) return rc;
+            const auto t0 = std::chrono::steady_clock::now();
+            for (int rep = 0; rep < 2; ++rep) {
+                rc = solve(c, c->spin(SPHI), c->spin(SXI), tol, c->max_iter, prec);
+                if (rc && rc != HMC_E_NOCONV) return rc;
+            }
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / 2;
+            ++n;
+            if (ms < best) {
+                best = ms;
+                best_block = b;
+                best_persist = pv;
+            }
+        }
+    }
+    int rc = set_block(c, best_block);
+    if (rc) return rc;
+    c->persist_vmax = best_persist;
+    c->part_vmax = -1;
+    forget_all(c);
+    if (out) {
+        out->block = best_block;
+        out->persistent_limit = best_persist;
+        out->solve_ms = best;
+        out->candidates = n;
+        out->pad = 0;
+    }
+    (void)saved_block;
+    (void)saved_persist;
     return HMC_OK;
 }
 

@@ -335,6 +335,31 @@ def test_batched_trajectories_match_single_chain_oracle(persistent):
             assert np.max(np.abs(qs[c] - qr)) < 1e-9
 
 
+@pytest.mark.parametrize("block", [128, 512])
+def test_other_workgroup_sizes_keep_parity(block):
+    shapes = [(8, 8, 2.0, 0.1), (34, 18, 1.5, 0.2), (64, 64, 2.0, 0.1)]
+    b = Batch(shapes, persistent=0)
+    b.lat.set_block_size(block)
+    q = [inputs.random_angles(s[0], s[1], 90 + i) for i, s in enumerate(shapes)]
+    phi = [inputs.random_spinor(s[0], s[1], 95 + i) for i, s in enumerate(shapes)]
+    b.set_q(q)
+    f, sf, res = b.lat.fermion_force(b.spinor_to_native(phi), tol=1e-14)
+    got = b.links_from_native(f)
+    for i, s in enumerate(shapes):
+        fr = oracle.fermion_force(q[i], phi[i], s[3], tol=1e-14)[0]
+        assert rel(got[i], fr) < 1e-10
+
+
+def test_autotune_picks_a_valid_configuration():
+    b = Batch([(16, 16, 2.0, 0.1), (32, 32, 3.0, 0.05), (64, 64, 2.0, 0.1)], seed=3)
+    b.lat.hot_start()
+    t = b.lat.autotune("mixed", 1e-10)
+    assert t["block"] in (128, 256, 512) and t["persistent_limit"] in (0, 1024, 2048)
+    assert t["candidates"] >= 3 and t["solve_ms"] > 0
+    r = b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2, prec="mixed")
+    assert all(s == 0 for s in r.status)
+
+
 def test_trajectory_is_bitwise_reproducible():
     out = []
     for _ in range(2):
