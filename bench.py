@@ -143,6 +143,64 @@ def cpu_baseline(args):
             "seconds_per_chain_traj_by_L": {str(k): round(v, 3) for k, v in per_L.items()}}
 
 
+def run_sweep(args):
+    """Roofline sweep on single large lattices (beta 2, m0 0.1, hot start): FP64 dslash,
+    and CG iterations in FP64 and in mixed precision (64 iteration slots, sampled events),
+    beside a plain device copy of 2 GiB as the measured bandwidth ceiling."""
+    import torch
+    import paper_1512_03812_amd as hmc
+    out = {"metric": "Dslash and CG iteration achieved HBM GB/s (single large lattices)",
+           "unit": "GB/s", "peak": HBM_PEAK_GBS, "sizes": []}
+    n = 1 << 30
+    a = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_ceiling_gbs"] = round(2 * n * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b
+    for L in args.sweep_sizes:
+        lat = hmc.Lattice(L, 2.0, 0.1, seed=args.seed)
+        lat.hot_start()
+        V = lat.V_total
+        psi = torch.randn(2, V, dtype=torch.complex128, device="cuda")
+        dst = lat.new_spinor()
+        for _ in range(3):
+            lat.dslash(psi, out=dst)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        reps = 20
+        torch.cuda.synchronize()
+        ev[0].record(lat.stream)
+        for _ in range(reps):
+            lat.dslash(psi, out=dst)
+        ev[1].record(lat.stream)
+        torch.cuda.synchronize()
+        us = 1e3 * ev[0].elapsed_time(ev[1]) / reps
+        row = {"L": L, "sites": V, "dslash64_us": round(us, 2),
+               "dslash64_gbs": round(96 * V / (us * 1e-6) / 1e9, 1)}
+        for prec in ("fp64", "mixed"):
+            lat.set_persistent_limit(0)
+            lat.set_timing(True)
+            lat.cg_solve(psi, tol=1e-30, max_iter=64, prec=prec)
+            s1, s2 = lat.kernel_stats(0), lat.kernel_stats(1)
+            lat.set_timing(False)
+            t1, t2 = s1["timed_ms"] * 1e-3, s2["timed_ms"] * 1e-3
+            row[f"cg_{prec}_step1_gbs"] = round(s1["timed_bytes"] / t1 / 1e9, 1)
+            row[f"cg_{prec}_step2_gbs"] = round(s2["timed_bytes"] / t2 / 1e9, 1)
+            row[f"cg_{prec}_iter_us"] = round(1e6 * (t1 + t2) / max(1, s2["timed_launches"]), 2)
+            row[f"cg_{prec}_iter_gbs"] = round((s1["timed_bytes"] + s2["timed_bytes"]) / (t1 + t2) / 1e9, 1)
+        out["sizes"].append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        del lat, psi, dst
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +212,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--sweep", action="store_true",
+                    help="roofline sweep on single large lattices instead of the HMC benchmark")
+    ap.add_argument("--sweep-sizes", type=int, nargs="+", default=[256, 512, 1024, 2048, 4096, 8192])
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket the CG kernels with events (roofline figure omitted)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -167,6 +228,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        run_sweep(args)
+        return
 
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20)

@@ -72,6 +72,7 @@ def lib():
             "orc_gauge_force": (None, [I, I, D, P, P]),
             "orc_dirac": (None, [I, I, D, P, P, P]),
             "orc_dirac_dagger": (None, [I, I, D, P, P, P]),
+            "orc_dirac_sites": (None, [I, I, D, P, P, I, P, P]),
             "orc_cg": (I, [I, I, D, P, P, P, D, I, P]),
             "orc_fermion_force_chixi": (None, [I, I, P, P, P, P]),
             "orc_fermion_force": (I, [I, I, D, P, P, D, I, P, P, P, P]),
@@ -170,6 +171,15 @@ def dirac(q, psi, m0) -> np.ndarray:
     q, psi = _links(q), _spinor(psi)
     out = np.zeros_like(psi)
     lib().orc_dirac(q.shape[1], q.shape[0], m0, _p(q), _p(psi), _p(out))
+    return out
+
+
+def dirac_sites(q, psi, m0, sites) -> np.ndarray:
+    """(D psi) at the lexicographic sites n = x + Lx t listed in `sites`; shape (len, 2)."""
+    q, psi = _links(q), _spinor(psi)
+    idx = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.zeros((idx.size, 2), dtype=np.complex128)
+    lib().orc_dirac_sites(q.shape[1], q.shape[0], m0, _p(q), _p(psi), int(idx.size), _p(idx), _p(out))
     return out
 
 

@@ -286,6 +286,32 @@ void orc_dirac(int Lx, int Lt, double m0, const double *q, const cplx *in, cplx 
 }
 
 /*
+ * (D psi) at the listed sites only (lexicographic indices sites[0..ns)), out[2*k + s]:
+ * the same definition as orc_dirac, evaluated one site at a time for sampled checks on
+ * lattices too large to sweep.
+ */
+void orc_dirac_sites(int Lx, int Lt, double m0, const double *q, const cplx *in, int ns,
+                     const long long *sites, cplx *out)
+{
+    for (int k = 0; k < ns; ++k) {
+        int n = (int)sites[k];
+        cplx acc[2] = {(2.0 + m0) * in[2 * n], (2.0 + m0) * in[2 * n + 1]};
+        for (int mu = 0; mu < 2; ++mu) {
+            int nf = hop(n, mu, +1, Lx, Lt), nb = hop(n, mu, -1, Lx, Lt);
+            cplx uf = flink(q, n, mu, Lx, Lt), ub = conj(flink(q, nb, mu, Lx, Lt));
+            cplx vf[2] = {uf * in[2 * nf], uf * in[2 * nf + 1]};
+            cplx vb[2] = {ub * in[2 * nb], ub * in[2 * nb + 1]};
+            cplx pf[2], pb[2];
+            proj(mu, -1, vf, pf);
+            proj(mu, +1, vb, pb);
+            for (int a = 0; a < 2; ++a) acc[a] -= 0.5 * (pf[a] + pb[a]);
+        }
+        out[2 * k] = acc[0];
+        out[2 * k + 1] = acc[1];
+    }
+}
+
+/*
  * D^dagger as the literal conjugate transpose of D_{n,m}: the forward hop carries
  * (1 + sigma_mu) U_mu(n), the backward hop (1 - sigma_mu) U_mu^dagger(n - mu)
  * (sigma_mu is hermitian).  gamma5-hermiticity D^dagger = sigma_3 D sigma_3 is

@@ -62,6 +62,7 @@ struct hmc_ctx {
     int Vtot = 0;
     int block = 256;
     int nlog_max = 0;  // workgroups of the table at the smallest workgroup size
+    bool has_large = false;  // some chain has more than kMaxChainBlocks workgroups
     std::vector<ChainInfo> chains;
     std::vector<BlockWork> work;
     uint64_t seed = 0;
@@ -79,7 +80,7 @@ struct hmc_ctx {
     hipStream_t stream = nullptr;
     size_t off_chains = 0, off_work = 0, off_active = 0, off_big = 0, off_small = 0, off_cg = 0,
            off_partials = 0,
-           off_sums = 0, off_metro = 0, off_status = 0, off_count = 0, off_links[kNumLinkBufs] = {},
+           off_sums = 0, off_fin = 0, off_metro = 0, off_status = 0, off_count = 0, off_links[kNumLinkBufs] = {},
            off_spin[kNumSpinBufs] = {}, off_U64 = 0, off_U32 = 0, off_spin32[kNumSpin32Bufs] = {};
     // ------------------------------------------------------------ solver partition
     hipStream_t side = nullptr;           // second stream for the persistent solver
@@ -151,21 +152,20 @@ int fail(hmc_ctx *c, int code, const char *fmt, ...) {
         if (!(ctx)->ws) return fail(ctx, HMC_E_INVAL, "context has no workspace bound");        \
     } while (0)
 
-// Block table: every chain gets ceil(V / (block * spt)) logical workgroups (chains
-// contiguous in logical order), with spt sites per thread chosen so that no chain has
-// more than kMaxChainBlocks workgroups (a consumer workgroup re-adds all of its chain's
-// partials).  Hardware workgroup h runs on XCD h % 8, and the j-th workgroup of XCD k
-// receives logical workgroup start_k + j, so each XCD sweeps one contiguous site range.
-constexpr int kMaxChainBlocks = 2048;
-
+// Block table: every chain gets ceil(V / block) logical workgroups, one site per thread
+// (chains contiguous in logical order).  Hardware workgroup h runs on XCD h % 8, and the
+// j-th workgroup of XCD k receives logical workgroup start_k + j, so each XCD sweeps one
+// contiguous site range and the workgroups resident on it at any time cover a few
+// consecutive lattice rows: the t +- 1 stencil rows are L2 hits.
 void build_tables(hmc_ctx *c) {
     std::vector<BlockWork> logical;
+    c->has_large = false;
     for (int ch = 0; ch < c->nchains; ++ch) {
         ChainInfo &ci = c->chains[ch];
-        const long long per = (long long)c->block * kMaxChainBlocks;
-        const int spt = (int)((ci.V + per - 1) / per);
+        const int spt = 1;
         ci.block0 = (int)logical.size();
         ci.nblocks = (ci.V + c->block * spt - 1) / (c->block * spt);
+        if (ci.nblocks > kMaxChainBlocks) c->has_large = true;
         for (int j = 0; j < ci.nblocks; ++j) {
             BlockWork w;
             w.chain = ch;
@@ -197,6 +197,7 @@ void layout_workspace(hmc_ctx *c, size_t N) {
     c->off_cg = take(sizeof(CGState) * 2 * C);
     c->off_partials = take(sizeof(double) * kMaxReduce * N);
     c->off_sums = take(sizeof(double) * 16 * C);
+    c->off_fin = take(sizeof(double) * 2 * C);
     c->off_metro = take(sizeof(MetroOut) * C);
     c->off_status = take(sizeof(int) * C);
     c->off_count = take(sizeof(int) * 4);
@@ -438,6 +439,8 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     f.U32 = c->U32();
     f.p1 = c->partials();
     f.p2 = c->partials() + full.nlog;
+    f.fin1 = c->at<double>(c->off_fin);
+    f.fin2 = f.fin1 + c->nchains;
     f.st = c->cg();
     void *pb[2];
     if (mixed) { pb[0] = c->spin32(FPA); pb[1] = c->spin32(FPB); }
@@ -465,6 +468,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     int slot = 0;
     if (big.nblocks > 0) {
     launch_cg_init(big, f, mixed, c->delta, c->stream);
+    if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
     // iteration slots: CG iterations plus, in mixed precision, FP64 residual recomputations
     const int max_slots = mixed ? max_iter + max_iter / 2 + 64 : max_iter;
     // Convergence checks: the first after check_every slots; the interval doubles (up to
@@ -473,8 +477,14 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     for (; slot < max_slots; ++slot) {
         void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
         slot_launch(c, slot, mixed,
-                    [&] { launch_cg_step1(g, f, mixed, slot, tol, po, pn, false, c->stream); },
-                    [&] { launch_cg_step2(g, f, mixed, slot, pn, c->stream); });
+                    [&] {
+                        launch_cg_step1(g, f, mixed, slot, tol, po, pn, false, c->stream);
+                        if (c->has_large) launch_finalize_large(big, f.p1, f.fin1, c->stream);
+                    },
+                    [&] {
+                        launch_cg_step2(g, f, mixed, slot, pn, c->stream);
+                        if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
+                    });
         if (slot + 1 == next_check) {
             int active = 0, live = 0;
             if ((rc = check_convergence(c, big, mixed ? max_iter : max_slots, &active, &live))) return rc;

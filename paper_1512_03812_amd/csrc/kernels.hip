@@ -55,12 +55,30 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *partials
     }
 }
 
-// The chain's total of one partial row, identical in every workgroup of the chain.
-__device__ __forceinline__ double chain_total(const double *__restrict__ row, const ChainInfo &ci) {
+// The chain's total of one partial row, identical in every workgroup of the chain: re-added
+// here for chains of at most kMaxChainBlocks workgroups, else read from fin (written by
+// k_finalize_large after the producer).
+__device__ __forceinline__ double chain_total(const double *__restrict__ row,
+                                              const double *__restrict__ fin, const ChainInfo &ci,
+                                              int chain) {
+    if (ci.nblocks > kMaxChainBlocks) return fin[chain];
     double a[1] = {0.0};
     for (int j = threadIdx.x; j < ci.nblocks; j += blockDim.x) a[0] += row[ci.block0 + j];
     block_sum_all<1>(a);
     return a[0];
+}
+
+__global__ void k_finalize_large(Geo g, const double *__restrict__ row, double *fin) {
+    const ChainInfo ci = g.chains[blockIdx.x];
+    if (ci.nblocks <= kMaxChainBlocks) return;
+    double v[1] = {0.0};
+    for (int j = threadIdx.x; j < ci.nblocks; j += blockDim.x) v[0] += row[ci.block0 + j];
+    block_sum_all<1>(v);
+    if (threadIdx.x == 0) fin[blockIdx.x] = v[0];
+}
+
+void launch_finalize_large(const Geo &g, const double *row, double *fin, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_large, dim3(g.nchains), dim3(1024), 0, s, g, row, fin);
 }
 
 template <int NV> __global__ void k_finalize(Geo g, const double *__restrict__ partials, double *out) {
@@ -278,7 +296,7 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     const int p_mode = prev->mode, p_iters = prev->iters, p_nupd = prev->n_updates;
     const double p_rho = prev->rho, p_rho_p = prev->rho_p, p_target = prev->target;
     const double p_phi2 = prev->phi2, p_rmax2 = prev->rmax2, delta2 = prev->delta2;
-    const double rho = chain_total(f.p2, ci);
+    const double rho = chain_total(f.p2, f.fin2, ci, w.chain);
     double n_rho = rho, n_rho_p = p_rho_p, n_target = p_target, n_phi2 = p_phi2, n_rmax2 = p_rmax2;
     double n_beta = 0.0;
     int n_iters = p_iters, n_nupd = p_nupd, n_conv = 0;
@@ -401,7 +419,7 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
         write_partials<1>(v, f.p2, g.nlog, w.logical);
         return;
     }
-    const double pAp = chain_total(f.p1, ci);
+    const double pAp = chain_total(f.p1, f.fin1, ci, w.chain);
     const R alpha = (R)(s_rho / pAp);
     const C *__restrict__ p = (const C *)p_new_v;
     const C *__restrict__ t;

@@ -40,6 +40,9 @@ enum { kModeInit = 0, kModeNormal = 1, kModeUpdate = 2 };
 
 // Partial sums: row k of partials holds one double per logical workgroup.
 constexpr int kMaxReduce = 8;
+// A consumer workgroup re-adds its chain's partials itself when the chain has at most this
+// many workgroups; larger chains get their totals from a finalize kernel instead.
+constexpr int kMaxChainBlocks = 2048;
 
 // ---------------------------------------------------------------- layout
 // to_native: nat <- lex, else lex <- nat
@@ -64,6 +67,7 @@ struct CGFields {
     const double2 *U64;
     const float2 *U32;
     double *p1, *p2;          // partial rows: ||D p||^2 (step 1) and ||r||^2 (step 2)
+    double *fin1, *fin2;      // per-chain totals of p1, p2 for chains above kMaxChainBlocks
     CGState *st;              // [2][nchains]
 };
 // x = 0, r = phi, partial ||phi||^2 -> p2, state[1] = initial.
@@ -77,6 +81,8 @@ void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, doub
 // D^dagger t with partial ||r||^2 (or the FP64 residual recomputation).
 void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
                      hipStream_t s);
+// fin[c] = sum of row's partials of chain c, for the chains above kMaxChainBlocks.
+void launch_finalize_large(const Geo &g, const double *row, double *fin, hipStream_t s);
 // x64 += x32 (end of a mixed solve).
 void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s);
 // Workgroups of chains not yet converged (st: both state parities) -> out[0..count[0]);

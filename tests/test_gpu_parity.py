@@ -149,6 +149,20 @@ def test_dslash_large_lattice_sampled():
     assert rel(got, oracle.dirac(q, psi, 0.05)) < 1e-13
 
 
+def test_dslash_2048_sampled_sites():
+    """2048 x 2048 (a size of the roofline sweep): D at 2000 random sites against the oracle."""
+    L = 2048
+    b = Batch([(L, L, 2.0, 0.1)])
+    q = inputs.random_angles(L, L, 7)
+    psi = inputs.random_spinor(L, L, 8)
+    b.set_q([q])
+    got = b.spinor_from_native(b.lat.dslash(b.spinor_to_native([psi])))[0].reshape(-1, 2)
+    sites = np.random.default_rng(9).integers(0, L * L, size=2000)
+    sites[:4] = [0, L - 1, L * L - L, L * L - 1]   # the corners and the time boundary
+    want = oracle.dirac_sites(q, psi, 0.1, sites)
+    assert rel(got[sites], want) < 1e-13
+
+
 # ------------------------------------------------------------------ gauge part
 @pytest.mark.parametrize("Lx,Lt", [(4, 4), (6, 10), (34, 18)])
 def test_gauge_force_and_action_parity(Lx, Lt):
