@@ -38,10 +38,13 @@ struct ChainInfo {
 static_assert(sizeof(ChainInfo) == 64, "ChainInfo is 64 bytes");
 
 // One entry per hardware workgroup (hardware order, XCD-aware permutation applied on the host).
-// A workgroup of B threads handles the chain-local sites start + tid + j*B, j < spt.
+// A workgroup of B threads handles the half-site indices [start, start + B/2) of BOTH parity
+// planes of its chain: threads [0, B/2) the even plane, [B/2, B) the odd plane.  The stencil
+// neighbours of a site lie in the other plane at nearby half-site indices, so the two halves
+// of the workgroup read each other's sites while they are still in cache.
 struct BlockWork {
     int chain;    // chain index
-    int start;    // first chain-local site handled by this workgroup
+    int start;    // first half-site index (within each parity plane) of this workgroup
     int logical;  // logical workgroup index (chains are contiguous in logical order)
     int spt;      // sites per thread
 };

@@ -152,8 +152,9 @@ int fail(hmc_ctx *c, int code, const char *fmt, ...) {
         if (!(ctx)->ws) return fail(ctx, HMC_E_INVAL, "context has no workspace bound");        \
     } while (0)
 
-// Block table: every chain gets ceil(V / block) logical workgroups, one site per thread
-// (chains contiguous in logical order).  Hardware workgroup h runs on XCD h % 8, and the
+// Block table: every chain gets ceil((V/2) / (block/2)) logical workgroups, one site per
+// thread, each covering the same half-site range of both parity planes (chains contiguous in
+// logical order).  Hardware workgroup h runs on XCD h % 8, and the
 // j-th workgroup of XCD k receives logical workgroup start_k + j, so each XCD sweeps one
 // contiguous site range and the workgroups resident on it at any time cover a few
 // consecutive lattice rows: the t +- 1 stencil rows are L2 hits.
@@ -164,12 +165,13 @@ void build_tables(hmc_ctx *c) {
         ChainInfo &ci = c->chains[ch];
         const int spt = 1;
         ci.block0 = (int)logical.size();
-        ci.nblocks = (ci.V + c->block * spt - 1) / (c->block * spt);
+        const int half = c->block / 2;
+        ci.nblocks = (ci.Vh + half * spt - 1) / (half * spt);
         if (ci.nblocks > kMaxChainBlocks) c->has_large = true;
         for (int j = 0; j < ci.nblocks; ++j) {
             BlockWork w;
             w.chain = ch;
-            w.start = j * c->block * spt;
+            w.start = j * half * spt;
             w.logical = (int)logical.size();
             w.spt = spt;
             logical.push_back(w);

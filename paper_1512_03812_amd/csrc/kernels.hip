@@ -1,8 +1,9 @@
 // HIP kernels (gfx950) of the Schwinger-model HMC hot path.
 //
-// Site kernels: workgroup b handles the sites start + tid + j*B (j < spt) of chain
-// work[b].chain; the host permutes the workgroup table so that each XCD receives a
-// contiguous range of sites (its L2 then holds the neighbouring rows of the stencil).
+// Site kernels: workgroup b handles the half-site indices [start, start + B/2) of both
+// parity planes of chain work[b].chain (the stencil neighbours of one plane are the other
+// plane's sites at nearby indices); the host permutes the workgroup table so that each XCD
+// receives a contiguous range of sites (its L2 then holds the neighbouring rows).
 //
 // Reductions use no atomics and no cross-workgroup fences: a producer kernel writes one
 // partial per workgroup (wavefront shuffle + LDS tree), and every consumer workgroup of a
@@ -148,11 +149,15 @@ __device__ __forceinline__ double norm2(float2 a) {
     return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
 }
 
-// Loop over the sites of this workgroup; `local` is the chain-local site index.
+// Loop over the sites of this workgroup; `local` is the chain-local site index.  Threads
+// [0, B/2) take the even plane and [B/2, B) the odd plane at the same half-site indices.
 #define SITES_LOOP                                                                \
+    const int half_ = (int)blockDim.x >> 1;                                       \
+    const int par_ = (int)threadIdx.x >= half_ ? 1 : 0;                           \
     for (int j_ = 0; j_ < w.spt; ++j_) {                                          \
-        const int local = w.start + (int)threadIdx.x + j_ * (int)blockDim.x;      \
-        if (local >= ci.V) break;
+        const int i_ = w.start + (int)threadIdx.x - par_ * half_ + j_ * half_;    \
+        if (i_ >= ci.Vh) break;                                                   \
+        const int local = par_ * ci.Vh + i_;
 #define SITES_BEGIN                                                               \
     const BlockWork w = g.work[blockIdx.x];                                       \
     const ChainInfo ci = g.chains[w.chain];                                       \
