@@ -14,6 +14,7 @@ the plain FP64 single-chain 32 x 32 path on the same GPU, and the CPU oracle tim
 bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +30,20 @@ METRIC = "HMC trajectories/sec at fixed acceptance; Dslash+CG achieved HBM GB/s"
 # The library attributes algorithmic bytes to its sampled, event-timed CG launches (bytes
 # per site: mixed FP32 slot 80 / 112 for step 1 / step 2, FP64 residual-recomputation slot
 # 144 / 208, FP64 solver 160 / 224; times the sites of the chains not yet converged).
+
+
+def hbm_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter record, or None
+    if the kernels have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_batched512.json")
+    src = os.path.join(ROOT, "paper_1512_03812_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(path))
+        if rec["kernel_source_sha256"] != hashlib.sha256(open(src, "rb").read()).hexdigest():
+            return None
+        return rec["kernels"][kernel]["hbm_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def workload(seed=1512, n_chains=512):
@@ -246,6 +261,9 @@ def main():
     s1, s2 = b["s1"], b["s2"]
     ach2 = s2["timed_bytes"] / (s2["timed_ms"] * 1e-3) / 1e9 if s2["timed_ms"] > 0 else 0.0
     t12 = (s1["timed_ms"] + s2["timed_ms"]) * 1e-3
+    avg_s2 = s2["timed_ms"] * 1e-3 / max(1, s2["timed_launches"])
+    tb = hbm_traffic("k_cg_step2<true>")
+    traffic = round(tb / avg_s2 / 1e9, 1) if (tb and avg_s2 > 0) else None
     cg_gbs = (s1["timed_bytes"] + s2["timed_bytes"]) / t12 / 1e9 if t12 > 0 else 0.0
     out = {
         "metric": METRIC,
@@ -276,7 +294,8 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "k_cg_step2<true> (mixed-precision CG step 2)",
             "achieved": round(ach2, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach2 / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(ach2 / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_bytes_per_launch": tb,
             "avg_launch_us": round(1e3 * s2["timed_ms"] / max(1, s2["timed_launches"]), 3),
             "avg_bytes_per_launch": round(s2["timed_bytes"] / max(1, s2["timed_launches"])),
             "timed_launches": s2["timed_launches"], "launches": s2["launches"],

@@ -128,8 +128,12 @@ size_t hmc_workspace_bytes(const hmc_ctx *ctx);
  * not copied). */
 int hmc_bind(hmc_ctx *ctx, void *dev_workspace, size_t bytes, void *hip_stream);
 
-/* Device pointer (and size in bytes) of a named field inside the workspace. */
+/* Device pointer (and size in bytes) of a named field inside the workspace.  The library
+ * keeps the complex links U = exp(i q) and solver results derived from q between calls;
+ * every hmc_field call, and every library call that changes q, invalidates them.  A caller
+ * that writes q through a pointer obtained earlier calls hmc_mark_links_changed first. */
 int hmc_field(hmc_ctx *ctx, int which, void **dev_ptr, size_t *bytes);
+int hmc_mark_links_changed(hmc_ctx *ctx);
 
 /* n_chains, V_total, and per chain (arrays of n_chains, any may be NULL) the flat
  * offset and extents. */

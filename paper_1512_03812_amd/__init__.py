@@ -147,6 +147,10 @@ class Lattice:
         off = p.value - self.workspace.data_ptr()
         return self.workspace[off:off + nb.value].view(dtype).view(*shape)
 
+    def mark_links_changed(self):
+        """Call after writing q through a tensor obtained from `q` earlier."""
+        self._check(self._lib.hmc_mark_links_changed(self._ctx))
+
     def new_links(self):
         return torch.zeros((2, self.V_total), dtype=torch.float64, device=self.device)
 

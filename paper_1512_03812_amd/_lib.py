@@ -53,6 +53,7 @@ SIGNATURES = {
     "hmc_workspace_bytes": (_SZ, [_P]),
     "hmc_bind": (_I, [_P, _P, _SZ, _P]),
     "hmc_field": (_I, [_P, _I, _P, _P]),
+    "hmc_mark_links_changed": (_I, [_P]),
     "hmc_geometry": (_I, [_P, _P, _P, _P, _P, _P]),
     "hmc_pack_links": (_I, [_P, _P, _P]),
     "hmc_unpack_links": (_I, [_P, _P, _P]),

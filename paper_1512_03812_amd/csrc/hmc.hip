@@ -883,6 +883,12 @@ int hmc_set_persistent_limit(hmc_ctx *c, int vmax) {
     return HMC_OK;
 }
 
+int hmc_mark_links_changed(hmc_ctx *c) {
+    if (!c) return HMC_E_INVAL;
+    forget_all(c);
+    return HMC_OK;
+}
+
 int hmc_set_block_size(hmc_ctx *c, int block) {
     CHECK_BOUND(c);
     return set_block(c, block);
@@ -910,7 +916,7 @@ int hmc_autotune(hmc_ctx *c, int prec, double tol, hmc_tune_info *out) {
         if (rc) return rc;
         for (int pv : persist) {
             c->persist_vmax = pv;
-            ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, -1);
+            ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, c->q_version);
             rc = solve(c, c->spin(SPHI), c->spin(SXI), tol, c->max_iter, prec);  // warm-up
             if (rc && rc != HMC_E_NOCONV) return rc;
             const auto t0 = std::chrono::steady_clock::now();
@@ -954,7 +960,7 @@ int hmc_set_check_interval(hmc_ctx *c, int every) {
 int hmc_dslash(hmc_ctx *c, const void *in, void *out) {
     CHECK_BOUND(c);
     if (!in || !out || in == out) return fail(c, HMC_E_INVAL, "need distinct in/out");
-    ensure_links(c, c->link(LQ), false, -1);
+    ensure_links(c, c->link(LQ), false, c->q_version);
     launch_dslash64(c->geo(), c->U64(), (const double2 *)in, (double2 *)out, false, c->stream);
     HIP_TRY(c, hipGetLastError());
     return HMC_OK;
@@ -963,7 +969,7 @@ int hmc_dslash(hmc_ctx *c, const void *in, void *out) {
 int hmc_dslash_dagger(hmc_ctx *c, const void *in, void *out) {
     CHECK_BOUND(c);
     if (!in || !out || in == out) return fail(c, HMC_E_INVAL, "need distinct in/out");
-    ensure_links(c, c->link(LQ), false, -1);
+    ensure_links(c, c->link(LQ), false, c->q_version);
     launch_dslash64(c->geo(), c->U64(), (const double2 *)in, (double2 *)out, true, c->stream);
     HIP_TRY(c, hipGetLastError());
     return HMC_OK;
@@ -975,7 +981,7 @@ int hmc_cg_solve(hmc_ctx *c, const void *phi, void *x, double tol, int max_iter,
     if (!phi || !x || phi == x) return fail(c, HMC_E_INVAL, "need distinct phi/x");
     if (!(tol >= 0) || max_iter < 1) return fail(c, HMC_E_INVAL, "bad tol/max_iter");
     if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
-    ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, -1);
+    ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, c->q_version);
     int rc = solve(c, (const double2 *)phi, (double2 *)x, tol, max_iter, prec);
     if (rc && rc != HMC_E_NOCONV) return rc;
     std::vector<double> t2(c->nchains);
@@ -991,7 +997,7 @@ int hmc_cg_solve(hmc_ctx *c, const void *phi, void *x, double tol, int max_iter,
 int hmc_fermion_force_chixi(hmc_ctx *c, const void *chi, const void *xi, double *f) {
     CHECK_BOUND(c);
     if (!chi || !xi || !f) return fail(c, HMC_E_INVAL, "null pointer");
-    ensure_links(c, c->link(LQ), false, -1);
+    ensure_links(c, c->link(LQ), false, c->q_version);
     launch_fermion_force(c->geo(), c->U64(), (const double2 *)chi, (const double2 *)xi, f, c->stream);
     HIP_TRY(c, hipGetLastError());
     return HMC_OK;
@@ -1003,7 +1009,7 @@ int hmc_fermion_force(hmc_ctx *c, const void *phi, double *f, double tol, int ma
     if (!phi) return fail(c, HMC_E_INVAL, "null pointer");
     if (!(tol >= 0) || max_iter < 1) return fail(c, HMC_E_INVAL, "bad tol/max_iter");
     if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
-    ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, -1);
+    ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, c->q_version);
     int rc = solve(c, (const double2 *)phi, c->spin(SXI), tol, max_iter, prec);
     if (rc && rc != HMC_E_NOCONV) return rc;
     launch_dslash64(c->geo(), c->U64(), c->spin(SXI), c->spin(SCHI), false, c->stream);
@@ -1026,7 +1032,7 @@ int hmc_fermion_force(hmc_ctx *c, const void *phi, double *f, double tol, int ma
 int hmc_total_force_chixi(hmc_ctx *c, const void *chi, const void *xi, double *F) {
     CHECK_BOUND(c);
     if (!chi || !xi || !F) return fail(c, HMC_E_INVAL, "null pointer");
-    ensure_links(c, c->link(LQ), false, -1);
+    ensure_links(c, c->link(LQ), false, c->q_version);
     launch_fermion_force(c->geo(), c->U64(), (const double2 *)chi, (const double2 *)xi, F, c->stream);
     launch_gauge_force(c->geo(), c->link(LQ), F, F, c->stream);
     HIP_TRY(c, hipGetLastError());
@@ -1046,7 +1052,7 @@ int hmc_actions(hmc_ctx *c, const void *phi, double tol, double *s_gauge, double
     CHECK_BOUND(c);
     const int C = c->nchains;
     if (phi && s_fermion) {
-        ensure_links(c, c->link(LQ), false, -1);
+        ensure_links(c, c->link(LQ), false, c->q_version);
         int rc = solve(c, (const double2 *)phi, c->spin(SXI), tol, c->max_iter, HMC_PREC_FP64);
         if (rc) return rc;
         c->ff_version = c->xi_version = -1;
