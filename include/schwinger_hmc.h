@@ -60,7 +60,9 @@ enum {
     HMC_OMELYAN_5STAGE = 1,    /* Eq. (4): 5-stage scheme, lambda = 1/6 */
     HMC_FORCE_GRADIENT = 2,    /* Eq. (5), force-gradient term via the shifted force */
     HMC_NESTED_FG = 3,         /* Eq. (10) */
-    HMC_ADAPTED_NESTED_FG = 4  /* Eq. (11) */
+    HMC_ADAPTED_NESTED_FG = 4, /* Eq. (11) */
+    HMC_NESTED_LEAPFROG = 5,   /* Eq. (8) */
+    HMC_NESTED_5STAGE = 6      /* Eq. (9) */
 };
 
 enum { HMC_PREC_FP64 = 0, HMC_PREC_MIXED = 1 };

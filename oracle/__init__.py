@@ -25,13 +25,16 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "schwinger_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-LEAPFROG, OMELYAN_5STAGE, FORCE_GRADIENT, NESTED_FG, ADAPTED_NESTED_FG = range(5)
+(LEAPFROG, OMELYAN_5STAGE, FORCE_GRADIENT, NESTED_FG, ADAPTED_NESTED_FG, NESTED_LEAPFROG,
+ NESTED_5STAGE) = range(7)
 SCHEMES = {
     "leapfrog": LEAPFROG,
     "omelyan": OMELYAN_5STAGE,
     "force_gradient": FORCE_GRADIENT,
     "nested_fg": NESTED_FG,
     "adapted_nested_fg": ADAPTED_NESTED_FG,
+    "nested_leapfrog": NESTED_LEAPFROG,
+    "nested_omelyan": NESTED_5STAGE,
 }
 FLAG_QUENCHED = 1
 STAGE_NAMES = {0: "A", 1: "B", 2: "BG", 3: "BF", 4: "BT", 5: "BTG", 6: "BTF"}

@@ -457,6 +457,8 @@ enum {
     SCHEME_FORCE_GRADIENT = 2,    /* Eq. (5), force-gradient term via the shifted force */
     SCHEME_NESTED_FG = 3,         /* Eq. (10) */
     SCHEME_ADAPTED_NESTED_FG = 4, /* Eq. (11) */
+    SCHEME_NESTED_LEAPFROG = 5,   /* Eq. (8)  */
+    SCHEME_NESTED_5STAGE = 6,     /* Eq. (9)  */
 };
 
 /* stage kinds recorded in the trace */
@@ -607,6 +609,18 @@ static void md_step(md_state *s, int scheme, double h, int M)
         stage_B(s, 1, h / 6.0);
         inner_leapfrog(s, h / 2.0, M);
         stage_B_fg(s, 1, 2.0 * h / 3.0, h);
+        inner_leapfrog(s, h / 2.0, M);
+        stage_B(s, 1, h / 6.0);
+        break;
+    case SCHEME_NESTED_LEAPFROG: /* Eq. (8): the inner leap-frog spans the whole step h */
+        stage_B(s, 1, h / 2.0);
+        inner_leapfrog(s, h, M);
+        stage_B(s, 1, h / 2.0);
+        break;
+    case SCHEME_NESTED_5STAGE: /* Eq. (9) */
+        stage_B(s, 1, h / 6.0);
+        inner_leapfrog(s, h / 2.0, M);
+        stage_B(s, 1, 2.0 * h / 3.0);
         inner_leapfrog(s, h / 2.0, M);
         stage_B(s, 1, h / 6.0);
         break;

@@ -659,6 +659,14 @@ int md_step(MD &md, int scheme, double h, int M) {
         T(stage_B_fg(md, 1, 2.0 * h / 3.0, h)); T(inner_leapfrog(md, h / 2.0, M));
         T(stage_B(md, 1, h / 6.0));
         break;
+    case HMC_NESTED_LEAPFROG:  // Eq. (8)
+        T(stage_B(md, 1, h / 2.0)); T(inner_leapfrog(md, h, M)); T(stage_B(md, 1, h / 2.0));
+        break;
+    case HMC_NESTED_5STAGE:  // Eq. (9)
+        T(stage_B(md, 1, h / 6.0)); T(inner_leapfrog(md, h / 2.0, M));
+        T(stage_B(md, 1, 2.0 * h / 3.0)); T(inner_leapfrog(md, h / 2.0, M));
+        T(stage_B(md, 1, h / 6.0));
+        break;
     default:
         return HMC_E_INVAL;
     }
@@ -667,10 +675,10 @@ int md_step(MD &md, int scheme, double h, int M) {
 }
 
 int check_md_args(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, int prec) {
-    if (scheme < HMC_LEAPFROG || scheme > HMC_ADAPTED_NESTED_FG)
+    if (scheme < HMC_LEAPFROG || scheme > HMC_NESTED_5STAGE)
         return fail(c, HMC_E_INVAL, "unknown scheme %d", scheme);
     if (!isfinite(tau) || n_outer < 1) return fail(c, HMC_E_INVAL, "need finite tau and n_outer >= 1");
-    if ((scheme == HMC_NESTED_FG || scheme == HMC_ADAPTED_NESTED_FG) && n_inner < 1)
+    if (scheme >= HMC_NESTED_FG && n_inner < 1)
         return fail(c, HMC_E_INVAL, "nested schemes need n_inner >= 1");
     if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
     return HMC_OK;
