@@ -37,6 +37,8 @@ SCHEMES = {
     "nested_omelyan": NESTED_5STAGE,
 }
 FLAG_QUENCHED = 1
+FLAG_FG_EXACT = 2
+FORCE_SETS = {"gauge": 0, "fermion": 1, "total": 2}
 STAGE_NAMES = {0: "A", 1: "B", 2: "BG", 3: "BF", 4: "BT", 5: "BTG", 6: "BTF"}
 
 
@@ -80,6 +82,10 @@ def lib():
             "orc_fermion_force_chixi": (None, [I, I, P, P, P, P]),
             "orc_fermion_force": (I, [I, I, D, P, P, D, I, P, P, P, P]),
             "orc_fermion_action": (D, [I, I, D, P, P, D, I]),
+            "orc_fg_term_gg": (None, [I, I, D, P, P]),
+            "orc_fg_term_fg": (None, [I, I, D, P, P, P]),
+            "orc_fg_term_fermion": (I, [I, I, D, P, P, P, P, D, I, P]),
+            "orc_force_gradient_term": (I, [I, I, D, D, P, P, I, D, I, P, P]),
             "orc_md_integrate": (I, [I, I, D, D, I, D, I, I, D, I, I, P, P, P, P, P, P, I]),
             "orc_hmc_trajectory": (I, [I, I, D, D, U64, U32, U32, I, D, I, I, D, I, I, P, P]),
         }
@@ -246,10 +252,56 @@ def fg_shifted_force(q, phi, beta, m0, h, which="fermion", tol=1e-12) -> np.ndar
     return F(np.asarray(q) - (h * h / 24.0) * F(q))
 
 
+# ---------------------------------------------------------------- force-gradient term (Eqs. (19)-(23))
+def fg_term_gg(q, beta) -> np.ndarray:
+    """C_GG from the eight-plaquette closed form of Sec. 3."""
+    q = _links(q)
+    C = np.empty_like(q)
+    lib().orc_fg_term_gg(q.shape[1], q.shape[0], beta, _p(q), _p(C))
+    return C
+
+
+def fg_term_fg(q, f, beta) -> np.ndarray:
+    """C_FG from the closed form of Sec. 3, given the fermion force f."""
+    q, f = _links(q), _links(f)
+    C = np.empty_like(q)
+    lib().orc_fg_term_fg(q.shape[1], q.shape[0], beta, _p(q), _p(f), _p(C))
+    return C
+
+
+def fg_term_fermion(q, chi, xi, v, m0, tol=1e-12, max_iter=100000):
+    """4 Re[Z1^+ w2 + w1^+ Z2 - chi^+ D'' xi v] of Eqs. (22)-(23) with weight v.
+
+    v = f gives C_FF, v = beta g gives C_GF.  Returns (C, CG iterations or -1)."""
+    q, chi, xi, v = _links(q), _spinor(chi), _spinor(xi), _links(v)
+    C = np.empty_like(q)
+    it = lib().orc_fg_term_fermion(q.shape[1], q.shape[0], m0, _p(q), _p(chi), _p(xi), _p(v), tol,
+                                   max_iter, _p(C))
+    return C, it
+
+
+def force_gradient_term(q, phi, beta, m0, which="total", tol=1e-12, max_iter=100000):
+    """C of Eq. (19) for the gauge, fermion or total force.  Returns (C, info dict)."""
+    q = _links(q)
+    phi = _spinor(phi if phi is not None else np.zeros(q.shape, dtype=np.complex128))
+    C = np.empty_like(q)
+    cnt = np.zeros(3, dtype=np.int64)
+    rc = lib().orc_force_gradient_term(q.shape[1], q.shape[0], beta, m0, _p(q), _p(phi),
+                                       FORCE_SETS[which], tol, max_iter, _p(C), _p(cnt))
+    return C, {"rc": rc, "n_solves": int(cnt[0]), "n_cg_iters": int(cnt[1]), "n_dinv": int(cnt[2])}
+
+
 # ---------------------------------------------------------------- molecular dynamics and HMC (Sec. 2)
+def _flags(quenched, fg_exact):
+    return (FLAG_QUENCHED if quenched else 0) | (FLAG_FG_EXACT if fg_exact else 0)
+
+
 def md_integrate(q, p, phi, beta, m0, scheme, tau, n_outer, n_inner=1, tol=1e-12, max_iter=100000,
-                 quenched=False, trace_cap=0):
-    """Integrates one trajectory from (q, p); returns (q', p', info dict[, trace])."""
+                 quenched=False, trace_cap=0, fg_exact=False):
+    """Integrates one trajectory from (q, p); returns (q', p', info dict[, trace]).
+
+    fg_exact: the force-gradient kicks use the exact C of Eqs. (19)-(23) instead of the
+    shifted force."""
     q = _links(q).copy()
     p = _links(p).copy()
     if phi is None:
@@ -257,14 +309,14 @@ def md_integrate(q, p, phi, beta, m0, scheme, tau, n_outer, n_inner=1, tol=1e-12
     phi = _spinor(phi)
     if isinstance(scheme, str):
         scheme = SCHEMES[scheme]
-    counters = np.zeros(3, dtype=np.int64)
+    counters = np.zeros(4, dtype=np.int64)
     kinds = np.zeros(max(trace_cap, 1), dtype=np.int32)
     eps = np.zeros(max(trace_cap, 1), dtype=np.float64)
     rc = lib().orc_md_integrate(q.shape[1], q.shape[0], beta, m0, scheme, tau, n_outer, n_inner,
-                                tol, max_iter, FLAG_QUENCHED if quenched else 0, _p(q), _p(p),
+                                tol, max_iter, _flags(quenched, fg_exact), _p(q), _p(p),
                                 _p(phi), _p(counters), _p(kinds), _p(eps), trace_cap)
     info = {"rc": rc, "n_solves": int(counters[0]), "n_cg_iters": int(counters[1]),
-            "n_stages": int(counters[2])}
+            "n_stages": int(counters[2]), "n_dinv": int(counters[3])}
     if trace_cap:
         n = min(int(counters[2]), trace_cap)
         info["trace"] = [(STAGE_NAMES[int(k)], float(e)) for k, e in zip(kinds[:n], eps[:n])]
@@ -280,15 +332,15 @@ def hamiltonian(q, p, phi, beta, m0, tol=1e-14, quenched=False) -> float:
 
 
 def hmc_trajectory(q, beta, m0, seed, chain, traj, scheme, tau, n_outer, n_inner=1, tol=1e-12,
-                   max_iter=100000, quenched=False):
+                   max_iter=100000, quenched=False, fg_exact=False):
     """One HMC update (Sec. 2.1).  Returns (q_new, info dict)."""
     q = _links(q).copy()
     if isinstance(scheme, str):
         scheme = SCHEMES[scheme]
-    info = np.zeros(8)
+    info = np.zeros(9)
     rc = lib().orc_hmc_trajectory(q.shape[1], q.shape[0], beta, m0, seed, chain, traj, scheme, tau,
-                                  n_outer, n_inner, tol, max_iter,
-                                  FLAG_QUENCHED if quenched else 0, _p(q), _p(info))
+                                  n_outer, n_inner, tol, max_iter, _flags(quenched, fg_exact),
+                                  _p(q), _p(info))
     return q, {"rc": rc, "dH": info[0], "accepted": bool(info[1]), "plaquette": info[2],
                "n_solves": int(info[3]), "n_cg_iters": int(info[4]), "H0": info[5], "H1": info[6],
-               "u": info[7]}
+               "u": info[7], "n_dinv": int(info[8])}

@@ -448,6 +448,240 @@ double orc_fermion_action(int Lx, int Lt, double m0, const double *q, const cplx
 }
 
 /* ------------------------------------------------------------------------- */
+/* Force-gradient term C (Eqs. (19)-(23))                                    */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * C_GG, the closed form given in Sec. 3 after Eq. (20):
+ *   C_GG(n, mu) = 2 beta^2 [ Im(4 P1 - P2 - P3 - P4 - P5) Re P1
+ *                          - Im(4 P2 - P1 - P6 - P7 - P8) Re P2 ],  nu != mu,
+ * with the eight plaquettes around the link written out as the paper lists them.
+ */
+void orc_fg_term_gg(int Lx, int Lt, double beta, const double *q, double *C)
+{
+    for (int n = 0; n < Lx * Lt; ++n)
+        for (int mu = 0; mu < 2; ++mu) {
+            int nu = 1 - mu;
+            int n_pm = hop(n, mu, +1, Lx, Lt), n_mm = hop(n, mu, -1, Lx, Lt);
+            int n_pn = hop(n, nu, +1, Lx, Lt), n_mn = hop(n, nu, -1, Lx, Lt);
+            int n_2pm = hop(n_pm, mu, +1, Lx, Lt), n_pm_pn = hop(n_pm, nu, +1, Lx, Lt);
+            int n_2pn = hop(n_pn, nu, +1, Lx, Lt), n_mm_pn = hop(n_mm, nu, +1, Lx, Lt);
+            int n_mm_mn = hop(n_mm, nu, -1, Lx, Lt), n_2mn = hop(n_mn, nu, -1, Lx, Lt);
+            int n_pm_mn = hop(n_pm, nu, -1, Lx, Lt), n_2mn_pm = hop(n_2mn, mu, +1, Lx, Lt);
+            int n_pm_mn_pm = hop(n_pm_mn, mu, +1, Lx, Lt);
+            cplx P1 = link(q, n, mu) * link(q, n_pm, nu) * conj(link(q, n_pn, mu)) * conj(link(q, n, nu));
+            cplx P2 = link(q, n_mn, mu) * link(q, n_pm_mn, nu) * conj(link(q, n, mu)) *
+                      conj(link(q, n_mn, nu));
+            cplx P3 = link(q, n_pm, mu) * link(q, n_2pm, nu) * conj(link(q, n_pm_pn, mu)) *
+                      conj(link(q, n_pm, nu));
+            cplx P4 = link(q, n_pn, mu) * link(q, n_pm_pn, nu) * conj(link(q, n_2pn, mu)) *
+                      conj(link(q, n_pn, nu));
+            cplx P5 = link(q, n_mm, mu) * link(q, n, nu) * conj(link(q, n_mm_pn, mu)) *
+                      conj(link(q, n_mm, nu));
+            cplx P6 = link(q, n_mm_mn, mu) * link(q, n_mn, nu) * conj(link(q, n_mm, mu)) *
+                      conj(link(q, n_mm_mn, nu));
+            cplx P7 = link(q, n_2mn, mu) * link(q, n_2mn_pm, nu) * conj(link(q, n_mn, mu)) *
+                      conj(link(q, n_2mn, nu));
+            cplx P8 = link(q, n_pm_mn, mu) * link(q, n_pm_mn_pm, nu) * conj(link(q, n_pm, mu)) *
+                      conj(link(q, n_pm_mn, nu));
+            C[2 * n + mu] = 2.0 * beta * beta *
+                            (cimag(4.0 * P1 - P2 - P3 - P4 - P5) * creal(P1) -
+                             cimag(4.0 * P2 - P1 - P6 - P7 - P8) * creal(P2));
+        }
+}
+
+/*
+ * C_FG, the closed form given in Sec. 3 after C_GG, from the fermion force f:
+ *   C_FG(n, mu) = 2 beta [ (f(n,mu) + f(n+mu,nu) - f(n+nu,mu) - f(n,nu)) Re P1
+ *                        + (f(n,mu) - f(n+mu-nu,nu) - f(n-nu,mu) + f(n-nu,nu)) Re P2 ].
+ */
+void orc_fg_term_fg(int Lx, int Lt, double beta, const double *q, const double *f, double *C)
+{
+    for (int n = 0; n < Lx * Lt; ++n)
+        for (int mu = 0; mu < 2; ++mu) {
+            int nu = 1 - mu;
+            int n_pm = hop(n, mu, +1, Lx, Lt), n_pn = hop(n, nu, +1, Lx, Lt);
+            int n_mn = hop(n, nu, -1, Lx, Lt), n_pm_mn = hop(n_pm, nu, -1, Lx, Lt);
+            double reP1 = creal(plaquette(q, n, mu, nu, Lx, Lt));
+            double reP2 = creal(plaquette(q, n_mn, mu, nu, Lx, Lt));
+            double a = f[2 * n + mu] + f[2 * n_pm + nu] - f[2 * n_pn + mu] - f[2 * n + nu];
+            double b = f[2 * n + mu] - f[2 * n_pm_mn + nu] - f[2 * n_mn + mu] + f[2 * n_mn + nu];
+            C[2 * n + mu] = 2.0 * beta * (a * reP1 + b * reP2);
+        }
+}
+
+/*
+ * The two non-zero site entries of w_{1,m,nu} (kind 1) or w_{2,m,nu} (kind 2), Sec. 3
+ * after Eq. (21):
+ *   w_{1,m,nu} = dD^dagger/dq_nu(m) chi:  at m + nu:  (i/2)(1 - sigma_nu) U_nu^dagger(m) chi(m)
+ *                                         at m:      -(i/2)(1 + sigma_nu) U_nu(m) chi(m + nu)
+ *   w_{2,m,nu} = dD/dq_nu(m) xi:          at m:      -(i/2)(1 - sigma_nu) U_nu(m) xi(m + nu)
+ *                                         at m + nu:  (i/2)(1 + sigma_nu) U_nu^dagger(m) xi(m)
+ * U is the fermion link (with the boundary sign).  at_m and at_mnu receive the spinors at
+ * sites m and m + nu.
+ */
+static void w_entries(int kind, int Lx, int Lt, const double *q, int m, int nu, const cplx *psi,
+                      cplx at_m[2], cplx at_mnu[2])
+{
+    int m_nu = hop(m, nu, +1, Lx, Lt);
+    cplx u = flink(q, m, nu, Lx, Lt);
+    cplx a[2] = {u * psi[2 * m_nu], u * psi[2 * m_nu + 1]};  /* U_nu(m) psi(m + nu) */
+    cplx b[2] = {conj(u) * psi[2 * m], conj(u) * psi[2 * m + 1]}; /* U_nu^dagger(m) psi(m) */
+    cplx pa[2], pb[2];
+    if (kind == 1) {
+        proj(nu, +1, a, pa);
+        proj(nu, -1, b, pb);
+        for (int s = 0; s < 2; ++s) { at_m[s] = -0.5 * I * pa[s]; at_mnu[s] = 0.5 * I * pb[s]; }
+    } else {
+        proj(nu, -1, a, pa);
+        proj(nu, +1, b, pb);
+        for (int s = 0; s < 2; ++s) { at_m[s] = -0.5 * I * pa[s]; at_mnu[s] = 0.5 * I * pb[s]; }
+    }
+}
+
+/* D^{-1} y = (D^dagger D)^{-1} D^dagger y and D^{dagger -1} y = D (D^dagger D)^{-1} y */
+static int solve_D(int Lx, int Lt, double m0, const double *q, const cplx *y, cplx *out,
+                   int dagger, double tol, int max_iter)
+{
+    int ns = 2 * Lx * Lt;
+    cplx *rhs = malloc(sizeof(cplx) * ns), *sol = malloc(sizeof(cplx) * ns);
+    if (dagger) memcpy(rhs, y, sizeof(cplx) * ns);
+    else orc_dirac_dagger(Lx, Lt, m0, q, y, rhs);
+    int it = orc_cg(Lx, Lt, m0, q, rhs, sol, tol, max_iter, NULL);
+    if (dagger) orc_dirac(Lx, Lt, m0, q, sol, out);
+    else memcpy(out, sol, sizeof(cplx) * ns);
+    free(rhs); free(sol);
+    return it;
+}
+
+/*
+ * The fermion-action part of C with weight vector v, Eqs. (22) and (23):
+ *   Z_1 = D^{dagger -1} sum_{m,nu} w_{1,m,nu} v(m,nu),
+ *   Z_2 = D^{-1} ( sum_{m,nu} w_{2,m,nu} v(m,nu) + Z_1 ),
+ *   C(n,mu) = 4 Re[ Z_1^dagger w_{2,n,mu} + w_{1,n,mu}^dagger Z_2
+ *                   - chi^dagger (d^2 D / dq_mu(n)^2) xi v(n,mu) ].
+ * v = f gives C_FF; v = beta g (the gauge force) gives C_GF (the remark after Eq. (23)).
+ * chi and xi are those of Eq. (18) at the same links.  d^2 D/dq_mu(n)^2 has the entries
+ * (1/2)(1 - sigma_mu) U_mu(n) at (n, n+mu) and (1/2)(1 + sigma_mu) U_mu^dagger(n) at
+ * (n+mu, n) (each link enters D through exp(i q), so two derivatives give -1 times the
+ * hopping entry).  Two inversions (Z_1 and Z_2).  Returns the CG iterations or -1.
+ */
+int orc_fg_term_fermion(int Lx, int Lt, double m0, const double *q, const cplx *chi,
+                        const cplx *xi, const double *v, double tol, int max_iter, double *C)
+{
+    int V = Lx * Lt, ns = 2 * V;
+    cplx *W1 = calloc(ns, sizeof(cplx)), *W2 = calloc(ns, sizeof(cplx));
+    cplx *Z1 = malloc(sizeof(cplx) * ns), *Z2 = malloc(sizeof(cplx) * ns);
+    cplx *y = malloc(sizeof(cplx) * ns);
+    for (int m = 0; m < V; ++m)
+        for (int nu = 0; nu < 2; ++nu) {
+            int m_nu = hop(m, nu, +1, Lx, Lt);
+            cplx e0[2], e1[2];
+            w_entries(1, Lx, Lt, q, m, nu, chi, e0, e1);
+            for (int s = 0; s < 2; ++s) {
+                W1[2 * m + s] += v[2 * m + nu] * e0[s];
+                W1[2 * m_nu + s] += v[2 * m + nu] * e1[s];
+            }
+            w_entries(2, Lx, Lt, q, m, nu, xi, e0, e1);
+            for (int s = 0; s < 2; ++s) {
+                W2[2 * m + s] += v[2 * m + nu] * e0[s];
+                W2[2 * m_nu + s] += v[2 * m + nu] * e1[s];
+            }
+        }
+    int it1 = solve_D(Lx, Lt, m0, q, W1, Z1, 1, tol, max_iter);
+    for (int k = 0; k < ns; ++k) y[k] = W2[k] + Z1[k];
+    int it2 = solve_D(Lx, Lt, m0, q, y, Z2, 0, tol, max_iter);
+    for (int n = 0; n < V; ++n)
+        for (int mu = 0; mu < 2; ++mu) {
+            int n_mu = hop(n, mu, +1, Lx, Lt);
+            cplx w1m[2], w1p[2], w2m[2], w2p[2];
+            w_entries(1, Lx, Lt, q, n, mu, chi, w1m, w1p);
+            w_entries(2, Lx, Lt, q, n, mu, xi, w2m, w2p);
+            cplx acc = 0;
+            for (int s = 0; s < 2; ++s) {
+                acc += conj(Z1[2 * n + s]) * w2m[s] + conj(Z1[2 * n_mu + s]) * w2p[s];
+                acc += conj(w1m[s]) * Z2[2 * n + s] + conj(w1p[s]) * Z2[2 * n_mu + s];
+            }
+            cplx u = flink(q, n, mu, Lx, Lt);
+            cplx a[2] = {u * xi[2 * n_mu], u * xi[2 * n_mu + 1]};
+            cplx b[2] = {conj(u) * xi[2 * n], conj(u) * xi[2 * n + 1]};
+            cplx pa[2], pb[2];
+            proj(mu, -1, a, pa);
+            proj(mu, +1, b, pb);
+            cplx d2 = 0;
+            for (int s = 0; s < 2; ++s)
+                d2 += conj(chi[2 * n + s]) * 0.5 * pa[s] + conj(chi[2 * n_mu + s]) * 0.5 * pb[s];
+            C[2 * n + mu] = 4.0 * creal(acc - d2 * v[2 * n + mu]);
+        }
+    free(W1); free(W2); free(Z1); free(Z2); free(y);
+    if (it1 < 0 || it2 < 0) return -1;
+    return it1 + it2;
+}
+
+/*
+ * C of Eq. (19) for the force set `which` (0: S_G, 1: S_F, 2: S_G + S_F), assembled from
+ * the parts of Eq. (20): C_GG; C_FF; C_GG + C_FG + C_GF + C_FF.  chi, xi and the fermion
+ * force f belong to the links q (unused when fermions == 0, which drops the fermion
+ * parts).  cnt accumulates [0] CG solves, [1] CG iterations, [2] inversions of D or
+ * D^dagger counted as in Sec. 3 (Z_1 and Z_2 one each), [3] failures.
+ */
+static void fg_term_from(int Lx, int Lt, double beta, double m0, const double *q, int which,
+                         int fermions, const cplx *chi, const cplx *xi, const double *f,
+                         double tol, int max_iter, double *C, long cnt[4])
+{
+    int nl = 2 * Lx * Lt;
+    double *part = malloc(sizeof(double) * nl), *g = malloc(sizeof(double) * nl);
+    for (int l = 0; l < nl; ++l) C[l] = 0;
+    if (which == 0 || which == 2) {
+        orc_fg_term_gg(Lx, Lt, beta, q, part);
+        for (int l = 0; l < nl; ++l) C[l] += part[l];
+    }
+    if ((which == 1 || which == 2) && fermions) {
+        if (which == 2) {
+            orc_fg_term_fg(Lx, Lt, beta, q, f, part); /* C_FG */
+            for (int l = 0; l < nl; ++l) C[l] += part[l];
+            orc_gauge_force(Lx, Lt, beta, q, g); /* C_GF: f replaced by beta g */
+            int it = orc_fg_term_fermion(Lx, Lt, m0, q, chi, xi, g, tol, max_iter, part);
+            cnt[0] += 2; cnt[2] += 2;
+            if (it < 0) { cnt[3]++; it = 2 * max_iter; }
+            cnt[1] += it;
+            for (int l = 0; l < nl; ++l) C[l] += part[l];
+        }
+        int it = orc_fg_term_fermion(Lx, Lt, m0, q, chi, xi, f, tol, max_iter, part); /* C_FF */
+        cnt[0] += 2; cnt[2] += 2;
+        if (it < 0) { cnt[3]++; it = 2 * max_iter; }
+        cnt[1] += it;
+        for (int l = 0; l < nl; ++l) C[l] += part[l];
+    }
+    free(part); free(g);
+}
+
+/*
+ * C of Eq. (19) at links q for the force set `which` (see fg_term_from), solving for chi
+ * and xi first (Eq. (18); two inversions).  counters (optional, 3 entries): CG solves, CG
+ * iterations, inversions.  Returns 0 or -3 if a solve did not converge.
+ */
+int orc_force_gradient_term(int Lx, int Lt, double beta, double m0, const double *q,
+                            const cplx *phi, int which, double tol, int max_iter, double *C,
+                            long *counters)
+{
+    int nl = 2 * Lx * Lt, ns = 2 * Lx * Lt;
+    long cnt[4] = {0, 0, 0, 0};
+    double *f = calloc(nl, sizeof(double));
+    cplx *chi = calloc(ns, sizeof(cplx)), *xi = calloc(ns, sizeof(cplx));
+    if (which == 1 || which == 2) {
+        int it = orc_fermion_force(Lx, Lt, m0, q, phi, tol, max_iter, f, chi, xi, NULL);
+        cnt[0]++; cnt[2] += 2;
+        if (it < 0) { cnt[3]++; it = max_iter; }
+        cnt[1] += it;
+    }
+    fg_term_from(Lx, Lt, beta, m0, q, which, 1, chi, xi, f, tol, max_iter, C, cnt);
+    if (counters) { counters[0] = cnt[0]; counters[1] = cnt[1]; counters[2] = cnt[2]; }
+    free(f); free(chi); free(xi);
+    return cnt[3] ? -3 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Molecular dynamics (Sec. 2.1, 2.2)                                        */
 /* ------------------------------------------------------------------------- */
 
@@ -473,6 +707,7 @@ enum {
 };
 
 #define FLAG_QUENCHED 1 /* drop S_F entirely (pure gauge HMC, used for exact-plaquette tests) */
+#define FLAG_FG_EXACT 2 /* force-gradient kicks use the exact C of Eqs. (19)-(23), not the shift */
 
 typedef struct {
     int Lx, Lt, flags;
@@ -481,8 +716,10 @@ typedef struct {
     double *q, *p;
     const cplx *phi;
     double *F, *F2, *qs; /* scratch: force, shifted force, saved links */
+    double *ff, *C;      /* fermion force of the last force evaluation; force-gradient term */
+    cplx *chi, *xi;      /* chi, xi (Eq. (18)) of the last fermion-force evaluation */
     /* counters */
-    long n_solves, n_cg_iters;
+    long n_solves, n_cg_iters, n_dinv;
     int failed;
     /* optional stage trace */
     int *trace_kind;
@@ -507,14 +744,13 @@ static void force(md_state *s, int which, const double *q, double *F)
     if (which == 0 || which == 2) orc_gauge_force(s->Lx, s->Lt, s->beta, q, F);
     else for (int l = 0; l < nl; ++l) F[l] = 0;
     if ((which == 1 || which == 2) && use_f) {
-        double *ff = malloc(sizeof(double) * nl);
-        int it = orc_fermion_force(s->Lx, s->Lt, s->m0, q, s->phi, s->tol, s->max_iter, ff, NULL,
-                                   NULL, NULL);
+        int it = orc_fermion_force(s->Lx, s->Lt, s->m0, q, s->phi, s->tol, s->max_iter, s->ff,
+                                   s->chi, s->xi, NULL);
         s->n_solves++;
+        s->n_dinv += 2;
         if (it < 0) { s->failed = 1; it = s->max_iter; }
         s->n_cg_iters += it;
-        for (int l = 0; l < nl; ++l) F[l] += ff[l];
-        free(ff);
+        for (int l = 0; l < nl; ++l) F[l] += s->ff[l];
     }
 }
 
@@ -542,7 +778,7 @@ static void stage_B(md_state *s, int which, double eps)
  * equals p - eps F + (h^3/72) C + O(h^5) with C = grad |F|^2 of Eq. (19).  The
  * links are restored afterwards.  `h` is the step of the level the kick belongs to.
  */
-static void stage_B_fg(md_state *s, int which, double eps, double h)
+static void stage_B_fg_shift(md_state *s, int which, double eps, double h)
 {
     int nl = 2 * s->Lx * s->Lt;
     force(s, which, s->q, s->F);
@@ -550,6 +786,33 @@ static void stage_B_fg(md_state *s, int which, double eps, double h)
     force(s, which, s->qs, s->F2);
     for (int l = 0; l < nl; ++l) s->p[l] -= eps * s->F2[l];
     trace(s, which == 0 ? ST_BTG : which == 1 ? ST_BTF : ST_BT, eps);
+}
+
+/*
+ * The same kick with the exact force-gradient term of Eq. (5): p' = p - eps F + (h^3/72) C
+ * with C from Eqs. (19)-(23) for the same force set (C_GG for the gauge force alone, C_FF
+ * for the fermion force alone as the nested schemes require, all four parts for the full
+ * force).
+ */
+static void stage_B_fg_exact(md_state *s, int which, double eps, double h)
+{
+    int nl = 2 * s->Lx * s->Lt;
+    long cnt[4] = {0, 0, 0, 0};
+    force(s, which, s->q, s->F);
+    fg_term_from(s->Lx, s->Lt, s->beta, s->m0, s->q, which, !(s->flags & FLAG_QUENCHED), s->chi,
+                 s->xi, s->ff, s->tol, s->max_iter, s->C, cnt);
+    s->n_solves += cnt[0];
+    s->n_cg_iters += cnt[1];
+    s->n_dinv += cnt[2];
+    if (cnt[3]) s->failed = 1;
+    for (int l = 0; l < nl; ++l) s->p[l] += -eps * s->F[l] + (h * h * h / 72.0) * s->C[l];
+    trace(s, which == 0 ? ST_BTG : which == 1 ? ST_BTF : ST_BT, eps);
+}
+
+static void stage_B_fg(md_state *s, int which, double eps, double h)
+{
+    if (s->flags & FLAG_FG_EXACT) stage_B_fg_exact(s, which, eps, h);
+    else stage_B_fg_shift(s, which, eps, h);
 }
 
 /* Delta_1(s)_M = (e^{s/(2M) B_1} e^{s/M A} e^{s/(2M) B_1})^M, the inner leapfrog of Eq. (8) */
@@ -631,8 +894,9 @@ static void md_step(md_state *s, int scheme, double h, int M)
  * Integrates Hamilton's equations (Eq. (2)) for a trajectory of length tau with
  * n_outer steps h = tau / n_outer; n_inner = M is the number of inner steps in
  * each inner call of the nested schemes.  q and p are updated in place.
- * counters[0] = fermion solves, counters[1] = total CG iterations,
- * counters[2] = stages recorded.  Returns 0, or -3 if a solve did not converge.
+ * counters[0] = CG solves, counters[1] = total CG iterations, counters[2] = stages
+ * recorded, counters[3] = inversions of D or D^dagger counted as in Sec. 3 (two per
+ * fermion-force evaluation, one each for Z_1 and Z_2).  Returns 0, or -3 if a solve did not converge.
  */
 int orc_md_integrate(int Lx, int Lt, double beta, double m0, int scheme, double tau, int n_outer,
                      int n_inner, double tol, int max_iter, int flags, double *q, double *p,
@@ -647,14 +911,19 @@ int orc_md_integrate(int Lx, int Lt, double beta, double m0, int scheme, double 
     s.F = malloc(sizeof(double) * nl);
     s.F2 = malloc(sizeof(double) * nl);
     s.qs = malloc(sizeof(double) * nl);
+    s.ff = calloc(nl, sizeof(double));
+    s.C = malloc(sizeof(double) * nl);
+    s.chi = calloc(nl, sizeof(cplx));
+    s.xi = calloc(nl, sizeof(cplx));
     s.trace_kind = trace_kind; s.trace_eps = trace_eps; s.trace_cap = trace_cap;
     double h = tau / n_outer;
     for (int k = 0; k < n_outer; ++k) md_step(&s, scheme, h, n_inner);
-    free(s.F); free(s.F2); free(s.qs);
+    free(s.F); free(s.F2); free(s.qs); free(s.ff); free(s.C); free(s.chi); free(s.xi);
     if (counters) {
         counters[0] = s.n_solves;
         counters[1] = s.n_cg_iters;
         counters[2] = s.trace_len;
+        counters[3] = s.n_dinv;
     }
     return s.failed ? -3 : 0;
 }
@@ -671,7 +940,8 @@ int orc_md_integrate(int Lx, int Lt, double beta, double m0, int scheme, double 
  *   per-term differences; accept iff Delta H <= 0 or u < exp(-Delta H) with u from stream 3.
  * info[0] = Delta H, info[1] = accepted (0/1), info[2] = mean plaquette after the update,
  * info[3] = fermion solves, info[4] = total CG iterations, info[5] = H0, info[6] = H1,
- * info[7] = Metropolis uniform.
+ * info[7] = Metropolis uniform, info[8] = inversions of D or D^dagger in the molecular
+ * dynamics (as counted by orc_md_integrate).
  * Returns 0, -3 (CG failure: trajectory rejected) or -5 (non-finite Delta H: rejected).
  */
 int orc_hmc_trajectory(int Lx, int Lt, double beta, double m0, uint64_t seed, uint32_t chain,
@@ -693,7 +963,7 @@ int orc_hmc_trajectory(int Lx, int Lt, double beta, double m0, uint64_t seed, ui
     } else {
         for (int k = 0; k < ns; ++k) phi[k] = 0;
     }
-    long counters[3] = {0, 0, 0};
+    long counters[4] = {0, 0, 0, 0};
     int rc = orc_md_integrate(Lx, Lt, beta, m0, scheme, tau, n_outer, n_inner, tol, max_iter,
                               flags, q, p, phi, counters, NULL, NULL, 0);
     double sf1 = 0, sf0 = 0;
@@ -730,7 +1000,7 @@ int orc_hmc_trajectory(int Lx, int Lt, double beta, double m0, uint64_t seed, ui
     if (info) {
         info[0] = dH; info[1] = accept; info[2] = orc_mean_plaquette(Lx, Lt, q);
         info[3] = (double)counters[0]; info[4] = (double)counters[1];
-        info[5] = kval(&h0); info[6] = kval(&h1); info[7] = u;
+        info[5] = kval(&h0); info[6] = kval(&h1); info[7] = u; info[8] = (double)counters[3];
     }
     free(q0); free(p); free(p0); free(zeta); free(phi); free(xi);
     return rc;
