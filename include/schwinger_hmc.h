@@ -67,8 +67,13 @@ enum {
 
 enum { HMC_PREC_FP64 = 0, HMC_PREC_MIXED = 1 };
 
-/* which force for hmc_fg_shifted_force */
+/* which force for hmc_fg_shifted_force, hmc_hessian_vector and hmc_force_gradient_term */
 enum { HMC_FORCE_GAUGE = 0, HMC_FORCE_FERMION = 1, HMC_FORCE_TOTAL = 2 };
+
+/* How the integrators' force-gradient kicks e^{eps B - (h^3/72) C} are formed (Sec. 2.2):
+ * HMC_FG_SHIFT (default): p -= eps F(q - (h^2/24) F(q)), the Taylor-expansion variant;
+ * HMC_FG_EXACT: p -= eps F(q) - (h^3/72) C(q) with C of Eq. (19) from hmc_force_gradient_term. */
+enum { HMC_FG_SHIFT = 0, HMC_FG_EXACT = 1 };
 
 /* named fields inside the bound workspace (hmc_field) */
 enum {
@@ -103,7 +108,8 @@ typedef struct {
     int status;          /* HMC_OK, HMC_E_NOCONV or HMC_E_NAN for this chain */
     int n_force_evals;   /* fermion-force evaluations of the molecular dynamics */
     int n_solves;        /* CG solves actually run (repeated forces at unchanged links are reused) */
-    int n_dinv;          /* inversions of D in the paper's count (2 per fermion-force evaluation) */
+    int n_dinv;          /* inversions of D in the paper's count: 2 per fermion-force evaluation,
+                            plus 2 per Hessian-vector solve of an exact force-gradient term */
     int pad;
     long long n_cg_iters;  /* total CG iterations of this chain over the trajectory */
 } hmc_traj_info;
@@ -249,6 +255,30 @@ int hmc_update_momenta(hmc_ctx *ctx, double eps, const double *F);
  * which == HMC_FORCE_GAUGE.  info: n_chains entries for the last solve (may be NULL). */
 int hmc_fg_shifted_force(hmc_ctx *ctx, double c_h2, int which, const void *phi, double *F_out,
                          int prec, hmc_cg_info *info);
+
+/* Hessian-vector product out = H v, H the matrix of second derivatives d^2 S / dq_a dq_b of
+ * S = S_G (which = HMC_FORCE_GAUGE), S_F (FERMION) or S_G + S_F (TOTAL) at the context's
+ * links, v and out real link fields (device, native layout, out may not alias v).  For the
+ * fermion part (Sec. 3, Eqs. (21)-(23)) xi = (D^dagger D)^{-1} phi and chi = D xi are
+ * solved for first (left in HMC_FIELD_XI/CHI), then one more solve of D^dagger D gives the
+ * Z_2 of Eq. (23) for the weight v (Z_1 follows as D Z_2 - dD[v] xi).  phi is needed unless
+ * which == HMC_FORCE_GAUGE.  Solver tolerance and iteration cap are those of
+ * hmc_set_solver.  info: n_chains entries for the Hessian solve (may be NULL).  Returns
+ * HMC_E_NOCONV if a solve did not converge (out is then inaccurate). */
+int hmc_hessian_vector(hmc_ctx *ctx, int which, const void *phi, const double *v, double *out,
+                       int prec, hmc_cg_info *info);
+
+/* The force-gradient term C = 2 H F = grad |F|^2 of Eq. (19) for the force set which:
+ * C_GG (GAUGE), C_FF (FERMION, the part the nested schemes use), or
+ * C_GG + C_FG + C_GF + C_FF (TOTAL) of Eq. (20).  Two solves of D^dagger D when the fermion
+ * part is included (force, then the Hessian solve).  C: real link field (device).  info:
+ * n_chains entries for the Hessian solve (may be NULL). */
+int hmc_force_gradient_term(hmc_ctx *ctx, int which, const void *phi, double *C, int prec,
+                            hmc_cg_info *info);
+
+/* Selects HMC_FG_SHIFT or HMC_FG_EXACT for the force-gradient kicks of hmc_trajectory and
+ * hmc_integrate (schemes HMC_FORCE_GRADIENT, HMC_NESTED_FG, HMC_ADAPTED_NESTED_FG). */
+int hmc_set_fg_mode(hmc_ctx *ctx, int mode);
 
 /* ---------------------------------------------------------------- HMC (Sec. 2.1, 2.2) */
 

@@ -233,6 +233,11 @@ class Lattice:
     def set_quenched(self, quenched: bool):
         self._check(self._lib.hmc_set_quenched(self._ctx, int(bool(quenched))))
 
+    def set_fg_mode(self, mode: str):
+        """"shift" (default): force-gradient kicks use the shifted force; "exact": they use
+        the force-gradient term C of Eq. (19) through a Hessian-vector product."""
+        self._check(self._lib.hmc_set_fg_mode(self._ctx, _lib.FG_MODES[mode]))
+
     def set_persistent_limit(self, vmax: int):
         """Chains of at most vmax sites solve inside one persistent workgroup (0: never)."""
         self._check(self._lib.hmc_set_persistent_limit(self._ctx, int(vmax)))
@@ -347,6 +352,31 @@ class Lattice:
         self._check(self._lib.hmc_fg_shifted_force(self._ctx, c_h2, w, _ptr(phi), _ptr(out),
                                                    _prec(prec), info))
         return out
+
+    def hessian_vector(self, v: torch.Tensor, which="total", phi=None, prec="fp64",
+                       out: Optional[torch.Tensor] = None):
+        """H v, H the second derivatives of S_G, S_F or S_G + S_F at the current links
+        (Sec. 3, Eqs. (21)-(23)).  Returns (out, CGResult of the Hessian solve or None)."""
+        w = _lib.FORCE_SETS[which] if isinstance(which, str) else int(which)
+        out = self.new_links() if out is None else out
+        info = (_lib.CGInfo * self.n_chains)()
+        rc = self._lib.hmc_hessian_vector(self._ctx, w, _ptr(phi), _ptr(v), _ptr(out), _prec(prec),
+                                          info)
+        if rc != _lib.HMC_E_NOCONV:
+            self._check(rc)
+        return out, (self._cg_result(info) if w != FORCE_GAUGE else None)
+
+    def force_gradient_term(self, which="total", phi=None, prec="fp64",
+                            out: Optional[torch.Tensor] = None):
+        """C = 2 H F of Eq. (19) for the gauge (C_GG), fermion (C_FF) or total force
+        (C_GG + C_FG + C_GF + C_FF).  Returns (C, CGResult of the Hessian solve or None)."""
+        w = _lib.FORCE_SETS[which] if isinstance(which, str) else int(which)
+        out = self.new_links() if out is None else out
+        info = (_lib.CGInfo * self.n_chains)()
+        rc = self._lib.hmc_force_gradient_term(self._ctx, w, _ptr(phi), _ptr(out), _prec(prec), info)
+        if rc != _lib.HMC_E_NOCONV:
+            self._check(rc)
+        return out, (self._cg_result(info) if w != FORCE_GAUGE else None)
 
     # ---------------------------------------------------------------- updates (Sec. 2.1)
     def update_links(self, eps: float):

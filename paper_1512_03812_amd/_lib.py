@@ -16,6 +16,9 @@ SCHEMES = {"leapfrog": LEAPFROG, "omelyan": OMELYAN_5STAGE, "force_gradient": FO
 PREC_FP64, PREC_MIXED = 0, 1
 PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
 FORCE_GAUGE, FORCE_FERMION, FORCE_TOTAL = 0, 1, 2
+FORCE_SETS = {"gauge": FORCE_GAUGE, "fermion": FORCE_FERMION, "total": FORCE_TOTAL}
+FG_SHIFT, FG_EXACT = 0, 1
+FG_MODES = {"shift": FG_SHIFT, "exact": FG_EXACT}
 FIELD_Q, FIELD_P, FIELD_PHI, FIELD_CHI, FIELD_XI, FIELD_F, FIELD_ZETA = range(7)
 
 
@@ -82,6 +85,9 @@ SIGNATURES = {
     "hmc_update_links": (_I, [_P, _D]),
     "hmc_update_momenta": (_I, [_P, _D, _P]),
     "hmc_fg_shifted_force": (_I, [_P, _D, _I, _P, _P, _I, _P]),
+    "hmc_hessian_vector": (_I, [_P, _I, _P, _P, _P, _I, _P]),
+    "hmc_force_gradient_term": (_I, [_P, _I, _P, _P, _I, _P]),
+    "hmc_set_fg_mode": (_I, [_P, _I]),
     "hmc_trajectory": (_I, [_P, _I, _D, _I, _I, _I, _P]),
     "hmc_integrate": (_I, [_P, _I, _D, _I, _I, _I, _P]),
     "hmc_refresh": (_I, [_P]),

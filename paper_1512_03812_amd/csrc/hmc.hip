@@ -25,7 +25,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Names of the real-link and spinor buffers carved out of the workspace.
 enum LinkBuf { LQ, LP, LQ0, LP0, LQS, LF, LFF, LFT, LG, kNumLinkBufs };
-enum SpinBuf { SPHI, SZETA, SXI, SCHI, SR, SPA, SPB, ST, kNumSpinBufs };
+enum SpinBuf { SPHI, SZETA, SXI, SCHI, SR, SPA, SPB, ST, SW, SY, SZ, kNumSpinBufs };
 enum Spin32Buf { FX, FR, FT, FPA, FPB, kNumSpin32Bufs };
 
 }  // namespace
@@ -73,6 +73,7 @@ struct hmc_ctx {
     double delta = 0.1;
     int check_every = 8;
     bool quenched = false;
+    int fg_mode = HMC_FG_SHIFT;
     int persist_vmax = 2048;  // chains with at most this many sites use the persistent solver
     // ------------------------------------------------------------ workspace
     size_t ws_bytes = 0;
@@ -81,7 +82,8 @@ struct hmc_ctx {
     size_t off_chains = 0, off_work = 0, off_active = 0, off_big = 0, off_small = 0, off_cg = 0,
            off_partials = 0,
            off_sums = 0, off_fin = 0, off_metro = 0, off_status = 0, off_count = 0, off_links[kNumLinkBufs] = {},
-           off_spin[kNumSpinBufs] = {}, off_U64 = 0, off_U32 = 0, off_spin32[kNumSpin32Bufs] = {};
+           off_spin[kNumSpinBufs] = {}, off_U64 = 0, off_U32 = 0, off_spin32[kNumSpin32Bufs] = {},
+           off_Uw = 0;
     // ------------------------------------------------------------ solver partition
     hipStream_t side = nullptr;           // second stream for the persistent solver
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
@@ -97,6 +99,7 @@ struct hmc_ctx {
     long links32_version = -1; // same for the FP32 copy
     long ff_version = -1;    // q version of the cached fermion force LFF (-1: none)
     long xi_version = -1;    // q version of the solution in SXI (-1: none / shifted links)
+    long chi_version = -1;   // q version of chi = D xi in SCHI
     std::string err;
     // per-solve bookkeeping of the last CG (host copies)
     std::vector<CGState> cg_host;
@@ -108,6 +111,7 @@ struct hmc_ctx {
     double2 *spin(int b) const { return at<double2>(off_spin[b]); }
     float2 *spin32(int b) const { return at<float2>(off_spin32[b]); }
     double2 *U64() const { return at<double2>(off_U64); }
+    double2 *Uw() const { return at<double2>(off_Uw); }
     float2 *U32() const { return at<float2>(off_U32); }
     CGState *cg() const { return at<CGState>(off_cg); }
     double *sums() const { return at<double>(off_sums); }
@@ -207,6 +211,7 @@ void layout_workspace(hmc_ctx *c, size_t N) {
     for (int b = 0; b < kNumSpinBufs; ++b) c->off_spin[b] = take(sizeof(double2) * 2 * V);
     c->off_U64 = take(sizeof(double2) * 2 * V);
     c->off_U32 = take(sizeof(float2) * 2 * V);
+    c->off_Uw = take(sizeof(double2) * 2 * V);
     for (int b = 0; b < kNumSpin32Bufs; ++b) c->off_spin32[b] = take(sizeof(float2) * 2 * V);
     c->ws_bytes = o;
 }
@@ -287,7 +292,7 @@ void forget_links(hmc_ctx *c) { c->links_version = c->links32_version = -1; }
 void forget_all(hmc_ctx *c) {
     c->q_version++;
     forget_links(c);
-    c->ff_version = c->xi_version = -1;
+    c->ff_version = c->xi_version = c->chi_version = -1;
 }
 
 // Rebuilds the list of workgroups of the unconverged chains; returns its length in *active
@@ -537,7 +542,24 @@ struct MD {
     std::vector<long long> iters;
     int force_evals = 0;
     int solves = 0;
+    int hvp_solves = 0;  // Hessian-vector solves of exact force-gradient terms
 };
+
+// Books one solve's iterations and per-chain convergence; returns rc unless it is only
+// HMC_E_NOCONV (recorded in md.status, the trajectory goes on and the chain is rejected).
+int note_solve(MD &md, int rc) {
+    hmc_ctx *c = md.c;
+    md.solves++;
+    for (int k = 0; k < c->nchains; ++k) {
+        md.iters[k] += c->cg_host[k].iters;
+        if (!c->cg_host[k].converged) md.chain_status[k] = HMC_E_NOCONV;
+    }
+    if (rc == HMC_E_NOCONV) {
+        md.status = rc;
+        return HMC_OK;
+    }
+    return rc;
+}
 
 // fermion force at links q (== LQ when version >= 0) into out; XI/CHI keep xi and chi.
 int fermion_force_at(MD &md, const double *q, long version, double *out) {
@@ -549,17 +571,11 @@ int fermion_force_at(MD &md, const double *q, long version, double *out) {
         return HMC_OK;
     }
     ensure_links(c, q, md.prec == HMC_PREC_MIXED, version);
-    int rc = solve(c, c->spin(SPHI), c->spin(SXI), md.tol, md.max_iter, md.prec);
-    md.solves++;
-    for (int k = 0; k < c->nchains; ++k) {
-        md.iters[k] += c->cg_host[k].iters;
-        if (!c->cg_host[k].converged) md.chain_status[k] = HMC_E_NOCONV;
-    }
-    if (rc == HMC_E_NOCONV) md.status = rc;
-    else if (rc) return rc;
+    int rc = note_solve(md, solve(c, c->spin(SPHI), c->spin(SXI), md.tol, md.max_iter, md.prec));
+    if (rc) return rc;
     launch_dslash64(c->geo(), c->U64(), c->spin(SXI), c->spin(SCHI), false, c->stream);
     launch_fermion_force(c->geo(), c->U64(), c->spin(SCHI), c->spin(SXI), out, c->stream);
-    c->xi_version = version;
+    c->xi_version = c->chi_version = version;
     if (version >= 0) {
         if (out != c->link(LFF))
             launch_copy(out, c->link(LFF), sizeof(double) * 2 * c->Vtot, c->stream);
@@ -599,7 +615,7 @@ int stage_B(MD &md, int which, double eps) {
 }
 
 // force-gradient kick: p -= eps F(q - (h^2/24) F(q)); q is untouched.
-int stage_B_fg(MD &md, int which, double eps, double h) {
+int stage_B_fg_shift(MD &md, int which, double eps, double h) {
     hmc_ctx *c = md.c;
     const Geo g = c->geo();
     int rc = force_at(md, which, c->link(LQ), c->q_version, c->link(LF));
@@ -610,6 +626,69 @@ int stage_B_fg(MD &md, int which, double eps, double h) {
     forget_links(c);
     launch_axpy_links(g, c->link(LP), -eps, c->link(LG), c->link(LP), c->stream);
     return HMC_OK;
+}
+
+// chi, xi (SCHI, SXI) at the current links LQ, solved for unless they are already there.
+int ensure_chixi(MD &md) {
+    hmc_ctx *c = md.c;
+    if (c->xi_version == c->q_version && c->chi_version == c->q_version) return HMC_OK;
+    ensure_links(c, c->link(LQ), md.prec == HMC_PREC_MIXED, c->q_version);
+    int rc = note_solve(md, solve(c, c->spin(SPHI), c->spin(SXI), md.tol, md.max_iter, md.prec));
+    if (rc) return rc;
+    launch_dslash64(c->geo(), c->U64(), c->spin(SXI), c->spin(SCHI), false, c->stream);
+    c->xi_version = c->chi_version = c->q_version;
+    return HMC_OK;
+}
+
+// out = scale * H v at the links LQ for the force set `which` (0 gauge, 1 fermion, 2 total;
+// Sec. 3, Eqs. (20)-(23)).  The fermion part needs chi and xi at LQ and one solve of
+// D^dagger D:  W = dD[v] xi,  Z2 = (D^dagger D)^{-1} (D^dagger W + dD[v]^dagger chi),
+// Z1 = D Z2 - W.  v must not be one of SW, SY, SZ.
+int hessian_vector(MD &md, int which, const double *v, double scale, double *out) {
+    hmc_ctx *c = md.c;
+    const Geo g = c->geo();
+    const bool gauge = which != HMC_FORCE_FERMION;
+    const bool fermion = which != HMC_FORCE_GAUGE && !c->quenched;
+    if (!fermion) {
+        launch_hessian_vector(g, nullptr, v, nullptr, nullptr, nullptr, nullptr, c->link(LQ), gauge,
+                              scale, out, c->stream);
+        return HMC_OK;
+    }
+    int rc = ensure_chixi(md);
+    if (rc) return rc;
+    ensure_links(c, c->link(LQ), md.prec == HMC_PREC_MIXED, c->q_version);
+    launch_weight_links(g, c->U64(), v, c->Uw(), c->stream);
+    launch_stencil2(g, false, c->Uw(), c->spin(SXI), false, nullptr, nullptr, nullptr, c->spin(SW),
+                    c->stream);
+    launch_stencil2(g, true, c->U64(), c->spin(SW), true, c->Uw(), c->spin(SCHI), nullptr,
+                    c->spin(SY), c->stream);
+    md.hvp_solves++;
+    rc = note_solve(md, solve(c, c->spin(SY), c->spin(SZ), md.tol, md.max_iter, md.prec));
+    if (rc) return rc;
+    launch_stencil2(g, false, c->U64(), c->spin(SZ), true, nullptr, nullptr, c->spin(SW), c->spin(SY),
+                    c->stream);
+    launch_hessian_vector(g, c->U64(), v, c->spin(SCHI), c->spin(SXI), c->spin(SY), c->spin(SZ),
+                          c->link(LQ), gauge, scale, out, c->stream);
+    return HMC_OK;
+}
+
+// force-gradient kick with the exact term of Eq. (5): p -= eps F(q) - (h^3/72) C(q) with
+// C = 2 H F (Eq. (19)) for the same force set.
+int stage_B_fg_exact(MD &md, int which, double eps, double h) {
+    hmc_ctx *c = md.c;
+    const Geo g = c->geo();
+    int rc = force_at(md, which, c->link(LQ), c->q_version, c->link(LF));
+    if (rc) return rc;
+    rc = hessian_vector(md, which, c->link(LF), 2.0, c->link(LG));
+    if (rc) return rc;
+    launch_axpy_links(g, c->link(LP), -eps, c->link(LF), c->link(LP), c->stream);
+    launch_axpy_links(g, c->link(LP), h * h * h / 72.0, c->link(LG), c->link(LP), c->stream);
+    return HMC_OK;
+}
+
+int stage_B_fg(MD &md, int which, double eps, double h) {
+    if (md.c->fg_mode == HMC_FG_EXACT) return stage_B_fg_exact(md, which, eps, h);
+    return stage_B_fg_shift(md, which, eps, h);
 }
 
 int inner_leapfrog(MD &md, double s, int M) {
@@ -702,6 +781,7 @@ void init_md(MD &md, hmc_ctx *c, int prec) {
     md.iters.assign(c->nchains, 0);
     c->ff_version = -1;
     c->xi_version = -1;
+    c->chi_version = -1;
     forget_links(c);
 }
 
@@ -1032,7 +1112,7 @@ int hmc_fermion_force(hmc_ctx *c, const void *phi, double *f, double tol, int ma
         if (rc2) return rc2;
         for (int k = 0; k < c->nchains; ++k) sf[k] = h[2 * c->nchains + k];
     }
-    c->ff_version = c->xi_version = -1;
+    c->ff_version = c->xi_version = c->chi_version = -1;
     HIP_TRY(c, hipGetLastError());
     return rc;
 }
@@ -1063,7 +1143,7 @@ int hmc_actions(hmc_ctx *c, const void *phi, double tol, double *s_gauge, double
         ensure_links(c, c->link(LQ), false, c->q_version);
         int rc = solve(c, (const double2 *)phi, c->spin(SXI), tol, c->max_iter, HMC_PREC_FP64);
         if (rc) return rc;
-        c->ff_version = c->xi_version = -1;
+        c->ff_version = c->xi_version = c->chi_version = -1;
     }
     double *dev = c->sums() + 12 * C;
     launch_gauge_energy(c->geo(), c->link(LQ), (phi && s_fermion) ? (const double2 *)phi : nullptr,
@@ -1112,10 +1192,55 @@ int hmc_fg_shifted_force(hmc_ctx *c, double c_h2, int which, const void *phi, do
     rc = force_at(md, which, c->link(LQS), -1, F_out);
     if (rc) return rc;
     forget_links(c);
-    c->ff_version = c->xi_version = -1;
+    c->ff_version = c->xi_version = c->chi_version = -1;
     if (which != HMC_FORCE_GAUGE) fill_cg_info(c, info, nullptr);
     HIP_TRY(c, hipGetLastError());
     return md.status;
+}
+
+int hmc_hessian_vector(hmc_ctx *c, int which, const void *phi, const double *v, double *out,
+                       int prec, hmc_cg_info *info) {
+    CHECK_BOUND(c);
+    if (!v || !out || (const void *)v == (const void *)out || which < 0 || which > 2)
+        return fail(c, HMC_E_INVAL, "bad arguments");
+    if (which != HMC_FORCE_GAUGE && !phi) return fail(c, HMC_E_INVAL, "phi needed");
+    if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
+    MD md;
+    init_md(md, c, prec);
+    if (phi && phi != c->spin(SPHI))
+        launch_copy(phi, c->spin(SPHI), sizeof(double2) * 2 * c->Vtot, c->stream);
+    int rc = hessian_vector(md, which, v, 1.0, out);
+    if (rc) return rc;
+    if (md.hvp_solves) fill_cg_info(c, info, nullptr);
+    HIP_TRY(c, hipGetLastError());
+    return md.status;
+}
+
+int hmc_force_gradient_term(hmc_ctx *c, int which, const void *phi, double *C, int prec,
+                            hmc_cg_info *info) {
+    CHECK_BOUND(c);
+    if (!C || C == c->link(LF) || which < 0 || which > 2)
+        return fail(c, HMC_E_INVAL, "bad arguments (C may not be the F field)");
+    if (which != HMC_FORCE_GAUGE && !phi) return fail(c, HMC_E_INVAL, "phi needed");
+    if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
+    MD md;
+    init_md(md, c, prec);
+    if (phi && phi != c->spin(SPHI))
+        launch_copy(phi, c->spin(SPHI), sizeof(double2) * 2 * c->Vtot, c->stream);
+    int rc = force_at(md, which, c->link(LQ), c->q_version, c->link(LF));
+    if (rc) return rc;
+    rc = hessian_vector(md, which, c->link(LF), 2.0, C);
+    if (rc) return rc;
+    if (md.hvp_solves) fill_cg_info(c, info, nullptr);
+    HIP_TRY(c, hipGetLastError());
+    return md.status;
+}
+
+int hmc_set_fg_mode(hmc_ctx *c, int mode) {
+    if (!c) return HMC_E_INVAL;
+    if (mode != HMC_FG_SHIFT && mode != HMC_FG_EXACT) return fail(c, HMC_E_INVAL, "bad force-gradient mode");
+    c->fg_mode = mode;
+    return HMC_OK;
 }
 
 static int finish_traj(hmc_ctx *c, MD &md, bool metropolis, hmc_traj_info *info) {
@@ -1125,13 +1250,8 @@ static int finish_traj(hmc_ctx *c, MD &md, bool metropolis, hmc_traj_info *info)
     // S_F at the final links: reuse xi if the last solve was at the current q
     if (fermions && c->xi_version != c->q_version) {
         ensure_links(c, c->link(LQ), md.prec == HMC_PREC_MIXED, c->q_version);
-        int rc = solve(c, c->spin(SPHI), c->spin(SXI), md.tol, md.max_iter, md.prec);
-        md.solves++;
-        for (int k = 0; k < C; ++k) {
-            md.iters[k] += c->cg_host[k].iters;
-            if (!c->cg_host[k].converged) md.chain_status[k] = HMC_E_NOCONV;
-        }
-        if (rc && rc != HMC_E_NOCONV) return rc;
+        int rc = note_solve(md, solve(c, c->spin(SPHI), c->spin(SXI), md.tol, md.max_iter, md.prec));
+        if (rc) return rc;
         c->xi_version = c->q_version;
     }
     // sums layout: [0, 7C) energies, [7C, 9C) refresh, [9C, 12C) gauge sums,
@@ -1169,7 +1289,7 @@ static int finish_traj(hmc_ctx *c, MD &md, bool metropolis, hmc_traj_info *info)
             t.plaquette = gh[C + k] / c->chains[k].V;
             t.n_force_evals = md.force_evals;
             t.n_solves = md.solves;
-            t.n_dinv = 2 * md.force_evals;
+            t.n_dinv = 2 * md.force_evals + 2 * md.hvp_solves;
             t.n_cg_iters = md.iters[k];
         }
         if (mh[k].status && status == HMC_OK) status = mh[k].status;
@@ -1244,7 +1364,7 @@ int hmc_integrate(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, 
         if ((rc = to_host(c, h.data(), es, sizeof(double) * 7 * C))) return rc;
         for (int k = 0; k < C; ++k) { r[k] = h[2 * C + k]; r[C + k] = h[5 * C + k]; }
         HIP_TRY(c, hipMemcpyAsync(rs, r.data(), sizeof(double) * 2 * C, hipMemcpyHostToDevice, c->stream));
-        c->xi_version = -1;
+        c->xi_version = c->chi_version = -1;
     }
     rc = run_md(md, scheme, tau, n_outer, n_inner);
     if (rc && rc != HMC_E_NOCONV) return rc;

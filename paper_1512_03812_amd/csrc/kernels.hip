@@ -913,6 +913,165 @@ void launch_gauge_force(const Geo &g, const double *q, const double *add, double
     hipLaunchKernelGGL(k_gauge_force, dim3(g.nblocks), dim3(g.block), 0, s, g, q, add, F);
 }
 
+// ================================================================ Hessian-vector products
+// The derivative of D along a link-field direction v, dD[v] = sum_a v_a dD/dq_a, is the
+// hopping part of D with every fermion link U_mu(n) replaced by i v_mu(n) U_mu(n), since each
+// link enters D as exp(i q).  k_weight_links writes those weighted links.
+__global__ void k_weight_links(Geo g, const double2 *__restrict__ U, const double *__restrict__ v,
+                               double2 *__restrict__ W) {
+    SITES_BEGIN
+    const Site s = decode_site(ci, local);
+    for (int mu = 0; mu < 2; ++mu) {
+        const size_t l = (size_t)mu * Vtot + s.flat;
+        W[l] = cscale(cmuli(U[l]), v[l]);
+    }
+    SITES_END
+}
+
+void launch_weight_links(const Geo &g, const double2 *U, const double *v, double2 *W,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_weight_links, dim3(g.nblocks), dim3(g.block), 0, s, g, U, v, W);
+}
+
+// out = S(L1; in1) [+ H(L2; in2)] [- sub], where S is the Wilson stencil with links L1 and mass
+// term 2 + m0 (mass1 != 0) or its hopping part alone (mass1 == 0), and H the hopping part
+// with links L2; DAG applies the dagger form to every stencil.
+template <bool DAG>
+__global__ void k_stencil2(Geo g, const double2 *__restrict__ L1, const double2 *__restrict__ in1,
+                           int mass1, const double2 *__restrict__ L2,
+                           const double2 *__restrict__ in2, const double2 *__restrict__ sub,
+                           double2 *__restrict__ out) {
+    SITES_BEGIN
+    const Site s = decode_site(ci, local);
+    const Nbr nb = neighbours(ci, s);
+    auto load1 = [&](int f, double2 &b0, double2 &b1) { b0 = in1[f]; b1 = in1[(size_t)Vtot + f]; };
+    double2 o0, o1;
+    dslash_site<double, DAG>(nb, s.flat, Vtot, L1, in1[s.flat], in1[(size_t)Vtot + s.flat],
+                             mass1 ? 2.0 + ci.m0 : 0.0, load1, o0, o1);
+    if (in2) {
+        auto load2 = [&](int f, double2 &b0, double2 &b1) { b0 = in2[f]; b1 = in2[(size_t)Vtot + f]; };
+        double2 h0, h1;
+        const double2 zero = make_double2(0.0, 0.0);
+        dslash_site<double, DAG>(nb, s.flat, Vtot, L2, zero, zero, 0.0, load2, h0, h1);
+        o0 = cadd(o0, h0);
+        o1 = cadd(o1, h1);
+    }
+    if (sub) {
+        o0 = csub(o0, sub[s.flat]);
+        o1 = csub(o1, sub[(size_t)Vtot + s.flat]);
+    }
+    out[s.flat] = o0;
+    out[(size_t)Vtot + s.flat] = o1;
+    SITES_END
+}
+
+void launch_stencil2(const Geo &g, bool dagger, const double2 *L1, const double2 *in1, bool mass1,
+                     const double2 *L2, const double2 *in2, const double2 *sub, double2 *out,
+                     hipStream_t s) {
+    if (dagger)
+        hipLaunchKernelGGL(k_stencil2<true>, dim3(g.nblocks), dim3(g.block), 0, s, g, L1, in1,
+                           mass1 ? 1 : 0, L2, in2, sub, out);
+    else
+        hipLaunchKernelGGL(k_stencil2<false>, dim3(g.nblocks), dim3(g.block), 0, s, g, L1, in1,
+                           mass1 ? 1 : 0, L2, in2, sub, out);
+}
+
+// The two hopping bilinears of the link (n, mu) for spinor fields X, Y:
+//   T1 = X(n)^dagger (1 - sigma_mu) U_mu(n) Y(n + mu),
+//   T2 = X(n + mu)^dagger (1 + sigma_mu) U_mu^dagger(n) Y(n),
+// through the rank-one projector forms of the force kernel.
+struct LinkSpinors {
+    double2 a0, a1;  // field at n
+    double2 b0, b1;  // field at n + mu
+};
+__device__ __forceinline__ LinkSpinors link_spinors(const double2 *__restrict__ f, int Vtot, int n,
+                                                    int nmu) {
+    LinkSpinors r;
+    r.a0 = f[n]; r.a1 = f[(size_t)Vtot + n];
+    r.b0 = f[nmu]; r.b1 = f[(size_t)Vtot + nmu];
+    return r;
+}
+template <int MU>
+__device__ __forceinline__ void bilinears(const LinkSpinors &X, const LinkSpinors &Y, double2 u,
+                                          double2 &T1, double2 &T2) {
+    if (MU == 0) {
+        T1 = cmulc(csub(X.a0, X.a1), cmul(u, csub(Y.b0, Y.b1)));
+        T2 = cmulc(cadd(X.b0, X.b1), cmulc(u, cadd(Y.a0, Y.a1)));
+    } else {
+        T1 = cmulc(cadd(X.a0, cmuli(X.a1)), cmul(u, cadd(Y.b0, cmuli(Y.b1))));
+        T2 = cmulc(csub(X.b0, cmuli(X.b1)), cmulc(u, csub(Y.a0, cmuli(Y.a1))));
+    }
+}
+
+// (H v)_a for S_F = phi^dagger (D^dagger D)^{-1} phi at the link a = (n, mu).  With
+// xi = (D^dagger D)^{-1} phi, chi = D xi, dD_a = dD/dq_a:
+//   (H v)_a = 2 Re[ Z1^dagger dD_a xi + chi^dagger dD_a Z2 - v_a chi^dagger d2D_a xi ],
+//   Z2 = D^{-1} (dD[v] xi + Z1), Z1 = D^{dagger -1} dD[v]^dagger chi   (Sec. 3, Eqs. (21)-(23)).
+// Here Z2 = (D^dagger D)^{-1} (D^dagger dD[v] xi + dD[v]^dagger chi), one normal-equation
+// solve, and Z1 = D Z2 - dD[v] xi.  dD_a has the entries -(i/2)(1 - sigma_mu) U at
+// (n, n+mu) and (i/2)(1 + sigma_mu) U^dagger at (n+mu, n); d2D_a is minus the hopping entries,
+// so with T1, T2 above:
+//   2 Re[X^dagger dD_a Y] = Im(T1 - T2),   2 Re[X^dagger d2D_a Y] = Re(T1 + T2).
+template <int MU>
+__device__ __forceinline__ double hvp_fermion_link(const LinkSpinors &chi, const LinkSpinors &xi,
+                                                   const LinkSpinors &z1, const LinkSpinors &z2,
+                                                   double2 u, double va) {
+    double2 t1, t2, s1, s2, c1, c2;
+    bilinears<MU>(z1, xi, u, t1, t2);
+    bilinears<MU>(chi, z2, u, s1, s2);
+    bilinears<MU>(chi, xi, u, c1, c2);
+    return (t1.y - t2.y) + (s1.y - s2.y) - va * (c1.x + c2.x);
+}
+
+// out = scale * (H v) for the action selected by the pointers: the fermion part when chi is
+// given (xi, z1, z2 as above), the gauge part when gauge != 0.  The gauge part follows from
+// F_x(n) = beta [sin th(n) - sin th(n - t)], F_t(n) = beta [sin th(n - x) - sin th(n)]:
+//   (H_G v)_x(n) = beta [cos th(n) dth(n) - cos th(n - t) dth(n - t)],
+//   (H_G v)_t(n) = beta [cos th(n - x) dth(n - x) - cos th(n) dth(n)],
+// with dth the plaquette combination of v.
+__global__ void k_hessian_vector(Geo g, const double2 *__restrict__ U, const double *__restrict__ v,
+                                 const double2 *__restrict__ chi, const double2 *__restrict__ xi,
+                                 const double2 *__restrict__ z1, const double2 *__restrict__ z2,
+                                 const double *__restrict__ q, int gauge, double scale,
+                                 double *__restrict__ out) {
+    SITES_BEGIN
+    const Site s = decode_site(ci, local);
+    const size_t lx = s.flat, lt = (size_t)Vtot + s.flat;
+    double hx = 0.0, ht = 0.0;
+    if (chi) {
+        const int nxp = flat_of(ci, wrap_inc(s.x, ci.Lx), s.t);
+        const int ntp = flat_of(ci, s.x, wrap_inc(s.t, ci.Lt));
+        {
+            const LinkSpinors C = link_spinors(chi, Vtot, s.flat, nxp), X = link_spinors(xi, Vtot, s.flat, nxp);
+            const LinkSpinors A = link_spinors(z1, Vtot, s.flat, nxp), B = link_spinors(z2, Vtot, s.flat, nxp);
+            hx += hvp_fermion_link<0>(C, X, A, B, U[lx], v[lx]);
+        }
+        {
+            const LinkSpinors C = link_spinors(chi, Vtot, s.flat, ntp), X = link_spinors(xi, Vtot, s.flat, ntp);
+            const LinkSpinors A = link_spinors(z1, Vtot, s.flat, ntp), B = link_spinors(z2, Vtot, s.flat, ntp);
+            ht += hvp_fermion_link<1>(C, X, A, B, U[lt], v[lt]);
+        }
+    }
+    if (gauge) {
+        const int tm = wrap_dec(s.t, ci.Lt), xm = wrap_dec(s.x, ci.Lx);
+        const double a0 = cos(plaq_angle(ci, q, Vtot, s.x, s.t)) * plaq_angle(ci, v, Vtot, s.x, s.t);
+        const double at = cos(plaq_angle(ci, q, Vtot, s.x, tm)) * plaq_angle(ci, v, Vtot, s.x, tm);
+        const double ax = cos(plaq_angle(ci, q, Vtot, xm, s.t)) * plaq_angle(ci, v, Vtot, xm, s.t);
+        hx += ci.beta * (a0 - at);
+        ht += ci.beta * (ax - a0);
+    }
+    out[lx] = scale * hx;
+    out[lt] = scale * ht;
+    SITES_END
+}
+
+void launch_hessian_vector(const Geo &g, const double2 *U, const double *v, const double2 *chi,
+                           const double2 *xi, const double2 *z1, const double2 *z2,
+                           const double *q, bool gauge, double scale, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_hessian_vector, dim3(g.nblocks), dim3(g.block), 0, s, g, U, v, chi, xi,
+                       z1, z2, q, gauge ? 1 : 0, scale, out);
+}
+
 // ================================================================ updates
 __global__ void k_axpy(const double *__restrict__ a, double c, const double *__restrict__ b,
                        double *__restrict__ out, size_t n) {

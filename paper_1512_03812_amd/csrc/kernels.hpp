@@ -108,6 +108,21 @@ void launch_fermion_force(const Geo &g, const double2 *U, const double2 *chi, co
 // F = dS_G/dq (Eq. (16)), plus add[] if add != null (add may alias F).
 void launch_gauge_force(const Geo &g, const double *q, const double *add, double *F, hipStream_t s);
 
+// ---------------------------------------------------------------- Hessian-vector products
+// W = i v U per link (the links of dD[v], the derivative of D along v).
+void launch_weight_links(const Geo &g, const double2 *U, const double *v, double2 *W, hipStream_t s);
+// out = S(L1; in1) [+ H(L2; in2)] [- sub]: S the Wilson stencil with links L1 (mass term
+// 2 + m0 if mass1, else hopping part only), H the hopping part with links L2 (in2 may be
+// null), sub may be null; dagger applies the dagger form to both.
+void launch_stencil2(const Geo &g, bool dagger, const double2 *L1, const double2 *in1, bool mass1,
+                     const double2 *L2, const double2 *in2, const double2 *sub, double2 *out,
+                     hipStream_t s);
+// out = scale * (H v): fermion part if chi != null (xi, z1, z2 as in the kernel), gauge part
+// if gauge (links q).
+void launch_hessian_vector(const Geo &g, const double2 *U, const double *v, const double2 *chi,
+                           const double2 *xi, const double2 *z1, const double2 *z2,
+                           const double *q, bool gauge, double scale, double *out, hipStream_t s);
+
 // ---------------------------------------------------------------- updates
 void launch_axpy_links(const Geo &g, const double *a, double c, const double *b, double *out,
                        hipStream_t s);  // out = a + c b over the real link fields

@@ -66,8 +66,9 @@ def test_workspace_size_and_geometry(lib):
     assert lib.hmc_geometry(ctx, ctypes.byref(n), ctypes.byref(vt), offs, None, None) == 0
     assert n.value == 3 and vt.value == 256 + 48 + 8
     assert list(offs) == [0, 256, 304]
-    # at least the FP64 fields: 9 real link fields, 8 spinors, links, FP32 fields
-    assert lib.hmc_workspace_bytes(ctx) >= vt.value * (9 * 16 + 8 * 32 + 32 + 16 + 5 * 16)
+    # at least the FP64 fields: 9 real link fields, 11 spinors, two complex link fields,
+    # the FP32 links and the FP32 solver fields
+    assert lib.hmc_workspace_bytes(ctx) >= vt.value * (9 * 16 + 11 * 32 + 2 * 32 + 16 + 5 * 16)
     assert lib.hmc_destroy(ctx) == 0
 
 
@@ -83,6 +84,10 @@ def test_unbound_context_is_rejected_without_touching_the_gpu(lib):
     assert lib.hmc_set_solver(ctx, 1e-10, 10, 0.1) == 0
     assert lib.hmc_set_trajectory_counter(ctx, 17) == 0
     assert lib.hmc_get_trajectory_counter(ctx) == 17
+    assert lib.hmc_set_fg_mode(ctx, 2) == -1
+    assert lib.hmc_set_fg_mode(ctx, 1) == 0 and lib.hmc_set_fg_mode(ctx, 0) == 0
+    assert lib.hmc_force_gradient_term(ctx, 2, buf, buf, 0, None) == -1
+    assert lib.hmc_hessian_vector(ctx, 0, None, buf, buf, 0, None) == -1
     assert lib.hmc_destroy(ctx) == 0
     assert lib.hmc_destroy(None) == -1
 

@@ -274,12 +274,13 @@ def test_md_parity(scheme):
 
 
 # ------------------------------------------------------------------ HMC trajectories
-def run_oracle_chain(Lx, Lt, beta, m0, seed, chain, n_traj, scheme, tau, n_outer, n_inner, tol):
+def run_oracle_chain(Lx, Lt, beta, m0, seed, chain, n_traj, scheme, tau, n_outer, n_inner, tol,
+                     fg_exact=False, quenched=False):
     q = oracle.random_links(Lx, Lt, seed, chain)
     out = []
     for t in range(n_traj):
         q, info = oracle.hmc_trajectory(q, beta, m0, seed, chain, t, scheme, tau, n_outer, n_inner,
-                                        tol=tol)
+                                        tol=tol, fg_exact=fg_exact, quenched=quenched)
         out.append((q.copy(), info))
     return out
 
@@ -382,6 +383,153 @@ def test_trajectory_is_bitwise_reproducible():
         r = [b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2) for _ in range(2)]
         out.append((b.lat.q.cpu().numpy().copy(), [x.dH for x in r]))
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
+# ------------------------------------------------------------------ exact force-gradient term
+def oracle_hessian_vector(q, phi, v, beta, m0, which, tol=1e-14):
+    """H v from the oracle: the C_FG closed form is twice the gauge Hessian applied to its
+    force argument, and the Z_1/Z_2 construction with weight v is twice the fermion one."""
+    out = np.zeros_like(q)
+    if which in ("gauge", "total"):
+        out += 0.5 * oracle.fg_term_fg(q, v, beta)
+    if which in ("fermion", "total"):
+        _, chi, xi, _, _ = oracle.fermion_force(q, phi, m0, tol=tol)
+        out += 0.5 * oracle.fg_term_fermion(q, chi, xi, v, m0, tol=tol)[0]
+    return out
+
+
+@pytest.mark.parametrize("persistent", SOLVERS)
+@pytest.mark.parametrize("which", ["gauge", "fermion", "total"])
+@pytest.mark.parametrize("Lx,Lt", [(8, 8), (6, 10), (34, 18)])
+def test_hessian_vector_parity(Lx, Lt, which, persistent):
+    beta, m0 = 1.7, 0.1
+    b = Batch([(Lx, Lt, beta, m0)], persistent=persistent)
+    q = inputs.random_angles(Lx, Lt, 111)
+    phi = inputs.random_spinor(Lx, Lt, 112)
+    v = inputs.random_momenta(Lx, Lt, 113)
+    b.set_q([q])
+    b.lat.set_solver(tol=1e-14)
+    out, res = b.lat.hessian_vector(b.links_to_native([v]), which, b.spinor_to_native([phi]))
+    ref = oracle_hessian_vector(q, phi, v, beta, m0, which)
+    assert rel(b.links_from_native(out)[0], ref) < 1e-9
+    if which != "gauge":
+        assert res.converged[0]
+
+
+@pytest.mark.parametrize("persistent", SOLVERS)
+@pytest.mark.parametrize("which", ["gauge", "fermion", "total"])
+def test_force_gradient_term_parity(which, persistent):
+    Lx, Lt, beta, m0 = 8, 6, 2.0, 0.1
+    b = Batch([(Lx, Lt, beta, m0)], persistent=persistent)
+    q = inputs.random_angles(Lx, Lt, 121)
+    phi = inputs.random_spinor(Lx, Lt, 122)
+    b.set_q([q])
+    b.lat.set_solver(tol=1e-14)
+    C, _ = b.lat.force_gradient_term(which, b.spinor_to_native([phi]))
+    ref, info = oracle.force_gradient_term(q, phi, beta, m0, which, tol=1e-14)
+    assert info["rc"] == 0
+    assert rel(b.links_from_native(C)[0], ref) < 1e-9
+
+
+def test_force_gradient_term_batch_of_uneven_chains():
+    shapes = [(8, 8, 2.0, 0.1), (4, 6, 1.5, 0.2), (34, 18, 3.0, 0.05), (2, 2, 1.0, 0.15),
+              (64, 64, 2.0, 0.1)]
+    b = Batch(shapes)
+    q = [inputs.random_angles(s[0], s[1], 130 + i) for i, s in enumerate(shapes)]
+    phi = [inputs.random_spinor(s[0], s[1], 140 + i) for i, s in enumerate(shapes)]
+    b.set_q(q)
+    b.lat.set_solver(tol=1e-14)
+    C, res = b.lat.force_gradient_term("total", b.spinor_to_native(phi))
+    got = b.links_from_native(C)
+    for i, s in enumerate(shapes):
+        ref, _ = oracle.force_gradient_term(q[i], phi[i], s[2], s[3], "total", tol=1e-14)
+        assert rel(got[i], ref) < 1e-9, i
+        assert res.converged[i]
+
+
+def test_force_gradient_term_128_and_mixed_precision():
+    """128 x 128 (the differentiation workload's size), FP64 and mixed precision."""
+    L, beta, m0 = 128, 2.0, 0.1
+    b = Batch([(L, L, beta, m0)])
+    q = inputs.smooth_angles(L, L, 151, 0.4)
+    phi = inputs.random_spinor(L, L, 152)
+    b.set_q([q])
+    ref, _ = oracle.force_gradient_term(q, phi, beta, m0, "fermion", tol=1e-13)
+    b.lat.set_solver(tol=1e-13)
+    C, res = b.lat.force_gradient_term("fermion", b.spinor_to_native([phi]))
+    assert res.converged[0] and rel(b.links_from_native(C)[0], ref) < 1e-8
+    b.lat.set_solver(tol=1e-10)
+    C, res = b.lat.force_gradient_term("fermion", b.spinor_to_native([phi]), prec="mixed")
+    assert res.converged[0] and rel(b.links_from_native(C)[0], ref) < 1e-6
+
+
+@pytest.mark.parametrize("scheme", ["force_gradient", "nested_fg", "adapted_nested_fg"])
+def test_md_parity_exact_force_gradient(scheme):
+    Lx, Lt, beta, m0 = 8, 8, 2.0, 0.1
+    b = Batch([(Lx, Lt, beta, m0)])
+    q = inputs.random_angles(Lx, Lt, 161)
+    p = inputs.random_momenta(Lx, Lt, 162)
+    phi = inputs.random_spinor(Lx, Lt, 163)
+    b.set_q([q])
+    b.links_to_native([p], out=b.lat.p)
+    b.spinor_to_native([phi], out=b.lat.phi)
+    b.lat.set_solver(tol=1e-14)
+    b.lat.set_fg_mode("exact")
+    res = b.lat.integrate(scheme, 1.0, 4, 3)
+    q1, p1, info = oracle.md_integrate(q, p, phi, beta, m0, scheme, 1.0, 4, 3, tol=1e-14,
+                                       fg_exact=True)
+    assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - q1)) < 1e-10
+    assert np.max(np.abs(b.links_from_native(b.lat.p)[0] - p1)) < 1e-10
+    dH_ref = oracle.hamiltonian(q1, p1, phi, beta, m0) - oracle.hamiltonian(q, p, phi, beta, m0)
+    assert abs(res.dH[0] - dH_ref) < 1e-10 * max(1.0, abs(dH_ref))
+
+
+@pytest.mark.parametrize("persistent", SOLVERS)
+@pytest.mark.parametrize("scheme,n_outer,n_inner", [
+    ("force_gradient", 4, 1), ("nested_fg", 4, 2), ("adapted_nested_fg", 4, 2)])
+def test_trajectory_parity_exact_force_gradient(scheme, n_outer, n_inner, persistent):
+    seed = 78
+    b = Batch([(8, 8, 2.0, 0.1)], seed=seed, persistent=persistent)
+    b.lat.hot_start()
+    b.lat.set_solver(tol=1e-13)
+    b.lat.set_fg_mode("exact")
+    ref = run_oracle_chain(8, 8, 2.0, 0.1, seed, 0, 3, scheme, 1.0, n_outer, n_inner, 1e-13,
+                           fg_exact=True)
+    for t in range(3):
+        r = b.lat.trajectory(scheme, 1.0, n_outer, n_inner)
+        qr, ir = ref[t]
+        assert r.accepted[0] == ir["accepted"]
+        assert abs(r.dH[0] - ir["dH"]) < 1e-10 * max(1.0, abs(ir["dH"]))
+        assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - qr)) < 1e-9
+
+
+def test_exact_force_gradient_inversion_counts():
+    """The library forms C_GF + C_FF with one Hessian solve (2 inversions), so Eq. (5) with
+    the exact term costs 8 inversions per step where the paper's separate Z solves cost
+    10; the nested schemes keep the paper's 8."""
+    b = Batch([(8, 8)], seed=3)
+    b.lat.hot_start()
+    b.lat.set_fg_mode("exact")
+    for scheme, per_step in {"force_gradient": 8, "nested_fg": 8, "adapted_nested_fg": 8}.items():
+        r = b.lat.trajectory(scheme, 1.0, 3, 2)
+        assert r.n_dinv == 3 * per_step, scheme
+        assert all(s == 0 for s in r.status)
+
+
+def test_quenched_exact_force_gradient_matches_oracle():
+    seed = 91
+    b = Batch([(8, 8, 2.0, 0.1)], seed=seed)
+    b.lat.hot_start()
+    b.lat.set_quenched(True)
+    b.lat.set_fg_mode("exact")
+    ref = run_oracle_chain(8, 8, 2.0, 0.1, seed, 0, 2, "force_gradient", 1.0, 4, 1, 1e-12,
+                           fg_exact=True, quenched=True)
+    for t in range(2):
+        r = b.lat.trajectory("force_gradient", 1.0, 4, 1)
+        qr, ir = ref[t]
+        assert r.accepted[0] == ir["accepted"] and r.n_dinv == 0
+        assert abs(r.dH[0] - ir["dH"]) < 1e-11 * max(1.0, abs(ir["dH"]))
+        assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - qr)) < 1e-10
 
 
 # ------------------------------------------------------------------ mixed precision
