@@ -109,7 +109,7 @@ struct hmc_ctx {
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
     double *link(int b) const { return at<double>(off_links[b]); }
     double2 *spin(int b) const { return at<double2>(off_spin[b]); }
-    float2 *spin32(int b) const { return at<float2>(off_spin32[b]); }
+    float4 *spin32(int b) const { return at<float4>(off_spin32[b]); }
     double2 *U64() const { return at<double2>(off_U64); }
     double2 *Uw() const { return at<double2>(off_Uw); }
     float2 *U32() const { return at<float2>(off_U32); }
@@ -212,7 +212,7 @@ void layout_workspace(hmc_ctx *c, size_t N) {
     c->off_U64 = take(sizeof(double2) * 2 * V);
     c->off_U32 = take(sizeof(float2) * 2 * V);
     c->off_Uw = take(sizeof(double2) * 2 * V);
-    for (int b = 0; b < kNumSpin32Bufs; ++b) c->off_spin32[b] = take(sizeof(float2) * 2 * V);
+    for (int b = 0; b < kNumSpin32Bufs; ++b) c->off_spin32[b] = take(sizeof(float4) * V);
     c->ws_bytes = o;
 }
 

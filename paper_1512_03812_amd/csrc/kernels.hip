@@ -149,6 +149,32 @@ __device__ __forceinline__ double norm2(float2 a) {
     return (double)a.x * (double)a.x + (double)a.y * (double)a.y;
 }
 
+// Spinor access.  FP64 fields are structure-of-arrays, [s][Vtot] double2 (the public native
+// layout).  The FP32 fields of the mixed-precision solver are internal and hold one float4
+// (s0.re, s0.im, s1.re, s1.im) per site, so a site's spinor is a single 16-byte access.
+__device__ __forceinline__ void sp_load(const double2 *__restrict__ a, int Vtot, int f, double2 &b0,
+                                        double2 &b1) {
+    b0 = a[f];
+    b1 = a[(size_t)Vtot + f];
+}
+__device__ __forceinline__ void sp_load(const float4 *__restrict__ a, int, int f, float2 &b0,
+                                        float2 &b1) {
+    const float4 v = a[f];
+    b0 = make_float2(v.x, v.y);
+    b1 = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void sp_store(double2 *__restrict__ a, int Vtot, int f, double2 b0,
+                                         double2 b1) {
+    a[f] = b0;
+    a[(size_t)Vtot + f] = b1;
+}
+__device__ __forceinline__ void sp_store(float4 *__restrict__ a, int, int f, float2 b0, float2 b1) {
+    a[f] = make_float4(b0.x, b0.y, b1.x, b1.y);
+}
+template <bool MIXED> struct Prec;
+template <> struct Prec<false> { using R = double; using S = double2; };  // S: spinor storage
+template <> struct Prec<true> { using R = float; using S = float4; };
+
 // Loop over the sites of this workgroup; `local` is the chain-local site index.  Threads
 // [0, B/2) take the even plane and [B/2, B) the odd plane at the same half-site indices.
 #define SITES_LOOP                                                                \
@@ -249,27 +275,23 @@ void launch_dslash64(const Geo &g, const double2 *U, const double2 *in, double2 
 // FP64 recomputation (or reached the target) the next slot recomputes
 // r = phi - D^dagger D (x64 + x32) in FP64, folds x32 into x64 and restarts the FP32
 // residual from it (reliable update); convergence is only declared on that FP64 residual.
-template <bool MIXED> struct Prec;
-template <> struct Prec<false> { using R = double; };
-template <> struct Prec<true> { using R = float; };
-
 template <bool MIXED>
 __global__ void k_cg_init(Geo g, CGFields f, double delta2) {
     double v[1] = {0.0};
     SITES_BEGIN
     const int fl = ci.off + local;
-    for (int sp = 0; sp < 2; ++sp) {
-        const size_t k = (size_t)sp * Vtot + fl;
-        const double2 a = f.phi[k];
-        f.x64[k] = make_double2(0.0, 0.0);
-        if (MIXED) {
-            f.x32[k] = make_float2(0.f, 0.f);
-            f.r32[k] = make_float2((float)a.x, (float)a.y);
-        } else {
-            f.r64[k] = a;
-        }
-        v[0] += norm2(a);
+    double2 a0, a1;
+    sp_load(f.phi, Vtot, fl, a0, a1);
+    const double2 z = make_double2(0.0, 0.0);
+    sp_store(f.x64, Vtot, fl, z, z);
+    if (MIXED) {
+        f.x32[fl] = make_float4(0.f, 0.f, 0.f, 0.f);
+        sp_store(f.r32, Vtot, fl, make_float2((float)a0.x, (float)a0.y),
+                 make_float2((float)a1.x, (float)a1.y));
+    } else {
+        sp_store(f.r64, Vtot, fl, a0, a1);
     }
+    v[0] += norm2(a0) + norm2(a1);
     SITES_END
     write_partials<1>(v, f.p2, g.nlog, w.logical);
     if (w.logical == ci.block0 && threadIdx.x == 0) {
@@ -284,6 +306,7 @@ template <bool MIXED>
 __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void *p_old_v,
                            void *p_new_v, int decide_only) {
     using R = typename Prec<MIXED>::R;
+    using S = typename Prec<MIXED>::S;
     using C = cplx_t<R>;
     const BlockWork w = g.work[blockIdx.x];
     const ChainInfo ci = g.chains[w.chain];
@@ -330,31 +353,32 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
         out->n_updates = n_nupd;
     }
     if (n_conv || decide_only) return;
-    const C *__restrict__ p_old = (const C *)p_old_v;
-    C *__restrict__ p_new = (C *)p_new_v;
+    const S *__restrict__ p_old = (const S *)p_old_v;
+    S *__restrict__ p_new = (S *)p_new_v;
     if (MIXED && update) {
         // FP64 residual recomputation, first half: t64 = D (x64 + x32); p carried over.
         SITES_LOOP
         const Site s = decode_site(ci, local);
         const Nbr nb = neighbours(ci, s);
         auto load = [&](int fl, double2 &b0, double2 &b1) {
-            const double2 y0 = f.x64[fl], y1 = f.x64[(size_t)Vtot + fl];
-            const float2 z0 = f.x32[fl], z1 = f.x32[(size_t)Vtot + fl];
-            b0 = make_double2(y0.x + (double)z0.x, y0.y + (double)z0.y);
-            b1 = make_double2(y1.x + (double)z1.x, y1.y + (double)z1.y);
+            double2 y0, y1;
+            sp_load(f.x64, Vtot, fl, y0, y1);
+            const float4 z = f.x32[fl];
+            b0 = make_double2(y0.x + (double)z.x, y0.y + (double)z.y);
+            b1 = make_double2(y1.x + (double)z.z, y1.y + (double)z.w);
         };
         double2 a0, a1, o0, o1;
         load(s.flat, a0, a1);
         dslash_site<double, false>(nb, s.flat, Vtot, f.U64, a0, a1, 2.0 + ci.m0, load, o0, o1);
-        f.t64[s.flat] = o0;
-        f.t64[(size_t)Vtot + s.flat] = o1;
-        p_new[s.flat] = p_old[s.flat];
-        p_new[(size_t)Vtot + s.flat] = p_old[(size_t)Vtot + s.flat];
+        sp_store(f.t64, Vtot, s.flat, o0, o1);
+        C q0, q1;
+        sp_load(p_old, Vtot, s.flat, q0, q1);
+        sp_store(p_new, Vtot, s.flat, q0, q1);
         SITES_END
         return;
     }
-    const C *__restrict__ r;
-    C *__restrict__ t;
+    const S *__restrict__ r;
+    S *__restrict__ t;
     const C *__restrict__ U;
     if constexpr (MIXED) { r = f.r32; t = f.t32; U = f.U32; }
     else { r = f.r64; t = f.t64; U = f.U64; }
@@ -364,10 +388,10 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     const Site s = decode_site(ci, local);
     const Nbr nb = neighbours(ci, s);
     auto load = [&](int fl, C &b0, C &b1) {
-        b0 = r[fl];
-        b1 = r[(size_t)Vtot + fl];
+        sp_load(r, Vtot, fl, b0, b1);
         if (!first) {
-            const C q0 = p_old[fl], q1 = p_old[(size_t)Vtot + fl];
+            C q0, q1;
+            sp_load(p_old, Vtot, fl, q0, q1);
             b0 = cmake<C>(b0.x + beta * q0.x, b0.y + beta * q0.y);
             b1 = cmake<C>(b1.x + beta * q1.x, b1.y + beta * q1.y);
         }
@@ -375,10 +399,8 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     C a0, a1, o0, o1;
     load(s.flat, a0, a1);
     dslash_site<R, false>(nb, s.flat, Vtot, U, a0, a1, (R)(2.0 + ci.m0), load, o0, o1);
-    p_new[s.flat] = a0;
-    p_new[(size_t)Vtot + s.flat] = a1;
-    t[s.flat] = o0;
-    t[(size_t)Vtot + s.flat] = o1;
+    sp_store(p_new, Vtot, s.flat, a0, a1);
+    sp_store(t, Vtot, s.flat, o0, o1);
     v[0] += norm2(o0) + norm2(o1);
     SITES_END
     write_partials<1>(v, f.p1, g.nlog, w.logical);
@@ -387,6 +409,7 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
 template <bool MIXED>
 __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
     using R = typename Prec<MIXED>::R;
+    using S = typename Prec<MIXED>::S;
     using C = cplx_t<R>;
     const BlockWork w = g.work[blockIdx.x];
     const ChainInfo ci = g.chains[w.chain];
@@ -408,49 +431,49 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
         double2 a0, a1;
         dslash_site<double, true>(nb, s.flat, Vtot, f.U64, f.t64[s.flat],
                                   f.t64[(size_t)Vtot + s.flat], 2.0 + ci.m0, load, a0, a1);
-        const double2 Ay[2] = {a0, a1};
-        for (int sp = 0; sp < 2; ++sp) {
-            const size_t k = (size_t)sp * Vtot + s.flat;
-            const double2 ph = f.phi[k];
-            const double2 rr = make_double2(ph.x - Ay[sp].x, ph.y - Ay[sp].y);
-            const double2 xx = f.x64[k];
-            const float2 zz = f.x32[k];
-            f.x64[k] = make_double2(xx.x + (double)zz.x, xx.y + (double)zz.y);
-            f.x32[k] = make_float2(0.f, 0.f);
-            f.r32[k] = make_float2((float)rr.x, (float)rr.y);
-            v[0] += norm2(rr);
-        }
+        double2 h0, h1, x0, x1;
+        sp_load(f.phi, Vtot, s.flat, h0, h1);
+        sp_load(f.x64, Vtot, s.flat, x0, x1);
+        const float4 z = f.x32[s.flat];
+        const double2 r0 = make_double2(h0.x - a0.x, h0.y - a0.y);
+        const double2 r1 = make_double2(h1.x - a1.x, h1.y - a1.y);
+        sp_store(f.x64, Vtot, s.flat, make_double2(x0.x + (double)z.x, x0.y + (double)z.y),
+                 make_double2(x1.x + (double)z.z, x1.y + (double)z.w));
+        f.x32[s.flat] = make_float4(0.f, 0.f, 0.f, 0.f);
+        sp_store(f.r32, Vtot, s.flat, make_float2((float)r0.x, (float)r0.y),
+                 make_float2((float)r1.x, (float)r1.y));
+        v[0] += norm2(r0) + norm2(r1);
         SITES_END
         write_partials<1>(v, f.p2, g.nlog, w.logical);
         return;
     }
     const double pAp = chain_total(f.p1, f.fin1, ci, w.chain);
     const R alpha = (R)(s_rho / pAp);
-    const C *__restrict__ p = (const C *)p_new_v;
-    const C *__restrict__ t;
-    C *__restrict__ r;
-    C *__restrict__ x;
+    const S *__restrict__ p = (const S *)p_new_v;
+    const S *__restrict__ t;
+    S *__restrict__ r;
+    S *__restrict__ x;
     const C *__restrict__ U;
     if constexpr (MIXED) { t = f.t32; r = f.r32; x = f.x32; U = f.U32; }
     else { t = f.t64; r = f.r64; x = f.x64; U = f.U64; }
     SITES_LOOP
     const Site s = decode_site(ci, local);
     const Nbr nb = neighbours(ci, s);
-    auto load = [&](int fl, C &b0, C &b1) { b0 = t[fl]; b1 = t[(size_t)Vtot + fl]; };
-    C a0, a1;
-    dslash_site<R, true>(nb, s.flat, Vtot, U, t[s.flat], t[(size_t)Vtot + s.flat],
-                         (R)(2.0 + ci.m0), load, a0, a1);
-    const C Ap[2] = {a0, a1};
-    for (int sp = 0; sp < 2; ++sp) {
-        const size_t k = (size_t)sp * Vtot + s.flat;
-        const C pp = p[k];
-        C xx = x[k], rr = r[k];
-        xx.x += alpha * pp.x; xx.y += alpha * pp.y;
-        rr.x -= alpha * Ap[sp].x; rr.y -= alpha * Ap[sp].y;
-        x[k] = xx;
-        r[k] = rr;
-        v[0] += norm2(rr);
-    }
+    auto load = [&](int fl, C &b0, C &b1) { sp_load(t, Vtot, fl, b0, b1); };
+    C t0, t1, a0, a1;
+    load(s.flat, t0, t1);
+    dslash_site<R, true>(nb, s.flat, Vtot, U, t0, t1, (R)(2.0 + ci.m0), load, a0, a1);
+    C p0, p1, x0, x1, r0, r1;
+    sp_load(p, Vtot, s.flat, p0, p1);
+    sp_load(x, Vtot, s.flat, x0, x1);
+    sp_load(r, Vtot, s.flat, r0, r1);
+    x0.x += alpha * p0.x; x0.y += alpha * p0.y;
+    x1.x += alpha * p1.x; x1.y += alpha * p1.y;
+    r0.x -= alpha * a0.x; r0.y -= alpha * a0.y;
+    r1.x -= alpha * a1.x; r1.y -= alpha * a1.y;
+    sp_store(x, Vtot, s.flat, x0, x1);
+    sp_store(r, Vtot, s.flat, r0, r1);
+    v[0] += norm2(r0) + norm2(r1);
     SITES_END
     write_partials<1>(v, f.p2, g.nlog, w.logical);
 }
@@ -458,13 +481,12 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
 __global__ void k_cg_finish_mixed(Geo g, CGFields f) {
     SITES_BEGIN
     const int fl = ci.off + local;
-    for (int sp = 0; sp < 2; ++sp) {
-        const size_t k = (size_t)sp * Vtot + fl;
-        const double2 xx = f.x64[k];
-        const float2 zz = f.x32[k];
-        f.x64[k] = make_double2(xx.x + (double)zz.x, xx.y + (double)zz.y);
-        f.x32[k] = make_float2(0.f, 0.f);
-    }
+    double2 x0, x1;
+    sp_load(f.x64, Vtot, fl, x0, x1);
+    const float4 z = f.x32[fl];
+    sp_store(f.x64, Vtot, fl, make_double2(x0.x + (double)z.x, x0.y + (double)z.y),
+             make_double2(x1.x + (double)z.z, x1.y + (double)z.w));
+    f.x32[fl] = make_float4(0.f, 0.f, 0.f, 0.f);
     SITES_END
 }
 
@@ -533,14 +555,13 @@ __device__ __noinline__ double wg_res64(ChainInfo ci, CGFields f, int Vtot, int 
         double2 a0, a1;
         dslash_site<double, true>(nb, s.flat, Vtot, f.U64, f.t64[s.flat],
                                   f.t64[(size_t)Vtot + s.flat], 2.0 + ci.m0, load, a0, a1);
-        const double2 Ay[2] = {a0, a1};
-        for (int sp = 0; sp < 2; ++sp) {
-            const size_t q = (size_t)sp * Vtot + s.flat;
-            const double2 ph = f.phi[q];
-            const double2 rr = make_double2(ph.x - Ay[sp].x, ph.y - Ay[sp].y);
-            f.r32[q] = make_float2((float)rr.x, (float)rr.y);
-            acc += norm2(rr);
-        }
+        double2 h0, h1;
+        sp_load(f.phi, Vtot, s.flat, h0, h1);
+        const double2 r0 = make_double2(h0.x - a0.x, h0.y - a0.y);
+        const double2 r1 = make_double2(h1.x - a1.x, h1.y - a1.y);
+        sp_store(f.r32, Vtot, s.flat, make_float2((float)r0.x, (float)r0.y),
+                 make_float2((float)r1.x, (float)r1.y));
+        acc += norm2(r0) + norm2(r1);
     }
     return acc;
 }
@@ -649,10 +670,9 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
 #pragma unroll
             for (int k = 0; k < SPT; ++k) {
                 if (!ok[k]) continue;
-                for (int sp = 0; sp < 2; ++sp) {
-                    const float2 rr = f.r32[(size_t)sp * Vtot + fl[k]];
-                    r[k][sp] = cmake<C>((R)rr.x, (R)rr.y);
-                }
+                const float4 rr = f.r32[fl[k]];
+                r[k][0] = cmake<C>((R)rr.x, (R)rr.y);
+                r[k][1] = cmake<C>((R)rr.z, (R)rr.w);
             }
             ++nupd;
             rmax2 = v[0];

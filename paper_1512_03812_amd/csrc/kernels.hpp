@@ -63,7 +63,7 @@ struct CGFields {
     const double2 *phi;       // FP64 right-hand side
     double2 *x64;             // FP64 solution (accumulated solution in mixed precision)
     double2 *r64, *t64;       // FP64 residual and D p (FP64 solver); t64 is also the mixed scratch
-    float2 *x32, *r32, *t32;  // mixed: FP32 partial solution, residual, D p
+    float4 *x32, *r32, *t32;  // mixed: FP32 partial solution, residual, D p (one float4 per site)
     const double2 *U64;
     const float2 *U32;
     double *p1, *p2;          // partial rows: ||D p||^2 (step 1) and ||r||^2 (step 2)
