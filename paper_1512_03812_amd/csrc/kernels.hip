@@ -175,6 +175,22 @@ template <bool MIXED> struct Prec;
 template <> struct Prec<false> { using R = double; using S = double2; };  // S: spinor storage
 template <> struct Prec<true> { using R = float; using S = float4; };
 
+// Workgroup staging of a spinor field in LDS.  A workgroup of B threads owns the half-site
+// range [w.start, w.start + B/2) of both parity planes of its chain, thread
+// par * B/2 + (i - w.start) the site (par, i), so the slot of a site is its thread index.
+// A stencil neighbour whose half-site index falls in the range is read from the slot; the
+// others (the rows above and below the workgroup's strip) come from global memory.
+template <typename C> struct LdsSpinor { C a, b; };
+extern __shared__ double smem_d[];
+
+// LDS slot of the site at flat index fl, or -1 if the workgroup does not own it.
+__device__ __forceinline__ int lds_slot(const ChainInfo &ci, const BlockWork &w, int half, int fl) {
+    const int loc = fl - ci.off;
+    const int par = loc >= ci.Vh ? 1 : 0;
+    const int k = loc - par * ci.Vh - w.start;
+    return (unsigned)k < (unsigned)half ? par * half + k : -1;
+}
+
 // Loop over the sites of this workgroup; `local` is the chain-local site index.  Threads
 // [0, B/2) take the even plane and [B/2, B) the odd plane at the same half-site indices.
 #define SITES_LOOP                                                                \
@@ -383,11 +399,14 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     if constexpr (MIXED) { r = f.r32; t = f.t32; U = f.U32; }
     else { r = f.r64; t = f.t64; U = f.U64; }
     const R beta = (R)n_beta;
-    double v[1] = {0.0};
-    SITES_LOOP
-    const Site s = decode_site(ci, local);
-    const Nbr nb = neighbours(ci, s);
-    auto load = [&](int fl, C &b0, C &b1) {
+    // p_new = r + beta p_old on the own site, staged in LDS for the neighbours inside the
+    // workgroup; t = D p_new (one site per thread: the tables use w.spt == 1).
+    LdsSpinor<C> *lds = (LdsSpinor<C> *)smem_d;
+    const int half = (int)blockDim.x >> 1;
+    const int par = (int)threadIdx.x >= half ? 1 : 0;
+    const int i = w.start + (int)threadIdx.x - par * half;
+    const bool own = i < ci.Vh;
+    auto direction = [&](int fl, C &b0, C &b1) {
         sp_load(r, Vtot, fl, b0, b1);
         if (!first) {
             C q0, q1;
@@ -396,13 +415,29 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
             b1 = cmake<C>(b1.x + beta * q1.x, b1.y + beta * q1.y);
         }
     };
-    C a0, a1, o0, o1;
-    load(s.flat, a0, a1);
-    dslash_site<R, false>(nb, s.flat, Vtot, U, a0, a1, (R)(2.0 + ci.m0), load, o0, o1);
-    sp_store(p_new, Vtot, s.flat, a0, a1);
-    sp_store(t, Vtot, s.flat, o0, o1);
-    v[0] += norm2(o0) + norm2(o1);
-    SITES_END
+    Site s;
+    C a0, a1;
+    if (own) {
+        s = decode_site(ci, par * ci.Vh + i);
+        direction(s.flat, a0, a1);
+        sp_store(p_new, Vtot, s.flat, a0, a1);
+        lds[threadIdx.x].a = a0;
+        lds[threadIdx.x].b = a1;
+    }
+    __syncthreads();
+    double v[1] = {0.0};
+    if (own) {
+        const Nbr nb = neighbours(ci, s);
+        auto load = [&](int fl, C &b0, C &b1) {
+            const int k = lds_slot(ci, w, half, fl);
+            if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
+            else direction(fl, b0, b1);
+        };
+        C o0, o1;
+        dslash_site<R, false>(nb, s.flat, Vtot, U, a0, a1, (R)(2.0 + ci.m0), load, o0, o1);
+        sp_store(t, Vtot, s.flat, o0, o1);
+        v[0] = norm2(o0) + norm2(o1);
+    }
     write_partials<1>(v, f.p1, g.nlog, w.logical);
 }
 
@@ -456,12 +491,30 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
     const C *__restrict__ U;
     if constexpr (MIXED) { t = f.t32; r = f.r32; x = f.x32; U = f.U32; }
     else { t = f.t64; r = f.r64; x = f.x64; U = f.U64; }
-    SITES_LOOP
-    const Site s = decode_site(ci, local);
+    // t of the own site staged in LDS for the neighbours inside the workgroup (one site per
+    // thread: the tables use w.spt == 1).
+    LdsSpinor<C> *lds = (LdsSpinor<C> *)smem_d;
+    const int half = (int)blockDim.x >> 1;
+    const int par = (int)threadIdx.x >= half ? 1 : 0;
+    const int i = w.start + (int)threadIdx.x - par * half;
+    const bool own = i < ci.Vh;
+    Site s;
+    C t0, t1;
+    if (own) {
+        s = decode_site(ci, par * ci.Vh + i);
+        sp_load(t, Vtot, s.flat, t0, t1);
+        lds[threadIdx.x].a = t0;
+        lds[threadIdx.x].b = t1;
+    }
+    __syncthreads();
+    if (own) {
     const Nbr nb = neighbours(ci, s);
-    auto load = [&](int fl, C &b0, C &b1) { sp_load(t, Vtot, fl, b0, b1); };
-    C t0, t1, a0, a1;
-    load(s.flat, t0, t1);
+    auto load = [&](int fl, C &b0, C &b1) {
+        const int k = lds_slot(ci, w, half, fl);
+        if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
+        else sp_load(t, Vtot, fl, b0, b1);
+    };
+    C a0, a1;
     dslash_site<R, true>(nb, s.flat, Vtot, U, t0, t1, (R)(2.0 + ci.m0), load, a0, a1);
     C p0, p1, x0, x1, r0, r1;
     sp_load(p, Vtot, s.flat, p0, p1);
@@ -474,7 +527,7 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
     sp_store(x, Vtot, s.flat, x0, x1);
     sp_store(r, Vtot, s.flat, r0, r1);
     v[0] += norm2(r0) + norm2(r1);
-    SITES_END
+    }
     write_partials<1>(v, f.p2, g.nlog, w.logical);
 }
 
@@ -498,19 +551,23 @@ void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, h
 void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
                      const void *p_old, void *p_new, bool decide_only, hipStream_t s) {
     if (mixed)
-        hipLaunchKernelGGL(k_cg_step1<true>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, slot,
-                           tol * tol, p_old, p_new, decide_only ? 1 : 0);
+        hipLaunchKernelGGL(k_cg_step1<true>, dim3(g.nblocks), dim3(g.block),
+                           g.block * sizeof(LdsSpinor<float2>), s, g, f, slot, tol * tol, p_old,
+                           p_new, decide_only ? 1 : 0);
     else
-        hipLaunchKernelGGL(k_cg_step1<false>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, slot,
-                           tol * tol, p_old, p_new, decide_only ? 1 : 0);
+        hipLaunchKernelGGL(k_cg_step1<false>, dim3(g.nblocks), dim3(g.block),
+                           g.block * sizeof(LdsSpinor<double2>), s, g, f, slot, tol * tol, p_old,
+                           p_new, decide_only ? 1 : 0);
 }
 
 void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
                      hipStream_t s) {
     if (mixed)
-        hipLaunchKernelGGL(k_cg_step2<true>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, slot, p_new);
+        hipLaunchKernelGGL(k_cg_step2<true>, dim3(g.nblocks), dim3(g.block),
+                           g.block * sizeof(LdsSpinor<float2>), s, g, f, slot, p_new);
     else
-        hipLaunchKernelGGL(k_cg_step2<false>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, slot, p_new);
+        hipLaunchKernelGGL(k_cg_step2<false>, dim3(g.nblocks), dim3(g.block),
+                           g.block * sizeof(LdsSpinor<double2>), s, g, f, slot, p_new);
 }
 
 void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s) {
@@ -572,7 +629,6 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
         int max_iter) {
     using R = typename Prec<MIXED>::R;
     using C = cplx_t<R>;
-    extern __shared__ double smem_d[];
     const int c = chain_list[blockIdx.x];
     const ChainInfo ci = g.chains[c];
     const int V = ci.V, Vtot = g.Vtot, off = ci.off;
