@@ -309,18 +309,20 @@ int check_convergence(hmc_ctx *c, const Geo &big, int max_iter, int *active, int
 }
 
 // Algorithmic bytes per lattice site of the CG step kernels (each distinct input read once,
-// each output written once; stencil neighbours come from cache).
-//   FP64 solver   step 1: r 32 + p_old 32 + U 32 read, p 32 + t 32 written      = 160
-//                 step 2: t 32 + U 32 + x 32 + p 32 + r 32 read, x 32 + r 32    = 224
-//   mixed, FP32   step 1: r 16 + p_old 16 + U 16 read, p 16 + t 16 written      =  80
-//                 step 2: t 16 + U 16 + x 16 + p 16 + r 16 read, x 16 + r 16    = 112
+// each output written once; stencil neighbours come from cache).  Step 1 also applies the
+// previous iteration's x update.
+//   FP64 solver   step 1: r 32 + p_old 32 + U 32 + x 32 read, p 32 + t 32 + x 32 = 224
+//                 step 2: t 32 + U 32 + r 32 read, r 32 written                  = 128
+//   mixed, FP32   step 1: r 16 + p_old 16 + U 16 + x 16 read, p 16 + t 16 + x 16 = 112
+//                 step 2: t 16 + U 16 + r 16 read, r 16 written                  =  64
 //   mixed, FP64 residual recomputation
-//                 step 1: x64 32 + x32 16 + U64 32 + p_old 16 read, t64 32 + p 16 = 144
-//                 step 2: t64 32 + U64 32 + phi 32 + x64 32 + x32 16 read,
-//                         x64 32 + x32 16 + r32 16 written                      = 208
-constexpr double kBytesFp64[2] = {160.0, 224.0};
-constexpr double kBytesFp32[2] = {80.0, 112.0};
-constexpr double kBytesUpdate[2] = {144.0, 208.0};
+//                 step 1: x64 32 + x32 16 + p_old 16 + U64 32 read, t64 32 + p 16 = 144
+//                 step 2: t64 32 + U64 32 + phi 32 + x64 32 + x32 16 + p 16 read,
+//                         x64 32 + x32 16 + r32 16 written                      = 224
+// (The first slot of a solve reads neither p_old nor x; it is counted like the others.)
+constexpr double kBytesFp64[2] = {224.0, 128.0};
+constexpr double kBytesFp32[2] = {112.0, 64.0};
+constexpr double kBytesUpdate[2] = {144.0, 224.0};
 
 hipEvent_t timer_event(hmc_ctx *c) {
     KernelTimer &T = c->timer;

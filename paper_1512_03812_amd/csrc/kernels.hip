@@ -291,6 +291,13 @@ void launch_dslash64(const Geo &g, const double2 *U, const double2 *in, double2 
 // FP64 recomputation (or reached the target) the next slot recomputes
 // r = phi - D^dagger D (x64 + x32) in FP64, folds x32 into x64 and restarts the FP32
 // residual from it (reliable update); convergence is only declared on that FP64 residual.
+//
+// The solution update x += alpha_k p_k of iteration k is deferred to step 1 of the next
+// slot, which reads p_k (as p_old) on its own sites anyway; step 2 then touches only t and
+// r.  The pending alpha travels in the state: step 2 of a normal slot stores its alpha,
+// step 1 of an update slot carries the pending alpha forward so that step 2 of that slot
+// folds it into x64 together with x32, and a chain that stops (converged, or the final
+// decision-only launch) applies it before leaving.
 template <bool MIXED>
 __global__ void k_cg_init(Geo g, CGFields f, double delta2) {
     double v[1] = {0.0};
@@ -340,6 +347,8 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     const int p_mode = prev->mode, p_iters = prev->iters, p_nupd = prev->n_updates;
     const double p_rho = prev->rho, p_rho_p = prev->rho_p, p_target = prev->target;
     const double p_phi2 = prev->phi2, p_rmax2 = prev->rmax2, delta2 = prev->delta2;
+    // x update still owed by the previous slot (none after the initial or an update slot)
+    const double pend = p_mode == kModeNormal ? prev->alpha : 0.0;
     const double rho = chain_total(f.p2, f.fin2, ci, w.chain);
     double n_rho = rho, n_rho_p = p_rho_p, n_target = p_target, n_phi2 = p_phi2, n_rmax2 = p_rmax2;
     double n_beta = 0.0;
@@ -367,12 +376,31 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
         out->rmax2 = n_rmax2; out->beta = n_beta; out->delta2 = delta2; out->iters = n_iters;
         out->converged = n_conv; out->mode = update ? kModeUpdate : kModeNormal;
         out->n_updates = n_nupd;
+        out->alpha = update ? pend : 0.0;
     }
-    if (n_conv || decide_only) return;
     const S *__restrict__ p_old = (const S *)p_old_v;
     S *__restrict__ p_new = (S *)p_new_v;
+    const R a_pend = (R)pend;
+    if (n_conv || decide_only) {
+        // the chain stops here: settle the owed x update on the own sites
+        if (pend != 0.0) {
+            SITES_LOOP
+            const int fl = ci.off + local;
+            C q0, q1, x0, x1;
+            sp_load(p_old, Vtot, fl, q0, q1);
+            if constexpr (MIXED) sp_load(f.x32, Vtot, fl, x0, x1);
+            else sp_load(f.x64, Vtot, fl, x0, x1);
+            x0.x += a_pend * q0.x; x0.y += a_pend * q0.y;
+            x1.x += a_pend * q1.x; x1.y += a_pend * q1.y;
+            if constexpr (MIXED) sp_store(f.x32, Vtot, fl, x0, x1);
+            else sp_store(f.x64, Vtot, fl, x0, x1);
+            SITES_END
+        }
+        return;
+    }
     if (MIXED && update) {
-        // FP64 residual recomputation, first half: t64 = D (x64 + x32); p carried over.
+        // FP64 residual recomputation, first half: t64 = D (x64 + x32 + pend p_old); p carried
+        // over (step 2 of this slot folds x32 + pend p into x64).
         SITES_LOOP
         const Site s = decode_site(ci, local);
         const Nbr nb = neighbours(ci, s);
@@ -380,8 +408,10 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
             double2 y0, y1;
             sp_load(f.x64, Vtot, fl, y0, y1);
             const float4 z = f.x32[fl];
-            b0 = make_double2(y0.x + (double)z.x, y0.y + (double)z.y);
-            b1 = make_double2(y1.x + (double)z.z, y1.y + (double)z.w);
+            C q0, q1;
+            sp_load(p_old, Vtot, fl, q0, q1);
+            b0 = make_double2(y0.x + (double)(z.x + a_pend * q0.x), y0.y + (double)(z.y + a_pend * q0.y));
+            b1 = make_double2(y1.x + (double)(z.z + a_pend * q1.x), y1.y + (double)(z.w + a_pend * q1.y));
         };
         double2 a0, a1, o0, o1;
         load(s.flat, a0, a1);
@@ -395,12 +425,14 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     }
     const S *__restrict__ r;
     S *__restrict__ t;
+    S *__restrict__ x;
     const C *__restrict__ U;
-    if constexpr (MIXED) { r = f.r32; t = f.t32; U = f.U32; }
-    else { r = f.r64; t = f.t64; U = f.U64; }
+    if constexpr (MIXED) { r = f.r32; t = f.t32; x = f.x32; U = f.U32; }
+    else { r = f.r64; t = f.t64; x = f.x64; U = f.U64; }
     const R beta = (R)n_beta;
-    // p_new = r + beta p_old on the own site, staged in LDS for the neighbours inside the
-    // workgroup; t = D p_new (one site per thread: the tables use w.spt == 1).
+    // Own site: x += pend p_old (deferred from the previous slot), p_new = r + beta p_old,
+    // staged in LDS for the neighbours inside the workgroup; t = D p_new (one site per
+    // thread: the tables use w.spt == 1).
     LdsSpinor<C> *lds = (LdsSpinor<C> *)smem_d;
     const int half = (int)blockDim.x >> 1;
     const int par = (int)threadIdx.x >= half ? 1 : 0;
@@ -419,7 +451,17 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     C a0, a1;
     if (own) {
         s = decode_site(ci, par * ci.Vh + i);
-        direction(s.flat, a0, a1);
+        sp_load(r, Vtot, s.flat, a0, a1);
+        if (!first) {
+            C q0, q1, x0, x1;
+            sp_load(p_old, Vtot, s.flat, q0, q1);
+            sp_load(x, Vtot, s.flat, x0, x1);
+            x0.x += a_pend * q0.x; x0.y += a_pend * q0.y;
+            x1.x += a_pend * q1.x; x1.y += a_pend * q1.y;
+            sp_store(x, Vtot, s.flat, x0, x1);
+            a0 = cmake<C>(a0.x + beta * q0.x, a0.y + beta * q0.y);
+            a1 = cmake<C>(a1.x + beta * q1.x, a1.y + beta * q1.y);
+        }
         sp_store(p_new, Vtot, s.flat, a0, a1);
         lds[threadIdx.x].a = a0;
         lds[threadIdx.x].b = a1;
@@ -449,31 +491,32 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
     const BlockWork w = g.work[blockIdx.x];
     const ChainInfo ci = g.chains[w.chain];
     const int Vtot = g.Vtot;
-    const CGState *st = f.st + (size_t)(slot & 1) * g.nchains + w.chain;
+    CGState *st = f.st + (size_t)(slot & 1) * g.nchains + w.chain;
     if (st->converged) return;
     const int mode = st->mode;
     const double s_rho = st->rho;
     double v[1] = {0.0};
     if (MIXED && mode == kModeUpdate) {
-        // second half: r64 = phi - D^dagger t64; x64 += x32; x32 = 0; r32 = r64.
+        // second half: r64 = phi - D^dagger t64; x64 += x32 + pend p; x32 = 0; r32 = r64.
+        const float a_pend = (float)st->alpha;
+        const float4 *__restrict__ p = (const float4 *)p_new_v;
         SITES_LOOP
         const Site s = decode_site(ci, local);
         const Nbr nb = neighbours(ci, s);
-        auto load = [&](int fl, double2 &b0, double2 &b1) {
-            b0 = f.t64[fl];
-            b1 = f.t64[(size_t)Vtot + fl];
-        };
-        double2 a0, a1;
-        dslash_site<double, true>(nb, s.flat, Vtot, f.U64, f.t64[s.flat],
-                                  f.t64[(size_t)Vtot + s.flat], 2.0 + ci.m0, load, a0, a1);
+        auto load = [&](int fl, double2 &b0, double2 &b1) { sp_load(f.t64, Vtot, fl, b0, b1); };
+        double2 a0, a1, t0, t1;
+        load(s.flat, t0, t1);
+        dslash_site<double, true>(nb, s.flat, Vtot, f.U64, t0, t1, 2.0 + ci.m0, load, a0, a1);
         double2 h0, h1, x0, x1;
         sp_load(f.phi, Vtot, s.flat, h0, h1);
         sp_load(f.x64, Vtot, s.flat, x0, x1);
         const float4 z = f.x32[s.flat];
+        const float4 q = p[s.flat];
         const double2 r0 = make_double2(h0.x - a0.x, h0.y - a0.y);
         const double2 r1 = make_double2(h1.x - a1.x, h1.y - a1.y);
-        sp_store(f.x64, Vtot, s.flat, make_double2(x0.x + (double)z.x, x0.y + (double)z.y),
-                 make_double2(x1.x + (double)z.z, x1.y + (double)z.w));
+        sp_store(f.x64, Vtot, s.flat,
+                 make_double2(x0.x + (double)(z.x + a_pend * q.x), x0.y + (double)(z.y + a_pend * q.y)),
+                 make_double2(x1.x + (double)(z.z + a_pend * q.z), x1.y + (double)(z.w + a_pend * q.w)));
         f.x32[s.flat] = make_float4(0.f, 0.f, 0.f, 0.f);
         sp_store(f.r32, Vtot, s.flat, make_float2((float)r0.x, (float)r0.y),
                  make_float2((float)r1.x, (float)r1.y));
@@ -483,14 +526,14 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
         return;
     }
     const double pAp = chain_total(f.p1, f.fin1, ci, w.chain);
-    const R alpha = (R)(s_rho / pAp);
-    const S *__restrict__ p = (const S *)p_new_v;
+    const double alpha_d = s_rho / pAp;
+    if (w.logical == ci.block0 && threadIdx.x == 0) st->alpha = alpha_d;  // owed to x (next slot)
+    const R alpha = (R)alpha_d;
     const S *__restrict__ t;
     S *__restrict__ r;
-    S *__restrict__ x;
     const C *__restrict__ U;
-    if constexpr (MIXED) { t = f.t32; r = f.r32; x = f.x32; U = f.U32; }
-    else { t = f.t64; r = f.r64; x = f.x64; U = f.U64; }
+    if constexpr (MIXED) { t = f.t32; r = f.r32; U = f.U32; }
+    else { t = f.t64; r = f.r64; U = f.U64; }
     // t of the own site staged in LDS for the neighbours inside the workgroup (one site per
     // thread: the tables use w.spt == 1).
     LdsSpinor<C> *lds = (LdsSpinor<C> *)smem_d;
@@ -508,25 +551,19 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
     }
     __syncthreads();
     if (own) {
-    const Nbr nb = neighbours(ci, s);
-    auto load = [&](int fl, C &b0, C &b1) {
-        const int k = lds_slot(ci, w, half, fl);
-        if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
-        else sp_load(t, Vtot, fl, b0, b1);
-    };
-    C a0, a1;
-    dslash_site<R, true>(nb, s.flat, Vtot, U, t0, t1, (R)(2.0 + ci.m0), load, a0, a1);
-    C p0, p1, x0, x1, r0, r1;
-    sp_load(p, Vtot, s.flat, p0, p1);
-    sp_load(x, Vtot, s.flat, x0, x1);
-    sp_load(r, Vtot, s.flat, r0, r1);
-    x0.x += alpha * p0.x; x0.y += alpha * p0.y;
-    x1.x += alpha * p1.x; x1.y += alpha * p1.y;
-    r0.x -= alpha * a0.x; r0.y -= alpha * a0.y;
-    r1.x -= alpha * a1.x; r1.y -= alpha * a1.y;
-    sp_store(x, Vtot, s.flat, x0, x1);
-    sp_store(r, Vtot, s.flat, r0, r1);
-    v[0] += norm2(r0) + norm2(r1);
+        const Nbr nb = neighbours(ci, s);
+        auto load = [&](int fl, C &b0, C &b1) {
+            const int k = lds_slot(ci, w, half, fl);
+            if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
+            else sp_load(t, Vtot, fl, b0, b1);
+        };
+        C a0, a1, r0, r1;
+        dslash_site<R, true>(nb, s.flat, Vtot, U, t0, t1, (R)(2.0 + ci.m0), load, a0, a1);
+        sp_load(r, Vtot, s.flat, r0, r1);
+        r0.x -= alpha * a0.x; r0.y -= alpha * a0.y;
+        r1.x -= alpha * a1.x; r1.y -= alpha * a1.y;
+        sp_store(r, Vtot, s.flat, r0, r1);
+        v[0] = norm2(r0) + norm2(r1);
     }
     write_partials<1>(v, f.p2, g.nlog, w.logical);
 }
@@ -767,7 +804,8 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
         for (int par = 0; par < 2; ++par) {
             CGState *o = f.st + (size_t)par * g.nchains + c;
             o->rho = rho; o->rho_p = rho_prev; o->target = target; o->phi2 = phi2; o->rmax2 = rmax2;
-            o->beta = 0.0; o->delta2 = delta2; o->iters = iters; o->converged = conv ? 1 : 0;
+            o->beta = 0.0; o->delta2 = delta2; o->alpha = 0.0; o->iters = iters;
+            o->converged = conv ? 1 : 0;
             o->mode = kModeNormal; o->n_updates = nupd;
         }
     }

@@ -29,11 +29,13 @@ struct CGState {
     double rmax2;   // mixed: ||r||^2 at the last FP64 residual recomputation
     double beta;    // beta of this slot's direction update
     double delta2;  // mixed: reliable-update trigger factor squared
+    double alpha;   // normal slot: this slot's alpha, whose x update the next slot applies;
+                    // update slot: the alpha still owed to x, folded in by its step 2
     int iters;      // CG iterations completed
     int converged;  // 1 once the stopping test passed
     int mode;       // kModeInit, kModeNormal or kModeUpdate (this slot)
     int n_updates;  // mixed: FP64 residual recomputations completed
-    int pad[6];
+    int pad[4];
 };
 static_assert(sizeof(CGState) % 16 == 0, "CGState alignment");
 enum { kModeInit = 0, kModeNormal = 1, kModeUpdate = 2 };
@@ -73,12 +75,14 @@ struct CGFields {
 // x = 0, r = phi, partial ||phi||^2 -> p2, state[1] = initial.
 void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, hipStream_t s);
 // Slot k, first kernel: decide (converged / beta / reliable update) from the partials of
-// the previous slot, then p_new = r + beta p_old and t = D p_new with partial ||t||^2
-// (or, in a reliable-update slot, t64 = D (x64 + x32)).  decide_only: state update only.
+// the previous slot, apply the previous slot's x += alpha p_old, then p_new = r + beta p_old
+// and t = D p_new with partial ||t||^2 (or, in a reliable-update slot,
+// t64 = D (x64 + x32 + alpha p_old)).  decide_only: state update and the owed x update only.
 void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
                      const void *p_old, void *p_new, bool decide_only, hipStream_t s);
-// Slot k, second kernel: alpha from the partials of step 1, x += alpha p, r -= alpha
-// D^dagger t with partial ||r||^2 (or the FP64 residual recomputation).
+// Slot k, second kernel: alpha from the partials of step 1 (kept in the state for the next
+// slot's x update), r -= alpha D^dagger t with partial ||r||^2 (or the FP64 residual
+// recomputation, which also folds x32 and the owed alpha p into x64).
 void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
                      hipStream_t s);
 // fin[c] = sum of row's partials of chain c, for the chains above kMaxChainBlocks.
