@@ -53,6 +53,7 @@ struct KernelTimer {
     double bytes[2] = {0.0, 0.0};
     long long timed[2] = {0, 0};
     long long launches = 0;  // all slots launched while timing was on
+    int since_sync = 0;      // slots launched since the host last waited for the stream
 };
 constexpr int kRingSlots = 32;
 
@@ -261,6 +262,7 @@ int make_ctx(hmc_ctx **out, int n, const int *Lx, const int *Lt, const double *b
 
 // ------------------------------------------------------------------ helpers on a bound context
 int sync(hmc_ctx *c) {
+    c->timer.since_sync = 0;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return HMC_OK;
 }
@@ -367,7 +369,12 @@ void timer_flush(hmc_ctx *c) {
 template <typename L1, typename L2> void slot_launch(hmc_ctx *c, int slot, bool mixed, L1 step1, L2 step2) {
     KernelTimer &T = c->timer;
     if (T.on) T.launches++;
-    if (!T.on || slot % T.sample_every != 0 || T.ring_used == kRingSlots || !T.ring) {
+    // Sampled slots sit mid-way between the convergence checks, a few slots after the host
+    // last waited: the stream then already holds the launches ahead, and the events measure
+    // the kernels rather than the host's latency in enqueuing them after a wait.
+    const int since = T.since_sync++;
+    if (!T.on || slot % T.sample_every != T.sample_every / 2 || since < 2 ||
+        T.ring_used == kRingSlots || !T.ring) {
         step1();
         step2();
         return;
@@ -395,7 +402,7 @@ int build_partition(hmc_ctx *c, int vmax) {
     if (c->part_vmax == vmax) return HMC_OK;
     std::vector<BlockWork> big;
     std::vector<int> small;
-    int svmax = 0;
+    int svmax = 0, rc = HMC_OK;
     for (int k = 0; k < c->nchains; ++k) {
         if (c->chains[k].V <= vmax) {
             small.push_back(k);
@@ -410,7 +417,7 @@ int build_partition(hmc_ctx *c, int vmax) {
     if (!small.empty())
         HIP_TRY(c, hipMemcpyAsync(c->at<int>(c->off_small), small.data(), sizeof(int) * small.size(),
                                   hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if ((rc = sync(c))) return rc;
     c->n_big_blocks = (int)big.size();
     c->n_small = (int)small.size();
     c->small_vmax = svmax;
@@ -791,7 +798,8 @@ void init_md(MD &md, hmc_ctx *c, int prec) {
 int set_block(hmc_ctx *c, int block) {
     if (block < kMinBlock || block > 1024 || block % 64) return fail(c, HMC_E_INVAL, "bad workgroup size");
     if (block == c->block) return HMC_OK;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int rc = sync(c);
+    if (rc) return rc;
     c->block = block;
     build_tables(c);
     HIP_TRY(c, hipMemcpyAsync(c->at<ChainInfo>(c->off_chains), c->chains.data(),
