@@ -62,7 +62,9 @@ enum {
     HMC_NESTED_FG = 3,         /* Eq. (10) */
     HMC_ADAPTED_NESTED_FG = 4, /* Eq. (11) */
     HMC_NESTED_LEAPFROG = 5,   /* Eq. (8) */
-    HMC_NESTED_5STAGE = 6      /* Eq. (9) */
+    HMC_NESTED_5STAGE = 6,     /* Eq. (9) */
+    HMC_OMELYAN_11STAGE = 7    /* Eq. (6), with the fourth-order sigma, eta, lambda, theta of
+                                  Omelyan, Mryglod and Folk (2003), their Eq. (71) */
 };
 
 enum { HMC_PREC_FP64 = 0, HMC_PREC_MIXED = 1 };

@@ -26,7 +26,7 @@ _SRC = os.path.join(_HERE, "schwinger_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 (LEAPFROG, OMELYAN_5STAGE, FORCE_GRADIENT, NESTED_FG, ADAPTED_NESTED_FG, NESTED_LEAPFROG,
- NESTED_5STAGE) = range(7)
+ NESTED_5STAGE, OMELYAN_11STAGE) = range(8)
 SCHEMES = {
     "leapfrog": LEAPFROG,
     "omelyan": OMELYAN_5STAGE,
@@ -35,6 +35,7 @@ SCHEMES = {
     "adapted_nested_fg": ADAPTED_NESTED_FG,
     "nested_leapfrog": NESTED_LEAPFROG,
     "nested_omelyan": NESTED_5STAGE,
+    "omelyan_11stage": OMELYAN_11STAGE,
 }
 FLAG_QUENCHED = 1
 FLAG_FG_EXACT = 2

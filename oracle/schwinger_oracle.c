@@ -693,7 +693,17 @@ enum {
     SCHEME_ADAPTED_NESTED_FG = 4, /* Eq. (11) */
     SCHEME_NESTED_LEAPFROG = 5,   /* Eq. (8)  */
     SCHEME_NESTED_5STAGE = 6,     /* Eq. (9)  */
+    SCHEME_OMELYAN_11STAGE = 7,   /* Eq. (6)  */
 };
+
+/*
+ * sigma, eta, lambda, theta of the 11-stage decomposition, Eq. (6): the fourth-order set
+ * of Omelyan, Mryglod and Folk (2003), their Eq. (71).
+ */
+#define OMF_SIGMA 0.08398315262876693
+#define OMF_ETA 0.2539785108410595
+#define OMF_LAMBDA 0.6822365335719091
+#define OMF_THETA (-0.03230286765269967)
 
 /* stage kinds recorded in the trace */
 enum {
@@ -887,6 +897,21 @@ static void md_step(md_state *s, int scheme, double h, int M)
         inner_leapfrog(s, h / 2.0, M);
         stage_B(s, 1, h / 6.0);
         break;
+    case SCHEME_OMELYAN_11STAGE: { /* Eq. (6) */
+        double bm = (1.0 - 2.0 * (OMF_LAMBDA + OMF_SIGMA)) / 2.0, am = 1.0 - 2.0 * (OMF_THETA + OMF_ETA);
+        stage_B(s, 2, OMF_SIGMA * h);
+        stage_A(s, OMF_ETA * h);
+        stage_B(s, 2, OMF_LAMBDA * h);
+        stage_A(s, OMF_THETA * h);
+        stage_B(s, 2, bm * h);
+        stage_A(s, am * h);
+        stage_B(s, 2, bm * h);
+        stage_A(s, OMF_THETA * h);
+        stage_B(s, 2, OMF_LAMBDA * h);
+        stage_A(s, OMF_ETA * h);
+        stage_B(s, 2, OMF_SIGMA * h);
+        break;
+    }
     }
 }
 

@@ -9,10 +9,11 @@ HMC_OK, HMC_E_INVAL, HMC_E_NOMEM, HMC_E_NOCONV, HMC_E_HIP, HMC_E_NAN = 0, -1, -2
 ERROR_NAMES = {0: "HMC_OK", -1: "HMC_E_INVAL", -2: "HMC_E_NOMEM", -3: "HMC_E_NOCONV",
                -4: "HMC_E_HIP", -5: "HMC_E_NAN"}
 (LEAPFROG, OMELYAN_5STAGE, FORCE_GRADIENT, NESTED_FG, ADAPTED_NESTED_FG, NESTED_LEAPFROG,
- NESTED_5STAGE) = range(7)
+ NESTED_5STAGE, OMELYAN_11STAGE) = range(8)
 SCHEMES = {"leapfrog": LEAPFROG, "omelyan": OMELYAN_5STAGE, "force_gradient": FORCE_GRADIENT,
            "nested_fg": NESTED_FG, "adapted_nested_fg": ADAPTED_NESTED_FG,
-           "nested_leapfrog": NESTED_LEAPFROG, "nested_omelyan": NESTED_5STAGE}
+           "nested_leapfrog": NESTED_LEAPFROG, "nested_omelyan": NESTED_5STAGE,
+           "omelyan_11stage": OMELYAN_11STAGE}
 PREC_FP64, PREC_MIXED = 0, 1
 PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
 FORCE_GAUGE, FORCE_FERMION, FORCE_TOTAL = 0, 1, 2

@@ -723,6 +723,13 @@ int inner_fg(MD &md, double s, int M) {
     return HMC_OK;
 }
 
+// sigma, eta, lambda, theta of Eq. (6): the fourth-order set of Omelyan, Mryglod and Folk
+// (2003), their Eq. (71)
+constexpr double kOmfSigma = 0.08398315262876693;
+constexpr double kOmfEta = 0.2539785108410595;
+constexpr double kOmfLambda = 0.6822365335719091;
+constexpr double kOmfTheta = -0.03230286765269967;
+
 int md_step(MD &md, int scheme, double h, int M) {
     int rc = HMC_OK;
 #define T(x) if ((rc = (x))) return rc
@@ -750,6 +757,16 @@ int md_step(MD &md, int scheme, double h, int M) {
     case HMC_NESTED_LEAPFROG:  // Eq. (8)
         T(stage_B(md, 1, h / 2.0)); T(inner_leapfrog(md, h, M)); T(stage_B(md, 1, h / 2.0));
         break;
+    case HMC_OMELYAN_11STAGE: {  // Eq. (6)
+        const double bm = (1.0 - 2.0 * (kOmfLambda + kOmfSigma)) / 2.0;
+        const double am = 1.0 - 2.0 * (kOmfTheta + kOmfEta);
+        T(stage_B(md, 2, kOmfSigma * h)); stage_A(md, kOmfEta * h);
+        T(stage_B(md, 2, kOmfLambda * h)); stage_A(md, kOmfTheta * h);
+        T(stage_B(md, 2, bm * h)); stage_A(md, am * h); T(stage_B(md, 2, bm * h));
+        stage_A(md, kOmfTheta * h); T(stage_B(md, 2, kOmfLambda * h));
+        stage_A(md, kOmfEta * h); T(stage_B(md, 2, kOmfSigma * h));
+        break;
+    }
     case HMC_NESTED_5STAGE:  // Eq. (9)
         T(stage_B(md, 1, h / 6.0)); T(inner_leapfrog(md, h / 2.0, M));
         T(stage_B(md, 1, 2.0 * h / 3.0)); T(inner_leapfrog(md, h / 2.0, M));
@@ -763,10 +780,12 @@ int md_step(MD &md, int scheme, double h, int M) {
 }
 
 int check_md_args(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, int prec) {
-    if (scheme < HMC_LEAPFROG || scheme > HMC_NESTED_5STAGE)
+    if (scheme < HMC_LEAPFROG || scheme > HMC_OMELYAN_11STAGE)
         return fail(c, HMC_E_INVAL, "unknown scheme %d", scheme);
     if (!isfinite(tau) || n_outer < 1) return fail(c, HMC_E_INVAL, "need finite tau and n_outer >= 1");
-    if (scheme >= HMC_NESTED_FG && n_inner < 1)
+    const bool nested = scheme == HMC_NESTED_FG || scheme == HMC_ADAPTED_NESTED_FG ||
+                        scheme == HMC_NESTED_LEAPFROG || scheme == HMC_NESTED_5STAGE;
+    if (nested && n_inner < 1)
         return fail(c, HMC_E_INVAL, "nested schemes need n_inner >= 1");
     if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
     return HMC_OK;

@@ -321,7 +321,8 @@ def test_trajectory_parity_all_schemes(scheme, n_outer, n_inner, persistent):
 
 def test_inversion_counts_per_step():
     counts = {"leapfrog": 4, "omelyan": 6, "force_gradient": 8, "nested_fg": 8,
-              "adapted_nested_fg": 8, "nested_leapfrog": 4, "nested_omelyan": 6}
+              "adapted_nested_fg": 8, "nested_leapfrog": 4, "nested_omelyan": 6,
+              "omelyan_11stage": 12}
     b = Batch([(8, 8)], seed=3)
     b.lat.hot_start()
     for scheme, per_step in counts.items():

@@ -402,7 +402,7 @@ def fine_reference():
 @pytest.mark.parametrize("scheme,order,nested", [
     ("leapfrog", 2, False), ("omelyan", 2, False), ("force_gradient", 4, False),
     ("nested_fg", 4, True), ("adapted_nested_fg", 4, True), ("nested_leapfrog", 2, True),
-    ("nested_omelyan", 2, True)])
+    ("nested_omelyan", 2, True), ("omelyan_11stage", 4, False)])
 def test_order_of_convergence(scheme, order, nested, fine_reference):
     """Global phase-space error and energy error scale as h^order; the nested
     force-gradient schemes reach order four effectively with M proportional to 1/h, the
