@@ -229,6 +229,93 @@ def run_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+# The paper's numerical study (Sec. 4): 32 x 32, beta 1, m0 = -0.231367, tau 2, micro step
+# h/10 in the nested schemes; |Delta H| over independent momentum (and pseudofermion) sets on
+# one thermalised configuration.  Schemes: (label, scheme, exact force-gradient term, inner
+# steps M).  Eqs. (5), (10), (11) carry the exact term C; the Taylor-shifted variant of Eq. (5)
+# is the "approx. force-gradient" row of Table 1.
+PAPER_SCHEMES = [("leapfrog", "leapfrog", False, 1), ("omelyan", "omelyan", False, 1),
+                 ("nested_leapfrog", "nested_leapfrog", False, 10),
+                 ("nested_omelyan", "nested_omelyan", False, 5),
+                 ("force_gradient", "force_gradient", True, 1),
+                 ("force_gradient_approx", "force_gradient", False, 1),
+                 ("nested_fg", "nested_fg", True, 5),
+                 ("adapted_nested_fg", "adapted_nested_fg", True, 5),
+                 ("omelyan_11stage", "omelyan_11stage", False, 1)]
+DINV_PER_STEP = {"leapfrog": 4, "omelyan": 6, "nested_leapfrog": 4, "nested_omelyan": 6,
+                 "force_gradient": 8, "nested_fg": 8, "adapted_nested_fg": 8, "omelyan_11stage": 12}
+
+
+def run_paper_study(args):
+    """Sec. 4: |Delta H| versus the step size for every integrator, and the inversions of D per
+    trajectory at 90% acceptance (Table 1), on a configuration thermalised here (the paper's
+    own configuration is not available): a statistical comparison only."""
+    import math
+    import torch
+    import paper_1512_03812_amd as hmc
+    L, beta, m0, tau = 32, 1.0, -0.231367, 2.0
+    th = hmc.Lattice(L, beta, m0, seed=args.seed)
+    th.hot_start()
+    th.set_solver(tol=1e-10, max_iter=50000)
+    acc = []
+    for k in range(args.study_therm):
+        acc += th.trajectory("adapted_nested_fg", 1.0, 20, 5, prec="mixed").accepted
+    q_lex = th.unpack_links(th.q)
+    sg, plaq, _ = th.actions()
+    print(json.dumps({"thermalisation": {"trajectories": args.study_therm,
+                                         "acceptance": sum(acc) / max(1, len(acc)),
+                                         "plaquette": plaq[0]}}), file=sys.stderr, flush=True)
+    n = args.study_sets
+    lat = hmc.Lattice.batch([L] * n, [L] * n, [beta] * n, [m0] * n, seed=args.seed + 1)
+    lat.set_solver(tol=1e-10, max_iter=50000)
+    q_all = q_lex.repeat(n)
+    out = {"metric": "paper study: <|Delta H|> vs h and inversions of D per trajectory at 90% acceptance",
+           "config": {"L": L, "beta": beta, "m0": m0, "tau": tau, "sets": n,
+                      "thermalisation_trajectories": args.study_therm, "plaquette": plaq[0],
+                      "cg": "mixed precision, true residual 1e-10"},
+           "schemes": []}
+    names = set(args.study_schemes) if args.study_schemes else None
+    for label, name, exact, M in PAPER_SCHEMES:
+        if names and label not in names:
+            continue
+        lat.set_fg_mode("exact" if exact else "shift")
+        # the paper's count (Sec. 3): the exact C of Eq. (5) costs 10 per step
+        dinv_step = 10 if (exact and name == "force_gradient") else DINV_PER_STEP[name]
+        rows = []
+        for n_outer in args.study_n:
+            lat.pack_links(q_all, out=lat.q)
+            lat.trajectory_counter = 0           # the same momentum sets for every point
+            lat.refresh()
+            t0 = time.perf_counter()
+            r = lat.integrate(name, tau, n_outer, M, prec="mixed")
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            dH = [d for d, st in zip(r.dH, r.status) if st == 0 and math.isfinite(d)]
+            a = sorted(abs(d) for d in dH)
+            mean = sum(a) / len(a)
+            sd = math.sqrt(sum((x - mean) ** 2 for x in a) / max(1, len(a) - 1))
+            accp = sum(min(1.0, math.exp(-d)) if d > -700 else 1.0 for d in dH) / n
+            row = {"h": tau / n_outer, "n_outer": n_outer, "M": M, "mean_abs_dH": mean, "std_abs_dH": sd,
+                   "median_abs_dH": a[len(a) // 2], "max_abs_dH": a[-1],
+                   "sets_abs_dH_above_10": sum(1 for x in a if x > 10.0),
+                   "mean_dH": sum(dH) / len(dH), "acceptance": accp, "failed": n - len(dH),
+                   "dinv_per_traj": dinv_step * n_outer, "dinv_per_traj_run": r.n_dinv,
+                   "seconds": round(dt, 3)}
+            rows.append(row)
+            print(json.dumps({"scheme": label, **row}), file=sys.stderr, flush=True)
+        # h at 90% acceptance: interpolate log(1 - acceptance) linearly in log h
+        h90 = None
+        pts = sorted((r["h"], 1.0 - r["acceptance"]) for r in rows if 0 < r["acceptance"] < 1)
+        for (h1, e1), (h2, e2) in zip(pts, pts[1:]):
+            if e1 <= 0.1 <= e2 and e1 > 0:
+                w = (math.log(0.1) - math.log(e1)) / (math.log(e2) - math.log(e1))
+                h90 = math.exp(math.log(h1) + w * (math.log(h2) - math.log(h1)))
+        out["schemes"].append({"scheme": label, "M": M, "dinv_per_step": dinv_step, "points": rows,
+                               "h_at_90pct": h90,
+                               "dinv_per_traj_at_90pct": (dinv_step * tau / h90) if h90 else None})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +333,12 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="roofline sweep on single large lattices instead of the HMC benchmark")
     ap.add_argument("--sweep-sizes", type=int, nargs="+", default=[256, 512, 1024, 2048, 4096, 8192])
+    ap.add_argument("--paper-study", action="store_true",
+                    help="the paper's integrator study (Sec. 4) instead of the HMC benchmark")
+    ap.add_argument("--study-sets", type=int, default=200)
+    ap.add_argument("--study-therm", type=int, default=200)
+    ap.add_argument("--study-n", type=int, nargs="+", default=[12, 16, 20, 24, 32, 48, 64, 96, 128, 192])
+    ap.add_argument("--study-schemes", nargs="+", default=None)
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket the CG kernels with events (roofline figure omitted)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -261,6 +354,9 @@ def main():
         sys.exit(2)
     if args.sweep:
         run_sweep(args)
+        return
+    if args.paper_study:
+        run_paper_study(args)
         return
 
     if args.copy_calibration:

@@ -533,6 +533,30 @@ def test_quenched_exact_force_gradient_matches_oracle():
         assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - qr)) < 1e-10
 
 
+@pytest.mark.parametrize("scheme,exact,M", [("adapted_nested_fg", True, 5), ("force_gradient", True, 1),
+                                            ("omelyan_11stage", False, 1), ("nested_leapfrog", False, 10)])
+def test_md_parity_at_the_papers_couplings(scheme, exact, M):
+    """The study's physics point (Sec. 4: beta 1, m0 = -0.231367, tau 2, micro step h/10) on
+    8 x 8 with smooth links."""
+    Lx, Lt, beta, m0 = 8, 8, 1.0, -0.231367
+    b = Batch([(Lx, Lt, beta, m0)])
+    q = inputs.smooth_angles(Lx, Lt, 171, 0.4)
+    p = inputs.random_momenta(Lx, Lt, 172)
+    phi = inputs.random_spinor(Lx, Lt, 173)
+    b.set_q([q])
+    b.links_to_native([p], out=b.lat.p)
+    b.spinor_to_native([phi], out=b.lat.phi)
+    b.lat.set_solver(tol=1e-14)
+    b.lat.set_fg_mode("exact" if exact else "shift")
+    res = b.lat.integrate(scheme, 2.0, 40, M)
+    q1, p1, _ = oracle.md_integrate(q, p, phi, beta, m0, scheme, 2.0, 40, M, tol=1e-14,
+                                    fg_exact=exact)
+    assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - q1)) < 1e-9
+    assert np.max(np.abs(b.links_from_native(b.lat.p)[0] - p1)) < 1e-9
+    dH_ref = oracle.hamiltonian(q1, p1, phi, beta, m0) - oracle.hamiltonian(q, p, phi, beta, m0)
+    assert abs(res.dH[0] - dH_ref) < 1e-9 * max(1.0, abs(dH_ref))
+
+
 # ------------------------------------------------------------------ mixed precision
 @pytest.mark.parametrize("persistent", SOLVERS)
 @pytest.mark.parametrize("Lx,m0", [(16, 0.1), (32, 0.05), (64, 0.05)])
