@@ -66,7 +66,7 @@ def run_batched(args):
     L, beta, m0 = workload(args.seed, args.chains)
     lat = hmc.Lattice.batch(L, L, beta, m0, seed=args.seed)
     lat.hot_start()
-    lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=0.1)
+    lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
     tune = None
     for w in range(args.warmup):
         lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
@@ -327,6 +327,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--reliable-delta", type=float, default=1e-3,
+                    help="mixed CG: FP64 residual recomputation when the FP32 residual has dropped "
+                         "by this factor")
     ap.add_argument("--persistent-limit", type=int, default=0,
                     help="persistent-solver limit in sites after tuning (default 0: off, so that "
                          "the timed CG kernels run alone; -1 keeps the tuned value)")

@@ -168,7 +168,7 @@ uint32_t hmc_get_trajectory_counter(const hmc_ctx *ctx);
 
 /* Solver tolerance and iteration cap used inside hmc_trajectory (default 1e-12, 100000).
  * reliable_delta: in mixed precision, the FP64 residual is recomputed whenever the
- * FP32 residual has dropped by this factor (default 0.1). */
+ * FP32 residual has dropped by this factor (default 1e-3). */
 int hmc_set_solver(hmc_ctx *ctx, double tol, int max_iter, double reliable_delta);
 
 /* Drop the fermion action (pure-gauge HMC; used to check the gauge part against the exact
@@ -188,7 +188,7 @@ int hmc_set_persistent_limit(hmc_ctx *ctx, int vmax);
 int hmc_set_block_size(hmc_ctx *ctx, int block);
 
 /* Autotuner: times CG solves of this context's own chains at its current links (with a
- * fresh pseudofermion; p and phi are overwritten) for workgroup sizes {128, 256, 512} and
+ * fresh pseudofermion; p and phi are overwritten) for workgroup sizes {128, 256, 512, 1024} and
  * each applicable persistent-solver limit {0, 1024, 2048}, and keeps the fastest. */
 typedef struct {
     int block;             /* chosen workgroup size */

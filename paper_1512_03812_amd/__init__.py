@@ -227,7 +227,7 @@ class Lattice:
     def hot_start(self):
         self._check(self._lib.hmc_hot_start(self._ctx))
 
-    def set_solver(self, tol=1e-12, max_iter=100000, reliable_delta=0.1):
+    def set_solver(self, tol=1e-12, max_iter=100000, reliable_delta=1e-3):
         self._check(self._lib.hmc_set_solver(self._ctx, tol, max_iter, reliable_delta))
 
     def set_quenched(self, quenched: bool):
@@ -415,12 +415,38 @@ class Lattice:
         return self._traj_result(info)
 
 
+class _ActionForce(torch.autograd.Function):
+    """F(q) = dS/dq = F_G + F_F from the chi, xi of the action's forward (Eqs. (16), (17)).
+
+    Its backward is the Hessian-vector product of Sec. 3 (Eq. (21), plus the gauge part),
+    computed by the HIP library, so the action is twice differentiable.  The Hessian solve
+    uses the tolerance set by Lattice.set_solver."""
+
+    @staticmethod
+    def forward(ctx, q, lat, phi, chi, xi):
+        lat.q.copy_(q)
+        F = lat.total_force_chixi(chi, xi)
+        ctx.lat = lat
+        ctx.save_for_backward(q, phi)
+        return F
+
+    @staticmethod
+    def backward(ctx, grad_F):
+        q, phi = ctx.saved_tensors
+        lat = ctx.lat
+        lat.q.copy_(q.detach())
+        hv, _ = lat.hessian_vector(grad_F.detach().contiguous(), "total", phi)
+        return hv, None, None, None, None
+
+
 class SchwingerAction(torch.autograd.Function):
     """S(q) = S_G(q) + phi^dagger (D^dagger D)^{-1} phi per chain (Eqs. (13), (14)).
 
     Forward solves xi and forms chi = D xi in the HIP library; backward is the
     hand-written adjoint kernel (the fermion force of Eq. (17)) plus the gauge force
-    of Eq. (16), scaled by the incoming gradient of each chain."""
+    of Eq. (16), scaled by the incoming gradient of each chain.  The force is itself a
+    differentiable function of q whose backward is the library's Hessian-vector product,
+    so second derivatives (create_graph=True, torch.autograd.functional.hvp) work too."""
 
     @staticmethod
     def forward(ctx, q: torch.Tensor, lat: Lattice, phi: torch.Tensor, tol: float = 1e-12,
@@ -429,15 +455,14 @@ class SchwingerAction(torch.autograd.Function):
         sf, _ = lat.fermion_action(phi, tol=tol, prec=prec)
         sg, _, _ = lat.actions(None)
         ctx.lat = lat
-        ctx.save_for_backward(q.detach().clone(), lat.chi.clone(), lat.xi.clone())
+        ctx.save_for_backward(q, lat.chi.clone(), lat.xi.clone(), phi)
         return torch.tensor([a + b for a, b in zip(sg, sf)], dtype=torch.float64, device=q.device)
 
     @staticmethod
     def backward(ctx, grad_s):
-        q, chi, xi = ctx.saved_tensors
+        q, chi, xi, phi = ctx.saved_tensors
         lat = ctx.lat
-        lat.q.copy_(q)
-        F = lat.total_force_chixi(chi, xi)
+        F = _ActionForce.apply(q, lat, phi, chi, xi)
         if lat.n_chains == 1:
             grad = grad_s[0] * F
         else:

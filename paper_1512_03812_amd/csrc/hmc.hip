@@ -71,7 +71,7 @@ struct hmc_ctx {
     // ------------------------------------------------------------ solver settings
     double tol = 1e-12;
     int max_iter = 100000;
-    double delta = 0.1;
+    double delta = 1e-3;
     int check_every = 8;
     bool quenched = false;
     int fg_mode = HMC_FG_SHIFT;
@@ -1024,7 +1024,7 @@ int hmc_autotune(hmc_ctx *c, int prec, double tol, hmc_tune_info *out) {
     if (vmin <= 1024) persist.push_back(1024);
     for (const ChainInfo &ci : c->chains)
         if (ci.V > 1024 && ci.V <= 2048) { persist.push_back(2048); break; }
-    const int blocks[3] = {128, 256, 512};
+    const int blocks[4] = {128, 256, 512, 1024};
     const int saved_block = c->block, saved_persist = c->persist_vmax;
     double best = 1e300;
     int best_block = saved_block, best_persist = saved_persist, n = 0;

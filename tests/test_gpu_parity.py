@@ -351,7 +351,7 @@ def test_batched_trajectories_match_single_chain_oracle(persistent):
             assert np.max(np.abs(qs[c] - qr)) < 1e-9
 
 
-@pytest.mark.parametrize("block", [128, 512])
+@pytest.mark.parametrize("block", [128, 512, 1024])
 def test_other_workgroup_sizes_keep_parity(block):
     shapes = [(8, 8, 2.0, 0.1), (34, 18, 1.5, 0.2), (64, 64, 2.0, 0.1)]
     b = Batch(shapes, persistent=0)
@@ -370,7 +370,7 @@ def test_autotune_picks_a_valid_configuration():
     b = Batch([(16, 16, 2.0, 0.1), (32, 32, 3.0, 0.05), (64, 64, 2.0, 0.1)], seed=3)
     b.lat.hot_start()
     t = b.lat.autotune("mixed", 1e-10)
-    assert t["block"] in (128, 256, 512) and t["persistent_limit"] in (0, 1024, 2048)
+    assert t["block"] in (128, 256, 512, 1024) and t["persistent_limit"] in (0, 1024, 2048)
     assert t["candidates"] >= 3 and t["solve_ms"] > 0
     r = b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2, prec="mixed")
     assert all(s == 0 for s in r.status)
@@ -555,6 +555,24 @@ def test_md_parity_at_the_papers_couplings(scheme, exact, M):
     assert np.max(np.abs(b.links_from_native(b.lat.p)[0] - p1)) < 1e-9
     dH_ref = oracle.hamiltonian(q1, p1, phi, beta, m0) - oracle.hamiltonian(q, p, phi, beta, m0)
     assert abs(res.dH[0] - dH_ref) < 1e-9 * max(1.0, abs(dH_ref))
+
+
+def test_autograd_second_derivative_is_the_hessian_vector_product():
+    """d/dq <v, dS/dq> through create_graph=True equals the oracle's H v (Eqs. (21)-(23))."""
+    m = hmc()
+    Lx, Lt, beta, m0 = 8, 12, 1.5, 0.1
+    b = Batch([(Lx, Lt, beta, m0)])
+    b.lat.set_solver(tol=1e-14)
+    q = inputs.random_angles(Lx, Lt, 181)
+    phi = inputs.random_spinor(Lx, Lt, 182)
+    v = inputs.random_momenta(Lx, Lt, 183)
+    qn = b.links_to_native([q]).clone().requires_grad_(True)
+    S = m.SchwingerAction.apply(qn, b.lat, b.spinor_to_native([phi]), 1e-14)
+    (g,) = torch.autograd.grad(S.sum(), qn, create_graph=True)
+    ref_g = oracle.gauge_force(q, beta) + oracle.fermion_force(q, phi, m0, tol=1e-14)[0]
+    assert rel(b.links_from_native(g.detach())[0], ref_g) < 1e-10
+    (hv,) = torch.autograd.grad((g * b.links_to_native([v])).sum(), qn)
+    assert rel(b.links_from_native(hv)[0], oracle_hessian_vector(q, phi, v, beta, m0, "total")) < 1e-8
 
 
 # ------------------------------------------------------------------ mixed precision
