@@ -170,9 +170,10 @@ def cpu_baseline(args):
 
 
 def run_sweep(args):
-    """Roofline sweep on single large lattices (beta 2, m0 0.1, hot start): FP64 dslash,
-    and CG iterations in FP64 and in mixed precision (64 iteration slots, sampled events),
-    beside a plain device copy of 2 GiB as the measured bandwidth ceiling."""
+    """Roofline sweep on single large lattices, and on one batch of equal chains (beta 2,
+    m0 0.1, hot start): FP64 dslash, and CG iterations in FP64 and in mixed precision (64
+    iteration slots, sampled events), beside a plain device copy of 2 GiB as the measured
+    bandwidth ceiling."""
     import torch
     import paper_1512_03812_amd as hmc
     out = {"metric": "Dslash and CG iteration achieved HBM GB/s (single large lattices)",
@@ -190,8 +191,12 @@ def run_sweep(args):
     torch.cuda.synchronize()
     out["copy_ceiling_gbs"] = round(2 * n * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
     del a, b
-    for L in args.sweep_sizes:
-        lat = hmc.Lattice(L, 2.0, 0.1, seed=args.seed)
+    cases = [(L, 1) for L in args.sweep_sizes]
+    if args.sweep_batch and args.sweep_batch[0] > 0:
+        cases.append((args.sweep_batch[1], args.sweep_batch[0]))
+    for L, nb in cases:
+        lat = (hmc.Lattice(L, 2.0, 0.1, seed=args.seed) if nb == 1 else
+               hmc.Lattice.batch([L] * nb, [L] * nb, 2.0, 0.1, seed=args.seed))
         lat.hot_start()
         V = lat.V_total
         psi = torch.randn(2, V, dtype=torch.complex128, device="cuda")
@@ -207,7 +212,7 @@ def run_sweep(args):
         ev[1].record(lat.stream)
         torch.cuda.synchronize()
         us = 1e3 * ev[0].elapsed_time(ev[1]) / reps
-        row = {"L": L, "sites": V, "dslash64_us": round(us, 2),
+        row = {"L": L, "chains": nb, "sites": V, "dslash64_us": round(us, 2),
                "dslash64_gbs": round(96 * V / (us * 1e-6) / 1e9, 1)}
         for prec in ("fp64", "mixed"):
             lat.set_persistent_limit(0)
@@ -244,6 +249,95 @@ PAPER_SCHEMES = [("leapfrog", "leapfrog", False, 1), ("omelyan", "omelyan", Fals
                  ("omelyan_11stage", "omelyan_11stage", False, 1)]
 DINV_PER_STEP = {"leapfrog": 4, "omelyan": 6, "nested_leapfrog": 4, "nested_omelyan": 6,
                  "force_gradient": 8, "nested_fg": 8, "adapted_nested_fg": 8, "omelyan_11stage": 12}
+
+
+# Step-count grids (n_outer, n_inner) per scheme for the acceptance table of the plain FP64
+# 32 x 32 configuration (beta 2, m0 0.1, tau 1).
+C2_GRID = {"leapfrog": [(8, 1), (16, 1), (32, 1), (64, 1)],
+           "omelyan": [(8, 1), (16, 1), (32, 1), (64, 1)],
+           "force_gradient": [(4, 1), (8, 1), (16, 1), (32, 1)],
+           "nested_fg": [(n, m) for n in (4, 8, 16) for m in (2, 4)],
+           "adapted_nested_fg": [(n, m) for n in (4, 8, 16) for m in (2, 4)]}
+C5_GRID = [(n, m) for n in (2, 3, 4, 6, 8) for m in (2, 4)]
+
+
+def run_acceptance_table(args):
+    """Trajectories/s at fixed (>= 90 %) acceptance.  Plain FP64 32 x 32: per scheme and
+    step-count pair, the acceptance over 100 chains (one batched trajectory each, from
+    configurations thermalised by 200 5-stage trajectories), and the single-chain FP64 rate;
+    the smallest setting with acceptance >= 0.9 is the scheme's point.  Batched workload: the
+    same scan of (n_outer, n_inner) for the adapted nested scheme in mixed precision."""
+    import math
+    import torch
+    import paper_1512_03812_amd as hmc
+    out = {"metric": "trajectories/s at >= 90% acceptance", "c2": {}, "c5": None}
+    n = args.table_chains
+    bat = hmc.Lattice.batch([32] * n, [32] * n, 2.0, 0.1, seed=args.seed)
+    bat.hot_start()
+    bat.set_solver(tol=1e-12)
+    for _ in range(args.table_therm):
+        bat.trajectory("omelyan", 1.0, 10, 1)
+    q_th = bat.q.clone()
+    traj0 = bat.trajectory_counter
+    one = hmc.Lattice(32, 2.0, 0.1, seed=args.seed)
+    one.set_solver(tol=1e-12)
+    one.pack_links(bat.unpack_links(q_th)[:2 * 1024], out=one.q)
+    q1 = one.q.clone()
+    for scheme, grid in C2_GRID.items():
+        rows = []
+        for n_outer, n_inner in grid:
+            bat.q.copy_(q_th)
+            bat.trajectory_counter = traj0
+            r = bat.trajectory(scheme, 1.0, n_outer, n_inner)
+            acc = sum(r.accepted) / n
+            one.q.copy_(q1)
+            one.trajectory(scheme, 1.0, n_outer, n_inner)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.table_single):
+                one.trajectory(scheme, 1.0, n_outer, n_inner)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.table_single
+            row = {"n_outer": n_outer, "n_inner": n_inner, "acceptance": acc,
+                   "mean_abs_dH": sum(abs(d) for d in r.dH) / n, "dinv_per_traj": r.n_dinv,
+                   "single_chain_traj_per_s": round(1.0 / dt, 2)}
+            rows.append(row)
+            print(json.dumps({"c2": scheme, **row}), file=sys.stderr, flush=True)
+        ok = [x for x in rows if x["acceptance"] >= 0.9]
+        best = min(ok, key=lambda x: (x["dinv_per_traj"], -x["single_chain_traj_per_s"])) if ok else None
+        out["c2"][scheme] = {"points": rows, "at_90pct": best}
+    # batched workload
+    L, beta, m0 = workload(args.seed, args.chains)
+    lat = hmc.Lattice.batch(L, L, beta, m0, seed=args.seed)
+    lat.hot_start()
+    lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
+    lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+    if not args.no_tune:
+        lat.autotune("mixed", 1e-10)
+    if args.persistent_limit >= 0:
+        lat.set_persistent_limit(args.persistent_limit)
+    for _ in range(2):
+        lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+    q5 = lat.q.clone()
+    t5 = lat.trajectory_counter
+    rows = []
+    for n_outer, n_inner in C5_GRID:
+        lat.q.copy_(q5)
+        lat.trajectory_counter = t5
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc = []
+        for _ in range(args.table_steps):
+            acc += lat.trajectory("adapted_nested_fg", 1.0, n_outer, n_inner, prec="mixed").accepted
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        row = {"n_outer": n_outer, "n_inner": n_inner, "acceptance": sum(acc) / len(acc),
+               "chain_traj_per_s": round(len(acc) / dt, 1)}
+        rows.append(row)
+        print(json.dumps({"c5": "adapted_nested_fg", **row}), file=sys.stderr, flush=True)
+    ok = [x for x in rows if x["acceptance"] >= 0.9]
+    out["c5"] = {"points": rows, "at_90pct": max(ok, key=lambda x: x["chain_traj_per_s"]) if ok else None}
+    print(json.dumps(out), flush=True)
 
 
 def run_paper_study(args):
@@ -336,6 +430,14 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="roofline sweep on single large lattices instead of the HMC benchmark")
     ap.add_argument("--sweep-sizes", type=int, nargs="+", default=[256, 512, 1024, 2048, 4096, 8192])
+    ap.add_argument("--sweep-batch", type=int, nargs=2, default=[1024, 128], metavar=("CHAINS", "L"),
+                    help="also sweep a batch of CHAINS chains of L x L (0 0: none)")
+    ap.add_argument("--acceptance-table", action="store_true",
+                    help="trajectories/s at >= 90%% acceptance per scheme and step count")
+    ap.add_argument("--table-chains", type=int, default=100)
+    ap.add_argument("--table-therm", type=int, default=200)
+    ap.add_argument("--table-single", type=int, default=3)
+    ap.add_argument("--table-steps", type=int, default=3)
     ap.add_argument("--paper-study", action="store_true",
                     help="the paper's integrator study (Sec. 4) instead of the HMC benchmark")
     ap.add_argument("--study-sets", type=int, default=200)
@@ -360,6 +462,9 @@ def main():
         return
     if args.paper_study:
         run_paper_study(args)
+        return
+    if args.acceptance_table:
+        run_acceptance_table(args)
         return
 
     if args.copy_calibration:

@@ -31,31 +31,30 @@ enum Spin32Buf { FX, FR, FT, FPA, FPB, kNumSpin32Bufs };
 }  // namespace
 
 // Sampled event timing of the two CG step kernels (kernel index 0: step 1, 1: step 2).
-// Every sample_every-th iteration slot is bracketed by HIP events, and the per-chain CG
-// state of that slot is copied to pinned host memory, so that the algorithmic bytes of
-// exactly those launches (active chains x sites x bytes per site of the slot's mode) can
-// be attributed to the measured durations.
+// Every sample_every-th iteration slot is bracketed by HIP events.  Step 1 of that slot
+// writes, for each chain it iterates, the algorithmic bytes of both steps (the chain's
+// sites times the bytes per site of the slot's mode) into a device row; at the end of the
+// solve one reduction sums the rows and a single copy brings the sums to the host, so the
+// bytes of exactly those launches are attributed to the measured durations with no copy
+// inside the iteration loop.
 struct TimedSlot {
     hipEvent_t ev[3];
-    int mixed;
-    int snap;  // index of the state snapshot in the pinned ring
+    int sample;  // row of the device byte table
 };
 
 struct KernelTimer {
     bool on = false;
-    int sample_every = 8;
+    int sample_every = 16;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     std::vector<TimedSlot> pending;
-    void *ring = nullptr;  // pinned: kRingSlots snapshots of the CG state (one parity)
-    int ring_used = 0;
+    double *sums_host = nullptr;  // pinned: [kMaxSamples][2] byte sums of the pending samples
     double ms[2] = {0.0, 0.0};
     double bytes[2] = {0.0, 0.0};
     long long timed[2] = {0, 0};
     long long launches = 0;  // all slots launched while timing was on
     int since_sync = 0;      // slots launched since the host last waited for the stream
 };
-constexpr int kRingSlots = 32;
 
 struct hmc_ctx {
     // ------------------------------------------------------------ geometry (host)
@@ -81,7 +80,7 @@ struct hmc_ctx {
     char *ws = nullptr;
     hipStream_t stream = nullptr;
     size_t off_chains = 0, off_work = 0, off_active = 0, off_big = 0, off_small = 0, off_cg = 0,
-           off_partials = 0,
+           off_partials = 0, off_samples = 0, off_sample_sums = 0,
            off_sums = 0, off_fin = 0, off_metro = 0, off_status = 0, off_count = 0, off_links[kNumLinkBufs] = {},
            off_spin[kNumSpinBufs] = {}, off_U64 = 0, off_U32 = 0, off_spin32[kNumSpin32Bufs] = {},
            off_Uw = 0;
@@ -203,6 +202,8 @@ void layout_workspace(hmc_ctx *c, size_t N) {
     c->off_small = take(sizeof(int) * C);
     c->off_cg = take(sizeof(CGState) * 2 * C);
     c->off_partials = take(sizeof(double) * kMaxReduce * N);
+    c->off_samples = take(sizeof(double) * 2 * kMaxSamples * C);
+    c->off_sample_sums = take(sizeof(double) * 2 * kMaxSamples);
     c->off_sums = take(sizeof(double) * 16 * C);
     c->off_fin = take(sizeof(double) * 2 * C);
     c->off_metro = take(sizeof(MetroOut) * C);
@@ -310,22 +311,6 @@ int check_convergence(hmc_ctx *c, const Geo &big, int max_iter, int *active, int
     return HMC_OK;
 }
 
-// Algorithmic bytes per lattice site of the CG step kernels (each distinct input read once,
-// each output written once; stencil neighbours come from cache).  Step 1 also applies the
-// previous iteration's x update.
-//   FP64 solver   step 1: r 32 + p_old 32 + U 32 + x 32 read, p 32 + t 32 + x 32 = 224
-//                 step 2: t 32 + U 32 + r 32 read, r 32 written                  = 128
-//   mixed, FP32   step 1: r 16 + p_old 16 + U 16 + x 16 read, p 16 + t 16 + x 16 = 112
-//                 step 2: t 16 + U 16 + r 16 read, r 16 written                  =  64
-//   mixed, FP64 residual recomputation
-//                 step 1: x64 32 + x32 16 + p_old 16 + U64 32 read, t64 32 + p 16 = 144
-//                 step 2: t64 32 + U64 32 + phi 32 + x64 32 + x32 16 + p 16 read,
-//                         x64 32 + x32 16 + r32 16 written                      = 224
-// (The first slot of a solve reads neither p_old nor x; it is counted like the others.)
-constexpr double kBytesFp64[2] = {224.0, 128.0};
-constexpr double kBytesFp32[2] = {112.0, 64.0};
-constexpr double kBytesUpdate[2] = {144.0, 224.0};
-
 hipEvent_t timer_event(hmc_ctx *c) {
     KernelTimer &T = c->timer;
     if (T.pool_used == T.pool.size()) {
@@ -336,37 +321,39 @@ hipEvent_t timer_event(hmc_ctx *c) {
     return T.pool[T.pool_used++];
 }
 
-// Called only after the stream was synchronised: every recorded event and snapshot is complete.
+// Sums the device byte rows of the pending samples into pinned memory (stream-ordered, no
+// wait); the caller synchronises before timer_flush.
+void timer_reduce(hmc_ctx *c) {
+    KernelTimer &T = c->timer;
+    if (T.pending.empty()) return;
+    const int n = (int)T.pending.size();
+    double *sums = c->at<double>(c->off_sample_sums);
+    launch_sample_sums(c->at<double>(c->off_samples), n, c->nchains, sums, c->stream);
+    (void)hipMemcpyAsync(T.sums_host, sums, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, c->stream);
+}
+
+// Called only after the stream was synchronised (following timer_reduce): every recorded
+// event and byte sum is complete.
 void timer_flush(hmc_ctx *c) {
     KernelTimer &T = c->timer;
     for (const TimedSlot &ts : T.pending) {
         float a = 0.f, b = 0.f;
         if (hipEventElapsedTime(&a, ts.ev[0], ts.ev[1]) != hipSuccess) continue;
         if (hipEventElapsedTime(&b, ts.ev[1], ts.ev[2]) != hipSuccess) continue;
-        const CGState *snap = (const CGState *)((char *)T.ring + (size_t)ts.snap * sizeof(CGState) * c->nchains);
-        double by[2] = {0.0, 0.0};
-        for (int k = 0; k < c->nchains; ++k) {
-            if (snap[k].converged) continue;
-            const double V = c->chains[k].V;
-            const double *per = !ts.mixed ? kBytesFp64 : snap[k].mode == kModeUpdate ? kBytesUpdate : kBytesFp32;
-            by[0] += V * per[0];
-            by[1] += V * per[1];
-        }
         T.ms[0] += a;
         T.ms[1] += b;
-        T.bytes[0] += by[0];
-        T.bytes[1] += by[1];
+        T.bytes[0] += T.sums_host[2 * ts.sample];
+        T.bytes[1] += T.sums_host[2 * ts.sample + 1];
         T.timed[0]++;
         T.timed[1]++;
     }
     T.pending.clear();
     T.pool_used = 0;
-    T.ring_used = 0;
 }
 
-// One CG slot (step 1 + step 2); sampled slots are bracketed by events and their state
-// snapshotted.
-template <typename L1, typename L2> void slot_launch(hmc_ctx *c, int slot, bool mixed, L1 step1, L2 step2) {
+// One CG slot (step 1 + step 2); a sampled slot is bracketed by events and its step 1
+// records the bytes of both steps in the row given to it (-1: not sampled).
+template <typename L1, typename L2> void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2) {
     KernelTimer &T = c->timer;
     if (T.on) T.launches++;
     // Sampled slots sit mid-way between the convergence checks, a few slots after the host
@@ -374,24 +361,19 @@ template <typename L1, typename L2> void slot_launch(hmc_ctx *c, int slot, bool 
     // the kernels rather than the host's latency in enqueuing them after a wait.
     const int since = T.since_sync++;
     if (!T.on || slot % T.sample_every != T.sample_every / 2 || since < 2 ||
-        T.ring_used == kRingSlots || !T.ring) {
-        step1();
+        (int)T.pending.size() == kMaxSamples || !T.sums_host) {
+        step1(-1);
         step2();
         return;
     }
     TimedSlot ts;
     for (int k = 0; k < 3; ++k) ts.ev[k] = timer_event(c);
-    ts.mixed = mixed ? 1 : 0;
-    ts.snap = T.ring_used++;
+    ts.sample = (int)T.pending.size();
     (void)hipEventRecord(ts.ev[0], c->stream);
-    step1();
+    step1(ts.sample);
     (void)hipEventRecord(ts.ev[1], c->stream);
     step2();
     (void)hipEventRecord(ts.ev[2], c->stream);
-    // the state written by step 1 of this slot stays valid until step 1 of slot + 2
-    (void)hipMemcpyAsync((char *)T.ring + (size_t)ts.snap * sizeof(CGState) * c->nchains,
-                         c->cg() + (size_t)(slot & 1) * c->nchains, sizeof(CGState) * c->nchains,
-                         hipMemcpyDeviceToHost, c->stream);
     T.pending.push_back(ts);
 }
 
@@ -458,6 +440,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     f.fin1 = c->at<double>(c->off_fin);
     f.fin2 = f.fin1 + c->nchains;
     f.st = c->cg();
+    f.samples = c->at<double>(c->off_samples);
     void *pb[2];
     if (mixed) { pb[0] = c->spin32(FPA); pb[1] = c->spin32(FPB); }
     else { pb[0] = c->spin(SPA); pb[1] = c->spin(SPB); }
@@ -492,9 +475,9 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     int interval = c->check_every, next_check = interval, last_active = big.nblocks;
     for (; slot < max_slots; ++slot) {
         void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
-        slot_launch(c, slot, mixed,
-                    [&] {
-                        launch_cg_step1(g, f, mixed, slot, tol, po, pn, false, c->stream);
+        slot_launch(c, slot,
+                    [&](int sample) {
+                        launch_cg_step1(g, f, mixed, slot, tol, po, pn, false, sample, c->stream);
                         if (c->has_large) launch_finalize_large(big, f.p1, f.fin1, c->stream);
                     },
                     [&] {
@@ -504,7 +487,6 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
         if (slot + 1 == next_check) {
             int active = 0, live = 0;
             if ((rc = check_convergence(c, big, mixed ? max_iter : max_slots, &active, &live))) return rc;
-            if (c->timer.on) timer_flush(c);
             if (active == 0 || (mixed && live == 0)) { ++slot; break; }
             g.work = c->at<BlockWork>(c->off_active);
             g.nblocks = active;
@@ -515,10 +497,11 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
         }
     }
     // fold the last slot's residual into the state (decision only), on every large chain
-    launch_cg_step1(big, f, mixed, slot, tol, pb[slot & 1], pb[(slot + 1) & 1], true, c->stream);
+    launch_cg_step1(big, f, mixed, slot, tol, pb[slot & 1], pb[(slot + 1) & 1], true, -1, c->stream);
     if (mixed) launch_cg_finish_mixed(big, f, c->stream);
     }
     if (c->n_small > 0) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->join_ev, 0));
+    if (c->timer.on) timer_reduce(c);
     if ((rc = to_host(c, c->cg_host.data(), c->cg() + (size_t)(slot & 1) * c->nchains,
                       sizeof(CGState) * c->nchains))) return rc;
     if (c->timer.on) timer_flush(c);
@@ -1409,12 +1392,15 @@ int hmc_set_timing(hmc_ctx *c, int on) {
         if (rc) return rc;
     }
     KernelTimer &T = c->timer;
-    if (on && !T.ring)
-        HIP_TRY(c, hipHostMalloc(&T.ring, sizeof(CGState) * c->nchains * kRingSlots, hipHostMallocDefault));
+    if (on && !T.sums_host)
+        HIP_TRY(c, hipHostMalloc((void **)&T.sums_host, sizeof(double) * 2 * kMaxSamples,
+                                 hipHostMallocDefault));
+    if (c->ws)  // rows of samples abandoned by an earlier error start from zero again
+        HIP_TRY(c, hipMemsetAsync(c->at<double>(c->off_samples), 0,
+                                  sizeof(double) * 2 * kMaxSamples * c->nchains, c->stream));
     T.on = on != 0;
     T.pending.clear();
     T.pool_used = 0;
-    T.ring_used = 0;
     T.ms[0] = T.ms[1] = 0.0;
     T.bytes[0] = T.bytes[1] = 0.0;
     T.timed[0] = T.timed[1] = 0;
@@ -1436,7 +1422,7 @@ int hmc_get_kernel_stats(hmc_ctx *c, int which, hmc_kernel_stat *out) {
 int hmc_destroy(hmc_ctx *c) {
     if (!c) return HMC_E_INVAL;
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
-    if (c->timer.ring) (void)hipHostFree(c->timer.ring);
+    if (c->timer.sums_host) (void)hipHostFree(c->timer.sums_host);
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);

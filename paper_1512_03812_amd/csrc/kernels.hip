@@ -327,7 +327,7 @@ __global__ void k_cg_init(Geo g, CGFields f, double delta2) {
 
 template <bool MIXED>
 __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void *p_old_v,
-                           void *p_new_v, int decide_only) {
+                           void *p_new_v, int decide_only, int sample) {
     using R = typename Prec<MIXED>::R;
     using S = typename Prec<MIXED>::S;
     using C = cplx_t<R>;
@@ -377,6 +377,12 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
         out->converged = n_conv; out->mode = update ? kModeUpdate : kModeNormal;
         out->n_updates = n_nupd;
         out->alpha = update ? pend : 0.0;
+        if (sample >= 0 && !n_conv && !decide_only) {
+            // timing: the algorithmic bytes of both steps of this slot for this chain
+            double* row = f.samples + ((size_t)sample * g.nchains + w.chain) * 2;
+            row[0] = ci.V * (!MIXED ? kBytesFp64Step1 : update ? kBytesUpdateStep1 : kBytesFp32Step1);
+            row[1] = ci.V * (!MIXED ? kBytesFp64Step2 : update ? kBytesUpdateStep2 : kBytesFp32Step2);
+        }
     }
     const S *__restrict__ p_old = (const S *)p_old_v;
     S *__restrict__ p_new = (S *)p_new_v;
@@ -586,15 +592,37 @@ void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, h
 }
 
 void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
-                     const void *p_old, void *p_new, bool decide_only, hipStream_t s) {
+                     const void *p_old, void *p_new, bool decide_only, int sample, hipStream_t s) {
     if (mixed)
         hipLaunchKernelGGL(k_cg_step1<true>, dim3(g.nblocks), dim3(g.block),
                            g.block * sizeof(LdsSpinor<float2>), s, g, f, slot, tol * tol, p_old,
-                           p_new, decide_only ? 1 : 0);
+                           p_new, decide_only ? 1 : 0, sample);
     else
         hipLaunchKernelGGL(k_cg_step1<false>, dim3(g.nblocks), dim3(g.block),
                            g.block * sizeof(LdsSpinor<double2>), s, g, f, slot, tol * tol, p_old,
-                           p_new, decide_only ? 1 : 0);
+                           p_new, decide_only ? 1 : 0, sample);
+}
+
+// One workgroup per sampled slot: the sum over chains of its byte row, which is then zeroed
+// for the next solve.
+__global__ void k_sample_sums(double *__restrict__ samples, int nchains, double *__restrict__ sums) {
+    double v[2] = {0.0, 0.0};
+    double *row = samples + (size_t)blockIdx.x * nchains * 2;
+    for (int c = threadIdx.x; c < nchains; c += blockDim.x) {
+        v[0] += row[2 * c];
+        v[1] += row[2 * c + 1];
+        row[2 * c] = 0.0;
+        row[2 * c + 1] = 0.0;
+    }
+    block_sum_all<2>(v);
+    if (threadIdx.x == 0) {
+        sums[2 * blockIdx.x] = v[0];
+        sums[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+void launch_sample_sums(double *samples, int n, int nchains, double *sums, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_sample_sums, dim3(n), dim3(256), 0, s, samples, nchains, sums);
 }
 
 void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,

@@ -40,6 +40,24 @@ struct CGState {
 static_assert(sizeof(CGState) % 16 == 0, "CGState alignment");
 enum { kModeInit = 0, kModeNormal = 1, kModeUpdate = 2 };
 
+// Sampled slots per solve whose bytes the timing records (rows of the device byte table).
+constexpr int kMaxSamples = 256;
+// Algorithmic bytes per lattice site of the CG step kernels (each distinct input read once,
+// each output written once; stencil neighbours come from cache).  Step 1 also applies the
+// previous iteration's x update.
+//   FP64 solver   step 1: r 32 + p_old 32 + U 32 + x 32 read, p 32 + t 32 + x 32 = 224
+//                 step 2: t 32 + U 32 + r 32 read, r 32 written                  = 128
+//   mixed, FP32   step 1: r 16 + p_old 16 + U 16 + x 16 read, p 16 + t 16 + x 16 = 112
+//                 step 2: t 16 + U 16 + r 16 read, r 16 written                  =  64
+//   mixed, FP64 residual recomputation
+//                 step 1: x64 32 + x32 16 + p_old 16 + U64 32 read, t64 32 + p 16 = 144
+//                 step 2: t64 32 + U64 32 + phi 32 + x64 32 + x32 16 + p 16 read,
+//                         x64 32 + x32 16 + r32 16 written                      = 224
+// (The first slot of a solve reads neither p_old nor x; it is counted like the others.)
+constexpr double kBytesFp64Step1 = 224.0, kBytesFp64Step2 = 128.0;
+constexpr double kBytesFp32Step1 = 112.0, kBytesFp32Step2 = 64.0;
+constexpr double kBytesUpdateStep1 = 144.0, kBytesUpdateStep2 = 224.0;
+
 // Partial sums: row k of partials holds one double per logical workgroup.
 constexpr int kMaxReduce = 8;
 // A consumer workgroup re-adds its chain's partials itself when the chain has at most this
@@ -71,6 +89,7 @@ struct CGFields {
     double *p1, *p2;          // partial rows: ||D p||^2 (step 1) and ||r||^2 (step 2)
     double *fin1, *fin2;      // per-chain totals of p1, p2 for chains above kMaxChainBlocks
     CGState *st;              // [2][nchains]
+    double *samples;          // timing: [kMaxSamples][nchains][2] bytes of sampled slots
 };
 // x = 0, r = phi, partial ||phi||^2 -> p2, state[1] = initial.
 void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, hipStream_t s);
@@ -79,7 +98,9 @@ void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, h
 // and t = D p_new with partial ||t||^2 (or, in a reliable-update slot,
 // t64 = D (x64 + x32 + alpha p_old)).  decide_only: state update and the owed x update only.
 void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
-                     const void *p_old, void *p_new, bool decide_only, hipStream_t s);
+                     const void *p_old, void *p_new, bool decide_only, int sample, hipStream_t s);
+// sums[2 b + k] = sum over chains of samples[b][chain][k], b < n; the rows are zeroed.
+void launch_sample_sums(double *samples, int n, int nchains, double *sums, hipStream_t s);
 // Slot k, second kernel: alpha from the partials of step 1 (kept in the state for the next
 // slot's x update), r -= alpha D^dagger t with partial ||r||^2 (or the FP64 residual
 // recomputation, which also folds x32 and the owed alpha p into x64).
