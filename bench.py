@@ -67,6 +67,7 @@ def run_batched(args):
     lat = hmc.Lattice.batch(L, L, beta, m0, seed=args.seed)
     lat.hot_start()
     lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
+    lat.set_check_interval(args.check_interval)
     tune = None
     for w in range(args.warmup):
         lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
@@ -421,6 +422,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--check-interval", type=int, default=32,
+                    help="CG slots between convergence checks (workgroup compaction)")
     ap.add_argument("--reliable-delta", type=float, default=1e-3,
                     help="mixed CG: FP64 residual recomputation when the FP32 residual has dropped "
                          "by this factor")

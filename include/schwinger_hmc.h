@@ -176,7 +176,8 @@ int hmc_set_solver(hmc_ctx *ctx, double tol, int max_iter, double reliable_delta
 int hmc_set_quenched(hmc_ctx *ctx, int quenched);
 
 /* Every `every` CG iterations the host reads back how many chains have converged
- * (default 8).  Iterations launched after a chain converged do no work for it. */
+ * (default 32; the interval doubles up to 4 times that while no chain converges).  Iterations
+ * launched after a chain converged do no work for it. */
 int hmc_set_check_interval(hmc_ctx *ctx, int every);
 
 /* Chains with at most vmax sites solve their CG inside one persistent workgroup (the

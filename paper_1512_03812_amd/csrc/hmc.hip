@@ -71,7 +71,7 @@ struct hmc_ctx {
     double tol = 1e-12;
     int max_iter = 100000;
     double delta = 1e-3;
-    int check_every = 8;
+    int check_every = 32;
     bool quenched = false;
     int fg_mode = HMC_FG_SHIFT;
     int persist_vmax = 2048;  // chains with at most this many sites use the persistent solver
@@ -471,7 +471,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     // iteration slots: CG iterations plus, in mixed precision, FP64 residual recomputations
     const int max_slots = mixed ? max_iter + max_iter / 2 + 64 : max_iter;
     // Convergence checks: the first after check_every slots; the interval doubles (up to
-    // 8x) while no chain converges and falls back when the active set shrinks.
+    // 4x) while no chain converges and falls back when the active set shrinks.
     int interval = c->check_every, next_check = interval, last_active = big.nblocks;
     for (; slot < max_slots; ++slot) {
         void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
@@ -490,7 +490,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
             if (active == 0 || (mixed && live == 0)) { ++slot; break; }
             g.work = c->at<BlockWork>(c->off_active);
             g.nblocks = active;
-            interval = active == last_active ? std::min(2 * interval, 8 * c->check_every)
+            interval = active == last_active ? std::min(2 * interval, 4 * c->check_every)
                                              : c->check_every;
             last_active = active;
             next_check = slot + 1 + interval;
