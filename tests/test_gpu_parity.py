@@ -196,6 +196,22 @@ def test_cg_parity(Lx, Lt, m0, persistent):
     assert rel(b.spinor_from_native(x)[0], xr) < 1e-10
 
 
+def test_cg_iterations_on_a_chain_above_2048_workgroups():
+    """1024 x 1024 (4096 workgroups of 256 threads: the reductions go through the finalize
+    kernel, and workgroup strips are shorter than a row): 12 FP64 CG iterations against the
+    oracle's 12."""
+    L = 1024
+    b = Batch([(L, L, 2.0, 0.1)], persistent=0)
+    q = inputs.random_angles(L, L, 191)
+    phi = inputs.random_spinor(L, L, 192)
+    b.set_q([q])
+    x, res = b.lat.cg_solve(b.spinor_to_native([phi]), tol=1e-30, max_iter=12)
+    assert not res.converged[0] and res.iters[0] == 12
+    xr, itr, _ = oracle.cg(q, phi, 0.1, tol=1e-30, max_iter=12)
+    assert itr == -1
+    assert rel(b.spinor_from_native(x)[0], xr) < 1e-11
+
+
 @pytest.mark.parametrize("persistent", SOLVERS)
 @pytest.mark.parametrize("Lx,Lt,m0", [(8, 8, 0.1), (6, 10, 0.05), (32, 32, 0.1)])
 def test_fermion_force_parity(Lx, Lt, m0, persistent):
