@@ -64,10 +64,14 @@ def run_batched(args):
     import torch
     import paper_1512_03812_amd as hmc
     L, beta, m0 = workload(args.seed, args.chains)
+    if args.uniform_L:
+        L = [args.uniform_L] * len(L)
     lat = hmc.Lattice.batch(L, L, beta, m0, seed=args.seed)
     lat.hot_start()
     lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
     lat.set_check_interval(args.check_interval)
+    if args.block:
+        lat.set_block_size(args.block)
     tune = None
     for w in range(args.warmup):
         lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
@@ -118,7 +122,17 @@ def run_single_fp64(args):
         acc += lat.trajectory("adapted_nested_fg", 1.0, 8, 4).accepted
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same trajectories replayed from a captured HIP graph
+    lat.set_graph(True)
+    lat.trajectory("adapted_nested_fg", 1.0, 8, 4)  # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n):
+        lat.trajectory("adapted_nested_fg", 1.0, 8, 4)
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - t0
     return {"value": n / dt, "unit": "trajectories/s", "ms_per_traj": 1e3 * dt / n,
+            "graph_value": n / dtg, "graph_ms_per_traj": 1e3 * dtg / n,
             "acceptance": sum(acc) / len(acc), "dtype": "f64",
             "config": "32x32, beta 2.0, m0 0.1, adapted nested FG tau 1 n_outer 8 n_inner 4, CG tol 1e-12"}
 
@@ -422,6 +436,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--block", type=int, default=0, help="fixed workgroup size (with --no-tune)")
+    ap.add_argument("--uniform-L", type=int, default=0,
+                    help="exploration: every chain of the batch L x L (not the benchmark workload)")
     ap.add_argument("--check-interval", type=int, default=32,
                     help="CG slots between convergence checks (workgroup compaction)")
     ap.add_argument("--reliable-delta", type=float, default=1e-3,

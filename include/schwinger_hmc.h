@@ -294,6 +294,16 @@ int hmc_set_fg_mode(hmc_ctx *ctx, int mode);
 int hmc_trajectory(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inner, int prec,
                    hmc_traj_info *info);
 
+/* Captured trajectories.  With on != 0, hmc_trajectory records its whole device work (refresh,
+ * molecular dynamics with every solve, energies, Metropolis) as one HIP graph on first use of
+ * a (scheme, tau, n_outer, n_inner, prec) schedule and replays that graph afterwards: one launch
+ * per trajectory and no host round trip until its results are read.  The results are those of
+ * the eager path, bit for bit.  Needs every chain within the persistent solver's limit (its
+ * solves have no host-driven loop); hmc_trajectory returns HMC_E_INVAL otherwise.  Any setter
+ * (solver, quenched, force-gradient mode, persistent limit, workgroup size) and a new binding
+ * discard the captured graphs.  Default off. */
+int hmc_set_graph(hmc_ctx *ctx, int on);
+
 /* The refresh of Sec. 2.1 alone, for the current trajectory counter (not incremented):
  * p ~ N(0,1) from Philox stream 1, zeta with density exp(-zeta^dagger zeta) from stream 2,
  * phi = D^dagger zeta at the current links (so S_F(U) = zeta^dagger zeta). */

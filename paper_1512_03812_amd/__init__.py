@@ -238,6 +238,11 @@ class Lattice:
         the force-gradient term C of Eq. (19) through a Hessian-vector product."""
         self._check(self._lib.hmc_set_fg_mode(self._ctx, _lib.FG_MODES[mode]))
 
+    def set_graph(self, on: bool):
+        """Capture each trajectory schedule as one HIP graph and replay it (every chain must
+        fit the persistent solver)."""
+        self._check(self._lib.hmc_set_graph(self._ctx, int(bool(on))))
+
     def set_persistent_limit(self, vmax: int):
         """Chains of at most vmax sites solve inside one persistent workgroup (0: never)."""
         self._check(self._lib.hmc_set_persistent_limit(self._ctx, int(vmax)))

@@ -89,6 +89,7 @@ SIGNATURES = {
     "hmc_hessian_vector": (_I, [_P, _I, _P, _P, _P, _I, _P]),
     "hmc_force_gradient_term": (_I, [_P, _I, _P, _P, _I, _P]),
     "hmc_set_fg_mode": (_I, [_P, _I]),
+    "hmc_set_graph": (_I, [_P, _I]),
     "hmc_trajectory": (_I, [_P, _I, _D, _I, _I, _I, _P]),
     "hmc_integrate": (_I, [_P, _I, _D, _I, _I, _I, _P]),
     "hmc_refresh": (_I, [_P]),

@@ -56,6 +56,19 @@ struct KernelTimer {
     int since_sync = 0;      // slots launched since the host last waited for the stream
 };
 
+// Solves whose results a captured trajectory can log on the device.
+constexpr int kMaxLoggedSolves = 1024;
+
+// A trajectory captured as one HIP graph, with the host-side counts of its schedule.
+struct GraphEntry {
+    int scheme, n_outer, n_inner, prec, fg_mode;
+    double tau;
+    long epoch;  // settings generation it was captured under
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int solves = 0, force_evals = 0, hvp_solves = 0, logged = 0;
+};
+
 struct hmc_ctx {
     // ------------------------------------------------------------ geometry (host)
     int nchains = 0;
@@ -74,13 +87,20 @@ struct hmc_ctx {
     int check_every = 32;
     bool quenched = false;
     int fg_mode = HMC_FG_SHIFT;
+    // ------------------------------------------------------------ captured trajectories
+    bool graph_on = false;
+    long graph_epoch = 0;          // bumped by every setting a captured graph bakes in
+    std::vector<GraphEntry> graphs;
+    bool deferring = false;        // capturing: solves log their results on the device
+    int log_count = 0;             // solves logged by the trajectory being captured
+    bool log_overflow = false;
     int persist_vmax = 2048;  // chains with at most this many sites use the persistent solver
     // ------------------------------------------------------------ workspace
     size_t ws_bytes = 0;
     char *ws = nullptr;
     hipStream_t stream = nullptr;
     size_t off_chains = 0, off_work = 0, off_active = 0, off_big = 0, off_small = 0, off_cg = 0,
-           off_partials = 0, off_samples = 0, off_sample_sums = 0,
+           off_partials = 0, off_samples = 0, off_sample_sums = 0, off_trajc = 0, off_log = 0,
            off_sums = 0, off_fin = 0, off_metro = 0, off_status = 0, off_count = 0, off_links[kNumLinkBufs] = {},
            off_spin[kNumSpinBufs] = {}, off_U64 = 0, off_U32 = 0, off_spin32[kNumSpin32Bufs] = {},
            off_Uw = 0;
@@ -203,6 +223,8 @@ void layout_workspace(hmc_ctx *c, size_t N) {
     c->off_cg = take(sizeof(CGState) * 2 * C);
     c->off_partials = take(sizeof(double) * kMaxReduce * N);
     c->off_samples = take(sizeof(double) * 2 * kMaxSamples * C);
+    c->off_trajc = take(sizeof(uint32_t));
+    c->off_log = take(sizeof(int) * 2 * kMaxLoggedSolves * C);
     c->off_sample_sums = take(sizeof(double) * 2 * kMaxSamples);
     c->off_sums = take(sizeof(double) * 16 * C);
     c->off_fin = take(sizeof(double) * 2 * C);
@@ -446,6 +468,20 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     else { pb[0] = c->spin(SPA); pb[1] = c->spin(SPB); }
     int rc = build_partition(c, persistent_limit(c, mixed));
     if (rc) return rc;
+    if (c->deferring) {
+        // inside a captured trajectory: every chain is a persistent-solver chain; the solve
+        // runs on the bound stream and logs its per-chain results on the device
+        if (c->n_small != c->nchains || launch_cg_wg(full, f, mixed, c->at<int>(c->off_small), c->n_small,
+                                                      c->small_vmax, tol, c->delta, max_iter, c->stream))
+            return fail(c, HMC_E_INVAL, "a captured trajectory needs every chain in the persistent solver");
+        if (c->log_count < kMaxLoggedSolves)
+            launch_log_solve(c->cg(), c->nchains, c->at<int>(c->off_log) + (size_t)2 * c->log_count * c->nchains,
+                             c->stream);
+        else
+            c->log_overflow = true;
+        c->log_count++;
+        return HMC_OK;
+    }
     // small chains: one persistent workgroup each, on the side stream
     if (c->n_small > 0) {
         HIP_TRY(c, hipEventRecord(c->fork_ev, c->stream));
@@ -542,6 +578,7 @@ struct MD {
 int note_solve(MD &md, int rc) {
     hmc_ctx *c = md.c;
     md.solves++;
+    if (c->deferring) return rc;  // iterations and convergence are read from the device log
     for (int k = 0; k < c->nchains; ++k) {
         md.iters[k] += c->cg_host[k].iters;
         if (!c->cg_host[k].converged) md.chain_status[k] = HMC_E_NOCONV;
@@ -803,6 +840,7 @@ int set_block(hmc_ctx *c, int block) {
     int rc = sync(c);
     if (rc) return rc;
     c->block = block;
+    c->graph_epoch++;
     build_tables(c);
     HIP_TRY(c, hipMemcpyAsync(c->at<ChainInfo>(c->off_chains), c->chains.data(),
                               sizeof(ChainInfo) * c->nchains, hipMemcpyHostToDevice, c->stream));
@@ -841,6 +879,7 @@ int hmc_bind(hmc_ctx *c, void *ws, size_t bytes, void *stream) {
     if (bytes < c->ws_bytes)
         return fail(c, HMC_E_NOMEM, "workspace has %zu bytes, needs %zu", bytes, c->ws_bytes);
     c->ws = (char *)ws;
+    c->graph_epoch++;
     c->stream = (hipStream_t)stream;
     if (!c->pinned) {
         c->pinned_bytes = align_up(sizeof(CGState) * c->nchains + sizeof(MetroOut) * c->nchains +
@@ -966,6 +1005,7 @@ int hmc_set_solver(hmc_ctx *c, double tol, int max_iter, double reliable_delta) 
     if (!(tol >= 0) || !isfinite(tol) || max_iter < 1 || !(reliable_delta > 0 && reliable_delta < 1))
         return fail(c, HMC_E_INVAL, "bad solver settings");
     c->tol = tol;
+    c->graph_epoch++;
     c->max_iter = max_iter;
     c->delta = reliable_delta;
     return HMC_OK;
@@ -974,12 +1014,14 @@ int hmc_set_solver(hmc_ctx *c, double tol, int max_iter, double reliable_delta) 
 int hmc_set_quenched(hmc_ctx *c, int quenched) {
     if (!c) return HMC_E_INVAL;
     c->quenched = quenched != 0;
+    c->graph_epoch++;
     return HMC_OK;
 }
 
 int hmc_set_persistent_limit(hmc_ctx *c, int vmax) {
     if (!c || vmax < 0) return HMC_E_INVAL;
     c->persist_vmax = vmax;
+    c->graph_epoch++;
     return HMC_OK;
 }
 
@@ -1038,6 +1080,7 @@ int hmc_autotune(hmc_ctx *c, int prec, double tol, hmc_tune_info *out) {
     if (rc) return rc;
     c->persist_vmax = best_persist;
     c->part_vmax = -1;
+    c->graph_epoch++;
     forget_all(c);
     if (out) {
         out->block = best_block;
@@ -1054,6 +1097,7 @@ int hmc_autotune(hmc_ctx *c, int prec, double tol, hmc_tune_info *out) {
 int hmc_set_check_interval(hmc_ctx *c, int every) {
     if (!c || every < 1) return HMC_E_INVAL;
     c->check_every = every;
+    c->graph_epoch++;
     return HMC_OK;
 }
 
@@ -1252,10 +1296,13 @@ int hmc_set_fg_mode(hmc_ctx *c, int mode) {
     if (!c) return HMC_E_INVAL;
     if (mode != HMC_FG_SHIFT && mode != HMC_FG_EXACT) return fail(c, HMC_E_INVAL, "bad force-gradient mode");
     c->fg_mode = mode;
+    c->graph_epoch++;
     return HMC_OK;
 }
 
-static int finish_traj(hmc_ctx *c, MD &md, bool metropolis, hmc_traj_info *info) {
+// The device part of the end of a trajectory: S_F at the final links, the energies, the
+// per-chain status, the Metropolis test (and the restore of rejected chains), the plaquettes.
+static int finish_traj_device(hmc_ctx *c, MD &md, bool metropolis) {
     const Geo g = c->geo();
     const int C = c->nchains;
     const bool fermions = !c->quenched;
@@ -1273,20 +1320,41 @@ static int finish_traj(hmc_ctx *c, MD &md, bool metropolis, hmc_traj_info *info)
     double *gs = c->sums() + 9 * C;     // [3][C]
     launch_energy(g, c->link(LQ), c->link(LQ0), c->link(LP), c->link(LP0),
                   fermions ? c->spin(SPHI) : nullptr, c->spin(SXI), c->partials(), es, c->stream);
-    HIP_TRY(c, hipMemcpyAsync(c->at<int>(c->off_status), md.chain_status.data(), sizeof(int) * C,
-                              hipMemcpyHostToDevice, c->stream));
+    if (c->deferring)
+        launch_chain_status(c->at<int>(c->off_log), std::min(c->log_count, kMaxLoggedSolves), C,
+                            c->at<int>(c->off_status), c->stream);
+    else
+        HIP_TRY(c, hipMemcpyAsync(c->at<int>(c->off_status), md.chain_status.data(), sizeof(int) * C,
+                                  hipMemcpyHostToDevice, c->stream));
     MetroOut *mo = c->at<MetroOut>(c->off_metro);
-    launch_metropolis(g, c->seed, c->traj, es, rs, c->at<int>(c->off_status), mo, fermions, c->stream);
+    launch_metropolis(g, c->seed, c->at<uint32_t>(c->off_trajc), es, rs, c->at<int>(c->off_status), mo,
+                      fermions, c->stream);
     if (metropolis) {
         launch_restore(g, mo, c->link(LQ0), c->link(LQ), c->stream);
         c->q_version++;
     }
     launch_gauge_energy(g, c->link(LQ), nullptr, c->spin(SXI), c->partials(), gs, c->stream);
+    return HMC_OK;
+}
+
+// The host part: reads the Metropolis results and plaquettes and fills info.  logged > 0:
+// the per-chain iterations come from the device log of that many solves.
+static int finish_traj_host(hmc_ctx *c, MD &md, bool metropolis, int logged, hmc_traj_info *info) {
+    const int C = c->nchains;
+    MetroOut *mo = c->at<MetroOut>(c->off_metro);
+    double *gs = c->sums() + 9 * C;
     std::vector<MetroOut> mh(C);
     std::vector<double> gh(3 * C);
     int rc = to_host(c, mh.data(), mo, sizeof(MetroOut) * C);
     if (rc) return rc;
     if ((rc = to_host(c, gh.data(), gs, sizeof(double) * 3 * C))) return rc;
+    if (logged > 0) {
+        std::vector<int> log((size_t)2 * logged * C);
+        HIP_TRY(c, hipMemcpy(log.data(), c->at<int>(c->off_log), sizeof(int) * log.size(),
+                             hipMemcpyDeviceToHost));
+        for (int k = 0; k < logged; ++k)
+            for (int ch = 0; ch < C; ++ch) md.iters[ch] += log[((size_t)k * C + ch) * 2];
+    }
     int status = HMC_OK;
     for (int k = 0; k < C; ++k) {
         if (info) {
@@ -1310,12 +1378,18 @@ static int finish_traj(hmc_ctx *c, MD &md, bool metropolis, hmc_traj_info *info)
     return status;
 }
 
+static int finish_traj(hmc_ctx *c, MD &md, bool metropolis, hmc_traj_info *info) {
+    int rc = finish_traj_device(c, md, metropolis);
+    if (rc) return rc;
+    return finish_traj_host(c, md, metropolis, 0, info);
+}
+
 static void refresh(hmc_ctx *c) {
     const Geo g = c->geo();
     const bool fermions = !c->quenched;
     double *rs = c->sums() + 7 * c->nchains;
-    launch_refresh(g, c->seed, c->traj, c->link(LP), c->spin(SZETA), fermions, c->partials(), rs,
-                   c->stream);
+    launch_refresh(g, c->seed, c->at<uint32_t>(c->off_trajc), c->link(LP), c->spin(SZETA), fermions,
+                   c->partials(), rs, c->stream);
     if (fermions) {
         ensure_links(c, c->link(LQ), false, c->q_version);
         launch_dslash64(g, c->U64(), c->spin(SZETA), c->spin(SPHI), true, c->stream);
@@ -1325,9 +1399,125 @@ static void refresh(hmc_ctx *c) {
 int hmc_refresh(hmc_ctx *c) {
     CHECK_BOUND(c);
     forget_all(c);
+    launch_set_u32(c->at<uint32_t>(c->off_trajc), c->traj, c->stream);
     refresh(c);
     HIP_TRY(c, hipGetLastError());
     return HMC_OK;
+}
+
+// One trajectory's device work: refresh (counter from the device), q0/p0 copies, the
+// molecular dynamics and the device part of the Metropolis step.
+static int trajectory_body(hmc_ctx *c, MD &md, int scheme, double tau, int n_outer, int n_inner) {
+    refresh(c);
+    launch_copy(c->link(LQ), c->link(LQ0), sizeof(double) * 2 * c->Vtot, c->stream);
+    launch_copy(c->link(LP), c->link(LP0), sizeof(double) * 2 * c->Vtot, c->stream);
+    int rc = run_md(md, scheme, tau, n_outer, n_inner);
+    if (rc && rc != HMC_E_NOCONV) return rc;
+    return finish_traj_device(c, md, true);
+}
+
+// Captures the trajectory body as one HIP graph.  Needs every chain in the persistent solver
+// (its solves then have no host-side loop); solves log their results on the device.
+static int graph_capture(hmc_ctx *c, GraphEntry &e) {
+    const bool mixed = e.prec == HMC_PREC_MIXED;
+    int rc = build_partition(c, persistent_limit(c, mixed));
+    if (rc) return rc;
+    if (c->n_small != c->nchains)
+        return fail(c, HMC_E_INVAL, "a captured trajectory needs every chain within the persistent "
+                                    "solver's limit (%d sites)", persistent_limit(c, mixed));
+    if (prepare_cg_wg(c->small_vmax, mixed))
+        return fail(c, HMC_E_INVAL, "the persistent solver's LDS request was refused");
+    MD md;
+    init_md(md, c, e.prec);
+    c->deferring = true;
+    c->log_count = 0;
+    c->log_overflow = false;
+    // The capture is recorded on the library's own stream (the bound stream may be the
+    // default stream, which cannot be captured); nothing runs until the graph is launched on
+    // the bound stream.
+    hipStream_t bound = c->stream;
+    c->stream = c->side;
+    hipError_t eb = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) {
+        c->stream = bound;
+        c->deferring = false;
+        (void)hipGetLastError();
+        return fail(c, HMC_E_HIP, "graph capture could not start: %s", hipGetErrorString(eb));
+    }
+    rc = trajectory_body(c, md, e.scheme, e.tau, e.n_outer, e.n_inner);
+    c->deferring = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->stream, &graph);
+    c->stream = bound;
+    forget_all(c);  // nothing ran: the host's bookkeeping of links and solutions is void
+    if (rc || ec != hipSuccess || c->log_overflow) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        if (rc) return rc;
+        if (c->log_overflow) return fail(c, HMC_E_INVAL, "more than %d solves in one trajectory", kMaxLoggedSolves);
+        return fail(c, HMC_E_HIP, "graph capture failed: %s", hipGetErrorString(ec));
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return fail(c, HMC_E_HIP, "graph instantiation failed");
+    }
+    e.graph = graph;
+    e.exec = exec;
+    e.solves = md.solves;
+    e.force_evals = md.force_evals;
+    e.hvp_solves = md.hvp_solves;
+    e.logged = c->log_count;
+    e.epoch = c->graph_epoch;
+    return HMC_OK;
+}
+
+static void drop_graph(GraphEntry &e) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    e.exec = nullptr;
+    e.graph = nullptr;
+}
+
+// A trajectory replayed from its captured graph (captured on first use of this schedule and
+// these settings).  Same device work, in the same order, as the eager trajectory.
+static int graph_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, int prec,
+                            hmc_traj_info *info) {
+    GraphEntry *e = nullptr;
+    for (GraphEntry &g : c->graphs)
+        if (g.epoch == c->graph_epoch && g.scheme == scheme && g.tau == tau && g.n_outer == n_outer &&
+            g.n_inner == n_inner && g.prec == prec && g.fg_mode == c->fg_mode)
+            e = &g;
+    if (!e) {
+        // settings changed since older graphs were captured: drop those
+        for (GraphEntry &g : c->graphs)
+            if (g.epoch != c->graph_epoch) drop_graph(g);
+        c->graphs.erase(std::remove_if(c->graphs.begin(), c->graphs.end(),
+                                       [](const GraphEntry &g) { return g.exec == nullptr; }),
+                        c->graphs.end());
+        GraphEntry ne;
+        ne.scheme = scheme; ne.tau = tau; ne.n_outer = n_outer; ne.n_inner = n_inner; ne.prec = prec;
+        ne.fg_mode = c->fg_mode;
+        int rc = graph_capture(c, ne);
+        if (rc) return rc;
+        c->graphs.push_back(ne);
+        e = &c->graphs.back();
+    }
+    launch_set_u32(c->at<uint32_t>(c->off_trajc), c->traj, c->stream);
+    HIP_TRY(c, hipGraphLaunch(e->exec, c->stream));
+    MD md;
+    md.c = c;
+    md.prec = prec;
+    md.chain_status.assign(c->nchains, HMC_OK);
+    md.iters.assign(c->nchains, 0);
+    md.solves = e->solves;
+    md.force_evals = e->force_evals;
+    md.hvp_solves = e->hvp_solves;
+    int rc = finish_traj_host(c, md, true, std::min(e->logged, kMaxLoggedSolves), info);
+    forget_all(c);
+    c->traj++;
+    return rc;
 }
 
 int hmc_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, int prec,
@@ -1335,16 +1525,21 @@ int hmc_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner,
     CHECK_BOUND(c);
     int rc = check_md_args(c, scheme, tau, n_outer, n_inner, prec);
     if (rc) return rc;
+    if (c->graph_on) return graph_trajectory(c, scheme, tau, n_outer, n_inner, prec, info);
     MD md;
     init_md(md, c, prec);
-    refresh(c);
-    launch_copy(c->link(LQ), c->link(LQ0), sizeof(double) * 2 * c->Vtot, c->stream);
-    launch_copy(c->link(LP), c->link(LP0), sizeof(double) * 2 * c->Vtot, c->stream);
-    rc = run_md(md, scheme, tau, n_outer, n_inner);
-    if (rc && rc != HMC_E_NOCONV) return rc;
-    rc = finish_traj(c, md, true, info);
+    launch_set_u32(c->at<uint32_t>(c->off_trajc), c->traj, c->stream);
+    rc = trajectory_body(c, md, scheme, tau, n_outer, n_inner);
+    if (rc) return rc;
+    rc = finish_traj_host(c, md, true, 0, info);
     c->traj++;
     return rc;
+}
+
+int hmc_set_graph(hmc_ctx *c, int on) {
+    if (!c) return HMC_E_INVAL;
+    c->graph_on = on != 0;
+    return HMC_OK;
 }
 
 int hmc_integrate(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, int prec,
@@ -1354,6 +1549,7 @@ int hmc_integrate(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, 
     if (rc) return rc;
     MD md;
     init_md(md, c, prec);
+    launch_set_u32(c->at<uint32_t>(c->off_trajc), c->traj, c->stream);
     // energies before: refresh sums from the current p; zeta^dagger zeta is not known, so the
     // initial S_F is solved for (stored in the refresh slot)
     const Geo g = c->geo();
@@ -1421,6 +1617,7 @@ int hmc_get_kernel_stats(hmc_ctx *c, int which, hmc_kernel_stat *out) {
 
 int hmc_destroy(hmc_ctx *c) {
     if (!c) return HMC_E_INVAL;
+    for (GraphEntry &g : c->graphs) drop_graph(g);
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
     if (c->timer.sums_host) (void)hipHostFree(c->timer.sums_host);
     if (c->side) (void)hipStreamDestroy(c->side);

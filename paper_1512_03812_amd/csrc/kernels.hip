@@ -839,9 +839,9 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
     }
 }
 
-template <bool MIXED, int SPT>
-static int launch_wg_inst(const Geo &g, const CGFields &f, const int *chains, int n, int block,
-                          double tol, double delta, int max_iter, size_t lds, hipStream_t s) {
+// Dynamic LDS above 64 KiB must be opted in per kernel; the grant is remembered per
+// instantiation.  Returns -1 (error state cleared) if the device refuses.
+template <bool MIXED, int SPT> static int grant_wg_lds(size_t lds) {
     static size_t granted = 64 * 1024;  // dynamic LDS available without opting in
     if (lds > granted) {
         if (hipFuncSetAttribute((const void *)k_cg_wg<MIXED, SPT>,
@@ -851,9 +851,24 @@ static int launch_wg_inst(const Geo &g, const CGFields &f, const int *chains, in
         }
         granted = lds;
     }
+    return 0;
+}
+
+template <bool MIXED, int SPT>
+static int launch_wg_inst(const Geo &g, const CGFields &f, const int *chains, int n, int block,
+                          double tol, double delta, int max_iter, size_t lds, hipStream_t s) {
+    if (grant_wg_lds<MIXED, SPT>(lds)) return -1;
     hipLaunchKernelGGL((k_cg_wg<MIXED, SPT>), dim3(n), dim3(block), lds, s, g, f, chains, tol * tol,
                        delta * delta, max_iter);
     return 0;
+}
+
+int prepare_cg_wg(int vmax, bool mixed) {
+    const size_t lds = cg_wg_lds_bytes(vmax, mixed);
+    const int spt = vmax > 1024 ? 2 : 1;
+    if (vmax > 2048) return -1;
+    if (mixed) return spt == 1 ? grant_wg_lds<true, 1>(lds) : grant_wg_lds<true, 2>(lds);
+    return spt == 1 ? grant_wg_lds<false, 1>(lds) : grant_wg_lds<false, 2>(lds);
 }
 
 size_t cg_wg_lds_bytes(int vmax, bool mixed) {
@@ -1264,9 +1279,11 @@ void launch_rng_links(const Geo &g, uint64_t seed, double *q, hipStream_t s) {
                        (uint32_t)(seed >> 32), q);
 }
 
-__global__ void k_refresh(Geo g, uint32_t k0, uint32_t k1, uint32_t traj, double *__restrict__ p,
-                          double2 *__restrict__ zeta, int fermions, double *partials) {
+__global__ void k_refresh(Geo g, uint32_t k0, uint32_t k1, const uint32_t *__restrict__ traj_dev,
+                          double *__restrict__ p, double2 *__restrict__ zeta, int fermions,
+                          double *partials) {
 #pragma clang fp contract(off)
+    const uint32_t traj = *traj_dev;
     double v[2] = {0.0, 0.0};
     SITES_BEGIN
     const Site s = decode_site(ci, local);
@@ -1291,7 +1308,7 @@ __global__ void k_refresh(Geo g, uint32_t k0, uint32_t k1, uint32_t traj, double
     write_partials<2>(v, partials, g.nlog, w.logical);
 }
 
-void launch_refresh(const Geo &g, uint64_t seed, uint32_t traj, double *p, double2 *zeta,
+void launch_refresh(const Geo &g, uint64_t seed, const uint32_t *traj, double *p, double2 *zeta,
                     bool fermions, double *partials, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_refresh, dim3(g.nblocks), dim3(g.block), 0, s, g, (uint32_t)seed,
                        (uint32_t)(seed >> 32), traj, p, zeta, fermions ? 1 : 0, partials);
@@ -1361,11 +1378,12 @@ void launch_gauge_energy(const Geo &g, const double *q, const double2 *phi, cons
 
 // Delta H = sum 1/2 (p'^2 - p^2) + beta sum (cos theta - cos theta') + (S_F' - S_F), then
 // accept iff Delta H <= 0 or u < exp(-Delta H) (Sec. 2.1).
-__global__ void k_metropolis(Geo g, uint32_t k0, uint32_t k1, uint32_t traj,
+__global__ void k_metropolis(Geo g, uint32_t k0, uint32_t k1, const uint32_t *__restrict__ traj_dev,
                              const double *__restrict__ es, const double *__restrict__ rs,
                              const int *__restrict__ cstat, MetroOut *out, int fermions) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.nchains) return;
+    const uint32_t traj = *traj_dev;
     const ChainInfo ci = g.chains[c];
     const int C = g.nchains;
     const double sf1 = fermions ? es[5 * C + c] : 0.0, sf0 = fermions ? rs[C + c] : 0.0;
@@ -1383,7 +1401,7 @@ __global__ void k_metropolis(Geo g, uint32_t k0, uint32_t k1, uint32_t traj,
     out[c] = m;
 }
 
-void launch_metropolis(const Geo &g, uint64_t seed, uint32_t traj, const double *esums,
+void launch_metropolis(const Geo &g, uint64_t seed, const uint32_t *traj, const double *esums,
                        const double *rsums, const int *chain_status, MetroOut *out, bool fermions,
                        hipStream_t s) {
     const int block = 64;
@@ -1400,6 +1418,44 @@ __global__ void k_restore(Geo g, const MetroOut *__restrict__ m, const double *_
     q[fl] = q0[fl];
     q[(size_t)Vtot + fl] = q0[(size_t)Vtot + fl];
     SITES_END
+}
+
+// ================================================================ device-side bookkeeping
+__global__ void k_set_u32(uint32_t *p, uint32_t v) { *p = v; }
+
+void launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, p, v);
+}
+
+// log[2c] = iterations, log[2c + 1] = converged of chain c's finished solve
+__global__ void k_log_solve(const CGState *__restrict__ st, int nchains, int *__restrict__ log) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nchains) return;
+    log[2 * c] = st[c].iters;
+    log[2 * c + 1] = st[c].converged;
+}
+
+void launch_log_solve(const CGState *st, int nchains, int *log, hipStream_t s) {
+    const int block = 256;
+    hipLaunchKernelGGL(k_log_solve, dim3((nchains + block - 1) / block), dim3(block), 0, s, st,
+                       nchains, log);
+}
+
+// status[c] = -3 (the library's "did not converge") if any of the n logged solves of chain c
+// did not converge, else 0
+__global__ void k_chain_status(const int *__restrict__ log, int n, int nchains, int *__restrict__ status) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nchains) return;
+    int st = 0;
+    for (int k = 0; k < n; ++k)
+        if (!log[((size_t)k * nchains + c) * 2 + 1]) st = -3;
+    status[c] = st;
+}
+
+void launch_chain_status(const int *log, int n, int nchains, int *status, hipStream_t s) {
+    const int block = 256;
+    hipLaunchKernelGGL(k_chain_status, dim3((nchains + block - 1) / block), dim3(block), 0, s, log, n,
+                       nchains, status);
 }
 
 void launch_restore(const Geo &g, const MetroOut *m, const double *q0, double *q, hipStream_t s) {

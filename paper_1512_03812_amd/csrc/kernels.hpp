@@ -119,6 +119,9 @@ void launch_compact(const Geo &full, const CGState *st, int max_iter, BlockWork 
 size_t cg_wg_lds_bytes(int vmax, bool mixed);
 int launch_cg_wg(const Geo &g, const CGFields &f, bool mixed, const int *chains, int n, int vmax,
                  double tol, double delta, int max_iter, hipStream_t s);
+// Grants the persistent solver's dynamic LDS for chains of up to vmax sites ahead of a
+// launch (so that no attribute call happens while a stream is captured).  -1 if refused.
+int prepare_cg_wg(int vmax, bool mixed);
 // Number of converged chains in one state parity -> *out.
 void launch_count_converged(const CGState *st_par, int n, int *out, hipStream_t s);
 
@@ -157,7 +160,7 @@ void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 void launch_rng_links(const Geo &g, uint64_t seed, double *q, hipStream_t s);
 // momenta (stream 1) and zeta (stream 2) for trajectory traj; per chain
 // out[0][c] = 1/2 sum p^2, out[1][c] = zeta^dagger zeta.
-void launch_refresh(const Geo &g, uint64_t seed, uint32_t traj, double *p, double2 *zeta,
+void launch_refresh(const Geo &g, uint64_t seed, const uint32_t *traj, double *p, double2 *zeta,
                     bool fermions, double *partials, double *out, hipStream_t s);
 
 // ---------------------------------------------------------------- energies and Metropolis
@@ -176,9 +179,16 @@ struct MetroOut {
     double dH, H0, H1, u;
     int accepted, status, pad[2];
 };
-void launch_metropolis(const Geo &g, uint64_t seed, uint32_t traj, const double *esums,
+void launch_metropolis(const Geo &g, uint64_t seed, const uint32_t *traj, const double *esums,
                        const double *rsums, const int *chain_status, MetroOut *out, bool fermions,
                        hipStream_t s);
+// Device-side bookkeeping (trajectories that run as one captured graph read their counter
+// and write their solver results on the device).
+void launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s);
+// iterations and convergence flag of every chain's finished solve (state st) -> log[2 c + k]
+void launch_log_solve(const CGState *st, int nchains, int *log, hipStream_t s);
+// status[c] = -3 if any of the n logged solves (log[k][c][2]) of chain c did not converge
+void launch_chain_status(const int *log, int n, int nchains, int *status, hipStream_t s);
 // q = q0 on the chains whose Metropolis test failed.
 void launch_restore(const Geo &g, const MetroOut *m, const double *q0, double *q, hipStream_t s);
 

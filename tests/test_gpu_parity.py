@@ -591,6 +591,46 @@ def test_autograd_second_derivative_is_the_hessian_vector_product():
     assert rel(b.links_from_native(hv)[0], oracle_hessian_vector(q, phi, v, beta, m0, "total")) < 1e-8
 
 
+# ------------------------------------------------------------------ captured trajectories
+@pytest.mark.parametrize("scheme,n_outer,n_inner,prec,exact", [
+    ("adapted_nested_fg", 4, 2, "fp64", False), ("force_gradient", 3, 1, "mixed", True),
+    ("omelyan", 5, 1, "fp64", False)])
+def test_graph_trajectories_match_eager_bitwise(scheme, n_outer, n_inner, prec, exact):
+    """Replays of a captured trajectory, with eager work and synchronisations between them and a
+    recapture after a setting changes, give the eager path's results bit for bit."""
+    shapes = [(8, 8, 2.0, 0.1), (16, 16, 1.5, 0.05), (6, 10, 3.0, 0.2), (32, 32, 2.0, 0.1)]
+    runs = []
+    for graph in (False, True):
+        b = Batch(shapes, seed=12)
+        b.lat.hot_start()
+        b.lat.set_solver(tol=1e-12)
+        b.lat.set_fg_mode("exact" if exact else "shift")
+        b.lat.set_graph(graph)
+        res = []
+        for t in range(4):
+            if t == 2:
+                b.lat.set_solver(tol=1e-12)   # discards captured graphs: the next one is recaptured
+            r = b.lat.trajectory(scheme, 1.0, n_outer, n_inner, prec=prec)
+            res.append((list(r.dH), list(r.accepted), list(r.n_cg_iters), r.n_dinv, r.n_solves))
+            b.lat.actions()
+            torch.cuda.synchronize()
+        runs.append((b.lat.q.cpu().numpy().copy(), res))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1] == runs[1][1]
+
+
+def test_graph_mode_needs_every_chain_in_the_persistent_solver():
+    m = hmc()
+    b = Batch([(8, 8), (64, 64)], seed=3)
+    b.lat.hot_start()
+    b.lat.set_graph(True)
+    with pytest.raises(m.HMCError):
+        b.lat.trajectory("adapted_nested_fg", 1.0, 2, 2)
+    b.lat.set_graph(False)
+    r = b.lat.trajectory("adapted_nested_fg", 1.0, 2, 2)
+    assert all(s == 0 for s in r.status)
+
+
 # ------------------------------------------------------------------ mixed precision
 @pytest.mark.parametrize("persistent", SOLVERS)
 @pytest.mark.parametrize("Lx,m0", [(16, 0.1), (32, 0.05), (64, 0.05)])
