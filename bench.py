@@ -13,8 +13,9 @@ workgroup size is autotuned; the persistent small-chain solver is off unless ask
 (--persistent-limit -1 keeps the tuned limit), so that every CG kernel in the timed region
 runs alone and its event-timed bandwidth is its own.
 Beside it: the dominant kernel's roofline figure (event-timed inside the timed region),
-the plain FP64 single-chain 32 x 32 path on the same GPU, and the CPU oracle timed on a
-bounded sample of the same workload.
+the plain FP64 single-chain 32 x 32 path on the same GPU, mixed against FP64 precision on
+a 256 x 256 lattice (beta 4, m0 0.05), and the CPU oracle timed on a bounded sample of the
+same workload.
 """
 import argparse
 import hashlib
@@ -135,6 +136,61 @@ def run_single_fp64(args):
             "graph_value": n / dtg, "graph_ms_per_traj": 1e3 * dtg / n,
             "acceptance": sum(acc) / len(acc), "dtype": "f64",
             "config": "32x32, beta 2.0, m0 0.1, adapted nested FG tau 1 n_outer 8 n_inner 4, CG tol 1e-12"}
+
+
+def run_precision(args, sizes, n_traj, n_therm):
+    """Mixed precision against FP64 on single lattices: beta 4, m0 0.05, adapted nested FG
+    tau 1, 8 x 4.  After n_therm untimed mixed trajectories from the hot start, each
+    trajectory is run three times from the same links and trajectory counter (so with the
+    same momenta and pseudofermion): FP64 CG to 1e-12 (the Delta H reference), FP64 to
+    1e-10 and mixed CG to a true residual of 1e-10.  The chain continues from the mixed
+    run.  Throughputs are timed per precision over the n_traj trajectories."""
+    import numpy as np
+    import torch
+    import paper_1512_03812_amd as hmc
+    out = []
+    for L in sizes:
+        lat = hmc.Lattice(L, 4.0, 0.05, seed=args.seed)
+        lat.hot_start()
+        lat.set_solver(tol=1e-10)
+        if not args.no_tune:
+            lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+            lat.autotune("mixed", 1e-10)
+        for _ in range(n_therm):
+            lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+        runs = (("fp64_1e-12", "fp64", 1e-12), ("fp64", "fp64", 1e-10), ("mixed", "mixed", 1e-10))
+        secs = {k: 0.0 for k, _, _ in runs}
+        dH = {k: [] for k, _, _ in runs}
+        acc = {k: [] for k, _, _ in runs}
+        for _ in range(n_traj):
+            q0 = lat.q.clone()
+            ctr = lat.trajectory_counter
+            for i, (key, prec, tol) in enumerate(runs):
+                if i:
+                    lat.q.copy_(q0)
+                    lat.mark_links_changed()
+                    lat.trajectory_counter = ctr
+                lat.set_solver(tol=tol)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec=prec)
+                torch.cuda.synchronize()
+                secs[key] += time.perf_counter() - t0
+                dH[key].append(r.dH[0])
+                acc[key].append(r.accepted[0])
+        ref = np.array(dH["fp64_1e-12"])
+        print(f"precision L={L}: done", file=sys.stderr, flush=True)
+        out.append({
+            "L": L, "trajectories": n_traj, "thermalisation": n_therm,
+            "traj_per_s": {k: round(n_traj / secs[k], 3) for k in secs},
+            "mixed_over_fp64": round(secs["fp64"] / secs["mixed"], 3),
+            "max_abs_dH_error": {k: float(np.max(np.abs(np.array(dH[k]) - ref)))
+                                 for k in ("fp64", "mixed")},
+            "accept_decisions_agree": {k: acc[k] == acc["fp64_1e-12"] for k in ("fp64", "mixed")},
+            "acceptance": round(sum(acc["mixed"]) / n_traj, 3),
+            "mean_abs_dH": round(float(np.mean(np.abs(ref))), 5),
+        })
+    return out
 
 
 def cpu_baseline(args):
@@ -464,6 +520,11 @@ def main():
     ap.add_argument("--study-therm", type=int, default=200)
     ap.add_argument("--study-n", type=int, nargs="+", default=[12, 16, 20, 24, 32, 48, 64, 96, 128, 192])
     ap.add_argument("--study-schemes", nargs="+", default=None)
+    ap.add_argument("--precision-study", action="store_true",
+                    help="mixed precision against FP64 on single lattices (beta 4, m0 0.05)")
+    ap.add_argument("--precision-sizes", type=int, nargs="+", default=[128, 256])
+    ap.add_argument("--precision-trajs", type=int, default=50)
+    ap.add_argument("--precision-therm", type=int, default=30)
     ap.add_argument("--no-timing", action="store_true",
                     help="do not bracket the CG kernels with events (roofline figure omitted)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -485,6 +546,11 @@ def main():
         return
     if args.acceptance_table:
         run_acceptance_table(args)
+        return
+    if args.precision_study:
+        print(json.dumps({"precision": run_precision(args, args.precision_sizes,
+                                                     args.precision_trajs,
+                                                     args.precision_therm)}), flush=True)
         return
 
     if args.copy_calibration:
@@ -554,6 +620,7 @@ def main():
     }
     if not args.no_single:
         out["fp64_single_chain"] = run_single_fp64(args)
+        out["precision"] = run_precision(args, [256], 3, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)

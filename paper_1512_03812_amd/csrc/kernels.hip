@@ -56,17 +56,18 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *partials
     }
 }
 
-// The chain's total of one partial row, identical in every workgroup of the chain: re-added
-// here for chains of at most kMaxChainBlocks workgroups, else read from fin (written by
-// k_finalize_large after the producer).
+// The chain's total of one partial row, identical in every wavefront of the chain: each
+// wavefront re-adds the partials of chains of at most kMaxChainBlocks workgroups itself (lane
+// l takes partials l, l + 64, ... in order, then a fixed shuffle tree), with no LDS and no
+// barrier, so the site loads issued before it stay in flight; larger chains read fin
+// (written by k_finalize_large after the producer).
 __device__ __forceinline__ double chain_total(const double *__restrict__ row,
                                               const double *__restrict__ fin, const ChainInfo &ci,
                                               int chain) {
     if (ci.nblocks > kMaxChainBlocks) return fin[chain];
-    double a[1] = {0.0};
-    for (int j = threadIdx.x; j < ci.nblocks; j += blockDim.x) a[0] += row[ci.block0 + j];
-    block_sum_all<1>(a);
-    return a[0];
+    double a = 0.0;
+    for (int j = (int)(threadIdx.x & 63); j < ci.nblocks; j += 64) a += row[ci.block0 + j];
+    return __shfl(wave_sum(a), 0, 64);
 }
 
 __global__ void k_finalize_large(Geo g, const double *__restrict__ row, double *fin) {
@@ -121,14 +122,27 @@ __device__ __forceinline__ Nbr neighbours(const ChainInfo &ci, const Site &s) {
 //   (1 + s sigma_1) v = (w, s w)     with w = v0 + s v1
 //   (1 + s sigma_2) v = (w, s i w)   with w = v0 - s i v1
 // D uses s = -1 on the forward hop and s = +1 on the backward hop; D^dagger the reverse.
+// The four links of the stencil at one site: U_x(n), U_t(n), U_x(n - x), U_t(n - t).
+template <typename C> struct SiteLinks { C xf, tf, xb, tb; };
+
+template <typename C>
+__device__ __forceinline__ SiteLinks<C> site_links(const C *__restrict__ U, const Nbr &nb, int flat,
+                                                   int Vtot) {
+    SiteLinks<C> l;
+    l.xf = U[flat];
+    l.tf = U[Vtot + flat];
+    l.xb = U[nb.xm];
+    l.tb = U[Vtot + nb.tm];
+    return l;
+}
+
 template <typename T, bool DAG, typename Load>
-__device__ __forceinline__ void dslash_site(const Nbr &nb, int flat, int Vtot,
-                                            const cplx_t<T> *__restrict__ U, cplx_t<T> own0,
-                                            cplx_t<T> own1, T mass, Load load, cplx_t<T> &o0,
-                                            cplx_t<T> &o1) {
+__device__ __forceinline__ void dslash_site_links(const Nbr &nb, const SiteLinks<cplx_t<T>> &lk,
+                                                  cplx_t<T> own0, cplx_t<T> own1, T mass, Load load,
+                                                  cplx_t<T> &o0, cplx_t<T> &o1) {
     using C = cplx_t<T>;
     constexpr T sf = DAG ? T(1) : T(-1);  // sign on the forward hop; backward is -sf
-    const C uxf = U[flat], utf = U[Vtot + flat], uxb = U[nb.xm], utb = U[Vtot + nb.tm];
+    const C uxf = lk.xf, utf = lk.tf, uxb = lk.xb, utb = lk.tb;
     C b0, b1;
     load(nb.xp, b0, b1);
     const C wxf = cmul(uxf, cadd(b0, cscale(b1, sf)));
@@ -142,6 +156,14 @@ __device__ __forceinline__ void dslash_site(const Nbr &nb, int flat, int Vtot,
     const C sum1 = cscale(cadd(csub(wxf, wxb), cmuli(csub(wtf, wtb))), sf);
     o0 = csub(cscale(own0, mass), cscale(sum0, T(0.5)));
     o1 = csub(cscale(own1, mass), cscale(sum1, T(0.5)));
+}
+
+template <typename T, bool DAG, typename Load>
+__device__ __forceinline__ void dslash_site(const Nbr &nb, int flat, int Vtot,
+                                            const cplx_t<T> *__restrict__ U, cplx_t<T> own0,
+                                            cplx_t<T> own1, T mass, Load load, cplx_t<T> &o0,
+                                            cplx_t<T> &o1) {
+    dslash_site_links<T, DAG>(nb, site_links(U, nb, flat, Vtot), own0, own1, mass, load, o0, o1);
 }
 
 __device__ __forceinline__ double norm2(double2 a) { return a.x * a.x + a.y * a.y; }
@@ -349,16 +371,44 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     const double p_phi2 = prev->phi2, p_rmax2 = prev->rmax2, delta2 = prev->delta2;
     // x update still owed by the previous slot (none after the initial or an update slot)
     const double pend = p_mode == kModeNormal ? prev->alpha : 0.0;
+    // The operands of a normal slot on the own site are loaded before the chain total, so
+    // their latency overlaps its partial loads (they go unused in the other modes).
+    const S *__restrict__ p_old = (const S *)p_old_v;
+    S *__restrict__ p_new = (S *)p_new_v;
+    const S *__restrict__ r;
+    S *__restrict__ t;
+    S *__restrict__ x;
+    const C *__restrict__ U;
+    if constexpr (MIXED) { r = f.r32; t = f.t32; x = f.x32; U = f.U32; }
+    else { r = f.r64; t = f.t64; x = f.x64; U = f.U64; }
+    const int half = (int)blockDim.x >> 1;
+    const int par = (int)threadIdx.x >= half ? 1 : 0;
+    const int i = w.start + (int)threadIdx.x - par * half;
+    const bool own = i < ci.Vh;
+    const bool first = p_mode == kModeInit;
+    Site s = {};
+    Nbr nb = {};
+    SiteLinks<C> lk = {};
+    C a0 = {}, a1 = {}, q0 = {}, q1 = {}, x0 = {}, x1 = {};
+    if (own) {
+        s = decode_site(ci, par * ci.Vh + i);
+        nb = neighbours(ci, s);
+        sp_load(r, Vtot, s.flat, a0, a1);
+        if (!first) {
+            sp_load(p_old, Vtot, s.flat, q0, q1);
+            sp_load(x, Vtot, s.flat, x0, x1);
+        }
+        lk = site_links(U, nb, s.flat, Vtot);
+    }
     const double rho = chain_total(f.p2, f.fin2, ci, w.chain);
     double n_rho = rho, n_rho_p = p_rho_p, n_target = p_target, n_phi2 = p_phi2, n_rmax2 = p_rmax2;
     double n_beta = 0.0;
     int n_iters = p_iters, n_nupd = p_nupd, n_conv = 0;
-    bool update = false, first = false;
-    if (p_mode == kModeInit) {
+    bool update = false;
+    if (first) {
         n_phi2 = rho; n_target = tol2 * rho; n_rmax2 = rho; n_rho_p = rho;
         n_iters = 0; n_nupd = 0;
         n_conv = rho <= n_target ? 1 : 0;
-        first = true;
     } else if (p_mode == kModeUpdate) {
         n_nupd = p_nupd + 1;
         n_rmax2 = rho;
@@ -384,8 +434,6 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
             row[1] = ci.V * (!MIXED ? kBytesFp64Step2 : update ? kBytesUpdateStep2 : kBytesFp32Step2);
         }
     }
-    const S *__restrict__ p_old = (const S *)p_old_v;
-    S *__restrict__ p_new = (S *)p_new_v;
     const R a_pend = (R)pend;
     if (n_conv || decide_only) {
         // the chain stops here: settle the owed x update on the own sites
@@ -429,39 +477,22 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
         SITES_END
         return;
     }
-    const S *__restrict__ r;
-    S *__restrict__ t;
-    S *__restrict__ x;
-    const C *__restrict__ U;
-    if constexpr (MIXED) { r = f.r32; t = f.t32; x = f.x32; U = f.U32; }
-    else { r = f.r64; t = f.t64; x = f.x64; U = f.U64; }
     const R beta = (R)n_beta;
     // Own site: x += pend p_old (deferred from the previous slot), p_new = r + beta p_old,
     // staged in LDS for the neighbours inside the workgroup; t = D p_new (one site per
     // thread: the tables use w.spt == 1).
     LdsSpinor<C> *lds = (LdsSpinor<C> *)smem_d;
-    const int half = (int)blockDim.x >> 1;
-    const int par = (int)threadIdx.x >= half ? 1 : 0;
-    const int i = w.start + (int)threadIdx.x - par * half;
-    const bool own = i < ci.Vh;
     auto direction = [&](int fl, C &b0, C &b1) {
         sp_load(r, Vtot, fl, b0, b1);
         if (!first) {
-            C q0, q1;
-            sp_load(p_old, Vtot, fl, q0, q1);
-            b0 = cmake<C>(b0.x + beta * q0.x, b0.y + beta * q0.y);
-            b1 = cmake<C>(b1.x + beta * q1.x, b1.y + beta * q1.y);
+            C c0, c1;
+            sp_load(p_old, Vtot, fl, c0, c1);
+            b0 = cmake<C>(b0.x + beta * c0.x, b0.y + beta * c0.y);
+            b1 = cmake<C>(b1.x + beta * c1.x, b1.y + beta * c1.y);
         }
     };
-    Site s;
-    C a0, a1;
     if (own) {
-        s = decode_site(ci, par * ci.Vh + i);
-        sp_load(r, Vtot, s.flat, a0, a1);
         if (!first) {
-            C q0, q1, x0, x1;
-            sp_load(p_old, Vtot, s.flat, q0, q1);
-            sp_load(x, Vtot, s.flat, x0, x1);
             x0.x += a_pend * q0.x; x0.y += a_pend * q0.y;
             x1.x += a_pend * q1.x; x1.y += a_pend * q1.y;
             sp_store(x, Vtot, s.flat, x0, x1);
@@ -475,14 +506,13 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     __syncthreads();
     double v[1] = {0.0};
     if (own) {
-        const Nbr nb = neighbours(ci, s);
         auto load = [&](int fl, C &b0, C &b1) {
             const int k = lds_slot(ci, w, half, fl);
             if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
             else direction(fl, b0, b1);
         };
         C o0, o1;
-        dslash_site<R, false>(nb, s.flat, Vtot, U, a0, a1, (R)(2.0 + ci.m0), load, o0, o1);
+        dslash_site_links<R, false>(nb, lk, a0, a1, (R)(2.0 + ci.m0), load, o0, o1);
         sp_store(t, Vtot, s.flat, o0, o1);
         v[0] = norm2(o0) + norm2(o1);
     }
@@ -531,41 +561,45 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
         write_partials<1>(v, f.p2, g.nlog, w.logical);
         return;
     }
-    const double pAp = chain_total(f.p1, f.fin1, ci, w.chain);
-    const double alpha_d = s_rho / pAp;
-    if (w.logical == ci.block0 && threadIdx.x == 0) st->alpha = alpha_d;  // owed to x (next slot)
-    const R alpha = (R)alpha_d;
     const S *__restrict__ t;
     S *__restrict__ r;
     const C *__restrict__ U;
     if constexpr (MIXED) { t = f.t32; r = f.r32; U = f.U32; }
     else { t = f.t64; r = f.r64; U = f.U64; }
-    // t of the own site staged in LDS for the neighbours inside the workgroup (one site per
-    // thread: the tables use w.spt == 1).
+    // The own site's t, r and links are loaded before the chain total, so their latency
+    // overlaps its partial loads.  t is staged in LDS for the neighbours inside the
+    // workgroup (one site per thread: the tables use w.spt == 1).
     LdsSpinor<C> *lds = (LdsSpinor<C> *)smem_d;
     const int half = (int)blockDim.x >> 1;
     const int par = (int)threadIdx.x >= half ? 1 : 0;
     const int i = w.start + (int)threadIdx.x - par * half;
     const bool own = i < ci.Vh;
-    Site s;
-    C t0, t1;
+    Site s = {};
+    Nbr nb = {};
+    SiteLinks<C> lk = {};
+    C t0 = {}, t1 = {}, r0 = {}, r1 = {};
     if (own) {
         s = decode_site(ci, par * ci.Vh + i);
+        nb = neighbours(ci, s);
         sp_load(t, Vtot, s.flat, t0, t1);
+        sp_load(r, Vtot, s.flat, r0, r1);
+        lk = site_links(U, nb, s.flat, Vtot);
         lds[threadIdx.x].a = t0;
         lds[threadIdx.x].b = t1;
     }
+    const double pAp = chain_total(f.p1, f.fin1, ci, w.chain);
+    const double alpha_d = s_rho / pAp;
+    if (w.logical == ci.block0 && threadIdx.x == 0) st->alpha = alpha_d;  // owed to x (next slot)
+    const R alpha = (R)alpha_d;
     __syncthreads();
     if (own) {
-        const Nbr nb = neighbours(ci, s);
         auto load = [&](int fl, C &b0, C &b1) {
             const int k = lds_slot(ci, w, half, fl);
             if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
             else sp_load(t, Vtot, fl, b0, b1);
         };
-        C a0, a1, r0, r1;
-        dslash_site<R, true>(nb, s.flat, Vtot, U, t0, t1, (R)(2.0 + ci.m0), load, a0, a1);
-        sp_load(r, Vtot, s.flat, r0, r1);
+        C a0, a1;
+        dslash_site_links<R, true>(nb, lk, t0, t1, (R)(2.0 + ci.m0), load, a0, a1);
         r0.x -= alpha * a0.x; r0.y -= alpha * a0.y;
         r1.x -= alpha * a1.x; r1.y -= alpha * a1.y;
         sp_store(r, Vtot, s.flat, r0, r1);

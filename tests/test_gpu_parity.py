@@ -659,6 +659,36 @@ def test_mixed_trajectory_matches_fp64_oracle(persistent):
         assert abs(r.dH[0] - ir["dH"]) < 1e-8
 
 
+def _precision_golden():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "precision_trajectories.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("L", [128, 256])
+def test_precision_workload_matches_oracle_trajectories(L):
+    """The precision workload (beta 4, m0 0.05, adapted nested FG tau 1, 8 x 4, hot start)
+    in mixed precision against stored FP64 oracle trajectories: the same accept decisions
+    and |Delta H error| <= 1e-8 with both solvers at 1e-12; at the workload's own true
+    residual of 1e-10 the decisions still agree and the error stays below 1e-6."""
+    g = _precision_golden()[str(L)]
+    for tol, bound in ((g["tol"], 1e-8), (1e-10, 1e-6)):
+        b = Batch([(L, L, g["beta"], g["m0"])], seed=g["seed"])
+        b.lat.hot_start()
+        b.lat.set_solver(tol=tol)
+        for t, ref in enumerate(g["trajectories"]):
+            print(f"L={L} tol={tol} trajectory {t}", flush=True)
+            r = b.lat.trajectory(g["scheme"], g["tau"], g["n_outer"], g["n_inner"], prec="mixed")
+            assert r.status[0] == 0
+            assert r.accepted[0] == ref["accepted"]
+            assert abs(r.dH[0] - ref["dH"]) <= bound, (t, r.dH[0], ref["dH"])
+            assert abs(r.H0[0] - ref["H0"]) <= 1e-11 * abs(ref["H0"])
+            assert abs(r.plaquette[0] - ref["plaquette"]) <= 1e-9
+            assert r.n_dinv == ref["n_dinv"]
+
+
 # ------------------------------------------------------------------ autograd form
 def test_autograd_action_gradient_matches_finite_differences_and_oracle():
     m = hmc()
