@@ -334,6 +334,14 @@ typedef struct {
 int hmc_set_timing(hmc_ctx *ctx, int on);
 int hmc_get_kernel_stats(hmc_ctx *ctx, int which, hmc_kernel_stat *out);
 
+/* Streaming copy dst = src of `bytes` bytes on the bound stream (device pointers, both
+ * 16-byte aligned, bytes a multiple of 16; src and dst must not overlap): one 16-byte
+ * nontemporal load and store per thread.  Not part of the method: it is the measured
+ * bandwidth ceiling placed beside the roofline figures, and the kernel whose HBM byte
+ * counters calibrate the counter readings of the others.  Returns HMC_E_INVAL for
+ * misaligned or unbound arguments. */
+int hmc_stream_copy(hmc_ctx *ctx, const void *src, void *dst, size_t bytes);
+
 /* ---------------------------------------------------------------- misc */
 
 const char *hmc_last_error(const hmc_ctx *ctx);

@@ -280,6 +280,16 @@ class Lattice:
         self._check(self._lib.hmc_set_trajectory_counter(self._ctx, int(t)))
 
     # ---------------------------------------------------------------- operators (Sec. 3)
+    def stream_copy(self, src: torch.Tensor, dst: torch.Tensor):
+        """dst = src by the library's streaming copy kernel (a bandwidth reference)."""
+        if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+            raise ValueError("stream_copy needs contiguous device tensors")
+        n = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() < n:
+            raise ValueError("dst is smaller than src")
+        self._check(self._lib.hmc_stream_copy(self._ctx, _ptr(src), _ptr(dst), n))
+        return dst
+
     def dslash(self, psi: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         out = self.new_spinor() if out is None else out
         self._check(self._lib.hmc_dslash(self._ctx, _ptr(psi), _ptr(out)))

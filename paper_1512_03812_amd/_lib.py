@@ -95,6 +95,7 @@ SIGNATURES = {
     "hmc_refresh": (_I, [_P]),
     "hmc_set_timing": (_I, [_P, _I]),
     "hmc_get_kernel_stats": (_I, [_P, _I, _P]),
+    "hmc_stream_copy": (_I, [_P, _P, _P, _SZ]),
     "hmc_last_error": (ctypes.c_char_p, [_P]),
     "hmc_destroy": (_I, [_P]),
 }

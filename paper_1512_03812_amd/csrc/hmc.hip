@@ -1110,6 +1110,16 @@ int hmc_dslash(hmc_ctx *c, const void *in, void *out) {
     return HMC_OK;
 }
 
+int hmc_stream_copy(hmc_ctx *c, const void *src, void *dst, size_t bytes) {
+    CHECK_BOUND(c);
+    if (!src || !dst || bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16)
+        return fail(c, HMC_E_INVAL, "stream copy needs 16-byte aligned pointers and a size in 16-byte units");
+    if (bytes / 16 > (size_t)0x7fffffff * 256) return fail(c, HMC_E_INVAL, "stream copy too large");
+    if (bytes) launch_stream_copy(src, dst, bytes / 16, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    return HMC_OK;
+}
+
 int hmc_dslash_dagger(hmc_ctx *c, const void *in, void *out) {
     CHECK_BOUND(c);
     if (!in || !out || in == out) return fail(c, HMC_E_INVAL, "need distinct in/out");

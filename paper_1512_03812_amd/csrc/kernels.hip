@@ -1455,6 +1455,20 @@ __global__ void k_restore(Geo g, const MetroOut *__restrict__ m, const double *_
 }
 
 // ================================================================ device-side bookkeeping
+// Streaming copy, one 16-byte nontemporal load and store per thread: the measured
+// bandwidth ceiling of the roofline figures and the calibration kernel of the HBM counters.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ void k_stream_copy(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+void launch_stream_copy(const void *src, void *dst, size_t n16, hipStream_t s) {
+    const unsigned blocks = (unsigned)((n16 + 255) / 256);
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, s, (const f32x4 *)src,
+                       (f32x4 *)dst, n16);
+}
+
 __global__ void k_set_u32(uint32_t *p, uint32_t v) { *p = v; }
 
 void launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s) {

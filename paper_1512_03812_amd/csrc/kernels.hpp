@@ -185,6 +185,8 @@ void launch_metropolis(const Geo &g, uint64_t seed, const uint32_t *traj, const 
 // Device-side bookkeeping (trajectories that run as one captured graph read their counter
 // and write their solver results on the device).
 void launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s);
+// dst = src, n16 16-byte elements (nontemporal streaming copy)
+void launch_stream_copy(const void *src, void *dst, size_t n16, hipStream_t s);
 // iterations and convergence flag of every chain's finished solve (state st) -> log[2 c + k]
 void launch_log_solve(const CGState *st, int nchains, int *log, hipStream_t s);
 // status[c] = -3 if any of the n logged solves (log[k][c][2]) of chain c did not converge

@@ -80,6 +80,16 @@ def test_pack_roundtrip_is_exact():
         assert np.array_equal(a, c)
 
 
+def test_stream_copy_is_exact():
+    b = Batch([(8, 8)])
+    src = torch.randn(1 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.zeros(1 << 20, dtype=torch.float64, device="cuda")
+    b.lat.stream_copy(src[: (1 << 20) - 6], dst)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[: (1 << 20) - 6], src[: (1 << 20) - 6])
+    assert not dst[(1 << 20) - 6:].any()
+
+
 def test_hot_start_uniforms_bit_identical():
     b = Batch([(8, 8), (6, 10), (32, 32)], seed=0xDEADBEEF12345)
     b.lat.hot_start()
