@@ -71,6 +71,7 @@ def run_batched(args):
     lat.hot_start()
     lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
     lat.set_check_interval(args.check_interval)
+    lat.set_fused_cg(args.cg_kernels == "fused")
     if args.block:
         lat.set_block_size(args.block)
     tune = None
@@ -279,6 +280,9 @@ def run_sweep(args):
         lat = (hmc.Lattice(L, 2.0, 0.1, seed=args.seed) if nb == 1 else
                hmc.Lattice.batch([L] * nb, [L] * nb, 2.0, 0.1, seed=args.seed))
         lat.hot_start()
+        lat.set_fused_cg(args.cg_kernels == "fused")
+        if args.block:
+            lat.set_block_size(args.block)
         V = lat.V_total
         psi = torch.randn(2, V, dtype=torch.complex128, device="cuda")
         dst = lat.new_spinor()
@@ -510,6 +514,8 @@ def main():
     ap.add_argument("--reliable-delta", type=float, default=1e-3,
                     help="mixed CG: FP64 residual recomputation when the FP32 residual has dropped "
                          "by this factor")
+    ap.add_argument("--cg-kernels", choices=["fused", "two"], default="two",
+                    help="one fused kernel per CG iteration where the chains allow it, or two")
     ap.add_argument("--persistent-limit", type=int, default=0,
                     help="persistent-solver limit in sites after tuning (default 0: off, so that "
                          "the timed CG kernels run alone; -1 keeps the tuned value)")

@@ -185,6 +185,19 @@ int hmc_set_check_interval(hmc_ctx *ctx, int every);
  * handle the larger chains; 0 disables it.  Default and maximum 2048. */
 int hmc_set_persistent_limit(hmc_ctx *ctx, int vmax);
 
+/* CG kernels of the multi-workgroup solver (Sec. 3 calls the solve "D^-1").  With on = 1
+ * a solve runs one fused kernel per CG iteration when every chain it iterates lets a
+ * workgroup own whole lattice rows (block/2 a multiple of Lx/2 with Lt at least 4 rows
+ * more than a workgroup owns, or the whole chain within one workgroup) and the LDS windows
+ * fit: the recurrences are regrouped so that one reduction point per iteration suffices
+ * (the squared residual norm that sets beta is predicted from <r, A p> and ||A p||^2), and
+ * the stencil rows two beyond a workgroup's own are recomputed.  Otherwise, or with on = 0
+ * (default), each iteration takes two kernels.  Both give the CG iterates up to rounding.
+ * The fused kernel moves 18 % fewer bytes per iteration and saves a kernel boundary, but
+ * the recomputed rows and its register use make it slower on MI355X (about 9 % on the
+ * batched workload), so it runs only when asked for. */
+int hmc_set_fused_cg(hmc_ctx *ctx, int on);
+
 /* Threads per workgroup of the site kernels (128..1024, multiple of 64; default 256). */
 int hmc_set_block_size(hmc_ctx *ctx, int block);
 
@@ -316,7 +329,8 @@ int hmc_integrate(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inner
 /* ---------------------------------------------------------------- kernel timing */
 
 /* Sampled event timing of the CG step kernels (which = 0: step 1, the x update and
- * t = D p; which = 1: step 2, r -= alpha D^dagger t).  While on, every 16th CG iteration
+ * t = D p, or the whole fused iteration; which = 1: step 2, r -= alpha D^dagger t).
+ * While on, every 16th CG iteration
  * slot (away from the host's convergence checks) is bracketed by HIP events on the bound
  * stream, and its step 1 records on the device the algorithmic bytes of both steps for
  * the chains it iterates (their sites times the bytes per site of the slot's mode); the
@@ -328,7 +342,8 @@ typedef struct {
     double timed_ms;          /* their summed event-measured duration */
     double timed_bytes;       /* their summed algorithmic bytes */
     int sample_every;         /* sampling period in slots */
-    int pad;
+    int fused;                /* 1: the solves ran the fused iteration, whose kernel is
+                                 index 0 (index 1 then holds nothing) */
 } hmc_kernel_stat;
 
 int hmc_set_timing(hmc_ctx *ctx, int on);

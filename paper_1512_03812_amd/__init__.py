@@ -247,6 +247,10 @@ class Lattice:
         """Chains of at most vmax sites solve inside one persistent workgroup (0: never)."""
         self._check(self._lib.hmc_set_persistent_limit(self._ctx, int(vmax)))
 
+    def set_fused_cg(self, on: bool):
+        """One fused kernel per CG iteration where the chains allow it, or two (default)."""
+        self._check(self._lib.hmc_set_fused_cg(self._ctx, 1 if on else 0))
+
     def set_block_size(self, block: int):
         self._check(self._lib.hmc_set_block_size(self._ctx, int(block)))
 
@@ -266,7 +270,8 @@ class Lattice:
         self._check(self._lib.hmc_set_timing(self._ctx, int(bool(on))))
 
     def kernel_stats(self, which: int) -> dict:
-        """Event timing of CG step 1 (which=0) or step 2 (which=1) since set_timing."""
+        """Event timing of CG step 1 (which=0) or step 2 (which=1) since set_timing; with
+        fused = 1, index 0 is the fused one-kernel iteration."""
         st = _lib.KernelStat()
         self._check(self._lib.hmc_get_kernel_stats(self._ctx, int(which), ctypes.byref(st)))
         return {k: getattr(st, k) for k, _ in st._fields_}

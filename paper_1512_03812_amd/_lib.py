@@ -46,7 +46,7 @@ class TuneInfo(ctypes.Structure):
 class KernelStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_longlong), ("timed_launches", ctypes.c_longlong),
                 ("timed_ms", ctypes.c_double), ("timed_bytes", ctypes.c_double),
-                ("sample_every", ctypes.c_int), ("pad", ctypes.c_int)]
+                ("sample_every", ctypes.c_int), ("fused", ctypes.c_int)]
 
 
 # name -> (restype, argtypes)
@@ -73,6 +73,7 @@ SIGNATURES = {
     "hmc_set_quenched": (_I, [_P, _I]),
     "hmc_set_check_interval": (_I, [_P, _I]),
     "hmc_set_persistent_limit": (_I, [_P, _I]),
+    "hmc_set_fused_cg": (_I, [_P, _I]),
     "hmc_set_block_size": (_I, [_P, _I]),
     "hmc_autotune": (_I, [_P, _I, _D, _P]),
     "hmc_dslash": (_I, [_P, _P, _P]),

@@ -25,8 +25,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Names of the real-link and spinor buffers carved out of the workspace.
 enum LinkBuf { LQ, LP, LQ0, LP0, LQS, LF, LFF, LFT, LG, kNumLinkBufs };
-enum SpinBuf { SPHI, SZETA, SXI, SCHI, SR, SPA, SPB, ST, SW, SY, SZ, kNumSpinBufs };
-enum Spin32Buf { FX, FR, FT, FPA, FPB, kNumSpin32Bufs };
+enum SpinBuf { SPHI, SZETA, SXI, SCHI, SR, SPA, SPB, ST, SW, SY, SZ, SR2, SS2, kNumSpinBufs };
+enum Spin32Buf { FX, FR, FT, FPA, FPB, FR2, FS2, kNumSpin32Bufs };
 
 }  // namespace
 
@@ -54,6 +54,7 @@ struct KernelTimer {
     long long timed[2] = {0, 0};
     long long launches = 0;  // all slots launched while timing was on
     int since_sync = 0;      // slots launched since the host last waited for the stream
+    bool fused = false;      // the sampled slots ran the fused iteration (index 0 holds it)
 };
 
 // Solves whose results a captured trajectory can log on the device.
@@ -95,6 +96,7 @@ struct hmc_ctx {
     int log_count = 0;             // solves logged by the trajectory being captured
     bool log_overflow = false;
     int persist_vmax = 2048;  // chains with at most this many sites use the persistent solver
+    bool fused_on = false;    // one kernel per CG iteration where every chain allows it
     // ------------------------------------------------------------ workspace
     size_t ws_bytes = 0;
     char *ws = nullptr;
@@ -438,6 +440,22 @@ int persistent_limit(hmc_ctx *c, bool mixed) {
     return v;
 }
 
+// LDS bytes of the fused iteration over the chains above vmax at the current workgroup
+// size, or 0 if one of them cannot use it (or the fused iteration is switched off).
+size_t fused_lds(hmc_ctx *c, int vmax, bool mixed) {
+    if (!c->fused_on) return 0;
+    int entries = 0;
+    for (const ChainInfo &ci : c->chains) {
+        if (ci.V <= vmax) continue;
+        int e = 0;
+        if (!cg_iter_eligible(ci, c->block, &e)) return 0;
+        entries = std::max(entries, e);
+    }
+    const size_t lds = cg_iter_lds_bytes(entries, mixed);
+    if (lds == 0 || lds + 1024 > c->lds_max || grant_cg_iter_lds(lds)) return 0;
+    return lds;
+}
+
 // CG on D^dagger D x = phi with the links already materialised (U64, and U32 if mixed).
 // Per-chain results land in c->cg_host.  Returns HMC_E_NOCONV if a chain did not converge.
 // Every check_every slots the host reads back how many workgroups still belong to
@@ -501,7 +519,58 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     big.nblocks = c->n_big_blocks;
     g = big;
     int slot = 0;
-    if (big.nblocks > 0) {
+    const size_t lds_iter = big.nblocks > 0 ? fused_lds(c, c->part_vmax, mixed) : 0;
+    c->timer.fused = lds_iter > 0;
+    if (lds_iter > 0) {
+        // one fused kernel per iteration: r, s, p double-buffered; partial rows [2][4]
+        CGIterFields fi;
+        fi.phi = phi;
+        fi.x64 = x;
+        fi.t64 = c->spin(ST);
+        fi.x32 = c->spin32(FX);
+        if (mixed) {
+            fi.r[0] = c->spin32(FR); fi.r[1] = c->spin32(FR2);
+            fi.s[0] = c->spin32(FT); fi.s[1] = c->spin32(FS2);
+            fi.p[0] = c->spin32(FPA); fi.p[1] = c->spin32(FPB);
+        } else {
+            fi.r[0] = c->spin(SR); fi.r[1] = c->spin(SR2);
+            fi.s[0] = c->spin(ST); fi.s[1] = c->spin(SS2);
+            fi.p[0] = c->spin(SPA); fi.p[1] = c->spin(SPB);
+        }
+        fi.U64 = c->U64();
+        fi.U32 = c->U32();
+        fi.Q = c->partials();
+        fi.st = c->cg();
+        fi.samples = f.samples;
+        CGFields fz = f;  // the initial kernel: r (buffer 0) = phi, x = 0, ||phi||^2 -> Q[1][1]
+        if (mixed) fz.r32 = (float4 *)fi.r[0];
+        else fz.r64 = (double2 *)fi.r[0];
+        fz.p2 = fi.Q + (size_t)5 * full.nlog;
+        launch_cg_init(big, fz, mixed, c->delta, c->stream);
+        const int max_slots = mixed ? max_iter + max_iter / 2 + 64 : max_iter + 1;
+        int interval = c->check_every, next_check = interval, last_active = big.nblocks;
+        for (; slot < max_slots; ++slot) {
+            slot_launch(c, slot,
+                        [&](int sample) {
+                            launch_cg_iter(g, fi, mixed, slot, tol, false, sample, lds_iter, c->stream);
+                        },
+                        [] {});
+            if (slot + 1 == next_check) {
+                int active = 0, live = 0;
+                if ((rc = check_convergence(c, big, max_iter, &active, &live))) return rc;
+                if (active == 0 || live == 0) { ++slot; break; }
+                g.work = c->at<BlockWork>(c->off_active);
+                g.nblocks = active;
+                interval = active == last_active ? std::min(2 * interval, 4 * c->check_every)
+                                                 : c->check_every;
+                last_active = active;
+                next_check = slot + 1 + interval;
+            }
+        }
+        // the last slot's residual decides the final state of every large chain
+        launch_cg_iter(big, fi, mixed, slot, tol, true, -1, lds_iter, c->stream);
+        if (mixed) launch_cg_finish_mixed(big, f, c->stream);
+    } else if (big.nblocks > 0) {
     launch_cg_init(big, f, mixed, c->delta, c->stream);
     if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
     // iteration slots: CG iterations plus, in mixed precision, FP64 residual recomputations
@@ -1021,6 +1090,13 @@ int hmc_set_quenched(hmc_ctx *c, int quenched) {
 int hmc_set_persistent_limit(hmc_ctx *c, int vmax) {
     if (!c || vmax < 0) return HMC_E_INVAL;
     c->persist_vmax = vmax;
+    c->graph_epoch++;
+    return HMC_OK;
+}
+
+int hmc_set_fused_cg(hmc_ctx *c, int on) {
+    if (!c) return HMC_E_INVAL;
+    c->fused_on = on != 0;
     c->graph_epoch++;
     return HMC_OK;
 }
@@ -1622,6 +1698,7 @@ int hmc_get_kernel_stats(hmc_ctx *c, int which, hmc_kernel_stat *out) {
     out->timed_ms = T.ms[which];
     out->timed_bytes = T.bytes[which];
     out->sample_every = T.sample_every;
+    out->fused = T.fused ? 1 : 0;
     return HMC_OK;
 }
 

@@ -673,6 +673,356 @@ void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_finish_mixed, dim3(g.nblocks), dim3(g.block), 0, s, g, f);
 }
 
+// ---------------------------------------------------------------- fused CG iteration
+// One kernel per CG iteration, for chains whose workgroups own whole lattice rows: a
+// workgroup of B threads owns rows [t0, t0 + nr) of both parity planes (nr = (B/2) / (Lx/2)),
+// or the whole chain.  The standard CG recurrences are regrouped so that each iteration
+// needs one grid-wide reduction point, which the kernel boundary provides: slot k
+// receives the dot products of slot k-1 (||t||^2 = <p, A p>, ||r||^2, Re<r, s>, ||s||^2 with
+// t = D p and s = A p = D^dagger t), takes the step alpha = ||r||^2 / ||t||^2 of the previous
+// direction (r -= alpha s, x += alpha p), predicts ||r_new||^2 = ||r||^2 - 2 alpha Re<r, s>
+// + alpha^2 ||s||^2 for beta, forms p = r + beta p, and applies A to it.  A needs p two rows
+// beyond the own rows: those rows are recomputed from the previous r, s, p (read, never the
+// same slot's output of another workgroup), staged with the own rows in LDS, and t is formed
+// on the own rows and one row beyond.  r, s and p are double-buffered (buf in the state);
+// x is only touched by its owner.
+
+// The element-wise CG step on one site: r_new = r - a s, p_new = r_new + b p.
+template <typename C, typename R>
+__device__ __forceinline__ void cg_advance(C r0, C r1, C s0, C s1, C q0, C q1, R a, R b, C &rn0,
+                                           C &rn1, C &pn0, C &pn1) {
+    rn0 = cmake<C>(r0.x - a * s0.x, r0.y - a * s0.y);
+    rn1 = cmake<C>(r1.x - a * s1.x, r1.y - a * s1.y);
+    pn0 = cmake<C>(rn0.x + b * q0.x, rn0.y + b * q0.y);
+    pn1 = cmake<C>(rn1.x + b * q1.x, rn1.y + b * q1.y);
+}
+
+__device__ __forceinline__ double dot_re(double2 a, double2 b) { return a.x * b.x + a.y * b.y; }
+__device__ __forceinline__ double dot_re(float2 a, float2 b) {
+    return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+}
+
+// Chain total of one partial row (chains of at most kMaxChainBlocks workgroups), identical in
+// every wavefront of the chain.
+__device__ __forceinline__ double chain_sum(const double *__restrict__ row, const ChainInfo &ci) {
+    double a = 0.0;
+    for (int j = (int)(threadIdx.x & 63); j < ci.nblocks; j += 64) a += row[ci.block0 + j];
+    return __shfl(wave_sum(a), 0, 64);
+}
+
+bool cg_iter_eligible(const ChainInfo &ci, int block, int *lds_entries) {
+    const int half = block / 2;
+    if (ci.nblocks > kMaxChainBlocks) return false;
+    if (ci.Vh <= half) {  // the whole chain in one workgroup: no halo rows
+        *lds_entries = 4 * ci.Vh;
+        return true;
+    }
+    if (half % ci.hx) return false;
+    const int nr = half / ci.hx;
+    if (ci.Lt < nr + 4) return false;  // the halo rows would wrap onto the own rows
+    *lds_entries = 2 * ci.hx * ((nr + 4) + (nr + 2));
+    return true;
+}
+
+size_t cg_iter_lds_bytes(int entries, bool mixed) {
+    return (size_t)entries * (mixed ? sizeof(LdsSpinor<float2>) : sizeof(LdsSpinor<double2>));
+}
+
+template <bool MIXED>
+__global__ void k_cg_iter(Geo g, CGIterFields f, int slot, double tol2, int decide_only, int sample) {
+    using R = typename Prec<MIXED>::R;
+    using S = typename Prec<MIXED>::S;
+    using C = cplx_t<R>;
+    const BlockWork w = g.work[blockIdx.x];
+    const ChainInfo ci = g.chains[w.chain];
+    const int Vtot = g.Vtot;
+    const bool leader = w.logical == ci.block0 && threadIdx.x == 0;
+    CGState *out = f.st + (size_t)(slot & 1) * g.nchains + w.chain;
+    const CGState *prev = f.st + (size_t)((slot + 1) & 1) * g.nchains + w.chain;
+    if (prev->converged) {
+        if (leader) *out = *prev;
+        return;
+    }
+    const int p_mode = prev->mode, p_iters = prev->iters, p_nupd = prev->n_updates, buf = prev->buf;
+    const double p_target = prev->target, p_phi2 = prev->phi2, p_rmax2 = prev->rmax2;
+    const double delta2 = prev->delta2, p_t2 = prev->t2, p_s2 = prev->s2;
+    const bool first = p_mode == kModeInit;
+
+    const S *__restrict__ r_old = (const S *)f.r[buf];
+    const S *__restrict__ s_old = (const S *)f.s[buf];
+    const S *__restrict__ p_old = (const S *)f.p[buf];
+    S *__restrict__ x;
+    const C *__restrict__ U;
+    if constexpr (MIXED) { x = f.x32; U = f.U32; }
+    else { x = f.x64; U = f.U64; }
+    const int hx = ci.hx, Lx = ci.Lx, Lt = ci.Lt, Vh = ci.Vh;
+    const int half = (int)blockDim.x >> 1;
+    const int par = (int)threadIdx.x >= half ? 1 : 0;
+    const int i = w.start + (int)threadIdx.x - par * half;
+    const bool own = i < Vh;
+    auto links_at = [&](int P, int t, int xh) {
+        const int xs = 2 * xh + ((P ^ t) & 1);
+        const int xm = xs == 0 ? Lx - 1 : xs - 1, tm = t == 0 ? Lt - 1 : t - 1;
+        const int fl = ci.off + P * Vh + t * hx + xh;
+        SiteLinks<C> l;
+        l.xf = U[fl];
+        l.tf = U[Vtot + fl];
+        l.xb = U[ci.off + (1 - P) * Vh + t * hx + (xm >> 1)];
+        l.tb = U[Vtot + ci.off + (1 - P) * Vh + tm * hx + xh];
+        return l;
+    };
+    // own site and its operands, loaded before the chain totals
+    const int ot = i / hx, oxh = i - ot * hx;  // own row and column
+    const int flat = ci.off + par * Vh + i;
+    SiteLinks<C> lk = {};
+    C r0 = {}, r1 = {}, z0 = {}, z1 = {}, q0 = {}, q1 = {};
+    if (own) {
+        sp_load(r_old, Vtot, flat, r0, r1);
+        if (!first) {
+            sp_load(s_old, Vtot, flat, z0, z1);
+            sp_load(p_old, Vtot, flat, q0, q1);
+        }
+        lk = links_at(par, ot, oxh);
+    }
+    const double *Qp = f.Q + (size_t)(((slot + 1) & 1) * 4) * g.nlog;
+    double *Qc = f.Q + (size_t)((slot & 1) * 4) * g.nlog;
+    const double ta = chain_sum(Qp, ci), tb = chain_sum(Qp + g.nlog, ci);
+    const double tc = chain_sum(Qp + 2 * g.nlog, ci), td = chain_sum(Qp + 3 * g.nlog, ci);
+
+    // decision for this slot
+    int n_mode = kModeNormal, n_iters = p_iters, n_nupd = p_nupd, n_conv = 0, n_buf = buf;
+    double n_target = p_target, n_phi2 = p_phi2, n_rmax2 = p_rmax2, n_t2 = p_t2, n_s2 = p_s2;
+    double alpha = 0.0, beta = 0.0;
+    if (first) {  // tb = ||phi||^2 from the initial kernel; p = r
+        n_phi2 = tb; n_target = tol2 * tb; n_rmax2 = tb; n_iters = 0; n_nupd = 0;
+        n_conv = tb <= n_target ? 1 : 0;
+        n_buf = buf ^ 1;
+    } else if (p_mode == kModeUpdate) {
+        n_mode = kModeUpdate2;
+    } else {
+        double A = ta, D2 = td;
+        if (p_mode == kModeUpdate2) {  // tb, tc: the recomputed residual against the last s
+            n_nupd = p_nupd + 1;
+            n_rmax2 = tb;
+            A = p_t2;
+            D2 = p_s2;
+            n_conv = tb <= n_target ? 1 : 0;
+        } else if (!MIXED) {
+            n_conv = tb <= n_target ? 1 : 0;
+        } else if (tb <= n_target || tb <= delta2 * n_rmax2) {
+            n_mode = kModeUpdate;
+            n_t2 = ta;
+            n_s2 = td;
+        }
+        if (!n_conv && n_mode == kModeNormal) {
+            alpha = tb / A;
+            beta = (tb - 2.0 * alpha * tc + alpha * alpha * D2) / tb;
+            if (!decide_only) {  // the step is taken by this slot
+                n_iters = p_iters + 1;
+                n_buf = buf ^ 1;
+            }
+        }
+    }
+    if (leader) {
+        out->rho = tb; out->rho_p = 0.0; out->target = n_target; out->phi2 = n_phi2;
+        out->rmax2 = n_rmax2; out->beta = beta; out->delta2 = delta2; out->alpha = alpha;
+        out->t2 = n_t2; out->s2 = n_s2; out->iters = n_iters; out->converged = n_conv;
+        out->mode = n_mode; out->n_updates = n_nupd; out->buf = n_buf;
+        if (sample >= 0 && !n_conv && !decide_only) {
+            double *row = f.samples + ((size_t)sample * g.nchains + w.chain) * 2;
+            row[0] = ci.V * (n_mode == kModeUpdate ? kBytesIterUpdate1
+                             : n_mode == kModeUpdate2 ? kBytesIterUpdate2
+                             : MIXED ? kBytesIterFp32 : kBytesIterFp64);
+            row[1] = 0.0;
+        }
+    }
+    if (n_conv || decide_only) return;
+
+    if (MIXED && n_mode == kModeUpdate) {
+        // residual recomputation, first slot: t64 = D (x64 + x32)
+        if (own) {
+            const Site s = decode_site(ci, par * Vh + i);
+            const Nbr nb = neighbours(ci, s);
+            auto load = [&](int fl, double2 &b0, double2 &b1) {
+                double2 y0, y1;
+                sp_load(f.x64, Vtot, fl, y0, y1);
+                const float4 zz = f.x32[fl];
+                b0 = make_double2(y0.x + (double)zz.x, y0.y + (double)zz.y);
+                b1 = make_double2(y1.x + (double)zz.z, y1.y + (double)zz.w);
+            };
+            double2 a0, a1, o0, o1;
+            load(s.flat, a0, a1);
+            dslash_site<double, false>(nb, s.flat, Vtot, f.U64, a0, a1, 2.0 + ci.m0, load, o0, o1);
+            sp_store(f.t64, Vtot, s.flat, o0, o1);
+        }
+        return;
+    }
+    if (MIXED && n_mode == kModeUpdate2) {
+        // second slot: r = phi - D^dagger t64 in FP64, x64 += x32, x32 = 0, r (FP32) in place;
+        // partials ||r||^2 and Re<r, s> against the unchanged s of the last direction
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        if (own) {
+            const Site s = decode_site(ci, par * Vh + i);
+            const Nbr nb = neighbours(ci, s);
+            auto load = [&](int fl, double2 &b0, double2 &b1) { sp_load(f.t64, Vtot, fl, b0, b1); };
+            double2 t0, t1, a0, a1;
+            load(s.flat, t0, t1);
+            dslash_site<double, true>(nb, s.flat, Vtot, f.U64, t0, t1, 2.0 + ci.m0, load, a0, a1);
+            double2 h0, h1, y0, y1;
+            sp_load(f.phi, Vtot, s.flat, h0, h1);
+            sp_load(f.x64, Vtot, s.flat, y0, y1);
+            const float4 zz = f.x32[s.flat];
+            const double2 e0 = make_double2(h0.x - a0.x, h0.y - a0.y);
+            const double2 e1 = make_double2(h1.x - a1.x, h1.y - a1.y);
+            sp_store(f.x64, Vtot, s.flat, make_double2(y0.x + (double)zz.x, y0.y + (double)zz.y),
+                     make_double2(y1.x + (double)zz.z, y1.y + (double)zz.w));
+            f.x32[s.flat] = make_float4(0.f, 0.f, 0.f, 0.f);
+            const C e0f = cmake<C>((R)e0.x, (R)e0.y), e1f = cmake<C>((R)e1.x, (R)e1.y);
+            sp_store((S *)f.r[buf], Vtot, s.flat, e0f, e1f);
+            v[1] = norm2(e0) + norm2(e1);
+            v[2] = dot_re(e0f, z0) + dot_re(e1f, z1);
+        }
+        write_partials<4>(v, Qc, g.nlog, w.logical);
+        return;
+    }
+
+    // normal slot
+    S *__restrict__ r_new = (S *)f.r[buf ^ 1];
+    S *__restrict__ s_new = (S *)f.s[buf ^ 1];
+    S *__restrict__ p_new = (S *)f.p[buf ^ 1];
+    const R ra = (R)alpha, rb = (R)beta;
+    const bool whole = ci.nblocks == 1;
+    const int t0 = w.start / hx;
+    const int nr = whole ? Lt : min(half, Vh - w.start) / hx;
+    const int Hp = whole ? 0 : 2, Ht = whole ? 0 : 1;
+    const int np = nr + 2 * Hp, nt = nr + 2 * Ht;
+    LdsSpinor<C> *lp = (LdsSpinor<C> *)smem_d;  // [2][np][hx]: p on rows t0 - Hp ...
+    LdsSpinor<C> *lt = lp + 2 * np * hx;        // [2][nt][hx]: t on rows t0 - Ht ...
+    auto wslot = [&](int P, int wr, int rows, int xh) { return (P * rows + wr) * hx + xh; };
+    // window slots of the stencil neighbours of the site (P, chain row t, xh), whose row
+    // sits at row wr of a window of `rows` rows
+    auto wnbr = [&](int P, int t, int xh, int wr, int rows) {
+        const int xs = 2 * xh + ((P ^ t) & 1);
+        const int xp = xs + 1 == Lx ? 0 : xs + 1, xm = xs == 0 ? Lx - 1 : xs - 1;
+        int up = wr + 1, dn = wr - 1;
+        if (whole) {
+            if (up == Lt) up = 0;
+            if (dn < 0) dn = Lt - 1;
+        }
+        Nbr n;
+        n.xp = wslot(1 - P, wr, rows, xp >> 1);
+        n.xm = wslot(1 - P, wr, rows, xm >> 1);
+        n.tp = wslot(1 - P, up, rows, xh);
+        n.tm = wslot(1 - P, dn, rows, xh);
+        return n;
+    };
+    C rn0 = {}, rn1 = {}, pn0 = {}, pn1 = {};
+    if (own) {
+        cg_advance(r0, r1, z0, z1, q0, q1, ra, rb, rn0, rn1, pn0, pn1);
+        if (!first) {
+            C x0, x1;
+            sp_load(x, Vtot, flat, x0, x1);
+            x0.x += ra * q0.x; x0.y += ra * q0.y;
+            x1.x += ra * q1.x; x1.y += ra * q1.y;
+            sp_store(x, Vtot, flat, x0, x1);
+        }
+        sp_store(r_new, Vtot, flat, rn0, rn1);
+        sp_store(p_new, Vtot, flat, pn0, pn1);
+        const int k = wslot(par, ot - t0 + Hp, np, oxh);
+        lp[k].a = pn0;
+        lp[k].b = pn1;
+    }
+    if (!whole) {
+        // p on the two rows below and above the own rows, from the previous r, s, p
+#pragma unroll 1
+        for (int h = threadIdx.x; h < 8 * hx; h += blockDim.x) {
+            const int P = h / (4 * hx), rem = h - P * 4 * hx, hr = rem / hx, hxh = rem - hr * hx;
+            int row = hr < 2 ? t0 - 2 + hr : t0 + nr + hr - 2;
+            row = row < 0 ? row + Lt : (row >= Lt ? row - Lt : row);
+            const int fl = ci.off + P * Vh + row * hx + hxh;
+            C hr0, hr1, hs0 = {}, hs1 = {}, hq0 = {}, hq1 = {}, a0, a1, b0, b1;
+            sp_load(r_old, Vtot, fl, hr0, hr1);
+            if (!first) {
+                sp_load(s_old, Vtot, fl, hs0, hs1);
+                sp_load(p_old, Vtot, fl, hq0, hq1);
+            }
+            cg_advance(hr0, hr1, hs0, hs1, hq0, hq1, ra, rb, a0, a1, b0, b1);
+            const int k = wslot(P, hr < 2 ? hr : nr + hr, np, hxh);
+            lp[k].a = b0;
+            lp[k].b = b1;
+        }
+    }
+    __syncthreads();
+    // t = D p on the own rows and one row beyond
+    const R mass = (R)(2.0 + ci.m0);
+    auto ld_p = [&](int k, C &b0, C &b1) { b0 = lp[k].a; b1 = lp[k].b; };
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    C tn0 = {}, tn1 = {};
+    if (own) {
+        const int wt = ot - t0 + Ht;
+        dslash_site_links<R, false>(wnbr(par, ot, oxh, wt + Hp - Ht, np), lk, pn0, pn1, mass, ld_p,
+                                    tn0, tn1);
+        const int k = wslot(par, wt, nt, oxh);
+        lt[k].a = tn0;
+        lt[k].b = tn1;
+        v[0] = norm2(tn0) + norm2(tn1);
+    }
+    if (!whole) {
+#pragma unroll 1
+        for (int h = threadIdx.x; h < 4 * hx; h += blockDim.x) {
+            const int P = h / (2 * hx), rem = h - P * 2 * hx, hr = rem / hx, hxh = rem - hr * hx;
+            int row = hr == 0 ? t0 - 1 : t0 + nr;
+            row = row < 0 ? row + Lt : (row >= Lt ? row - Lt : row);
+            const int wt = hr == 0 ? 0 : nr + 1, wp = wt + 1;
+            C a0, a1, o0, o1;
+            ld_p(wslot(P, wp, np, hxh), a0, a1);
+            dslash_site_links<R, false>(wnbr(P, row, hxh, wp, np), links_at(P, row, hxh), a0, a1,
+                                        mass, ld_p, o0, o1);
+            const int k = wslot(P, wt, nt, hxh);
+            lt[k].a = o0;
+            lt[k].b = o1;
+        }
+    }
+    __syncthreads();
+    // s = D^dagger t on the own rows
+    if (own) {
+        auto ld_t = [&](int k, C &b0, C &b1) { b0 = lt[k].a; b1 = lt[k].b; };
+        const int wt = ot - t0 + Ht;
+        C sn0, sn1;
+        dslash_site_links<R, true>(wnbr(par, ot, oxh, wt, nt), lk, tn0, tn1, mass, ld_t, sn0, sn1);
+        sp_store(s_new, Vtot, flat, sn0, sn1);
+        v[1] = norm2(rn0) + norm2(rn1);
+        v[2] = dot_re(rn0, sn0) + dot_re(rn1, sn1);
+        v[3] = norm2(sn0) + norm2(sn1);
+    }
+    write_partials<4>(v, Qc, g.nlog, w.logical);
+}
+
+void launch_cg_iter(const Geo &g, const CGIterFields &f, bool mixed, int slot, double tol,
+                    bool decide_only, int sample, size_t lds_bytes, hipStream_t s) {
+    if (mixed)
+        hipLaunchKernelGGL(k_cg_iter<true>, dim3(g.nblocks), dim3(g.block), lds_bytes, s, g, f, slot,
+                           tol * tol, decide_only ? 1 : 0, sample);
+    else
+        hipLaunchKernelGGL(k_cg_iter<false>, dim3(g.nblocks), dim3(g.block), lds_bytes, s, g, f, slot,
+                           tol * tol, decide_only ? 1 : 0, sample);
+}
+
+int grant_cg_iter_lds(size_t lds_bytes) {
+    static size_t granted[2] = {64 * 1024, 64 * 1024};
+    for (int m = 0; m < 2; ++m) {
+        if (lds_bytes <= granted[m]) continue;
+        const void *fn = m ? (const void *)k_cg_iter<true> : (const void *)k_cg_iter<false>;
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return -1;
+        }
+        granted[m] = lds_bytes;
+    }
+    return 0;
+}
+
 // ---------------------------------------------------------------- persistent small-chain CG
 // One workgroup runs a whole solve for one small chain.  The search direction p and
 // t = D p live in LDS (dynamic shared memory, 2 x 2V complex); r, x, the site geometry and

@@ -31,14 +31,18 @@ struct CGState {
     double delta2;  // mixed: reliable-update trigger factor squared
     double alpha;   // normal slot: this slot's alpha, whose x update the next slot applies;
                     // update slot: the alpha still owed to x, folded in by its step 2
+    double t2;      // fused iteration: ||D p||^2 of the last direction (kept across an update)
+    double s2;      // fused iteration: ||D^dagger D p||^2 of the last direction
     int iters;      // CG iterations completed
     int converged;  // 1 once the stopping test passed
-    int mode;       // kModeInit, kModeNormal or kModeUpdate (this slot)
+    int mode;       // kModeInit, kModeNormal, kModeUpdate (this slot), kModeUpdate2
     int n_updates;  // mixed: FP64 residual recomputations completed
-    int pad[4];
+    int buf;        // fused iteration: which of the two buffers holds r, s and p
+    int pad[3];
 };
 static_assert(sizeof(CGState) % 16 == 0, "CGState alignment");
-enum { kModeInit = 0, kModeNormal = 1, kModeUpdate = 2 };
+// kModeUpdate2: the second half of a fused-iteration residual recomputation.
+enum { kModeInit = 0, kModeNormal = 1, kModeUpdate = 2, kModeUpdate2 = 3 };
 
 // Sampled slots per solve whose bytes the timing records (rows of the device byte table).
 constexpr int kMaxSamples = 256;
@@ -57,6 +61,15 @@ constexpr int kMaxSamples = 256;
 constexpr double kBytesFp64Step1 = 224.0, kBytesFp64Step2 = 128.0;
 constexpr double kBytesFp32Step1 = 112.0, kBytesFp32Step2 = 64.0;
 constexpr double kBytesUpdateStep1 = 144.0, kBytesUpdateStep2 = 224.0;
+// The fused iteration (one kernel per CG iteration):
+//   normal slot, FP64  : r, s, p, x 4 x 32 + U 32 read, r, s, p, x 4 x 32 written = 288
+//   normal slot, FP32  : r, s, p, x 4 x 16 + U 16 read, r, s, p, x 4 x 16 written = 144
+//   mixed, residual recomputation, first slot : x64 32 + x32 16 + U64 32 read,
+//                                                t64 32 written                   = 112
+//                                  second slot: t64 32 + U64 32 + phi 32 + x64 32 + x32 16
+//                                                + s 16 read, x64 32 + x32 16 + r 16  = 224
+constexpr double kBytesIterFp64 = 288.0, kBytesIterFp32 = 144.0;
+constexpr double kBytesIterUpdate1 = 112.0, kBytesIterUpdate2 = 224.0;
 
 // Partial sums: row k of partials holds one double per logical workgroup.
 constexpr int kMaxReduce = 8;
@@ -106,6 +119,36 @@ void launch_sample_sums(double *samples, int n, int nchains, double *sums, hipSt
 // recomputation, which also folds x32 and the owed alpha p into x64).
 void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
                      hipStream_t s);
+// Fused CG iteration: one kernel per iteration for chains whose workgroups own whole
+// lattice rows (see cg_iter_eligible).  Slot k applies the previous iteration's step
+// (r -= alpha s, x += alpha p, with the squared norm of the new residual predicted from the
+// previous slot's dot products), forms p = r + beta p, and computes t = D p on the own rows
+// and one row beyond, and s = D^dagger t on the own rows, recomputing p two rows beyond the
+// own rows from the previous r, s and p (so no other workgroup's output of the same slot is
+// read).  Partials of ||t||^2, ||r||^2, Re<r, s>, ||s||^2 go to Q[k & 1].  Mixed precision:
+// a reliable update takes two slots (t64 = D x, then r = phi - D^dagger t64).
+struct CGIterFields {
+    const double2 *phi;
+    double2 *x64;
+    double2 *t64;     // mixed: FP64 scratch of the residual recomputation
+    float4 *x32;      // mixed: FP32 solution increment since the last recomputation
+    void *r[2], *s[2], *p[2];  // two buffers each, FP32 float4 (mixed) or FP64 double2 SoA
+    const double2 *U64;
+    const float2 *U32;
+    double *Q;        // partial rows [2 slot parities][4][nlog]
+    CGState *st;      // [2][nchains]
+    double *samples;  // as CGFields::samples
+};
+// Whether chain ci can use the fused iteration with workgroups of `block` threads, and its
+// LDS entries (complex spinors) per workgroup.
+bool cg_iter_eligible(const ChainInfo &ci, int block, int *lds_entries);
+// Dynamic LDS bytes of the fused iteration for `entries` spinor entries.
+size_t cg_iter_lds_bytes(int entries, bool mixed);
+void launch_cg_iter(const Geo &g, const CGIterFields &f, bool mixed, int slot, double tol,
+                    bool decide_only, int sample, size_t lds_bytes, hipStream_t s);
+// Lets both instantiations use lds_bytes of dynamic LDS; -1 if the device refuses.
+int grant_cg_iter_lds(size_t lds_bytes);
+
 // fin[c] = sum of row's partials of chain c, for the chains above kMaxChainBlocks.
 void launch_finalize_large(const Geo &g, const double *row, double *fin, hipStream_t s);
 // x64 += x32 (end of a mixed solve).

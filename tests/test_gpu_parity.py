@@ -191,11 +191,13 @@ def test_gauge_force_and_action_parity(Lx, Lt):
 SOLVERS = [0, 2048]  # persistent limit: 0 = multi-workgroup slot kernels only
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("persistent", SOLVERS)
 @pytest.mark.parametrize("Lx,Lt,m0", [(4, 4, 0.1), (8, 8, 0.1), (6, 10, 0.05), (34, 18, 0.1),
                                       (32, 32, 0.1), (64, 32, 0.1)])
-def test_cg_parity(Lx, Lt, m0, persistent):
+def test_cg_parity(Lx, Lt, m0, persistent, fused):
     b = Batch([(Lx, Lt, 2.0, m0)], persistent=persistent)
+    b.lat.set_fused_cg(fused)
     q = inputs.random_angles(Lx, Lt, 31)
     phi = inputs.random_spinor(Lx, Lt, 32)
     b.set_q([q])
@@ -204,6 +206,58 @@ def test_cg_parity(Lx, Lt, m0, persistent):
     assert res.converged[0] and abs(res.iters[0] - itr) <= 2
     assert res.rel_resid_true[0] < 1e-12
     assert rel(b.spinor_from_native(x)[0], xr) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("block", [128, 256, 1024])
+def test_fused_and_two_kernel_iterations_agree(prec, block):
+    """A batch of uneven chains (whole-chain workgroups, several workgroups per chain, one
+    row per workgroup at block 128 for L = 128) solved with one fused kernel per iteration
+    and with two kernels: the same solution within the tolerance, about the same number of
+    iterations, and the oracle's solution."""
+    shapes = [(16, 16, 2.0, 0.1), (32, 32, 1.5, 0.05), (64, 16, 3.0, 0.2), (128, 32, 2.0, 0.08),
+              (8, 8, 1.0, 0.1), (128, 8, 2.0, 0.1)]
+    b = Batch(shapes, persistent=0)
+    b.lat.set_block_size(block)
+    qs = [inputs.random_angles(Lx, Lt, 300 + k) for k, (Lx, Lt, _, _) in enumerate(shapes)]
+    phis = [inputs.random_spinor(Lx, Lt, 400 + k) for k, (Lx, Lt, _, _) in enumerate(shapes)]
+    b.set_q(qs)
+    phi = b.spinor_to_native(phis)
+    tol = 1e-13 if prec == "fp64" else 1e-11
+    out = {}
+    for fused in (True, False):
+        b.lat.set_fused_cg(fused)
+        b.lat.set_timing(True)
+        x, res = b.lat.cg_solve(phi, tol=tol, prec=prec)
+        st = b.lat.kernel_stats(0)
+        b.lat.set_timing(False)
+        assert all(res.converged), (fused, res)
+        out[fused] = (b.spinor_from_native(x), res, st)
+    # which chains the fused kernel can take depends on the block (L x 8 with 128 needs 8 rows)
+    assert out[False][2]["fused"] == 0
+    for k, (Lx, Lt, beta, m0) in enumerate(shapes):
+        xf, xt = out[True][0][k], out[False][0][k]
+        assert rel(xf, xt) < (1e-10 if prec == "fp64" else 1e-8), k
+        assert abs(out[True][1].iters[k] - out[False][1].iters[k]) <= 3, k
+        xr, _, _ = oracle.cg(qs[k], phis[k], m0, tol=1e-14)
+        assert rel(xf, xr) < (1e-10 if prec == "fp64" else 1e-8), k
+
+
+def test_fused_iteration_runs_where_eligible():
+    b = Batch([(32, 32, 2.0, 0.1), (64, 64, 2.0, 0.1)], persistent=0)
+    b.lat.set_block_size(256)
+    b.lat.set_fused_cg(True)
+    phi = b.spinor_to_native([inputs.random_spinor(32, 32, 5), inputs.random_spinor(64, 64, 6)])
+    b.lat.set_timing(True)
+    b.lat.cg_solve(phi, tol=1e-10, prec="mixed")
+    assert b.lat.kernel_stats(0)["fused"] == 1 and b.lat.kernel_stats(0)["timed_launches"] > 0
+    # 34 x 34 at block 256: Lx/2 = 17 does not divide 128 and the chain needs two workgroups
+    b2 = Batch([(34, 34, 2.0, 0.1)], persistent=0)
+    b2.lat.set_block_size(256)
+    b2.lat.set_fused_cg(True)
+    b2.lat.set_timing(True)
+    b2.lat.cg_solve(b2.spinor_to_native([inputs.random_spinor(34, 34, 7)]), tol=1e-10)
+    assert b2.lat.kernel_stats(0)["fused"] == 0
 
 
 def test_cg_iterations_on_a_chain_above_2048_workgroups():
