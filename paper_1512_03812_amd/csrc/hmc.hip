@@ -104,7 +104,7 @@ struct hmc_ctx {
     size_t off_chains = 0, off_work = 0, off_active = 0, off_big = 0, off_small = 0, off_cg = 0,
            off_partials = 0, off_samples = 0, off_sample_sums = 0, off_trajc = 0, off_log = 0,
            off_sums = 0, off_fin = 0, off_metro = 0, off_status = 0, off_count = 0, off_links[kNumLinkBufs] = {},
-           off_spin[kNumSpinBufs] = {}, off_U64 = 0, off_U32 = 0, off_spin32[kNumSpin32Bufs] = {},
+           off_spin[kNumSpinBufs] = {}, off_U64 = 0, off_A32 = 0, off_spin32[kNumSpin32Bufs] = {},
            off_Uw = 0;
     // ------------------------------------------------------------ solver partition
     hipStream_t side = nullptr;           // second stream for the persistent solver
@@ -134,7 +134,7 @@ struct hmc_ctx {
     float4 *spin32(int b) const { return at<float4>(off_spin32[b]); }
     double2 *U64() const { return at<double2>(off_U64); }
     double2 *Uw() const { return at<double2>(off_Uw); }
-    float2 *U32() const { return at<float2>(off_U32); }
+    float *A32() const { return at<float>(off_A32); }
     CGState *cg() const { return at<CGState>(off_cg); }
     double *sums() const { return at<double>(off_sums); }
     Geo geo() const {
@@ -236,7 +236,7 @@ void layout_workspace(hmc_ctx *c, size_t N) {
     for (int b = 0; b < kNumLinkBufs; ++b) c->off_links[b] = take(sizeof(double) * 2 * V);
     for (int b = 0; b < kNumSpinBufs; ++b) c->off_spin[b] = take(sizeof(double2) * 2 * V);
     c->off_U64 = take(sizeof(double2) * 2 * V);
-    c->off_U32 = take(sizeof(float2) * 2 * V);
+    c->off_A32 = take(sizeof(float) * 2 * V);
     c->off_Uw = take(sizeof(double2) * 2 * V);
     for (int b = 0; b < kNumSpin32Bufs; ++b) c->off_spin32[b] = take(sizeof(float4) * V);
     c->ws_bytes = o;
@@ -309,7 +309,7 @@ void ensure_links(hmc_ctx *c, const double *q, bool need32, long version) {
     const bool have64 = version >= 0 && c->links_version == version;
     const bool have32 = version >= 0 && c->links32_version == version;
     if (have64 && (!need32 || have32)) return;
-    launch_make_links(c->geo(), q, c->U64(), need32 ? c->U32() : nullptr, c->stream);
+    launch_make_links(c->geo(), q, c->U64(), need32 ? c->A32() : nullptr, c->stream);
     c->links_version = version;
     c->links32_version = need32 ? version : -1;
 }
@@ -456,7 +456,7 @@ size_t fused_lds(hmc_ctx *c, int vmax, bool mixed) {
     return lds;
 }
 
-// CG on D^dagger D x = phi with the links already materialised (U64, and U32 if mixed).
+// CG on D^dagger D x = phi with the links already materialised (U64, and the FP32 angles if mixed).
 // Per-chain results land in c->cg_host.  Returns HMC_E_NOCONV if a chain did not converge.
 // Every check_every slots the host reads back how many workgroups still belong to
 // unconverged chains and launches only those from then on.
@@ -474,7 +474,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     f.r32 = c->spin32(FR);
     f.t32 = c->spin32(FT);
     f.U64 = c->U64();
-    f.U32 = c->U32();
+    f.A32 = c->A32();
     f.p1 = c->partials();
     f.p2 = c->partials() + full.nlog;
     f.fin1 = c->at<double>(c->off_fin);
@@ -538,7 +538,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
             fi.p[0] = c->spin(SPA); fi.p[1] = c->spin(SPB);
         }
         fi.U64 = c->U64();
-        fi.U32 = c->U32();
+        fi.A32 = c->A32();
         fi.Q = c->partials();
         fi.st = c->cg();
         fi.samples = f.samples;

@@ -12,6 +12,8 @@
 // the host needs go through a one-workgroup-per-chain finalize kernel.
 #include <math.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace shmc {
@@ -117,25 +119,47 @@ __device__ __forceinline__ Nbr neighbours(const ChainInfo &ci, const Site &s) {
     return n;
 }
 
+// The four links of the stencil at one site: U_x(n), U_t(n), U_x(n - x), U_t(n - t).
+template <typename C> struct SiteLinks { C xf, tf, xb, tb; };
+
+// Links of the FP32 stencil: one FP32 angle per link (the fermion boundary sign folded in as
+// an added pi, wrapped to [-pi, pi]); U = cos + i sin is formed where the link is used, so
+// the FP32 solver reads 4 bytes per link instead of 8.
+struct LinkA32 {
+    const float *A;
+};
+__device__ __forceinline__ float2 link_at(LinkA32 L, int i) {
+    float sn, cs;
+    __sincosf(L.A[i], &sn, &cs);
+    return make_float2(cs, sn);
+}
+template <typename C> __device__ __forceinline__ C link_at(const C *__restrict__ U, int i) {
+    return U[i];
+}
+
+// The links a solver of the given precision reads: FP64 complex links, or FP32 angles.
+typedef const double2 *__restrict__ Link64;
+template <bool MIXED> using LinkSrc = typename std::conditional<MIXED, LinkA32, Link64>::type;
+template <bool MIXED, typename F> __device__ __forceinline__ LinkSrc<MIXED> link_source(const F &f) {
+    if constexpr (MIXED) return LinkA32{f.A32};
+    else return f.U64;
+}
+
+template <typename Src>
+__device__ __forceinline__ auto site_links(Src U, const Nbr &nb, int flat, int Vtot) {
+    SiteLinks<decltype(link_at(U, 0))> l;
+    l.xf = link_at(U, flat);
+    l.tf = link_at(U, Vtot + flat);
+    l.xb = link_at(U, nb.xm);
+    l.tb = link_at(U, Vtot + nb.tm);
+    return l;
+}
+
 // (D a)(n) or (D^dagger a)(n) at one site, Sec. 3.  own0/own1: a(n); load(f, b0, b1)
 // fetches a at flat index f.  The hopping projectors (1 -/+ sigma_mu) have rank one:
 //   (1 + s sigma_1) v = (w, s w)     with w = v0 + s v1
 //   (1 + s sigma_2) v = (w, s i w)   with w = v0 - s i v1
 // D uses s = -1 on the forward hop and s = +1 on the backward hop; D^dagger the reverse.
-// The four links of the stencil at one site: U_x(n), U_t(n), U_x(n - x), U_t(n - t).
-template <typename C> struct SiteLinks { C xf, tf, xb, tb; };
-
-template <typename C>
-__device__ __forceinline__ SiteLinks<C> site_links(const C *__restrict__ U, const Nbr &nb, int flat,
-                                                   int Vtot) {
-    SiteLinks<C> l;
-    l.xf = U[flat];
-    l.tf = U[Vtot + flat];
-    l.xb = U[nb.xm];
-    l.tb = U[Vtot + nb.tm];
-    return l;
-}
-
 template <typename T, bool DAG, typename Load>
 __device__ __forceinline__ void dslash_site_links(const Nbr &nb, const SiteLinks<cplx_t<T>> &lk,
                                                   cplx_t<T> own0, cplx_t<T> own1, T mass, Load load,
@@ -158,11 +182,10 @@ __device__ __forceinline__ void dslash_site_links(const Nbr &nb, const SiteLinks
     o1 = csub(cscale(own1, mass), cscale(sum1, T(0.5)));
 }
 
-template <typename T, bool DAG, typename Load>
-__device__ __forceinline__ void dslash_site(const Nbr &nb, int flat, int Vtot,
-                                            const cplx_t<T> *__restrict__ U, cplx_t<T> own0,
-                                            cplx_t<T> own1, T mass, Load load, cplx_t<T> &o0,
-                                            cplx_t<T> &o1) {
+template <typename T, bool DAG, typename Load, typename Src>
+__device__ __forceinline__ void dslash_site(const Nbr &nb, int flat, int Vtot, Src U,
+                                            cplx_t<T> own0, cplx_t<T> own1, T mass, Load load,
+                                            cplx_t<T> &o0, cplx_t<T> &o1) {
     dslash_site_links<T, DAG>(nb, site_links(U, nb, flat, Vtot), own0, own1, mass, load, o0, o1);
 }
 
@@ -268,21 +291,24 @@ void launch_pack_spinor(const Geo &g, double2 *lex, double2 *nat, bool to_native
 // U_mu(n) = exp(i q_mu(n)); the t-link leaving the last time slice carries the
 // antiperiodic fermion boundary sign.
 __global__ void k_make_links(Geo g, const double *__restrict__ q, double2 *__restrict__ U64,
-                             float2 *__restrict__ U32) {
+                             float *__restrict__ A32) {
     SITES_BEGIN
     const Site s = decode_site(ci, local);
     for (int mu = 0; mu < 2; ++mu) {
+        const double th = q[(size_t)mu * Vtot + s.flat];
+        const bool bc = mu == 1 && s.t == ci.Lt - 1;
         double sn, cs;
-        sincos(q[(size_t)mu * Vtot + s.flat], &sn, &cs);
-        if (mu == 1 && s.t == ci.Lt - 1) { sn = -sn; cs = -cs; }
+        sincos(th, &sn, &cs);
+        if (bc) { sn = -sn; cs = -cs; }
         U64[(size_t)mu * Vtot + s.flat] = make_double2(cs, sn);
-        if (U32) U32[(size_t)mu * Vtot + s.flat] = make_float2((float)cs, (float)sn);
+        // FP32 angle: the boundary sign as +pi, wrapped in FP64 before rounding
+        if (A32) A32[(size_t)mu * Vtot + s.flat] = (float)remainder(bc ? th + M_PI : th, 2.0 * M_PI);
     }
     SITES_END
 }
 
-void launch_make_links(const Geo &g, const double *q, double2 *U64, float2 *U32, hipStream_t s) {
-    hipLaunchKernelGGL(k_make_links, dim3(g.nblocks), dim3(g.block), 0, s, g, q, U64, U32);
+void launch_make_links(const Geo &g, const double *q, double2 *U64, float *A32, hipStream_t s) {
+    hipLaunchKernelGGL(k_make_links, dim3(g.nblocks), dim3(g.block), 0, s, g, q, U64, A32);
 }
 
 // ================================================================ Dirac operator
@@ -378,9 +404,9 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
     const S *__restrict__ r;
     S *__restrict__ t;
     S *__restrict__ x;
-    const C *__restrict__ U;
-    if constexpr (MIXED) { r = f.r32; t = f.t32; x = f.x32; U = f.U32; }
-    else { r = f.r64; t = f.t64; x = f.x64; U = f.U64; }
+    if constexpr (MIXED) { r = f.r32; t = f.t32; x = f.x32; }
+    else { r = f.r64; t = f.t64; x = f.x64; }
+    const LinkSrc<MIXED> U = link_source<MIXED>(f);
     const int half = (int)blockDim.x >> 1;
     const int par = (int)threadIdx.x >= half ? 1 : 0;
     const int i = w.start + (int)threadIdx.x - par * half;
@@ -563,9 +589,9 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
     }
     const S *__restrict__ t;
     S *__restrict__ r;
-    const C *__restrict__ U;
-    if constexpr (MIXED) { t = f.t32; r = f.r32; U = f.U32; }
-    else { t = f.t64; r = f.r64; U = f.U64; }
+    if constexpr (MIXED) { t = f.t32; r = f.r32; }
+    else { t = f.t64; r = f.r64; }
+    const LinkSrc<MIXED> U = link_source<MIXED>(f);
     // The own site's t, r and links are loaded before the chain total, so their latency
     // overlaps its partial loads.  t is staged in LDS for the neighbours inside the
     // workgroup (one site per thread: the tables use w.spt == 1).
@@ -752,9 +778,9 @@ __global__ void k_cg_iter(Geo g, CGIterFields f, int slot, double tol2, int deci
     const S *__restrict__ s_old = (const S *)f.s[buf];
     const S *__restrict__ p_old = (const S *)f.p[buf];
     S *__restrict__ x;
-    const C *__restrict__ U;
-    if constexpr (MIXED) { x = f.x32; U = f.U32; }
-    else { x = f.x64; U = f.U64; }
+    if constexpr (MIXED) x = f.x32;
+    else x = f.x64;
+    const LinkSrc<MIXED> U = link_source<MIXED>(f);
     const int hx = ci.hx, Lx = ci.Lx, Lt = ci.Lt, Vh = ci.Vh;
     const int half = (int)blockDim.x >> 1;
     const int par = (int)threadIdx.x >= half ? 1 : 0;
@@ -765,10 +791,10 @@ __global__ void k_cg_iter(Geo g, CGIterFields f, int slot, double tol2, int deci
         const int xm = xs == 0 ? Lx - 1 : xs - 1, tm = t == 0 ? Lt - 1 : t - 1;
         const int fl = ci.off + P * Vh + t * hx + xh;
         SiteLinks<C> l;
-        l.xf = U[fl];
-        l.tf = U[Vtot + fl];
-        l.xb = U[ci.off + (1 - P) * Vh + t * hx + (xm >> 1)];
-        l.tb = U[Vtot + ci.off + (1 - P) * Vh + tm * hx + xh];
+        l.xf = link_at(U, fl);
+        l.tf = link_at(U, Vtot + fl);
+        l.xb = link_at(U, ci.off + (1 - P) * Vh + t * hx + (xm >> 1));
+        l.tb = link_at(U, Vtot + ci.off + (1 - P) * Vh + tm * hx + xh);
         return l;
     };
     // own site and its operands, loaded before the chain totals
@@ -1083,8 +1109,7 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
     const int V = ci.V, Vtot = g.Vtot, off = ci.off;
     C *ps = (C *)smem_d;  // [2][V]
     C *ts = ps + 2 * V;   // [2][V]
-    const C *__restrict__ U;
-    if constexpr (MIXED) U = f.U32; else U = f.U64;
+    const LinkSrc<MIXED> U = link_source<MIXED>(f);
     const R mass = (R)(2.0 + ci.m0);
 
     Nbr nb[SPT];

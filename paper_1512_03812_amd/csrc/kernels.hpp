@@ -51,24 +51,25 @@ constexpr int kMaxSamples = 256;
 // previous iteration's x update.
 //   FP64 solver   step 1: r 32 + p_old 32 + U 32 + x 32 read, p 32 + t 32 + x 32 = 224
 //                 step 2: t 32 + U 32 + r 32 read, r 32 written                  = 128
-//   mixed, FP32   step 1: r 16 + p_old 16 + U 16 + x 16 read, p 16 + t 16 + x 16 = 112
-//                 step 2: t 16 + U 16 + r 16 read, r 16 written                  =  64
+//   mixed, FP32   step 1: r 16 + p_old 16 + U 8 + x 16 read, p 16 + t 16 + x 16  = 104
+//                 step 2: t 16 + U 8 + r 16 read, r 16 written                   =  56
+//                 (U: the two FP32 link angles of the site)
 //   mixed, FP64 residual recomputation
 //                 step 1: x64 32 + x32 16 + p_old 16 + U64 32 read, t64 32 + p 16 = 144
 //                 step 2: t64 32 + U64 32 + phi 32 + x64 32 + x32 16 + p 16 read,
 //                         x64 32 + x32 16 + r32 16 written                      = 224
 // (The first slot of a solve reads neither p_old nor x; it is counted like the others.)
 constexpr double kBytesFp64Step1 = 224.0, kBytesFp64Step2 = 128.0;
-constexpr double kBytesFp32Step1 = 112.0, kBytesFp32Step2 = 64.0;
+constexpr double kBytesFp32Step1 = 104.0, kBytesFp32Step2 = 56.0;
 constexpr double kBytesUpdateStep1 = 144.0, kBytesUpdateStep2 = 224.0;
 // The fused iteration (one kernel per CG iteration):
 //   normal slot, FP64  : r, s, p, x 4 x 32 + U 32 read, r, s, p, x 4 x 32 written = 288
-//   normal slot, FP32  : r, s, p, x 4 x 16 + U 16 read, r, s, p, x 4 x 16 written = 144
+//   normal slot, FP32  : r, s, p, x 4 x 16 + U 8 read, r, s, p, x 4 x 16 written  = 136
 //   mixed, residual recomputation, first slot : x64 32 + x32 16 + U64 32 read,
 //                                                t64 32 written                   = 112
 //                                  second slot: t64 32 + U64 32 + phi 32 + x64 32 + x32 16
 //                                                + s 16 read, x64 32 + x32 16 + r 16  = 224
-constexpr double kBytesIterFp64 = 288.0, kBytesIterFp32 = 144.0;
+constexpr double kBytesIterFp64 = 288.0, kBytesIterFp32 = 136.0;
 constexpr double kBytesIterUpdate1 = 112.0, kBytesIterUpdate2 = 224.0;
 
 // Partial sums: row k of partials holds one double per logical workgroup.
@@ -84,8 +85,8 @@ void launch_pack_spinor(const Geo &g, double2 *lex, double2 *nat, bool to_native
 
 // ---------------------------------------------------------------- links
 // U = exp(i q) with the antiperiodic sign on the t-links leaving the last time slice;
-// U32 (may be null) receives the FP32 copy.
-void launch_make_links(const Geo &g, const double *q, double2 *U64, float2 *U32, hipStream_t s);
+// A32 (may be null) receives the FP32 angles of the mixed-precision solver.
+void launch_make_links(const Geo &g, const double *q, double2 *U64, float *A32, hipStream_t s);
 
 // ---------------------------------------------------------------- Dirac operator
 void launch_dslash64(const Geo &g, const double2 *U, const double2 *in, double2 *out, bool dagger,
@@ -98,7 +99,7 @@ struct CGFields {
     double2 *r64, *t64;       // FP64 residual and D p (FP64 solver); t64 is also the mixed scratch
     float4 *x32, *r32, *t32;  // mixed: FP32 partial solution, residual, D p (one float4 per site)
     const double2 *U64;
-    const float2 *U32;
+    const float *A32;  // FP32 link angles [2][Vtot] (boundary sign folded in as +pi)
     double *p1, *p2;          // partial rows: ||D p||^2 (step 1) and ||r||^2 (step 2)
     double *fin1, *fin2;      // per-chain totals of p1, p2 for chains above kMaxChainBlocks
     CGState *st;              // [2][nchains]
@@ -134,7 +135,7 @@ struct CGIterFields {
     float4 *x32;      // mixed: FP32 solution increment since the last recomputation
     void *r[2], *s[2], *p[2];  // two buffers each, FP32 float4 (mixed) or FP64 double2 SoA
     const double2 *U64;
-    const float2 *U32;
+    const float *A32;  // FP32 link angles [2][Vtot] (boundary sign folded in as +pi)
     double *Q;        // partial rows [2 slot parities][4][nlog]
     CGState *st;      // [2][nchains]
     double *samples;  // as CGFields::samples
