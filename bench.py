@@ -511,7 +511,7 @@ def main():
                     help="exploration: every chain of the batch L x L (not the benchmark workload)")
     ap.add_argument("--check-interval", type=int, default=32,
                     help="CG slots between convergence checks (workgroup compaction)")
-    ap.add_argument("--reliable-delta", type=float, default=1e-3,
+    ap.add_argument("--reliable-delta", type=float, default=1e-4,
                     help="mixed CG: FP64 residual recomputation when the FP32 residual has dropped "
                          "by this factor")
     ap.add_argument("--cg-kernels", choices=["fused", "two"], default="two",

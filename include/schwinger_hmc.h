@@ -168,7 +168,7 @@ uint32_t hmc_get_trajectory_counter(const hmc_ctx *ctx);
 
 /* Solver tolerance and iteration cap used inside hmc_trajectory (default 1e-12, 100000).
  * reliable_delta: in mixed precision, the FP64 residual is recomputed whenever the
- * FP32 residual has dropped by this factor (default 1e-3). */
+ * FP32 residual has dropped by this factor (default 1e-4). */
 int hmc_set_solver(hmc_ctx *ctx, double tol, int max_iter, double reliable_delta);
 
 /* Drop the fermion action (pure-gauge HMC; used to check the gauge part against the exact

@@ -227,7 +227,7 @@ class Lattice:
     def hot_start(self):
         self._check(self._lib.hmc_hot_start(self._ctx))
 
-    def set_solver(self, tol=1e-12, max_iter=100000, reliable_delta=1e-3):
+    def set_solver(self, tol=1e-12, max_iter=100000, reliable_delta=1e-4):
         self._check(self._lib.hmc_set_solver(self._ctx, tol, max_iter, reliable_delta))
 
     def set_quenched(self, quenched: bool):

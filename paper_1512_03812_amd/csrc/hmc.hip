@@ -84,7 +84,7 @@ struct hmc_ctx {
     // ------------------------------------------------------------ solver settings
     double tol = 1e-12;
     int max_iter = 100000;
-    double delta = 1e-3;
+    double delta = 1e-4;
     int check_every = 32;
     bool quenched = false;
     int fg_mode = HMC_FG_SHIFT;
