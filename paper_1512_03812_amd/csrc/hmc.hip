@@ -31,15 +31,17 @@ enum Spin32Buf { FX, FR, FT, FPA, FPB, FR2, FS2, kNumSpin32Bufs };
 }  // namespace
 
 // Sampled event timing of the two CG step kernels (kernel index 0: step 1, 1: step 2).
-// Every sample_every-th iteration slot is bracketed by HIP events.  Step 1 of that slot
-// writes, for each chain it iterates, the algorithmic bytes of both steps (the chain's
-// sites times the bytes per site of the slot's mode) into a device row; at the end of the
-// solve one reduction sums the rows and a single copy brings the sums to the host, so the
-// bytes of exactly those launches are attributed to the measured durations with no copy
-// inside the iteration loop.
+// In every sample_every-th iteration slot each kernel is launched with a start and an end
+// event that its own dispatch stamps (no marker packets, so the durations are the kernels'
+// own).  Step 1 of that slot writes, for each chain it iterates, the algorithmic bytes of
+// both steps (the chain's sites times the bytes per site of the slot's mode) into a device
+// row; at the end of the solve one reduction sums the rows and a single copy brings the
+// sums to the host, so the bytes of exactly those launches are attributed to the measured
+// durations with no copy inside the iteration loop.
 struct TimedSlot {
-    hipEvent_t ev[3];
-    int sample;  // row of the device byte table
+    hipEvent_t ev[4];  // step 1 start, end; step 2 start, end
+    int sample;        // row of the device byte table
+    bool two;          // step 2 was launched (not the fused iteration)
 };
 
 struct KernelTimer {
@@ -363,21 +365,25 @@ void timer_flush(hmc_ctx *c) {
     for (const TimedSlot &ts : T.pending) {
         float a = 0.f, b = 0.f;
         if (hipEventElapsedTime(&a, ts.ev[0], ts.ev[1]) != hipSuccess) continue;
-        if (hipEventElapsedTime(&b, ts.ev[1], ts.ev[2]) != hipSuccess) continue;
+        if (ts.two && hipEventElapsedTime(&b, ts.ev[2], ts.ev[3]) != hipSuccess) continue;
         T.ms[0] += a;
-        T.ms[1] += b;
         T.bytes[0] += T.sums_host[2 * ts.sample];
-        T.bytes[1] += T.sums_host[2 * ts.sample + 1];
         T.timed[0]++;
-        T.timed[1]++;
+        if (ts.two) {
+            T.ms[1] += b;
+            T.bytes[1] += T.sums_host[2 * ts.sample + 1];
+            T.timed[1]++;
+        }
     }
     T.pending.clear();
     T.pool_used = 0;
 }
 
-// One CG slot (step 1 + step 2); a sampled slot is bracketed by events and its step 1
-// records the bytes of both steps in the row given to it (-1: not sampled).
-template <typename L1, typename L2> void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2) {
+// One CG slot (step 1 + step 2, or the fused iteration with no step 2); in a sampled slot
+// each kernel gets its start and end events and step 1 records the bytes of both steps in
+// the row given to it (-1: not sampled).
+template <typename L1, typename L2>
+void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2, bool two = true) {
     KernelTimer &T = c->timer;
     if (T.on) T.launches++;
     // Sampled slots sit mid-way between the convergence checks, a few slots after the host
@@ -386,18 +392,16 @@ template <typename L1, typename L2> void slot_launch(hmc_ctx *c, int slot, L1 st
     const int since = T.since_sync++;
     if (!T.on || slot % T.sample_every != T.sample_every / 2 || since < 2 ||
         (int)T.pending.size() == kMaxSamples || !T.sums_host) {
-        step1(-1);
-        step2();
+        step1(-1, nullptr, nullptr);
+        if (two) step2(nullptr, nullptr);
         return;
     }
     TimedSlot ts;
-    for (int k = 0; k < 3; ++k) ts.ev[k] = timer_event(c);
+    for (int k = 0; k < 4; ++k) ts.ev[k] = timer_event(c);
     ts.sample = (int)T.pending.size();
-    (void)hipEventRecord(ts.ev[0], c->stream);
-    step1(ts.sample);
-    (void)hipEventRecord(ts.ev[1], c->stream);
-    step2();
-    (void)hipEventRecord(ts.ev[2], c->stream);
+    ts.two = two;
+    step1(ts.sample, ts.ev[0], ts.ev[1]);
+    if (two) step2(ts.ev[2], ts.ev[3]);
     T.pending.push_back(ts);
 }
 
@@ -551,10 +555,11 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
         int interval = c->check_every, next_check = interval, last_active = big.nblocks;
         for (; slot < max_slots; ++slot) {
             slot_launch(c, slot,
-                        [&](int sample) {
-                            launch_cg_iter(g, fi, mixed, slot, tol, false, sample, lds_iter, c->stream);
+                        [&](int sample, hipEvent_t e0, hipEvent_t e1) {
+                            launch_cg_iter(g, fi, mixed, slot, tol, false, sample, lds_iter, c->stream,
+                                           e0, e1);
                         },
-                        [] {});
+                        [](hipEvent_t, hipEvent_t) {}, false);
             if (slot + 1 == next_check) {
                 int active = 0, live = 0;
                 if ((rc = check_convergence(c, big, max_iter, &active, &live))) return rc;
@@ -581,12 +586,12 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     for (; slot < max_slots; ++slot) {
         void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
         slot_launch(c, slot,
-                    [&](int sample) {
-                        launch_cg_step1(g, f, mixed, slot, tol, po, pn, false, sample, c->stream);
+                    [&](int sample, hipEvent_t e0, hipEvent_t e1) {
+                        launch_cg_step1(g, f, mixed, slot, tol, po, pn, false, sample, c->stream, e0, e1);
                         if (c->has_large) launch_finalize_large(big, f.p1, f.fin1, c->stream);
                     },
-                    [&] {
-                        launch_cg_step2(g, f, mixed, slot, pn, c->stream);
+                    [&](hipEvent_t e0, hipEvent_t e1) {
+                        launch_cg_step2(g, f, mixed, slot, pn, c->stream, e0, e1);
                         if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
                     });
         if (slot + 1 == next_check) {

@@ -16,6 +16,8 @@
 
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
+
 namespace shmc {
 
 constexpr int kMaxWaves = kMaxBlock / 64;
@@ -651,16 +653,26 @@ void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, h
     else hipLaunchKernelGGL(k_cg_init<false>, dim3(g.nblocks), dim3(g.block), 0, s, g, f, delta * delta);
 }
 
+// A launch whose start and end are stamped into ev0 and ev1 by the dispatch itself (no
+// marker packets around it), or a plain launch when ev0 is null.
+template <typename K, typename... A>
+static void launch_stamped(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1, A... args) {
+    if (ev0) hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, ev0, ev1, 0u, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
 void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
-                     const void *p_old, void *p_new, bool decide_only, int sample, hipStream_t s) {
+                     const void *p_old, void *p_new, bool decide_only, int sample, hipStream_t s,
+                     hipEvent_t ev0, hipEvent_t ev1) {
     if (mixed)
-        hipLaunchKernelGGL(k_cg_step1<true>, dim3(g.nblocks), dim3(g.block),
-                           g.block * sizeof(LdsSpinor<float2>), s, g, f, slot, tol * tol, p_old,
-                           p_new, decide_only ? 1 : 0, sample);
+        launch_stamped(k_cg_step1<true>, dim3(g.nblocks), dim3(g.block),
+                       g.block * sizeof(LdsSpinor<float2>), s, ev0, ev1, g, f, slot, tol * tol, p_old,
+                       p_new, decide_only ? 1 : 0, sample);
     else
-        hipLaunchKernelGGL(k_cg_step1<false>, dim3(g.nblocks), dim3(g.block),
-                           g.block * sizeof(LdsSpinor<double2>), s, g, f, slot, tol * tol, p_old,
-                           p_new, decide_only ? 1 : 0, sample);
+        launch_stamped(k_cg_step1<false>, dim3(g.nblocks), dim3(g.block),
+                       g.block * sizeof(LdsSpinor<double2>), s, ev0, ev1, g, f, slot, tol * tol, p_old,
+                       p_new, decide_only ? 1 : 0, sample);
 }
 
 // One workgroup per sampled slot: the sum over chains of its byte row, which is then zeroed
@@ -686,13 +698,13 @@ void launch_sample_sums(double *samples, int n, int nchains, double *sums, hipSt
 }
 
 void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
-                     hipStream_t s) {
+                     hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (mixed)
-        hipLaunchKernelGGL(k_cg_step2<true>, dim3(g.nblocks), dim3(g.block),
-                           g.block * sizeof(LdsSpinor<float2>), s, g, f, slot, p_new);
+        launch_stamped(k_cg_step2<true>, dim3(g.nblocks), dim3(g.block),
+                       g.block * sizeof(LdsSpinor<float2>), s, ev0, ev1, g, f, slot, p_new);
     else
-        hipLaunchKernelGGL(k_cg_step2<false>, dim3(g.nblocks), dim3(g.block),
-                           g.block * sizeof(LdsSpinor<double2>), s, g, f, slot, p_new);
+        launch_stamped(k_cg_step2<false>, dim3(g.nblocks), dim3(g.block),
+                       g.block * sizeof(LdsSpinor<double2>), s, ev0, ev1, g, f, slot, p_new);
 }
 
 void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s) {
@@ -1025,13 +1037,14 @@ __global__ void k_cg_iter(Geo g, CGIterFields f, int slot, double tol2, int deci
 }
 
 void launch_cg_iter(const Geo &g, const CGIterFields &f, bool mixed, int slot, double tol,
-                    bool decide_only, int sample, size_t lds_bytes, hipStream_t s) {
+                    bool decide_only, int sample, size_t lds_bytes, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1) {
     if (mixed)
-        hipLaunchKernelGGL(k_cg_iter<true>, dim3(g.nblocks), dim3(g.block), lds_bytes, s, g, f, slot,
-                           tol * tol, decide_only ? 1 : 0, sample);
+        launch_stamped(k_cg_iter<true>, dim3(g.nblocks), dim3(g.block), lds_bytes, s, ev0, ev1, g, f,
+                       slot, tol * tol, decide_only ? 1 : 0, sample);
     else
-        hipLaunchKernelGGL(k_cg_iter<false>, dim3(g.nblocks), dim3(g.block), lds_bytes, s, g, f, slot,
-                           tol * tol, decide_only ? 1 : 0, sample);
+        launch_stamped(k_cg_iter<false>, dim3(g.nblocks), dim3(g.block), lds_bytes, s, ev0, ev1, g, f,
+                       slot, tol * tol, decide_only ? 1 : 0, sample);
 }
 
 int grant_cg_iter_lds(size_t lds_bytes) {

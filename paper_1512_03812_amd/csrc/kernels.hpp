@@ -111,15 +111,17 @@ void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, h
 // the previous slot, apply the previous slot's x += alpha p_old, then p_new = r + beta p_old
 // and t = D p_new with partial ||t||^2 (or, in a reliable-update slot,
 // t64 = D (x64 + x32 + alpha p_old)).  decide_only: state update and the owed x update only.
+// ev0/ev1 (optional): stamped with the kernel's own start and end (timing).
 void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
-                     const void *p_old, void *p_new, bool decide_only, int sample, hipStream_t s);
+                     const void *p_old, void *p_new, bool decide_only, int sample, hipStream_t s,
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // sums[2 b + k] = sum over chains of samples[b][chain][k], b < n; the rows are zeroed.
 void launch_sample_sums(double *samples, int n, int nchains, double *sums, hipStream_t s);
 // Slot k, second kernel: alpha from the partials of step 1 (kept in the state for the next
 // slot's x update), r -= alpha D^dagger t with partial ||r||^2 (or the FP64 residual
 // recomputation, which also folds x32 and the owed alpha p into x64).
 void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
-                     hipStream_t s);
+                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Fused CG iteration: one kernel per iteration for chains whose workgroups own whole
 // lattice rows (see cg_iter_eligible).  Slot k applies the previous iteration's step
 // (r -= alpha s, x += alpha p, with the squared norm of the new residual predicted from the
@@ -146,7 +148,8 @@ bool cg_iter_eligible(const ChainInfo &ci, int block, int *lds_entries);
 // Dynamic LDS bytes of the fused iteration for `entries` spinor entries.
 size_t cg_iter_lds_bytes(int entries, bool mixed);
 void launch_cg_iter(const Geo &g, const CGIterFields &f, bool mixed, int slot, double tol,
-                    bool decide_only, int sample, size_t lds_bytes, hipStream_t s);
+                    bool decide_only, int sample, size_t lds_bytes, hipStream_t s,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Lets both instantiations use lds_bytes of dynamic LDS; -1 if the device refuses.
 int grant_cg_iter_lds(size_t lds_bytes);
 
