@@ -197,7 +197,7 @@ def run_precision(args, sizes, n_traj, n_therm):
 def cpu_baseline(args):
     """The oracle (plain FP64 C, one thread) on a bounded, stratified sample of the workload:
     full oracle trajectories (adapted nested FG, tau 1, 8 x 4, CG to 1e-10) from the hot
-    start of the first 4 chains with L = 16, the first 3 with L = 32 and the first 2 with
+    start of the first 6 chains with L = 16, the first 4 with L = 32 and the first 3 with
     L = 64; for L = 128 one fermion-force solve at its hot start, scaled by the
     trajectory/solve time ratio measured on the L = 64 chain.  Per-size mean times are
     weighted by the workload's count of chains of each size."""
@@ -216,7 +216,7 @@ def cpu_baseline(args):
         oracle.fermion_force(q, phi, m0[c], tol=1e-10)
         return time.perf_counter() - t0
 
-    for Ls, k in ((16, 4), (32, 3), (64, 2)):
+    for Ls, k in ((16, 6), (32, 4), (64, 3)):
         ts = []
         for c in first(Ls, k):
             q = oracle.random_links(Ls, Ls, args.seed, c)
@@ -234,8 +234,8 @@ def cpu_baseline(args):
     sample_s = time.perf_counter() - t_begin
     return {"value": round(len(L) / total, 4), "unit": "chain-trajectories/s", "cores": 1,
             "kind": "oracle",
-            "sample": ("full oracle trajectories from the hot start of the first 4 L=16, 3 L=32 and "
-                       "2 L=64 chains; L=128 from one oracle solve times the trajectory/solve ratio "
+            "sample": ("full oracle trajectories from the hot start of the first 6 L=16, 4 L=32 and "
+                       "3 L=64 chains; L=128 from one oracle solve times the trajectory/solve ratio "
                        f"({ratio:.1f}) of the L=64 chain; weighted by the workload's L counts; "
                        f"sample CPU time {sample_s:.1f} s"),
             "seconds_per_chain_traj_by_L": {str(k): round(v, 3) for k, v in per_L.items()}}
