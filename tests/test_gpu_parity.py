@@ -753,6 +753,47 @@ def test_precision_workload_matches_oracle_trajectories(L):
             assert r.n_dinv == ref["n_dinv"]
 
 
+# ------------------------------------------------------------------ exact physics of the batch
+def test_batched_quenched_plaquette_is_exact():
+    """Quenched 2-D U(1) on 4 x 4 tori, 128 chains advanced together: the mean plaquette
+    against the character-expansion value (pinned independently of the oracle)."""
+    from tests.test_oracle_pins import exact_mean_plaquette
+    n, beta = 128, 2.0
+    b = Batch([(4, 4, beta, 0.1)] * n, seed=555)
+    b.lat.hot_start()
+    b.lat.set_quenched(True)
+    per_chain = np.zeros(n)
+    for t in range(140):
+        r = b.lat.trajectory("omelyan", 1.0, 5, 1)
+        assert all(st == 0 for st in r.status)
+        if t >= 40:
+            per_chain += np.array(r.plaquette)
+    per_chain /= 100
+    mean = per_chain.mean()
+    err = per_chain.std(ddof=1) / math.sqrt(n)
+    exact = exact_mean_plaquette(beta, 16)
+    assert abs(mean - exact) < 4 * err + 1e-4, (mean, exact, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_creutz_equality(prec):
+    """<exp(-Delta H)> = 1 over equilibrium chains: 64 chains of 8 x 8 (beta 2, m0 0.2),
+    adapted nested FG tau 1, 4 x 2 steps, 30 trajectories after 20 of thermalisation."""
+    n = 64
+    b = Batch([(8, 8, 2.0, 0.2)] * n, seed=777)
+    b.lat.hot_start()
+    b.lat.set_solver(tol=1e-12 if prec == "fp64" else 1e-10)
+    vals = np.zeros(n)
+    for t in range(50):
+        r = b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2, prec=prec)
+        assert all(st == 0 for st in r.status)
+        if t >= 20:
+            vals += np.exp(-np.array(r.dH))
+    vals /= 30
+    err = vals.std(ddof=1) / math.sqrt(n)
+    assert abs(vals.mean() - 1.0) < 4 * err + 1e-3, (vals.mean(), err)
+
+
 # ------------------------------------------------------------------ autograd form
 def test_autograd_action_gradient_matches_finite_differences_and_oracle():
     m = hmc()
