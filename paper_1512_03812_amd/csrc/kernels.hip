@@ -49,14 +49,28 @@ template <int NV> __device__ __forceinline__ void block_sum_all(double (&v)[NV])
     __syncthreads();
 }
 
-// One partial per workgroup into row k of partials (k < NV).
+// One partial per workgroup into row k of partials (k < NV).  It ends its kernel (every
+// caller's last use of LDS), so one barrier suffices: the wavefront sums meet in LDS and
+// thread 0 adds them in a fixed order.
 template <int NV>
 __device__ __forceinline__ void write_partials(double (&v)[NV], double *partials, int nlog,
                                                int logical) {
-    block_sum_all<NV>(v);
+    __shared__ double wsum[NV][kMaxWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) wsum[k][wave] = v[k];
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) partials[(size_t)k * nlog + logical] = v[k];
+        for (int k = 0; k < NV; ++k) {
+            double a = 0.0;
+            for (int w = 0; w < nw; ++w) a += wsum[k][w];
+            partials[(size_t)k * nlog + logical] = a;
+        }
     }
 }
 
