@@ -1334,7 +1334,7 @@ int launch_cg_wg(const Geo &g, const CGFields &f, bool mixed, const int *chains,
 // right after convergence, so its other parity may still hold the state before it).
 // count[1] receives the number of unconverged chains that still have iterations left
 // (iters < max_iter).
-__global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGState *__restrict__ st,
+__global__ void k_compact(const BlockWork *__restrict__ work, int n, CGState *__restrict__ st,
                           const ChainInfo *__restrict__ chains, int nchains, int max_iter,
                           BlockWork *__restrict__ out, int *count) {
     __shared__ int wave_cnt[kMaxWaves];
@@ -1377,10 +1377,18 @@ __global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGSta
     double live[1] = {0.0};
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int c = work[i].chain;
-        if (work[i].logical != chains[c].block0) continue;  // count each chain once
-        if (!st[c].converged && !st[nchains + c].converged &&
-            (st[c].iters < max_iter || st[nchains + c].iters < max_iter))
+        if (work[i].logical != chains[c].block0) continue;  // each chain once
+        const int c0 = st[c].converged, c1 = st[nchains + c].converged;
+        if (!c0 && !c1 && (st[c].iters < max_iter || st[nchains + c].iters < max_iter))
             live[0] += 1.0;
+        // A chain that converged in the last slot before this check is dropped with only that
+        // slot's parity marked; the other parity still holds the state one slot earlier.
+        // Copying the final state over it keeps the chain's decision, owed x update included,
+        // from being taken again by a later launch that reads that parity.
+        if (c0 != c1) {
+            if (c0) st[nchains + c] = st[c];
+            else st[c] = st[nchains + c];
+        }
     }
     block_sum_all<1>(live);
     if (threadIdx.x == 0) {
@@ -1389,7 +1397,7 @@ __global__ void k_compact(const BlockWork *__restrict__ work, int n, const CGSta
     }
 }
 
-void launch_compact(const Geo &full, const CGState *st, int max_iter, BlockWork *out, int *count,
+void launch_compact(const Geo &full, CGState *st, int max_iter, BlockWork *out, int *count,
                     hipStream_t s) {
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, full.work, full.nblocks, st,
                        full.chains, full.nchains, max_iter, out, count);

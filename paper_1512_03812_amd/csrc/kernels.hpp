@@ -158,8 +158,9 @@ void launch_finalize_large(const Geo &g, const double *row, double *fin, hipStre
 // x64 += x32 (end of a mixed solve).
 void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s);
 // Workgroups of chains not yet converged (st: both state parities) -> out[0..count[0]);
-// count[1] = unconverged chains with iterations left (< max_iter).
-void launch_compact(const Geo &full, const CGState *st, int max_iter, BlockWork *out, int *count,
+// count[1] = unconverged chains with iterations left (< max_iter).  A chain converged in one
+// parity only gets its final state copied into the other.
+void launch_compact(const Geo &full, CGState *st, int max_iter, BlockWork *out, int *count,
                     hipStream_t s);
 // Persistent solver: one workgroup per chain of chains[0..n), each with at most vmax sites
 // (LDS holds p and t: 4 * vmax complex).  Returns -1 if vmax does not fit.

@@ -243,6 +243,32 @@ def test_fused_and_two_kernel_iterations_agree(prec, block):
         assert rel(xf, xr) < (1e-10 if prec == "fp64" else 1e-8), k
 
 
+@pytest.mark.parametrize("prec,fused", [("fp64", False), ("mixed", False), ("fp64", True),
+                                        ("mixed", True)])
+def test_solution_does_not_depend_on_the_check_interval(prec, fused):
+    """The CG iterates of a chain do not depend on when the host compacts the workgroup list:
+    the same bits for every check interval, also for chains that converge in the last slot
+    before a check."""
+    shapes = [(16, 16, 2.0, 0.1), (32, 32, 1.5, 0.05), (64, 16, 3.0, 0.2), (8, 8, 1.0, 0.3),
+              (32, 16, 2.0, 0.15), (16, 32, 2.5, 0.08)]
+    b = Batch(shapes, persistent=0)
+    b.lat.set_fused_cg(fused)
+    b.set_q([inputs.random_angles(Lx, Lt, 500 + k) for k, (Lx, Lt, _, _) in enumerate(shapes)])
+    phi = b.spinor_to_native([inputs.random_spinor(Lx, Lt, 600 + k)
+                              for k, (Lx, Lt, _, _) in enumerate(shapes)])
+    ref = None
+    for every in (32, 1, 2, 3, 5, 7):
+        b.lat.set_check_interval(every)
+        x, res = b.lat.cg_solve(phi, tol=1e-12 if prec == "fp64" else 1e-10, prec=prec)
+        assert all(res.converged)
+        got = (x.cpu().numpy().copy(), list(res.iters))
+        if ref is None:
+            ref = got
+        else:
+            assert got[1] == ref[1], (every, got[1], ref[1])
+            assert np.array_equal(got[0], ref[0]), every
+
+
 def test_fused_iteration_runs_where_eligible():
     b = Batch([(32, 32, 2.0, 0.1), (64, 64, 2.0, 0.1)], persistent=0)
     b.lat.set_block_size(256)
