@@ -72,6 +72,7 @@ def run_batched(args):
     lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
     lat.set_check_interval(args.check_interval)
     lat.set_fused_cg(args.cg_kernels == "fused")
+    lat.set_cg_groups(args.cg_groups)
     if args.block:
         lat.set_block_size(args.block)
     tune = None
@@ -514,6 +515,8 @@ def main():
     ap.add_argument("--reliable-delta", type=float, default=1e-4,
                     help="mixed CG: FP64 residual recomputation when the FP32 residual has dropped "
                          "by this factor")
+    ap.add_argument("--cg-groups", type=int, choices=[1, 2], default=1,
+                    help="sets of chains whose CG kernels run concurrently on two streams")
     ap.add_argument("--cg-kernels", choices=["fused", "two"], default="two",
                     help="one fused kernel per CG iteration where the chains allow it, or two")
     ap.add_argument("--persistent-limit", type=int, default=0,

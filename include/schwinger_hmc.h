@@ -185,6 +185,16 @@ int hmc_set_check_interval(hmc_ctx *ctx, int every);
  * handle the larger chains; 0 disables it.  Default and maximum 2048. */
 int hmc_set_persistent_limit(hmc_ctx *ctx, int vmax);
 
+/* The chains that the multi-workgroup CG kernels iterate are split into `groups` (1 or 2)
+ * sets of about equal sites; with 2 the second set iterates on a library-owned stream
+ * beside the bound one, so that one set's kernels can fill the GPU while the other's ramp
+ * up, drain or wait at a kernel boundary.  Each chain's arithmetic is the same either way:
+ * results are bit-identical.  A batch with a chain above 2048 workgroups uses one set.
+ * The sampled timing then reports, per kernel, both sets' bytes over the span from the
+ * first start to the last end.  Default 1: on the batched workload 2 sets gained 0.5-3.7 %,
+ * as both sets still wait together at every convergence check. */
+int hmc_set_cg_groups(hmc_ctx *ctx, int groups);
+
 /* CG kernels of the multi-workgroup solver (Sec. 3 calls the solve "D^-1").  With on = 1
  * a solve runs one fused kernel per CG iteration when every chain it iterates lets a
  * workgroup own whole lattice rows (block/2 a multiple of Lx/2 with Lt at least 4 rows

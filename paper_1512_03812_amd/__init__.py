@@ -247,6 +247,10 @@ class Lattice:
         """Chains of at most vmax sites solve inside one persistent workgroup (0: never)."""
         self._check(self._lib.hmc_set_persistent_limit(self._ctx, int(vmax)))
 
+    def set_cg_groups(self, groups: int):
+        """1 (default) or 2 concurrently iterating sets of the multi-workgroup chains."""
+        self._check(self._lib.hmc_set_cg_groups(self._ctx, int(groups)))
+
     def set_fused_cg(self, on: bool):
         """One fused kernel per CG iteration where the chains allow it, or two (default)."""
         self._check(self._lib.hmc_set_fused_cg(self._ctx, 1 if on else 0))

@@ -74,6 +74,7 @@ SIGNATURES = {
     "hmc_set_check_interval": (_I, [_P, _I]),
     "hmc_set_persistent_limit": (_I, [_P, _I]),
     "hmc_set_fused_cg": (_I, [_P, _I]),
+    "hmc_set_cg_groups": (_I, [_P, _I]),
     "hmc_set_block_size": (_I, [_P, _I]),
     "hmc_autotune": (_I, [_P, _I, _D, _P]),
     "hmc_dslash": (_I, [_P, _P, _P]),

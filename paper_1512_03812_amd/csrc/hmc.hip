@@ -39,9 +39,10 @@ enum Spin32Buf { FX, FR, FT, FPA, FPB, FR2, FS2, kNumSpin32Bufs };
 // sums to the host, so the bytes of exactly those launches are attributed to the measured
 // durations with no copy inside the iteration loop.
 struct TimedSlot {
-    hipEvent_t ev[4];  // step 1 start, end; step 2 start, end
-    int sample;        // row of the device byte table
-    bool two;          // step 2 was launched (not the fused iteration)
+    hipEvent_t ev[2][4];  // per chain group: step 1 start, end; step 2 start, end
+    int ngroups;          // groups launched in this slot (their kernels run concurrently)
+    int sample;           // row of the device byte table (shared by the groups' chains)
+    bool two;             // step 2 was launched (not the fused iteration)
 };
 
 struct KernelTimer {
@@ -111,6 +112,14 @@ struct hmc_ctx {
     // ------------------------------------------------------------ solver partition
     hipStream_t side = nullptr;           // second stream for the persistent solver
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    // Two concurrent groups of multi-workgroup chains: group 1 iterates on `aux` beside
+    // group 0 on the bound stream, so that one group's kernels fill the GPU while the
+    // other's ramp up, drain or wait at a kernel boundary.
+    int cg_groups = 1;                    // 1 or 2 (hmc_set_cg_groups)
+    hipStream_t aux = nullptr;
+    hipEvent_t aux_fork_ev = nullptr, aux_join_ev = nullptr;
+    int grp_nb[2] = {0, 0};               // workgroups of each group in the big list
+    int part_groups = -1;                 // cg_groups the partition was built for
     int part_vmax = -1;                   // vmax the device partition tables were built for
     int n_big_blocks = 0, n_small = 0, small_vmax = 0;
     size_t lds_max = 64 * 1024;           // dynamic LDS a workgroup may opt in to
@@ -362,10 +371,25 @@ void timer_reduce(hmc_ctx *c) {
 // event and byte sum is complete.
 void timer_flush(hmc_ctx *c) {
     KernelTimer &T = c->timer;
+    // With two groups, a kernel's duration is the span from the earlier group's start to
+    // the later group's end, and its bytes are both groups' (the kernels run concurrently).
+    auto span = [&](const TimedSlot &ts, int k, float *ms) {
+        float lo = 0.f, hi = 0.f;
+        for (int g = 0; g < ts.ngroups; ++g) {
+            float s0 = 0.f, s1 = 0.f;
+            if (hipEventElapsedTime(&s0, ts.ev[0][2 * k], ts.ev[g][2 * k]) != hipSuccess ||
+                hipEventElapsedTime(&s1, ts.ev[0][2 * k], ts.ev[g][2 * k + 1]) != hipSuccess)
+                return false;
+            lo = g ? std::min(lo, s0) : s0;
+            hi = g ? std::max(hi, s1) : s1;
+        }
+        *ms = hi - lo;
+        return true;
+    };
     for (const TimedSlot &ts : T.pending) {
         float a = 0.f, b = 0.f;
-        if (hipEventElapsedTime(&a, ts.ev[0], ts.ev[1]) != hipSuccess) continue;
-        if (ts.two && hipEventElapsedTime(&b, ts.ev[2], ts.ev[3]) != hipSuccess) continue;
+        if (!span(ts, 0, &a)) continue;
+        if (ts.two && !span(ts, 1, &b)) continue;
         T.ms[0] += a;
         T.bytes[0] += T.sums_host[2 * ts.sample];
         T.timed[0]++;
@@ -383,7 +407,7 @@ void timer_flush(hmc_ctx *c) {
 // each kernel gets its start and end events and step 1 records the bytes of both steps in
 // the row given to it (-1: not sampled).
 template <typename L1, typename L2>
-void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2, bool two = true) {
+void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2, bool two = true, int ngroups = 1) {
     KernelTimer &T = c->timer;
     if (T.on) T.launches++;
     // Sampled slots sit mid-way between the convergence checks, a few slots after the host
@@ -392,16 +416,22 @@ void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2, bool two = true) {
     const int since = T.since_sync++;
     if (!T.on || slot % T.sample_every != T.sample_every / 2 || since < 2 ||
         (int)T.pending.size() == kMaxSamples || !T.sums_host) {
-        step1(-1, nullptr, nullptr);
-        if (two) step2(nullptr, nullptr);
+        for (int g = 0; g < ngroups; ++g) {
+            step1(g, -1, nullptr, nullptr);
+            if (two) step2(g, nullptr, nullptr);
+        }
         return;
     }
     TimedSlot ts;
-    for (int k = 0; k < 4; ++k) ts.ev[k] = timer_event(c);
+    for (int g = 0; g < ngroups; ++g)
+        for (int k = 0; k < 4; ++k) ts.ev[g][k] = timer_event(c);
+    ts.ngroups = ngroups;
     ts.sample = (int)T.pending.size();
     ts.two = two;
-    step1(ts.sample, ts.ev[0], ts.ev[1]);
-    if (two) step2(ts.ev[2], ts.ev[3]);
+    for (int g = 0; g < ngroups; ++g) {
+        step1(g, ts.sample, ts.ev[g][0], ts.ev[g][1]);
+        if (two) step2(g, ts.ev[g][2], ts.ev[g][3]);
+    }
     T.pending.push_back(ts);
 }
 
@@ -409,7 +439,7 @@ void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2, bool two = true) {
 // multi-workgroup slot kernels, and uploads the workgroup list of the latter and the chain
 // list of the former.
 int build_partition(hmc_ctx *c, int vmax) {
-    if (c->part_vmax == vmax) return HMC_OK;
+    if (c->part_vmax == vmax && c->part_groups == c->cg_groups) return HMC_OK;
     std::vector<BlockWork> big;
     std::vector<int> small;
     int svmax = 0, rc = HMC_OK;
@@ -419,8 +449,27 @@ int build_partition(hmc_ctx *c, int vmax) {
             svmax = std::max(svmax, c->chains[k].V);
         }
     }
-    for (const BlockWork &w : c->work)
-        if (c->chains[w.chain].V > vmax) big.push_back(w);
+    // the large chains, split into groups of about equal sites (largest first, each to the
+    // lighter group); the big list holds group 0's workgroups, then group 1's
+    std::vector<int> grp(c->nchains, 0), order;
+    for (int k = 0; k < c->nchains; ++k)
+        if (c->chains[k].V > vmax) order.push_back(k);
+    if (c->cg_groups == 2) {
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return c->chains[a].V > c->chains[b].V; });
+        long long load[2] = {0, 0};
+        for (int k : order) {
+            grp[k] = load[1] < load[0] ? 1 : 0;
+            load[grp[k]] += c->chains[k].V;
+        }
+    }
+    c->grp_nb[0] = c->grp_nb[1] = 0;
+    for (int g = 0; g < 2; ++g)
+        for (const BlockWork &w : c->work)
+            if (c->chains[w.chain].V > vmax && grp[w.chain] == g) {
+                big.push_back(w);
+                c->grp_nb[g]++;
+            }
     if (!big.empty())
         HIP_TRY(c, hipMemcpyAsync(c->at<BlockWork>(c->off_big), big.data(), sizeof(BlockWork) * big.size(),
                                   hipMemcpyHostToDevice, c->stream));
@@ -432,6 +481,7 @@ int build_partition(hmc_ctx *c, int vmax) {
     c->n_small = (int)small.size();
     c->small_vmax = svmax;
     c->part_vmax = vmax;
+    c->part_groups = c->cg_groups;
     return HMC_OK;
 }
 
@@ -555,11 +605,11 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
         int interval = c->check_every, next_check = interval, last_active = big.nblocks;
         for (; slot < max_slots; ++slot) {
             slot_launch(c, slot,
-                        [&](int sample, hipEvent_t e0, hipEvent_t e1) {
+                        [&](int, int sample, hipEvent_t e0, hipEvent_t e1) {
                             launch_cg_iter(g, fi, mixed, slot, tol, false, sample, lds_iter, c->stream,
                                            e0, e1);
                         },
-                        [](hipEvent_t, hipEvent_t) {}, false);
+                        [](int, hipEvent_t, hipEvent_t) {}, false);
             if (slot + 1 == next_check) {
                 int active = 0, live = 0;
                 if ((rc = check_convergence(c, big, max_iter, &active, &live))) return rc;
@@ -576,30 +626,71 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
         launch_cg_iter(big, fi, mixed, slot, tol, true, -1, lds_iter, c->stream);
         if (mixed) launch_cg_finish_mixed(big, f, c->stream);
     } else if (big.nblocks > 0) {
+    // Two groups of chains iterate concurrently, group 1 on the aux stream, unless a chain
+    // needs the finalize kernel (it reads every chain's partials) or a group is empty.
+    const int ng = c->cg_groups == 2 && !c->has_large && c->grp_nb[0] > 0 && c->grp_nb[1] > 0 ? 2 : 1;
+    hipStream_t gs[2] = {c->stream, c->aux};
+    Geo gfull[2] = {big, big};
+    if (ng == 2) {
+        gfull[0].nblocks = c->grp_nb[0];
+        gfull[1].work = big.work + c->grp_nb[0];
+        gfull[1].nblocks = c->grp_nb[1];
+    }
+    Geo gc[2] = {gfull[0], gfull[1]};
+    BlockWork *act[2] = {c->at<BlockWork>(c->off_active),
+                         c->at<BlockWork>(c->off_active) + (ng == 2 ? c->grp_nb[0] : 0)};
+    int *counts = c->at<int>(c->off_count);  // [active, live] per group
+    bool done[2] = {false, ng < 2};
     launch_cg_init(big, f, mixed, c->delta, c->stream);
     if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
+    if (ng == 2) {
+        HIP_TRY(c, hipEventRecord(c->aux_fork_ev, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->aux, c->aux_fork_ev, 0));
+    }
     // iteration slots: CG iterations plus, in mixed precision, FP64 residual recomputations
     const int max_slots = mixed ? max_iter + max_iter / 2 + 64 : max_iter;
+    const int max_it = mixed ? max_iter : max_slots;
     // Convergence checks: the first after check_every slots; the interval doubles (up to
     // 4x) while no chain converges and falls back when the active set shrinks.
     int interval = c->check_every, next_check = interval, last_active = big.nblocks;
     for (; slot < max_slots; ++slot) {
         void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
+        int gl[2], n = 0;  // groups still iterating
+        for (int gi = 0; gi < 2; ++gi)
+            if (!done[gi]) gl[n++] = gi;
         slot_launch(c, slot,
-                    [&](int sample, hipEvent_t e0, hipEvent_t e1) {
-                        launch_cg_step1(g, f, mixed, slot, tol, po, pn, false, sample, c->stream, e0, e1);
-                        if (c->has_large) launch_finalize_large(big, f.p1, f.fin1, c->stream);
+                    [&](int k, int sample, hipEvent_t e0, hipEvent_t e1) {
+                        const int gi = gl[k];
+                        launch_cg_step1(gc[gi], f, mixed, slot, tol, po, pn, false, sample, gs[gi], e0, e1);
+                        if (c->has_large) launch_finalize_large(big, f.p1, f.fin1, gs[gi]);
                     },
-                    [&](hipEvent_t e0, hipEvent_t e1) {
-                        launch_cg_step2(g, f, mixed, slot, pn, c->stream, e0, e1);
-                        if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
-                    });
+                    [&](int k, hipEvent_t e0, hipEvent_t e1) {
+                        const int gi = gl[k];
+                        launch_cg_step2(gc[gi], f, mixed, slot, pn, gs[gi], e0, e1);
+                        if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, gs[gi]);
+                    },
+                    true, n);
         if (slot + 1 == next_check) {
-            int active = 0, live = 0;
-            if ((rc = check_convergence(c, big, mixed ? max_iter : max_slots, &active, &live))) return rc;
-            if (active == 0 || (mixed && live == 0)) { ++slot; break; }
-            g.work = c->at<BlockWork>(c->off_active);
-            g.nblocks = active;
+            for (int gi = 0; gi < 2; ++gi)
+                if (!done[gi]) launch_compact(gfull[gi], c->cg(), max_it, act[gi], counts + 2 * gi, gs[gi]);
+            if (!done[1] && ng == 2) {
+                HIP_TRY(c, hipEventRecord(c->aux_join_ev, c->aux));
+                HIP_TRY(c, hipStreamWaitEvent(c->stream, c->aux_join_ev, 0));
+            }
+            int nh[4] = {0, 0, 0, 0};
+            if ((rc = to_host(c, nh, counts, sizeof(nh)))) return rc;
+            int active = 0;
+            for (int gi = 0; gi < 2; ++gi) {
+                if (done[gi]) continue;
+                if (nh[2 * gi] == 0 || (mixed && nh[2 * gi + 1] == 0)) {
+                    done[gi] = true;
+                } else {
+                    gc[gi].work = act[gi];
+                    gc[gi].nblocks = nh[2 * gi];
+                    active += nh[2 * gi];
+                }
+            }
+            if (done[0] && done[1]) { ++slot; break; }
             interval = active == last_active ? std::min(2 * interval, 4 * c->check_every)
                                              : c->check_every;
             last_active = active;
@@ -607,8 +698,14 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
         }
     }
     // fold the last slot's residual into the state (decision only), on every large chain
-    launch_cg_step1(big, f, mixed, slot, tol, pb[slot & 1], pb[(slot + 1) & 1], true, -1, c->stream);
-    if (mixed) launch_cg_finish_mixed(big, f, c->stream);
+    for (int gi = 0; gi < ng; ++gi) {
+        launch_cg_step1(gfull[gi], f, mixed, slot, tol, pb[slot & 1], pb[(slot + 1) & 1], true, -1, gs[gi]);
+        if (mixed) launch_cg_finish_mixed(gfull[gi], f, gs[gi]);
+    }
+    if (ng == 2) {
+        HIP_TRY(c, hipEventRecord(c->aux_join_ev, c->aux));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->aux_join_ev, 0));
+    }
     }
     if (c->n_small > 0) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->join_ev, 0));
     if (c->timer.on) timer_reduce(c);
@@ -975,6 +1072,11 @@ int hmc_bind(hmc_ctx *c, void *ws, size_t bytes, void *stream) {
         HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
     }
+    if (!c->aux) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->aux_fork_ev, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->aux_join_ev, hipEventDisableTiming));
+    }
     c->part_vmax = -1;
     HIP_TRY(c, hipMemcpyAsync(c->at<ChainInfo>(c->off_chains), c->chains.data(),
                               sizeof(ChainInfo) * c->nchains, hipMemcpyHostToDevice, c->stream));
@@ -1095,6 +1197,13 @@ int hmc_set_quenched(hmc_ctx *c, int quenched) {
 int hmc_set_persistent_limit(hmc_ctx *c, int vmax) {
     if (!c || vmax < 0) return HMC_E_INVAL;
     c->persist_vmax = vmax;
+    c->graph_epoch++;
+    return HMC_OK;
+}
+
+int hmc_set_cg_groups(hmc_ctx *c, int groups) {
+    if (!c || groups < 1 || groups > 2) return HMC_E_INVAL;
+    c->cg_groups = groups;
     c->graph_epoch++;
     return HMC_OK;
 }
@@ -1713,6 +1822,9 @@ int hmc_destroy(hmc_ctx *c) {
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
     if (c->timer.sums_host) (void)hipHostFree(c->timer.sums_host);
     if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
+    if (c->aux_fork_ev) (void)hipEventDestroy(c->aux_fork_ev);
+    if (c->aux_join_ev) (void)hipEventDestroy(c->aux_join_ev);
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     if (c->pinned) (void)hipHostFree(c->pinned);

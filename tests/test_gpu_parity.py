@@ -269,6 +269,27 @@ def test_solution_does_not_depend_on_the_check_interval(prec, fused):
             assert np.array_equal(got[0], ref[0]), every
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_two_chain_groups_match_one_bitwise(prec):
+    """The multi-workgroup chains split into two concurrently iterating sets give the same
+    bits as one set: trajectories of a batch of uneven chains."""
+    shapes = [(16, 16, 2.0, 0.1), (32, 32, 1.5, 0.05), (64, 16, 3.0, 0.2), (8, 8, 1.0, 0.3),
+              (32, 16, 2.0, 0.15), (16, 32, 2.5, 0.08), (64, 64, 2.0, 0.1)]
+    res = []
+    for groups in (1, 2):
+        b = Batch(shapes, seed=31, persistent=0)
+        b.lat.set_cg_groups(groups)
+        b.lat.hot_start()
+        b.lat.set_solver(tol=1e-12 if prec == "fp64" else 1e-10)
+        out = []
+        for _ in range(2):
+            r = b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2, prec=prec)
+            out.append((list(r.dH), list(r.accepted), list(r.n_cg_iters)))
+        res.append((out, b.lat.q.cpu().numpy().copy()))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
+
+
 def test_fused_iteration_runs_where_eligible():
     b = Batch([(32, 32, 2.0, 0.1), (64, 64, 2.0, 0.1)], persistent=0)
     b.lat.set_block_size(256)
