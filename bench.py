@@ -106,6 +106,44 @@ def run_batched(args):
                 cg_iters_per_traj=iters / max(1, args.steps))
 
 
+def run_concurrent(args, n_ctx=2):
+    """The same workload as n_ctx contexts (chains k, k + n_ctx, ... in context k), each on a
+    stream of its own, advanced together by hmc_trajectories_concurrent (one host thread per
+    context): chain-trajectories/s over the same number of timed steps."""
+    import torch
+    import paper_1512_03812_amd as hmc
+    L, beta, m0 = workload(args.seed, args.chains)
+    lats = []
+    for k in range(n_ctx):
+        idx = list(range(k, len(L), n_ctx))
+        with torch.cuda.stream(torch.cuda.Stream()):
+            lat = hmc.Lattice.batch([L[i] for i in idx], [L[i] for i in idx], [beta[i] for i in idx],
+                                    [m0[i] for i in idx], seed=args.seed + 7919 * k)
+            lat.hot_start()
+            lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
+            lat.set_check_interval(args.check_interval)
+            lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+            if not args.no_tune:
+                lat.autotune("mixed", 1e-10)
+            lat.set_persistent_limit(args.persistent_limit if args.persistent_limit >= 0 else 0)
+        lats.append(lat)
+    for _ in range(max(0, args.warmup - 1)):
+        hmc.trajectories_concurrent(lats, "adapted_nested_fg", 1.0, 8, 4, "mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc = []
+    for _ in range(args.steps):
+        for r in hmc.trajectories_concurrent(lats, "adapted_nested_fg", 1.0, 8, 4, "mixed"):
+            acc += r.accepted
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": round(len(L) * args.steps / dt, 3), "unit": "chain-trajectories/s",
+            "contexts": n_ctx, "ms_per_step": round(1e3 * dt / args.steps, 3),
+            "acceptance": round(sum(acc) / len(acc), 4),
+            "how": ("the workload's chains split over two contexts (even and odd chain indices), "
+                    "each on its own stream, advanced by hmc_trajectories_concurrent")}
+
+
 def run_single_fp64(args):
     """The plain FP64 single-chain path: 32 x 32, beta 2, m0 0.1, same scheme."""
     import torch
@@ -506,6 +544,8 @@ def main():
     ap.add_argument("--single-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the two-context concurrent run of the workload")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--block", type=int, default=0, help="fixed workgroup size (with --no-tune)")
     ap.add_argument("--uniform-L", type=int, default=0,
@@ -640,6 +680,8 @@ def main():
                                      "timed_launches": st["timed_launches"]}
                      for k, st in ((0, s1), (1, s2))},
     }
+    if not args.no_concurrent:
+        out["concurrent_contexts"] = run_concurrent(args)
     if not args.no_single:
         out["fp64_single_chain"] = run_single_fp64(args)
         out["precision"] = run_precision(args, [256], 3, 2)

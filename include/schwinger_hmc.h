@@ -317,6 +317,16 @@ int hmc_set_fg_mode(hmc_ctx *ctx, int mode);
 int hmc_trajectory(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inner, int prec,
                    hmc_traj_info *info);
 
+/* hmc_trajectory on n (1..8) contexts at once, one host thread each (the calling thread
+ * takes ctxs[0]).  Every context must be bound, each to a stream of its own; their work
+ * overlaps on the GPU, so that one context's kernels fill the gaps of another (its host
+ * waits at convergence checks, the tail of its solves).  Each context computes exactly what
+ * hmc_trajectory computes.  infos[k] (may be NULL, or NULL entries): n_chains entries of
+ * context k; rcs[k] (may be NULL): its return code.  Returns the first nonzero code, or
+ * HMC_E_INVAL for a repeated context or stream. */
+int hmc_trajectories_concurrent(hmc_ctx **ctxs, int n, int scheme, double tau, int n_outer,
+                                int n_inner, int prec, hmc_traj_info **infos, int *rcs);
+
 /* Captured trajectories.  With on != 0, hmc_trajectory records its whole device work (refresh,
  * molecular dynamics with every solve, energies, Metropolis) as one HIP graph on first use of
  * a (scheme, tau, n_outer, n_inner, prec) schedule and replays that graph afterwards: one launch

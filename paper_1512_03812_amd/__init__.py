@@ -493,3 +493,27 @@ class SchwingerAction(torch.autograd.Function):
             scale = torch.repeat_interleave(grad_s, torch.tensor(lat.V, device=grad_s.device))
             grad = F * scale[None, :]
         return grad, None, None, None, None
+
+
+def trajectories_concurrent(lattices, scheme="adapted_nested_fg", tau=1.0, n_outer=8, n_inner=4,
+                            prec="fp64"):
+    """One HMC trajectory on each of several Lattice objects at once (hmc_trajectories_concurrent:
+    one host thread per context; each must have been created on a stream of its own).
+    Returns one TrajResult per lattice, each what lattice.trajectory would have returned."""
+    lats = list(lattices)
+    if not lats:
+        return []
+    lib = lats[0]._lib
+    n = len(lats)
+    infos = [(_lib.TrajInfo * lat.n_chains)() for lat in lats]
+    ctxs = (ctypes.c_void_p * n)(*[lat._ctx.value for lat in lats])
+    iptr = (ctypes.c_void_p * n)(*[ctypes.cast(i, ctypes.c_void_p).value for i in infos])
+    rcs = (ctypes.c_int * n)()
+    rc = lib.hmc_trajectories_concurrent(ctxs, n, _scheme(scheme), tau, n_outer, n_inner,
+                                         _prec(prec), iptr, rcs)
+    if rc == _lib.HMC_E_INVAL and all(r == 0 for r in rcs):
+        raise HMCError(rc, "trajectories_concurrent needs distinct bound lattices on distinct streams")
+    for lat, r in zip(lats, rcs):
+        if r not in (0, _lib.HMC_E_NOCONV, _lib.HMC_E_NAN):
+            lat._check(r)
+    return [lat._traj_result(i) for lat, i in zip(lats, infos)]

@@ -93,6 +93,7 @@ SIGNATURES = {
     "hmc_set_fg_mode": (_I, [_P, _I]),
     "hmc_set_graph": (_I, [_P, _I]),
     "hmc_trajectory": (_I, [_P, _I, _D, _I, _I, _I, _P]),
+    "hmc_trajectories_concurrent": (_I, [_P, _I, _I, _D, _I, _I, _I, _P, _P]),
     "hmc_integrate": (_I, [_P, _I, _D, _I, _I, _I, _P]),
     "hmc_refresh": (_I, [_P]),
     "hmc_set_timing": (_I, [_P, _I]),

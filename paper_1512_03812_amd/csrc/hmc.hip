@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/schwinger_hmc.h"
@@ -59,6 +60,9 @@ struct KernelTimer {
     int since_sync = 0;      // slots launched since the host last waited for the stream
     bool fused = false;      // the sampled slots ran the fused iteration (index 0 holds it)
 };
+
+// Contexts hmc_trajectories_concurrent advances at once (one host thread each).
+constexpr int kMaxConcurrent = 8;
 
 // Solves whose results a captured trajectory can log on the device.
 constexpr int kMaxLoggedSolves = 1024;
@@ -116,6 +120,7 @@ struct hmc_ctx {
     // group 0 on the bound stream, so that one group's kernels fill the GPU while the
     // other's ramp up, drain or wait at a kernel boundary.
     int cg_groups = 1;                    // 1 or 2 (hmc_set_cg_groups)
+    int device = 0;                       // the device current at hmc_bind
     hipStream_t aux = nullptr;
     hipEvent_t aux_fork_ev = nullptr, aux_join_ev = nullptr;
     int grp_nb[2] = {0, 0};               // workgroups of each group in the big list
@@ -1052,6 +1057,7 @@ int hmc_bind(hmc_ctx *c, void *ws, size_t bytes, void *stream) {
     c->ws = (char *)ws;
     c->graph_epoch++;
     c->stream = (hipStream_t)stream;
+    HIP_TRY(c, hipGetDevice(&c->device));
     if (!c->pinned) {
         c->pinned_bytes = align_up(sizeof(CGState) * c->nchains + sizeof(MetroOut) * c->nchains +
                                    sizeof(double) * 16 * c->nchains + 4096);
@@ -1734,6 +1740,34 @@ int hmc_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner,
     rc = finish_traj_host(c, md, true, 0, info);
     c->traj++;
     return rc;
+}
+
+int hmc_trajectories_concurrent(hmc_ctx **ctxs, int n, int scheme, double tau, int n_outer,
+                                int n_inner, int prec, hmc_traj_info **infos, int *rcs) {
+    if (!ctxs || n < 1 || n > kMaxConcurrent) return HMC_E_INVAL;
+    for (int k = 0; k < n; ++k) {
+        if (!ctxs[k] || !ctxs[k]->ws) return HMC_E_INVAL;
+        for (int j = 0; j < k; ++j)
+            if (ctxs[j] == ctxs[k] || ctxs[j]->stream == ctxs[k]->stream) return HMC_E_INVAL;
+    }
+    std::vector<int> rc(n, HMC_OK);
+    auto run = [&](int k) {
+        if (hipSetDevice(ctxs[k]->device) != hipSuccess) {
+            rc[k] = fail(ctxs[k], HMC_E_HIP, "hipSetDevice failed in a concurrent trajectory");
+            return;
+        }
+        rc[k] = hmc_trajectory(ctxs[k], scheme, tau, n_outer, n_inner, prec, infos ? infos[k] : nullptr);
+    };
+    std::vector<std::thread> th;
+    for (int k = 1; k < n; ++k) th.emplace_back(run, k);
+    run(0);
+    for (std::thread &t : th) t.join();
+    int first = HMC_OK;
+    for (int k = 0; k < n; ++k) {
+        if (rcs) rcs[k] = rc[k];
+        if (first == HMC_OK) first = rc[k];
+    }
+    return first;
 }
 
 int hmc_set_graph(hmc_ctx *c, int on) {

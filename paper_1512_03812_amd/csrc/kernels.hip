@@ -12,6 +12,7 @@
 // the host needs go through a one-workgroup-per-chain finalize kernel.
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -1063,6 +1064,8 @@ void launch_cg_iter(const Geo &g, const CGIterFields &f, bool mixed, int slot, d
 
 int grant_cg_iter_lds(size_t lds_bytes) {
     static size_t granted[2] = {64 * 1024, 64 * 1024};
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
     for (int m = 0; m < 2; ++m) {
         if (lds_bytes <= granted[m]) continue;
         const void *fn = m ? (const void *)k_cg_iter<true> : (const void *)k_cg_iter<false>;
@@ -1279,6 +1282,8 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
 // instantiation.  Returns -1 (error state cleared) if the device refuses.
 template <bool MIXED, int SPT> static int grant_wg_lds(size_t lds) {
     static size_t granted = 64 * 1024;  // dynamic LDS available without opting in
+    static std::mutex mu;               // contexts may run on several host threads
+    std::lock_guard<std::mutex> lock(mu);
     if (lds > granted) {
         if (hipFuncSetAttribute((const void *)k_cg_wg<MIXED, SPT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {

@@ -290,6 +290,44 @@ def test_two_chain_groups_match_one_bitwise(prec):
     assert np.array_equal(res[0][1], res[1][1])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_concurrent_contexts_match_sequential(prec):
+    """hmc_trajectories_concurrent: two contexts on two streams advanced from two host threads
+    give the bits each context gives alone."""
+    m = hmc()
+    shapes = [[(16, 16, 2.0, 0.1), (32, 32, 1.5, 0.05), (8, 8, 1.0, 0.3)],
+              [(64, 16, 3.0, 0.2), (32, 16, 2.0, 0.15), (16, 32, 2.5, 0.08)]]
+
+    def build():
+        out = []
+        for k, sh in enumerate(shapes):
+            with torch.cuda.stream(torch.cuda.Stream()):
+                b = Batch(sh, seed=40 + k, persistent=0)
+                b.lat.hot_start()
+                b.lat.set_solver(tol=1e-12 if prec == "fp64" else 1e-10)
+            out.append(b)
+        torch.cuda.synchronize()
+        return out
+
+    conc, seq = build(), build()
+    for _ in range(2):
+        rc = m.trajectories_concurrent([b.lat for b in conc], "adapted_nested_fg", 1.0, 4, 2, prec)
+        rs = [b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2, prec=prec) for b in seq]
+        for a, b in zip(rc, rs):
+            assert list(a.dH) == list(b.dH) and list(a.accepted) == list(b.accepted)
+            assert list(a.n_cg_iters) == list(b.n_cg_iters)
+    torch.cuda.synchronize()
+    for a, b in zip(conc, seq):
+        assert torch.equal(a.lat.q, b.lat.q)
+
+
+def test_concurrent_contexts_refuse_a_shared_stream():
+    m = hmc()
+    a, b = Batch([(8, 8)]), Batch([(8, 8)])
+    with pytest.raises(m.HMCError):
+        m.trajectories_concurrent([a.lat, b.lat])
+
+
 def test_fused_iteration_runs_where_eligible():
     b = Batch([(32, 32, 2.0, 0.1), (64, 64, 2.0, 0.1)], persistent=0)
     b.lat.set_block_size(256)
