@@ -234,50 +234,74 @@ def run_precision(args, sizes, n_traj, n_therm):
 
 
 def cpu_baseline(args):
-    """The oracle (plain FP64 C, one thread) on a bounded, stratified sample of the workload:
-    full oracle trajectories (adapted nested FG, tau 1, 8 x 4, CG to 1e-10) from the hot
-    start of the first 6 chains with L = 16, the first 4 with L = 32 and the first 3 with
-    L = 64; for L = 128 one fermion-force solve at its hot start, scaled by the
-    trajectory/solve time ratio measured on the L = 64 chain.  Per-size mean times are
-    weighted by the workload's count of chains of each size."""
+    """The oracle (plain FP64 C) on a bounded, stratified sample of the workload: full oracle
+    trajectories (adapted nested FG, tau 1, 8 x 4, CG to 1e-10) from the hot start of the
+    first 6 chains with L = 16, the first 4 with L = 32 and the first 3 with L = 64; for
+    L = 128 one fermion-force solve at its hot start, scaled by the trajectory/solve time
+    ratio measured on the L = 64 chains.  Per-size mean times are weighted by the workload's
+    count of chains of each size.  The sample runs twice: on one core, then as concurrent
+    threads on the host's cores (the oracle keeps no global state and its ctypes calls
+    release the interpreter lock), where each core advances its own chains; `value` is that
+    all-cores figure, with the per-task times taken under the full load."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
     L, beta, m0 = workload(args.seed, args.chains)
-    t_begin = time.perf_counter()
-    per_L, solve_t = {}, {}
 
     def first(Ls, k):
         return [i for i, l in enumerate(L) if l == Ls][:k]
 
-    def solve_time(Ls, c):
-        q = oracle.random_links(Ls, Ls, args.seed, c)
-        phi = oracle.dirac_dagger(q, oracle.random_zeta(Ls, Ls, args.seed, c, 0), m0[c])
+    def traj_task(c):
+        q = oracle.random_links(L[c], L[c], args.seed, c)
+        t0 = time.perf_counter()
+        oracle.hmc_trajectory(q, beta[c], m0[c], args.seed, c, 0, "adapted_nested_fg", 1.0, 8, 4,
+                              tol=1e-10)
+        return ("traj", L[c], time.perf_counter() - t0)
+
+    def solve_task(c):
+        q = oracle.random_links(L[c], L[c], args.seed, c)
+        phi = oracle.dirac_dagger(q, oracle.random_zeta(L[c], L[c], args.seed, c, 0), m0[c])
         t0 = time.perf_counter()
         oracle.fermion_force(q, phi, m0[c], tol=1e-10)
-        return time.perf_counter() - t0
+        return ("solve", L[c], time.perf_counter() - t0)
 
-    for Ls, k in ((16, 6), (32, 4), (64, 3)):
-        ts = []
-        for c in first(Ls, k):
-            q = oracle.random_links(Ls, Ls, args.seed, c)
-            t0 = time.perf_counter()
-            oracle.hmc_trajectory(q, beta[c], m0[c], args.seed, c, 0, "adapted_nested_fg", 1.0, 8, 4,
-                                  tol=1e-10)
-            ts.append(time.perf_counter() - t0)
-        if ts:
-            per_L[Ls] = sum(ts) / len(ts)
-    ratio = per_L[64] / solve_time(64, first(64, 1)[0]) if 64 in per_L else 33.0
-    c128 = first(128, 1)
-    if c128:
-        per_L[128] = ratio * solve_time(128, c128[0])
-    total = sum(per_L[Ls] * L.count(Ls) for Ls in per_L)
-    sample_s = time.perf_counter() - t_begin
-    return {"value": round(len(L) / total, 4), "unit": "chain-trajectories/s", "cores": 1,
-            "kind": "oracle",
-            "sample": ("full oracle trajectories from the hot start of the first 6 L=16, 4 L=32 and "
-                       "3 L=64 chains; L=128 from one oracle solve times the trajectory/solve ratio "
-                       f"({ratio:.1f}) of the L=64 chain; weighted by the workload's L counts; "
-                       f"sample CPU time {sample_s:.1f} s"),
-            "seconds_per_chain_traj_by_L": {str(k): round(v, 3) for k, v in per_L.items()}}
+    tasks = [(traj_task, c) for Ls, k in ((16, 6), (32, 4), (64, 3)) for c in first(Ls, k)]
+    tasks += [(solve_task, c) for Ls in (64, 128) for c in first(Ls, 1)]
+
+    def estimate(results):
+        per_L = {}
+        for Ls in (16, 32, 64):
+            ts = [t for kind, l, t in results if kind == "traj" and l == Ls]
+            if ts:
+                per_L[Ls] = sum(ts) / len(ts)
+        s64 = [t for kind, l, t in results if kind == "solve" and l == 64]
+        s128 = [t for kind, l, t in results if kind == "solve" and l == 128]
+        ratio = per_L[64] / s64[0] if (64 in per_L and s64) else 33.0
+        if s128:
+            per_L[128] = ratio * s128[0]
+        return per_L, ratio, sum(per_L[Ls] * L.count(Ls) for Ls in per_L)
+
+    t_begin = time.perf_counter()
+    one = [fn(c) for fn, c in tasks]
+    per_L1, ratio1, total1 = estimate(one)
+    t_one = time.perf_counter() - t_begin
+    cores = max(1, min(16, os.cpu_count() or 1, len(tasks)))
+    t_begin = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        many = list(ex.map(lambda fc: fc[0](fc[1]), tasks))
+    per_L, ratio, total = estimate(many)
+    t_many = time.perf_counter() - t_begin
+    return {"value": round(cores * len(L) / total, 4), "unit": "chain-trajectories/s",
+            "cores": cores, "kind": "oracle",
+            "sample": (f"{len(tasks)} oracle tasks: full trajectories from the hot start of the "
+                       "first 6 L=16, 4 L=32 and 3 L=64 chains, and one solve each of the first L=64 "
+                       f"and L=128 chain (L=128 trajectory = solve x the L=64 trajectory/solve ratio, "
+                       f"{ratio:.1f}); weighted by the workload's L counts; run once on 1 core "
+                       f"({t_one:.1f} s) and once as {cores} concurrent threads ({t_many:.1f} s wall), "
+                       f"whose per-task times give value = {cores} x chains / weighted time"),
+            "single_core_value": round(len(L) / total1, 4),
+            "seconds_per_chain_traj_by_L": {str(k): round(v, 3) for k, v in per_L.items()},
+            "seconds_per_chain_traj_by_L_single_core": {str(k): round(v, 3) for k, v in per_L1.items()}}
 
 
 def run_sweep(args):
