@@ -66,9 +66,9 @@ def test_workspace_size_and_geometry(lib):
     assert lib.hmc_geometry(ctx, ctypes.byref(n), ctypes.byref(vt), offs, None, None) == 0
     assert n.value == 3 and vt.value == 256 + 48 + 8
     assert list(offs) == [0, 256, 304]
-    # at least the FP64 fields: 9 real link fields, 11 spinors, two complex link fields,
-    # the FP32 links and the FP32 solver fields
-    assert lib.hmc_workspace_bytes(ctx) >= vt.value * (9 * 16 + 11 * 32 + 2 * 32 + 16 + 5 * 16)
+    # at least: 9 real link fields, 13 FP64 spinors, two complex link fields, the FP32 link
+    # angles and 7 FP32 solver spinors
+    assert lib.hmc_workspace_bytes(ctx) >= vt.value * (9 * 16 + 13 * 32 + 2 * 32 + 8 + 7 * 16)
     assert lib.hmc_destroy(ctx) == 0
 
 
@@ -88,6 +88,15 @@ def test_unbound_context_is_rejected_without_touching_the_gpu(lib):
     assert lib.hmc_set_fg_mode(ctx, 1) == 0 and lib.hmc_set_fg_mode(ctx, 0) == 0
     assert lib.hmc_force_gradient_term(ctx, 2, buf, buf, 0, None) == -1
     assert lib.hmc_hessian_vector(ctx, 0, None, buf, buf, 0, None) == -1
+    assert lib.hmc_stream_copy(ctx, buf, buf, 16) == -1
+    assert lib.hmc_set_cg_groups(ctx, 0) == -1 and lib.hmc_set_cg_groups(ctx, 3) == -1
+    assert lib.hmc_set_cg_groups(ctx, 2) == 0 and lib.hmc_set_cg_groups(ctx, 1) == 0
+    assert lib.hmc_set_fused_cg(ctx, 1) == 0 and lib.hmc_set_fused_cg(ctx, 0) == 0
+    ctxs = (ctypes.c_void_p * 9)(*([ctx.value] * 9))
+    assert lib.hmc_trajectories_concurrent(None, 1, 4, 1.0, 4, 2, 0, None, None) == -1
+    assert lib.hmc_trajectories_concurrent(ctxs, 0, 4, 1.0, 4, 2, 0, None, None) == -1
+    assert lib.hmc_trajectories_concurrent(ctxs, 9, 4, 1.0, 4, 2, 0, None, None) == -1
+    assert lib.hmc_trajectories_concurrent(ctxs, 1, 4, 1.0, 4, 2, 0, None, None) == -1  # unbound
     assert lib.hmc_destroy(ctx) == 0
     assert lib.hmc_destroy(None) == -1
 
