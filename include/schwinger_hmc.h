@@ -350,7 +350,7 @@ int hmc_integrate(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inner
 
 /* Sampled event timing of the CG step kernels (which = 0: step 1, the x update and
  * t = D p, or the whole fused iteration; which = 1: step 2, r -= alpha D^dagger t).
- * While on, in every 16th CG iteration slot (away from the host's convergence checks) each
+ * While on, in every 32nd CG iteration slot (away from the host's convergence checks) each
  * kernel is launched with a start and an end HIP event that its own dispatch stamps, and
  * step 1 records on the device the algorithmic bytes of both steps for the chains it
  * iterates (their sites times the bytes per site of the slot's mode); the bytes are summed

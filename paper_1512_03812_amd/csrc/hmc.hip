@@ -48,7 +48,7 @@ struct TimedSlot {
 
 struct KernelTimer {
     bool on = false;
-    int sample_every = 16;
+    int sample_every = 32;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     std::vector<TimedSlot> pending;
