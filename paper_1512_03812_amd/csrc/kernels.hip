@@ -50,6 +50,22 @@ template <int NV> __device__ __forceinline__ void block_sum_all(double (&v)[NV])
     __syncthreads();
 }
 
+// Workgroup sum of one value with one barrier, every thread receiving the total: the
+// wavefront sums meet in LDS buffer `buf` (0 or 1) and each thread adds them in a fixed
+// order.  Alternating the buffer between consecutive calls makes a second barrier
+// unnecessary: a thread can only rewrite a buffer after the other buffer's barrier, which
+// every thread reaches after reading it.
+__device__ __forceinline__ double block_sum_bcast(double v, int buf) {
+    __shared__ double sh[2][kMaxWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) sh[buf][wave] = v;
+    __syncthreads();
+    double a = 0.0;
+    for (int w = 0; w < nw; ++w) a += sh[buf][w];
+    return a;
+}
+
 // One partial per workgroup into row k of partials (k < NV).  It ends its kernel (every
 // caller's last use of LDS), so one barrier suffices: the wavefront sums meet in LDS and
 // thread 0 adds them in a fixed order.
@@ -1185,7 +1201,7 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
             ts[V + fl[k] - off] = o1;
             v[0] += norm2(o0) + norm2(o1);
         }
-        block_sum_all<1>(v);
+        v[0] = block_sum_bcast(v[0], 0);  // also makes ts visible
         const R alpha = (R)(rho / v[0]);
         // x += alpha p, r -= alpha D^dagger t
         v[0] = 0.0;
@@ -1202,7 +1218,7 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
                 v[0] += norm2(r[k][sp]);
             }
         }
-        block_sum_all<1>(v);
+        v[0] = block_sum_bcast(v[0], 1);
         const double rho_new = v[0];
         ++iters;
         double beta = rho_new / rho;
