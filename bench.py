@@ -615,7 +615,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the chains of this workload are independent and "
-              "this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+              "the library has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
