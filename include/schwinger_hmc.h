@@ -323,7 +323,8 @@ int hmc_trajectory(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inne
  * waits at convergence checks, the tail of its solves).  Each context computes exactly what
  * hmc_trajectory computes.  infos[k] (may be NULL, or NULL entries): n_chains entries of
  * context k; rcs[k] (may be NULL): its return code.  Returns the first nonzero code, or
- * HMC_E_INVAL for a repeated context or stream. */
+ * HMC_E_INVAL for a repeated context or stream.  The calling thread's current HIP device is
+ * the same on return as on entry. */
 int hmc_trajectories_concurrent(hmc_ctx **ctxs, int n, int scheme, double tau, int n_outer,
                                 int n_inner, int prec, hmc_traj_info **infos, int *rcs);
 

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <exception>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1758,10 +1759,20 @@ int hmc_trajectories_concurrent(hmc_ctx **ctxs, int n, int scheme, double tau, i
         }
         rc[k] = hmc_trajectory(ctxs[k], scheme, tau, n_outer, n_inner, prec, infos ? infos[k] : nullptr);
     };
+    // the calling thread runs context 0; its current device is restored afterwards
+    int caller_dev = 0;
+    if (hipGetDevice(&caller_dev) != hipSuccess) return fail(ctxs[0], HMC_E_HIP, "hipGetDevice failed");
     std::vector<std::thread> th;
-    for (int k = 1; k < n; ++k) th.emplace_back(run, k);
+    for (int k = 1; k < n; ++k) {
+        try {
+            th.emplace_back(run, k);
+        } catch (const std::exception &) {
+            rc[k] = fail(ctxs[k], HMC_E_INVAL, "could not start a host thread for a concurrent trajectory");
+        }
+    }
     run(0);
     for (std::thread &t : th) t.join();
+    (void)hipSetDevice(caller_dev);
     int first = HMC_OK;
     for (int k = 0; k < n; ++k) {
         if (rcs) rcs[k] = rc[k];

@@ -12,6 +12,7 @@
 // the host needs go through a one-workgroup-per-chain finalize kernel.
 #include <math.h>
 
+#include <map>
 #include <mutex>
 #include <type_traits>
 
@@ -1078,21 +1079,33 @@ void launch_cg_iter(const Geo &g, const CGIterFields &f, bool mixed, int slot, d
                        slot, tol * tol, decide_only ? 1 : 0, sample);
 }
 
-int grant_cg_iter_lds(size_t lds_bytes) {
-    static size_t granted[2] = {64 * 1024, 64 * 1024};
-    static std::mutex mu;
-    std::lock_guard<std::mutex> lock(mu);
-    for (int m = 0; m < 2; ++m) {
-        if (lds_bytes <= granted[m]) continue;
-        const void *fn = m ? (const void *)k_cg_iter<true> : (const void *)k_cg_iter<false>;
-        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
-            hipSuccess) {
+// The dynamic LDS granted so far to a kernel on each device (the attribute is set on the
+// current device); 64 KiB is available without opting in.
+struct LdsGrant {
+    std::map<int, size_t> granted;
+    std::mutex mu;  // contexts may run on several host threads
+    int raise(const void *fn, size_t lds) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) {
             (void)hipGetLastError();
             return -1;
         }
-        granted[m] = lds_bytes;
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = granted.emplace(dev, (size_t)64 * 1024).first;
+        if (lds <= it->second) return 0;
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+            (void)hipGetLastError();  // clear the error state: the caller falls back
+            return -1;
+        }
+        it->second = lds;
+        return 0;
     }
-    return 0;
+};
+
+int grant_cg_iter_lds(size_t lds_bytes) {
+    static LdsGrant grant[2];
+    if (grant[0].raise((const void *)k_cg_iter<false>, lds_bytes)) return -1;
+    return grant[1].raise((const void *)k_cg_iter<true>, lds_bytes);
 }
 
 // ---------------------------------------------------------------- persistent small-chain CG
@@ -1295,20 +1308,10 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
 }
 
 // Dynamic LDS above 64 KiB must be opted in per kernel; the grant is remembered per
-// instantiation.  Returns -1 (error state cleared) if the device refuses.
+// instantiation and device.  Returns -1 (error state cleared) if the device refuses.
 template <bool MIXED, int SPT> static int grant_wg_lds(size_t lds) {
-    static size_t granted = 64 * 1024;  // dynamic LDS available without opting in
-    static std::mutex mu;               // contexts may run on several host threads
-    std::lock_guard<std::mutex> lock(mu);
-    if (lds > granted) {
-        if (hipFuncSetAttribute((const void *)k_cg_wg<MIXED, SPT>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
-            (void)hipGetLastError();  // clear the error state: the caller falls back
-            return -1;
-        }
-        granted = lds;
-    }
-    return 0;
+    static LdsGrant grant;
+    return grant.raise((const void *)k_cg_wg<MIXED, SPT>, lds);
 }
 
 template <bool MIXED, int SPT>
