@@ -242,13 +242,27 @@ __device__ __forceinline__ void sp_load(const float4 *__restrict__ a, int, int f
     b0 = make_float2(v.x, v.y);
     b1 = make_float2(v.z, v.w);
 }
+
+// Spinor stores are write-through: the sc1 bit sends each 16-byte store through the L2 to
+// memory at once, so an XCD's L2 holds no dirty lines of these fields when the kernel ends
+// and the writeback that the end of a kernel makes (the next kernel reads the fields through
+// the other XCDs' L2s) has little left to do.  On the batched workload this shortens the CG
+// step kernels by 2-4 %.  The store is inline assembly: no builtin gives a global store with
+// this bit (the buffer-store builtin does, but its 32-bit offsets cannot span the largest
+// fields).  A VALU write to the data registers of a store wider than 8 bytes must trail it
+// by one wait state; the compiler cannot see inside the asm, so the asm carries the wait.
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_wt(void *p, f4v v) {
+    asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 1" : : "v"(p), "v"(v) : "memory");
+}
 __device__ __forceinline__ void sp_store(double2 *__restrict__ a, int Vtot, int f, double2 b0,
                                          double2 b1) {
-    a[f] = b0;
-    a[(size_t)Vtot + f] = b1;
+    store_wt(a + f, __builtin_bit_cast(f4v, b0));
+    store_wt(a + (size_t)Vtot + f, __builtin_bit_cast(f4v, b1));
 }
 __device__ __forceinline__ void sp_store(float4 *__restrict__ a, int, int f, float2 b0, float2 b1) {
-    a[f] = make_float4(b0.x, b0.y, b1.x, b1.y);
+    f4v v = {b0.x, b0.y, b1.x, b1.y};
+    store_wt(a + f, v);
 }
 template <bool MIXED> struct Prec;
 template <> struct Prec<false> { using R = double; using S = double2; };  // S: spinor storage
