@@ -243,24 +243,38 @@ __device__ __forceinline__ void sp_load(const float4 *__restrict__ a, int, int f
     b1 = make_float2(v.z, v.w);
 }
 
-// Spinor stores are write-through: the sc1 bit sends each 16-byte store through the L2 to
-// memory at once, so an XCD's L2 holds no dirty lines of these fields when the kernel ends
-// and the writeback that the end of a kernel makes (the next kernel reads the fields through
-// the other XCDs' L2s) has little left to do.  On the batched workload this shortens the CG
-// step kernels by 2-4 %.  The store is inline assembly: no builtin gives a global store with
-// this bit (the buffer-store builtin does, but its 32-bit offsets cannot span the largest
-// fields).  A VALU write to the data registers of a store wider than 8 bytes must trail it
-// by one wait state; the compiler cannot see inside the asm, so the asm carries the wait.
+__device__ __forceinline__ void sp_store(double2 *__restrict__ a, int Vtot, int f, double2 b0,
+                                         double2 b1) {
+    a[f] = b0;
+    a[(size_t)Vtot + f] = b1;
+}
+__device__ __forceinline__ void sp_store(float4 *__restrict__ a, int, int f, float2 b0, float2 b1) {
+    a[f] = make_float4(b0.x, b0.y, b1.x, b1.y);
+}
+
+// Write-through spinor stores, for the CG step kernels: the sc1 bit sends each 16-byte
+// store through the L2 to memory at once, so an XCD's L2 holds no dirty lines of these
+// fields when the kernel ends and the writeback that the end of a kernel makes (the next
+// kernel reads the fields through the other XCDs' L2s) has little left to do.  On the batched
+// workload this shortens the step kernels by 2-4 %.
+// - The store is inline assembly: no builtin gives a global store with this bit (the
+//   buffer-store builtin does, but its 32-bit offsets cannot span the largest fields).
+// - A VALU write to the data registers of a store wider than 8 bytes must trail it by one
+//   wait state; the compiler cannot see inside the asm, so the asm carries the wait.
+// - The compiler does not count these stores as outstanding, so a barrier after them does
+//   not wait for them: a kernel may use them only for fields that no other thread of it
+//   reads afterwards (true of the step kernels, whose stencil reads come from LDS or from
+//   fields the kernel does not write).  The end of the kernel waits for them.
 typedef float f4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void store_wt(void *p, f4v v) {
     asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 1" : : "v"(p), "v"(v) : "memory");
 }
-__device__ __forceinline__ void sp_store(double2 *__restrict__ a, int Vtot, int f, double2 b0,
-                                         double2 b1) {
+__device__ __forceinline__ void sp_store_wt(double2 *__restrict__ a, int Vtot, int f, double2 b0,
+                                            double2 b1) {
     store_wt(a + f, __builtin_bit_cast(f4v, b0));
     store_wt(a + (size_t)Vtot + f, __builtin_bit_cast(f4v, b1));
 }
-__device__ __forceinline__ void sp_store(float4 *__restrict__ a, int, int f, float2 b0, float2 b1) {
+__device__ __forceinline__ void sp_store_wt(float4 *__restrict__ a, int, int f, float2 b0, float2 b1) {
     f4v v = {b0.x, b0.y, b1.x, b1.y};
     store_wt(a + f, v);
 }
@@ -520,8 +534,8 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
             else sp_load(f.x64, Vtot, fl, x0, x1);
             x0.x += a_pend * q0.x; x0.y += a_pend * q0.y;
             x1.x += a_pend * q1.x; x1.y += a_pend * q1.y;
-            if constexpr (MIXED) sp_store(f.x32, Vtot, fl, x0, x1);
-            else sp_store(f.x64, Vtot, fl, x0, x1);
+            if constexpr (MIXED) sp_store_wt(f.x32, Vtot, fl, x0, x1);
+            else sp_store_wt(f.x64, Vtot, fl, x0, x1);
             SITES_END
         }
         return;
@@ -544,10 +558,10 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
         double2 a0, a1, o0, o1;
         load(s.flat, a0, a1);
         dslash_site<double, false>(nb, s.flat, Vtot, f.U64, a0, a1, 2.0 + ci.m0, load, o0, o1);
-        sp_store(f.t64, Vtot, s.flat, o0, o1);
+        sp_store_wt(f.t64, Vtot, s.flat, o0, o1);
         C q0, q1;
         sp_load(p_old, Vtot, s.flat, q0, q1);
-        sp_store(p_new, Vtot, s.flat, q0, q1);
+        sp_store_wt(p_new, Vtot, s.flat, q0, q1);
         SITES_END
         return;
     }
@@ -569,11 +583,11 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
         if (!first) {
             x0.x += a_pend * q0.x; x0.y += a_pend * q0.y;
             x1.x += a_pend * q1.x; x1.y += a_pend * q1.y;
-            sp_store(x, Vtot, s.flat, x0, x1);
+            sp_store_wt(x, Vtot, s.flat, x0, x1);
             a0 = cmake<C>(a0.x + beta * q0.x, a0.y + beta * q0.y);
             a1 = cmake<C>(a1.x + beta * q1.x, a1.y + beta * q1.y);
         }
-        sp_store(p_new, Vtot, s.flat, a0, a1);
+        sp_store_wt(p_new, Vtot, s.flat, a0, a1);
         lds[threadIdx.x].a = a0;
         lds[threadIdx.x].b = a1;
     }
@@ -587,7 +601,7 @@ __global__ void k_cg_step1(Geo g, CGFields f, int slot, double tol2, const void 
         };
         C o0, o1;
         dslash_site_links<R, false>(nb, lk, a0, a1, (R)(2.0 + ci.m0), load, o0, o1);
-        sp_store(t, Vtot, s.flat, o0, o1);
+        sp_store_wt(t, Vtot, s.flat, o0, o1);
         v[0] = norm2(o0) + norm2(o1);
     }
     write_partials<1>(v, f.p1, g.nlog, w.logical);
@@ -624,11 +638,11 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
         const float4 q = p[s.flat];
         const double2 r0 = make_double2(h0.x - a0.x, h0.y - a0.y);
         const double2 r1 = make_double2(h1.x - a1.x, h1.y - a1.y);
-        sp_store(f.x64, Vtot, s.flat,
+        sp_store_wt(f.x64, Vtot, s.flat,
                  make_double2(x0.x + (double)(z.x + a_pend * q.x), x0.y + (double)(z.y + a_pend * q.y)),
                  make_double2(x1.x + (double)(z.z + a_pend * q.z), x1.y + (double)(z.w + a_pend * q.w)));
         f.x32[s.flat] = make_float4(0.f, 0.f, 0.f, 0.f);
-        sp_store(f.r32, Vtot, s.flat, make_float2((float)r0.x, (float)r0.y),
+        sp_store_wt(f.r32, Vtot, s.flat, make_float2((float)r0.x, (float)r0.y),
                  make_float2((float)r1.x, (float)r1.y));
         v[0] += norm2(r0) + norm2(r1);
         SITES_END
@@ -676,7 +690,7 @@ __global__ void k_cg_step2(Geo g, CGFields f, int slot, const void *p_new_v) {
         dslash_site_links<R, true>(nb, lk, t0, t1, (R)(2.0 + ci.m0), load, a0, a1);
         r0.x -= alpha * a0.x; r0.y -= alpha * a0.y;
         r1.x -= alpha * a1.x; r1.y -= alpha * a1.y;
-        sp_store(r, Vtot, s.flat, r0, r1);
+        sp_store_wt(r, Vtot, s.flat, r0, r1);
         v[0] = norm2(r0) + norm2(r1);
     }
     write_partials<1>(v, f.p2, g.nlog, w.logical);
