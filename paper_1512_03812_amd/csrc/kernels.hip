@@ -1386,61 +1386,72 @@ int launch_cg_wg(const Geo &g, const CGFields &f, bool mixed, const int *chains,
 // right after convergence, so its other parity may still hold the state before it).
 // count[1] receives the number of unconverged chains that still have iterations left
 // (iters < max_iter).
-__global__ void k_compact(const BlockWork *__restrict__ work, int n, CGState *__restrict__ st,
-                          const ChainInfo *__restrict__ chains, int nchains, int max_iter,
-                          BlockWork *__restrict__ out, int *count) {
-    __shared__ int wave_cnt[kMaxWaves];
-    __shared__ int base;
+__global__ void __launch_bounds__(1024)
+k_compact(const BlockWork *__restrict__ work, int n, CGState *__restrict__ st,
+          const ChainInfo *__restrict__ chains, int nchains, int max_iter,
+          BlockWork *__restrict__ out, int *count) {
+    // The list is taken kEntries * blockDim.x entries at a time; thread t holds entries
+    // t, t + B, t + 2B, ... of the round in registers.  All loads of a round are issued before
+    // any of them is used, so a round costs two memory latencies, and one barrier orders it.
+    constexpr int kEntries = 4;
+    __shared__ int cnt[kEntries][kMaxWaves];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (threadIdx.x == 0) base = 0;
-    __syncthreads();
-    for (int chunk = 0; chunk < n; chunk += blockDim.x) {
-        const int i = chunk + threadIdx.x;
-        int ch = 0, start = 0, logical = 0, spt = 0;
-        bool keep = false;
-        if (i < n) {
-            ch = work[i].chain;
-            start = work[i].start;
-            logical = work[i].logical;
-            spt = work[i].spt;
-            keep = st[ch].converged == 0 && st[nchains + ch].converged == 0;
+    const int B = (int)blockDim.x;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int base = 0;
+    double live[1] = {0.0};
+    for (int r0 = 0; r0 < n; r0 += kEntries * B) {
+        BlockWork wk[kEntries];
+        bool valid[kEntries], keep[kEntries];
+#pragma unroll
+        for (int k = 0; k < kEntries; ++k) {
+            const int i = r0 + k * B + (int)threadIdx.x;
+            valid[k] = i < n;
+            wk[k] = work[valid[k] ? i : 0];
         }
-        const unsigned long long m = __ballot(keep);
-        const int before = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) wave_cnt[wave] = __popcll(m);
-        __syncthreads();
-        int off = base;
-        for (int v = 0; v < wave; ++v) off += wave_cnt[v];
-        if (keep) {
-            BlockWork *o = out + off + before;
-            o->chain = ch;
-            o->start = start;
-            o->logical = logical;
-            o->spt = spt;
+        int c0[kEntries], c1[kEntries], lead[kEntries], left[kEntries];
+#pragma unroll
+        for (int k = 0; k < kEntries; ++k) {
+            const int c = wk[k].chain;
+            c0[k] = st[c].converged;
+            c1[k] = st[nchains + c].converged;
+            lead[k] = wk[k].logical == chains[c].block0;
+            left[k] = st[c].iters < max_iter || st[nchains + c].iters < max_iter;
+        }
+#pragma unroll
+        for (int k = 0; k < kEntries; ++k) {
+            keep[k] = valid[k] && !c0[k] && !c1[k];
+            if (valid[k] && lead[k]) {  // once per chain
+                if (keep[k] && left[k]) live[0] += 1.0;
+                // A chain that converged in the last slot before this check is dropped with
+                // only that slot's parity marked; the other parity still holds the state one
+                // slot earlier.  Copying the final state over it keeps the chain's decision,
+                // owed x update included, from being taken again by a later launch that reads
+                // that parity.  (Either way at least one parity reads converged, so the keep
+                // decisions of the chain's other entries do not depend on this copy.)
+                const int c = wk[k].chain;
+                if (c0[k] != c1[k]) {
+                    if (c0[k]) st[nchains + c] = st[c];
+                    else st[c] = st[nchains + c];
+                }
+            }
+            const unsigned long long m = __ballot(keep[k]);
+            if (lane == 0) cnt[k][wave] = __popcll(m);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int v = 0; v < nw; ++v) tot += wave_cnt[v];
+#pragma unroll
+        for (int k = 0; k < kEntries; ++k) {
+            int off = base, tot = 0;
+            for (int v = 0; v < nw; ++v) {
+                const int x = cnt[k][v];
+                off += v < wave ? x : 0;
+                tot += x;
+            }
+            const unsigned long long m = __ballot(keep[k]);
+            if (keep[k]) out[off + __popcll(m & below)] = wk[k];
             base += tot;
         }
-        __syncthreads();
-    }
-    double live[1] = {0.0};
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int c = work[i].chain;
-        if (work[i].logical != chains[c].block0) continue;  // each chain once
-        const int c0 = st[c].converged, c1 = st[nchains + c].converged;
-        if (!c0 && !c1 && (st[c].iters < max_iter || st[nchains + c].iters < max_iter))
-            live[0] += 1.0;
-        // A chain that converged in the last slot before this check is dropped with only that
-        // slot's parity marked; the other parity still holds the state one slot earlier.
-        // Copying the final state over it keeps the chain's decision, owed x update included,
-        // from being taken again by a later launch that reads that parity.
-        if (c0 != c1) {
-            if (c0) st[nchains + c] = st[c];
-            else st[c] = st[nchains + c];
-        }
+        __syncthreads();  // cnt is rewritten by the next round
     }
     block_sum_all<1>(live);
     if (threadIdx.x == 0) {
