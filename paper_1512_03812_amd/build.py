@@ -23,6 +23,8 @@ def command(out: str):
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
             # packed FP32 instructions stay off (plain scalar/vector FP32 code only)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # the leading scalar kernel arguments (up to 8 dwords) arrive preloaded in SGPRs
+            "-mllvm", "-amdgpu-kernarg-preload-count=8",
             "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
             *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
 
