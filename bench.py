@@ -34,8 +34,8 @@ METRIC = "HMC trajectories/sec at fixed acceptance; Dslash+CG achieved HBM GB/s"
 # The library attributes algorithmic bytes to its sampled, event-timed CG launches (bytes
 # per site: mixed FP32 slot 112 / 64 for step 1 / step 2, FP64 residual-recomputation slot
 # 144 / 224, FP64 solver 224 / 128; times the sites of the chains not yet converged).
-KERNELS = {0: ("k_cg_step1<true>", "mixed-precision CG step 1: x update, direction, t = D p"),
-           1: ("k_cg_step2<true>", "mixed-precision CG step 2: r -= alpha D^dagger t")}
+KERNELS = {0: ("k_cg_step1<true, false>", "mixed-precision CG step 1: x update, direction, t = D p"),
+           1: ("k_cg_step2<true, false>", "mixed-precision CG step 2: r -= alpha D^dagger t")}
 
 
 def hbm_traffic(kernel):

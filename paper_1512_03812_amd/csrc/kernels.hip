@@ -265,18 +265,36 @@ __device__ __forceinline__ void sp_store(float4 *__restrict__ a, int, int f, flo
 //   not wait for them: a kernel may use them only for fields that no other thread of it
 //   reads afterwards (true of the step kernels, whose stencil reads come from LDS or from
 //   fields the kernel does not write).  The end of the kernel waits for them.
+// - NT adds the non-temporal bit, with which the line is not kept in the Infinity Cache.
+//   That pays when the solver's fields are far larger than that cache (256 MB) and costs
+//   when they fit: on single lattices and batches, an FP32 iteration is 2-4 % faster with it
+//   from 16.7 M sites up, about the same at 4.2 M and 20 % slower at 1 M (the batched
+//   workload, 1.6 M sites, 8 % slower); an FP64 iteration 6-8 % faster from 4.2 M up.
+//   stream_fields() makes the choice.
 typedef float f4v __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void store_wt(void *p, f4v v) {
-    asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 1" : : "v"(p), "v"(v) : "memory");
+template <bool NT> __device__ __forceinline__ void store_wt(void *p, f4v v) {
+    if constexpr (NT)
+        asm volatile("global_store_dwordx4 %0, %1, off sc1 nt\n\ts_nop 1" : : "v"(p), "v"(v) : "memory");
+    else
+        asm volatile("global_store_dwordx4 %0, %1, off sc1\n\ts_nop 1" : : "v"(p), "v"(v) : "memory");
 }
+template <bool NT>
 __device__ __forceinline__ void sp_store_wt(double2 *__restrict__ a, int Vtot, int f, double2 b0,
                                             double2 b1) {
-    store_wt(a + f, __builtin_bit_cast(f4v, b0));
-    store_wt(a + (size_t)Vtot + f, __builtin_bit_cast(f4v, b1));
+    store_wt<NT>(a + f, __builtin_bit_cast(f4v, b0));
+    store_wt<NT>(a + (size_t)Vtot + f, __builtin_bit_cast(f4v, b1));
 }
+template <bool NT>
 __device__ __forceinline__ void sp_store_wt(float4 *__restrict__ a, int, int f, float2 b0, float2 b1) {
     f4v v = {b0.x, b0.y, b1.x, b1.y};
-    store_wt(a + f, v);
+    store_wt<NT>(a + f, v);
+}
+
+// Non-temporal stores in the step kernels when the fields one iteration touches (about
+// 88 B/site in FP32 with FP32 link angles, 192 B/site in FP64) exceed twice the Infinity Cache.
+static bool stream_fields(const Geo &g, bool mixed) {
+    const double bytes = (double)g.Vtot * (mixed ? 88.0 : 192.0);
+    return bytes > 512.0 * 1024 * 1024;
 }
 template <bool MIXED> struct Prec;
 template <> struct Prec<false> { using R = double; using S = double2; };  // S: spinor storage
@@ -439,7 +457,7 @@ __global__ void k_cg_init(Geo g, CGFields f, double delta2) {
 // the CG states) and the slot as leading scalar arguments: the library is built with kernarg
 // preloading, so these arrive in SGPRs at wave launch and the first table load does not wait
 // for a kernarg load.  (Geo and CGFields still carry the same pointers for the rest.)
-template <bool MIXED>
+template <bool MIXED, bool NT>
 __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
                            CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f,
                            double tol2, const void *p_old_v, void *p_new_v, int decide_only,
@@ -542,8 +560,8 @@ __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *
             else sp_load(f.x64, Vtot, fl, x0, x1);
             x0.x += a_pend * q0.x; x0.y += a_pend * q0.y;
             x1.x += a_pend * q1.x; x1.y += a_pend * q1.y;
-            if constexpr (MIXED) sp_store_wt(f.x32, Vtot, fl, x0, x1);
-            else sp_store_wt(f.x64, Vtot, fl, x0, x1);
+            if constexpr (MIXED) sp_store_wt<NT>(f.x32, Vtot, fl, x0, x1);
+            else sp_store_wt<NT>(f.x64, Vtot, fl, x0, x1);
             SITES_END
         }
         return;
@@ -566,10 +584,10 @@ __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *
         double2 a0, a1, o0, o1;
         load(s.flat, a0, a1);
         dslash_site<double, false>(nb, s.flat, Vtot, f.U64, a0, a1, 2.0 + ci.m0, load, o0, o1);
-        sp_store_wt(f.t64, Vtot, s.flat, o0, o1);
+        sp_store_wt<NT>(f.t64, Vtot, s.flat, o0, o1);
         C q0, q1;
         sp_load(p_old, Vtot, s.flat, q0, q1);
-        sp_store_wt(p_new, Vtot, s.flat, q0, q1);
+        sp_store_wt<NT>(p_new, Vtot, s.flat, q0, q1);
         SITES_END
         return;
     }
@@ -591,11 +609,11 @@ __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *
         if (!first) {
             x0.x += a_pend * q0.x; x0.y += a_pend * q0.y;
             x1.x += a_pend * q1.x; x1.y += a_pend * q1.y;
-            sp_store_wt(x, Vtot, s.flat, x0, x1);
+            sp_store_wt<NT>(x, Vtot, s.flat, x0, x1);
             a0 = cmake<C>(a0.x + beta * q0.x, a0.y + beta * q0.y);
             a1 = cmake<C>(a1.x + beta * q1.x, a1.y + beta * q1.y);
         }
-        sp_store_wt(p_new, Vtot, s.flat, a0, a1);
+        sp_store_wt<NT>(p_new, Vtot, s.flat, a0, a1);
         lds[threadIdx.x].a = a0;
         lds[threadIdx.x].b = a1;
     }
@@ -609,13 +627,13 @@ __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *
         };
         C o0, o1;
         dslash_site_links<R, false>(nb, lk, a0, a1, (R)(2.0 + ci.m0), load, o0, o1);
-        sp_store_wt(t, Vtot, s.flat, o0, o1);
+        sp_store_wt<NT>(t, Vtot, s.flat, o0, o1);
         v[0] = norm2(o0) + norm2(o1);
     }
     write_partials<1>(v, f.p1, g.nlog, w.logical);
 }
 
-template <bool MIXED>
+template <bool MIXED, bool NT>
 __global__ void k_cg_step2(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
                            CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f,
                            const void *p_new_v) {
@@ -655,11 +673,11 @@ __global__ void k_cg_step2(const BlockWork *__restrict__ work, const ChainInfo *
         const float4 q = p[s.flat];
         const double2 r0 = make_double2(h0.x - a0.x, h0.y - a0.y);
         const double2 r1 = make_double2(h1.x - a1.x, h1.y - a1.y);
-        sp_store_wt(f.x64, Vtot, s.flat,
+        sp_store_wt<NT>(f.x64, Vtot, s.flat,
                  make_double2(x0.x + (double)(z.x + a_pend * q.x), x0.y + (double)(z.y + a_pend * q.y)),
                  make_double2(x1.x + (double)(z.z + a_pend * q.z), x1.y + (double)(z.w + a_pend * q.w)));
         f.x32[s.flat] = make_float4(0.f, 0.f, 0.f, 0.f);
-        sp_store_wt(f.r32, Vtot, s.flat, make_float2((float)r0.x, (float)r0.y),
+        sp_store_wt<NT>(f.r32, Vtot, s.flat, make_float2((float)r0.x, (float)r0.y),
                  make_float2((float)r1.x, (float)r1.y));
         v[0] += norm2(r0) + norm2(r1);
         SITES_END
@@ -707,7 +725,7 @@ __global__ void k_cg_step2(const BlockWork *__restrict__ work, const ChainInfo *
         dslash_site_links<R, true>(nb, lk, t0, t1, (R)(2.0 + ci.m0), load, a0, a1);
         r0.x -= alpha * a0.x; r0.y -= alpha * a0.y;
         r1.x -= alpha * a1.x; r1.y -= alpha * a1.y;
-        sp_store_wt(r, Vtot, s.flat, r0, r1);
+        sp_store_wt<NT>(r, Vtot, s.flat, r0, r1);
         v[0] = norm2(r0) + norm2(r1);
     }
     write_partials<1>(v, f.p2, g.nlog, w.logical);
@@ -739,19 +757,28 @@ static void launch_stamped(K kernel, dim3 grid, dim3 block, size_t lds, hipStrea
     else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
 }
 
+template <bool MIXED, bool NT>
+static void launch_step1_inst(const Geo &g, const CGFields &f, int slot, double tol, const void *p_old,
+                              void *p_new, bool decide_only, int sample, hipStream_t s, hipEvent_t ev0,
+                              hipEvent_t ev1) {
+    using C = cplx_t<typename Prec<MIXED>::R>;
+    launch_stamped(k_cg_step1<MIXED, NT>, dim3(g.nblocks), dim3(g.block), g.block * sizeof(LdsSpinor<C>),
+                   s, ev0, ev1, g.work, g.chains, f.st, slot, g.nchains, g, f, tol * tol, p_old, p_new,
+                   decide_only ? 1 : 0, sample);
+}
+
 void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
                      const void *p_old, void *p_new, bool decide_only, int sample, hipStream_t s,
                      hipEvent_t ev0, hipEvent_t ev1) {
-    if (mixed)
-        launch_stamped(k_cg_step1<true>, dim3(g.nblocks), dim3(g.block),
-                       g.block * sizeof(LdsSpinor<float2>), s, ev0, ev1,
-                       g.work, g.chains, f.st, slot, g.nchains, g, f, tol * tol, p_old,
-                       p_new, decide_only ? 1 : 0, sample);
+    const bool nt = stream_fields(g, mixed);
+    if (mixed && nt)
+        launch_step1_inst<true, true>(g, f, slot, tol, p_old, p_new, decide_only, sample, s, ev0, ev1);
+    else if (mixed)
+        launch_step1_inst<true, false>(g, f, slot, tol, p_old, p_new, decide_only, sample, s, ev0, ev1);
+    else if (nt)
+        launch_step1_inst<false, true>(g, f, slot, tol, p_old, p_new, decide_only, sample, s, ev0, ev1);
     else
-        launch_stamped(k_cg_step1<false>, dim3(g.nblocks), dim3(g.block),
-                       g.block * sizeof(LdsSpinor<double2>), s, ev0, ev1,
-                       g.work, g.chains, f.st, slot, g.nchains, g, f, tol * tol, p_old,
-                       p_new, decide_only ? 1 : 0, sample);
+        launch_step1_inst<false, false>(g, f, slot, tol, p_old, p_new, decide_only, sample, s, ev0, ev1);
 }
 
 // One workgroup per sampled slot: the sum over chains of its byte row, which is then zeroed
@@ -776,16 +803,21 @@ void launch_sample_sums(double *samples, int n, int nchains, double *sums, hipSt
     if (n > 0) hipLaunchKernelGGL(k_sample_sums, dim3(n), dim3(256), 0, s, samples, nchains, sums);
 }
 
+template <bool MIXED, bool NT>
+static void launch_step2_inst(const Geo &g, const CGFields &f, int slot, const void *p_new, hipStream_t s,
+                              hipEvent_t ev0, hipEvent_t ev1) {
+    using C = cplx_t<typename Prec<MIXED>::R>;
+    launch_stamped(k_cg_step2<MIXED, NT>, dim3(g.nblocks), dim3(g.block), g.block * sizeof(LdsSpinor<C>),
+                   s, ev0, ev1, g.work, g.chains, f.st, slot, g.nchains, g, f, p_new);
+}
+
 void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (mixed)
-        launch_stamped(k_cg_step2<true>, dim3(g.nblocks), dim3(g.block),
-                       g.block * sizeof(LdsSpinor<float2>), s, ev0, ev1,
-                       g.work, g.chains, f.st, slot, g.nchains, g, f, p_new);
-    else
-        launch_stamped(k_cg_step2<false>, dim3(g.nblocks), dim3(g.block),
-                       g.block * sizeof(LdsSpinor<double2>), s, ev0, ev1,
-                       g.work, g.chains, f.st, slot, g.nchains, g, f, p_new);
+    const bool nt = stream_fields(g, mixed);
+    if (mixed && nt) launch_step2_inst<true, true>(g, f, slot, p_new, s, ev0, ev1);
+    else if (mixed) launch_step2_inst<true, false>(g, f, slot, p_new, s, ev0, ev1);
+    else if (nt) launch_step2_inst<false, true>(g, f, slot, p_new, s, ev0, ev1);
+    else launch_step2_inst<false, false>(g, f, slot, p_new, s, ev0, ev1);
 }
 
 void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s) {
