@@ -291,6 +291,32 @@ def test_two_chain_groups_match_one_bitwise(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_streaming_stores_keep_the_bits(prec):
+    """A batch of 400 chains of 128 x 128 (6.6 M sites: its solver fields exceed twice the
+    Infinity Cache, so the CG step kernels store with the non-temporal bit, in FP64 and in
+    mixed precision) gives each chain the bits that a batch of its first 8 chains gives (0.13 M
+    sites, plain write-through stores): the store policy changes where lines are cached,
+    not what is computed."""
+    m = hmc()
+    out = []
+    for n in (400, 8):
+        lat = m.Lattice.batch([128] * n, [128] * n, 2.0, [0.1 + 0.01 * (c % 5) for c in range(n)],
+                              seed=77)
+        lat.set_persistent_limit(0)
+        lat.hot_start()
+        lat.refresh()
+        x, r = lat.cg_solve(lat.phi, tol=1e-12 if prec == "fp64" else 1e-10, prec=prec)
+        torch.cuda.synchronize()
+        out.append((x[:, :8 * 128 * 128].cpu().numpy().copy(), r.iters[:8], r.converged[:8]))
+        del lat, x
+        torch.cuda.empty_cache()
+    (xb, ib, cb), (xs, is_, cs) = out
+    assert all(cb) and all(cs)
+    assert ib == is_
+    assert np.array_equal(xb, xs)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_concurrent_contexts_match_sequential(prec):
     """hmc_trajectories_concurrent: two contexts on two streams advanced from two host threads
     give the bits each context gives alone."""
