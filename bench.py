@@ -306,8 +306,8 @@ def cpu_baseline(args):
 
 def run_sweep(args):
     """Roofline sweep on single large lattices, and on one batch of equal chains (beta 2,
-    m0 0.1, hot start): FP64 dslash, and CG iterations in FP64 and in mixed precision (128
-    iteration slots, sampled events), beside the library's streaming copy of 1 GiB (and
+    m0 0.1, hot start): FP64 dslash, and CG iterations in FP64 and in mixed precision (512
+    iteration slots, every 32nd event-timed), beside the library's streaming copy of 1 GiB (and
     torch's copy) as the measured bandwidth ceiling."""
     import torch
     import paper_1512_03812_amd as hmc
@@ -365,7 +365,7 @@ def run_sweep(args):
         for prec in ("fp64", "mixed"):
             lat.set_persistent_limit(0)
             lat.set_timing(True)
-            lat.cg_solve(psi, tol=1e-30, max_iter=128, prec=prec)
+            lat.cg_solve(psi, tol=1e-30, max_iter=512, prec=prec)
             s1, s2 = lat.kernel_stats(0), lat.kernel_stats(1)
             lat.set_timing(False)
             t1, t2 = s1["timed_ms"] * 1e-3, s2["timed_ms"] * 1e-3
