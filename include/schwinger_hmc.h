@@ -204,7 +204,7 @@ int hmc_set_cg_groups(hmc_ctx *ctx, int groups);
  * the stencil rows two beyond a workgroup's own are recomputed.  Otherwise, or with on = 0
  * (default), each iteration takes two kernels.  Both give the CG iterates up to rounding.
  * The fused kernel moves 18 % fewer bytes per iteration and saves a kernel boundary, but
- * the recomputed rows and its register use make it slower on MI355X (about 9 % on the
+ * the recomputed rows and its register use make it slower on MI355X (about 15 % on the
  * batched workload), so it runs only when asked for. */
 int hmc_set_fused_cg(hmc_ctx *ctx, int on);
 
