@@ -864,6 +864,46 @@ def test_precision_workload_matches_oracle_trajectories(L):
             assert r.n_dinv == ref["n_dinv"]
 
 
+def _batched_golden():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "batched_workload_trajectories.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def test_full_batched_workload_matches_oracle_on_sampled_chains():
+    """The batched benchmark workload at its full size (512 chains of 16^2 to 128^2, 1.56 M
+    sites) in the launch configuration the benchmark times (workgroups of 256, persistent
+    solver off), in mixed precision: the first trajectory from the hot start, on sampled
+    chains (the first chain of each size and the 128^2 chain with the smallest mass), against
+    stored FP64 oracle trajectories.  The same accept decisions and |Delta H error| <= 1e-8
+    with both solvers at 1e-12; at the workload's own true residual of 1e-10 the decisions
+    still agree and the error stays below 1e-6."""
+    from bench import workload
+    g = _batched_golden()
+    L, beta, m0 = workload(g["seed"], g["n_chains"])
+    for tol, bound in ((g["tol"], 1e-8), (1e-10, 1e-6)):
+        print(f"512-chain workload, tol={tol}", flush=True)
+        lat = hmc().Lattice.batch(L, L, beta, m0, seed=g["seed"])
+        lat.set_persistent_limit(0)
+        lat.set_block_size(256)
+        lat.hot_start()
+        lat.set_solver(tol=tol, max_iter=20000)
+        r = lat.trajectory(g["scheme"], g["tau"], g["n_outer"], g["n_inner"], prec="mixed")
+        assert all(st == 0 for st in r.status)
+        assert r.n_dinv == g["chains"][0]["n_dinv"]
+        for ref in g["chains"]:
+            c = ref["chain"]
+            assert (L[c], beta[c], m0[c]) == (ref["L"], ref["beta"], ref["m0"])
+            assert r.accepted[c] == ref["accepted"], c
+            assert abs(r.dH[c] - ref["dH"]) <= bound, (c, r.dH[c], ref["dH"])
+            assert abs(r.H0[c] - ref["H0"]) <= 1e-11 * abs(ref["H0"]), c
+            assert abs(r.plaquette[c] - ref["plaquette"]) <= 1e-9, c
+        del lat
+        torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------------------ exact physics of the batch
 def test_batched_quenched_plaquette_is_exact():
     """Quenched 2-D U(1) on 4 x 4 tori, 128 chains advanced together: the mean plaquette
