@@ -1,0 +1,34 @@
+"""The stored oracle trajectories match what the oracle computes now (the cheap entries are
+recomputed) and the inputs they were made for (the batched workload recipe)."""
+import json
+import os
+
+import oracle
+
+HERE = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(HERE, name)) as fh:
+        return json.load(fh)
+
+
+def test_batched_golden_matches_the_workload_recipe_and_the_oracle():
+    from bench import workload
+    g = _load("batched_workload_trajectories.json")
+    L, beta, m0 = workload(g["seed"], g["n_chains"])
+    assert sorted({c["L"] for c in g["chains"]}) == [16, 32, 64, 128]
+    for ref in g["chains"]:
+        c = ref["chain"]
+        assert (L[c], beta[c], m0[c]) == (ref["L"], ref["beta"], ref["m0"])
+    for ref in g["chains"]:
+        if ref["L"] > 32:
+            continue  # the larger chains take the oracle tens of seconds
+        c = ref["chain"]
+        q = oracle.random_links(ref["L"], ref["L"], g["seed"], c)
+        _, info = oracle.hmc_trajectory(q, ref["beta"], ref["m0"], g["seed"], c, 0, g["scheme"],
+                                        g["tau"], g["n_outer"], g["n_inner"], tol=g["tol"])
+        assert info["accepted"] == ref["accepted"]
+        assert abs(info["dH"] - ref["dH"]) <= 1e-12 * max(1.0, abs(ref["dH"]))
+        assert abs(info["H0"] - ref["H0"]) <= 1e-12 * abs(ref["H0"])
+        assert info["n_dinv"] == ref["n_dinv"]
