@@ -237,7 +237,11 @@ int hmc_dslash_dagger(hmc_ctx *ctx, const void *in, void *out);
  * one solve is two inversions of D).  Stops per chain when ||r|| <= tol ||phi||;
  * prec = HMC_PREC_MIXED runs the iterations in FP32 with FP64 reliable updates and
  * stops on the FP64 true residual.  info: array of n_chains (may be NULL).
- * Returns HMC_E_NOCONV if any chain hit max_iter (x then holds its last iterate). */
+ * Each chain stops on its own: a chain that reaches max_iter iterations, or whose residual
+ * norm is not finite (a NaN or Inf in its links or phi), stops unconverged with x holding its
+ * last iterate, while the other chains go on; info[c].converged tells them apart.  Returns
+ * HMC_E_NAN if some chain's residual was not finite, else HMC_E_NOCONV if some chain hit
+ * max_iter, else HMC_OK. */
 int hmc_cg_solve(hmc_ctx *ctx, const void *phi, void *x, double tol, int max_iter, int prec,
                  hmc_cg_info *info);
 
@@ -263,7 +267,9 @@ int hmc_gauge_force(hmc_ctx *ctx, double *g);
 
 /* Actions per chain (host arrays of n_chains, any may be NULL): S_G (Eq. (13)), mean
  * plaquette, and, if phi is not NULL, S_F = phi^dagger (D^dagger D)^{-1} phi (Eq. (14))
- * solved to tol in FP64. */
+ * solved to tol in FP64.  If a chain's solve stops unconverged, S_G and the plaquette are still
+ * filled, that chain's S_F is NaN and the call returns HMC_E_NOCONV (iteration cap) or
+ * HMC_E_NAN (non-finite residual). */
 int hmc_actions(hmc_ctx *ctx, const void *phi, double tol, double *s_gauge, double *plaquette,
                 double *s_fermion);
 
@@ -312,8 +318,11 @@ int hmc_set_fg_mode(hmc_ctx *ctx, int mode);
  * streams 1 and 2 (phi = D^dagger zeta), molecular dynamics with the given scheme
  * (h = tau / n_outer; n_inner = M inner steps per inner call of the nested schemes,
  * ignored otherwise), Delta H in FP64, Metropolis test with stream 3, links restored on
- * rejection.  info: n_chains entries (may be NULL).  Returns HMC_OK, or the first
- * failing chain's status (the failing chain is rejected, the others proceed). */
+ * rejection.  info: n_chains entries (may be NULL).  A chain fails when one of its solves
+ * stops unconverged (status HMC_E_NOCONV at the iteration cap of hmc_set_solver,
+ * HMC_E_NAN on a non-finite residual) or its Delta H is not finite (HMC_E_NAN); a failing
+ * chain is rejected and gets its links back, and every other chain computes exactly what it
+ * computes without the failing one.  Returns HMC_OK, or the first failing chain's status. */
 int hmc_trajectory(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inner, int prec,
                    hmc_traj_info *info);
 

@@ -69,6 +69,8 @@ def lib():
             "orc_philox4x32_10": (None, [P, P, P]),
             "orc_uniform_pair": (None, [U64, U32, U32, U32, U32, P]),
             "orc_gaussian_pair": (None, [U64, U32, U32, U32, U32, P]),
+            "orc_ln_unit": (D, [D]),
+            "orc_sincos_turn": (None, [D, P, P]),
             "orc_random_links": (None, [I, I, U64, U32, P]),
             "orc_random_momenta": (None, [I, I, U64, U32, U32, P]),
             "orc_random_zeta": (None, [I, I, U64, U32, U32, P]),
@@ -128,6 +130,20 @@ def uniform_pair(seed, chain, traj, stream, index) -> np.ndarray:
     out = np.zeros(2)
     lib().orc_uniform_pair(seed, chain, traj, stream, index, _p(out))
     return out
+
+
+def ln_unit(y: float) -> float:
+    """ln y for 0 < y <= 1 by the written method of the Box-Muller step (Cody-Waite reduction,
+    atanh series)."""
+    return lib().orc_ln_unit(float(y))
+
+
+def sincos_turn(u: float):
+    """(sin 2 pi u, cos 2 pi u) for 0 <= u < 1 by the written method of the Box-Muller step
+    (exact quadrant reduction, Taylor series on [-pi/4, pi/4])."""
+    sn, cs = ctypes.c_double(), ctypes.c_double()
+    lib().orc_sincos_turn(float(u), ctypes.byref(sn), ctypes.byref(cs))
+    return sn.value, cs.value
 
 
 def gaussian_pair(seed, chain, traj, stream, index) -> np.ndarray:

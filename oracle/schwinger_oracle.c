@@ -91,7 +91,8 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
  *   index   : lexicographic link index 2n+mu (streams 0, 1), spinor index 2n+s
  *             (stream 2), 0 (stream 3)
  *   uniform : 64-bit word (w0 | w1 << 32) >> 11, times 2^-53, in [0, 1)
- *   gaussian pair (Box-Muller): r = sqrt(-2 log(1 - ua)), (r cos(2 pi ub), r sin(2 pi ub))
+ *   gaussian pair (Box-Muller): r = sqrt(-2 ln(1 - ua)), (r cos(2 pi ub), r sin(2 pi ub)),
+ *             with ln, sin and cos evaluated as below (orc_ln_unit, orc_sincos_turn)
  */
 enum { STREAM_LINKS = 0, STREAM_MOMENTA = 1, STREAM_PSEUDOFERMION = 2, STREAM_METROPOLIS = 3 };
 
@@ -118,15 +119,98 @@ void orc_uniform_pair(uint64_t seed, uint32_t chain, uint32_t traj, uint32_t str
     out[1] = u01(w[2], w[3]);
 }
 
+/*
+ * The logarithm and the sine and cosine of Box-Muller, written out so that the GPU path can
+ * evaluate the same sequence of IEEE operations (+, -, *, / rounded to nearest; the file is
+ * compiled without contraction into fused multiply-adds) and obtain the same bits.  The
+ * method is the argument reduction of Cody and Waite (Software Manual for the Elementary
+ * Functions, 1980) with truncated series whose coefficients are exact reciprocals:
+ *
+ * ln y, 0 < y <= 1:  y = m 2^e with m in [1/sqrt 2, sqrt 2) (frexp, exact);
+ *   f = (m - 1) / (m + 1), s = f^2;  ln m = 2 atanh f = 2 (f + f s (1/3 + s (1/5 + ...
+ *   + s (1/23)))) (|f| <= 0.1716, s <= 0.0295: the first omitted term is below 2^-60 of f);
+ *   ln y = (e C2 + ln m) + e C1, with C1 = 355/512 and C2 = ln 2 - C1 rounded
+ *   (C1 has 9 significant bits, so e C1 is exact).
+ *
+ * sin and cos of 2 pi u, 0 <= u < 1 (u a multiple of 2^-53):  n = floor(4u + 1/2) and
+ *   d = u - n/4 in [-1/8, 1/8] (both exact); x = d P1 + d P2 with P1 + P2 = 2 pi
+ *   (P1 = 2 pi rounded, P2 the rounded remainder), |x| <= pi/4;
+ *   z = x^2, sin x = x - x (z Q), Q = 1/3! - z/5! + z^2/7! - ... - z^9/21!,
+ *   cos x = 1 - z P, P = 1/2! - z/4! + z^2/6! - ... + z^10/22! (both by Horner's rule from
+ *   the highest power; the first omitted terms are below 2^-60 of the result); the quadrant
+ *   n mod 4 then rotates (sin x, cos x) by multiples of pi/2.
+ */
+double orc_ln_unit(double y)
+{
+    int e;
+    double m = frexp(y, &e);                      /* y = m 2^e, m in [1/2, 1) */
+    if (m < 0.70710678118654752440) { m = m * 2.0; e = e - 1; }
+    const double f = (m - 1.0) / (m + 1.0);
+    const double s = f * f;
+    double poly = 1.0 / 23.0;
+    poly = 1.0 / 21.0 + s * poly;
+    poly = 1.0 / 19.0 + s * poly;
+    poly = 1.0 / 17.0 + s * poly;
+    poly = 1.0 / 15.0 + s * poly;
+    poly = 1.0 / 13.0 + s * poly;
+    poly = 1.0 / 11.0 + s * poly;
+    poly = 1.0 / 9.0 + s * poly;
+    poly = 1.0 / 7.0 + s * poly;
+    poly = 1.0 / 5.0 + s * poly;
+    poly = 1.0 / 3.0 + s * poly;
+    const double lnm = 2.0 * (f + f * (s * poly));
+    const double C1 = 0.693359375, C2 = -2.121944400546905827679e-4;
+    const double de = (double)e;
+    return (de * C2 + lnm) + de * C1;
+}
+
+void orc_sincos_turn(double u, double *sn, double *cs)
+{
+    const double n = floor(4.0 * u + 0.5);
+    const double d = u - 0.25 * n;
+    const double P1 = 6.283185307179586, P2 = 2.4492935982947064e-16;
+    const double x = d * P1 + d * P2;
+    const double z = x * x;
+    double ps = -1.0 / 51090942171709440000.0;    /* -1/21! */
+    ps = 1.0 / 121645100408832000.0 + z * ps;     /*  1/19! */
+    ps = -1.0 / 355687428096000.0 + z * ps;       /* -1/17! */
+    ps = 1.0 / 1307674368000.0 + z * ps;          /*  1/15! */
+    ps = -1.0 / 6227020800.0 + z * ps;            /* -1/13! */
+    ps = 1.0 / 39916800.0 + z * ps;               /*  1/11! */
+    ps = -1.0 / 362880.0 + z * ps;                /* -1/9! */
+    ps = 1.0 / 5040.0 + z * ps;                   /*  1/7! */
+    ps = -1.0 / 120.0 + z * ps;                   /* -1/5! */
+    ps = 1.0 / 6.0 + z * ps;                      /*  1/3! */
+    const double sx = x - x * (z * ps);
+    double pc = 1.0 / 1124000727777607680000.0;   /*  1/22! */
+    pc = -1.0 / 2432902008176640000.0 + z * pc;   /* -1/20! */
+    pc = 1.0 / 6402373705728000.0 + z * pc;       /*  1/18! */
+    pc = -1.0 / 20922789888000.0 + z * pc;        /* -1/16! */
+    pc = 1.0 / 87178291200.0 + z * pc;            /*  1/14! */
+    pc = -1.0 / 479001600.0 + z * pc;             /* -1/12! */
+    pc = 1.0 / 3628800.0 + z * pc;                /*  1/10! */
+    pc = -1.0 / 40320.0 + z * pc;                 /* -1/8! */
+    pc = 1.0 / 720.0 + z * pc;                    /*  1/6! */
+    pc = -1.0 / 24.0 + z * pc;                    /* -1/4! */
+    pc = 1.0 / 2.0 + z * pc;                      /*  1/2! */
+    const double cx = 1.0 - z * pc;
+    switch (((int)n) & 3) {
+    case 0: *sn = sx; *cs = cx; break;
+    case 1: *sn = cx; *cs = -sx; break;
+    case 2: *sn = -sx; *cs = -cx; break;
+    default: *sn = -cx; *cs = sx; break;
+    }
+}
+
 void orc_gaussian_pair(uint64_t seed, uint32_t chain, uint32_t traj, uint32_t stream,
                        uint32_t index, double out[2])
 {
-    double u[2];
+    double u[2], sn, cs;
     orc_uniform_pair(seed, chain, traj, stream, index, u);
-    double r = sqrt(-2.0 * log(1.0 - u[0]));
-    double a = 6.283185307179586 * u[1];
-    out[0] = r * cos(a);
-    out[1] = r * sin(a);
+    double r = sqrt(-2.0 * orc_ln_unit(1.0 - u[0]));
+    orc_sincos_turn(u[1], &sn, &cs);
+    out[0] = r * cs;
+    out[1] = r * sn;
 }
 
 /* uniform hot start q in [-pi, pi) */

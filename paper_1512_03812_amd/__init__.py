@@ -126,8 +126,16 @@ class Lattice:
 
     # ---------------------------------------------------------------- plumbing
     def _check(self, rc):
-        if rc != 0 and rc != _lib.HMC_E_NOCONV:
+        """Raises HMCError for every nonzero code, an unconverged solve included."""
+        if rc != 0:
             raise HMCError(rc, self._lib.hmc_last_error(self._ctx).decode())
+        return rc
+
+    def _check_solve(self, rc):
+        """As _check, except for the codes that say some chains stopped unconverged
+        (HMC_E_NOCONV, HMC_E_NAN): the caller returns per-chain solver results that say which."""
+        if rc not in (0, _lib.HMC_E_NOCONV, _lib.HMC_E_NAN):
+            self._check(rc)
         return rc
 
     def __del__(self):
@@ -319,23 +327,25 @@ class Lattice:
         """x = (D^dagger D)^{-1} phi; returns (x, CGResult)."""
         out = self.new_spinor() if out is None else out
         info = (_lib.CGInfo * self.n_chains)()
-        self._check(self._lib.hmc_cg_solve(self._ctx, _ptr(phi), _ptr(out), tol, max_iter,
-                                           _prec(prec), info))
+        self._check_solve(self._lib.hmc_cg_solve(self._ctx, _ptr(phi), _ptr(out), tol, max_iter,
+                                                 _prec(prec), info))
         return out, self._cg_result(info)
 
     # ---------------------------------------------------------------- forces (Sec. 3)
     def fermion_force(self, phi: torch.Tensor, tol=1e-12, max_iter=100000, prec="fp64",
                       out: Optional[torch.Tensor] = None):
-        """f = dS_F/dq (Eq. (17)); returns (f, S_F per chain, CGResult)."""
+        """f = dS_F/dq (Eq. (17)); returns (f, S_F per chain, CGResult).  A chain whose solve
+        stopped unconverged is flagged in CGResult.converged (its f is not the force)."""
         out = self.new_links() if out is None else out
         info = (_lib.CGInfo * self.n_chains)()
         sf = (ctypes.c_double * self.n_chains)()
-        self._check(self._lib.hmc_fermion_force(self._ctx, _ptr(phi), _ptr(out), tol, max_iter,
-                                                _prec(prec), info, sf))
+        self._check_solve(self._lib.hmc_fermion_force(self._ctx, _ptr(phi), _ptr(out), tol,
+                                                      max_iter, _prec(prec), info, sf))
         return out, list(sf), self._cg_result(info)
 
     def fermion_action(self, phi: torch.Tensor, tol=1e-12, max_iter=100000, prec="fp64"):
-        """S_F per chain (Eq. (14)); leaves xi and chi = D xi in the workspace."""
+        """S_F per chain (Eq. (14)); leaves xi and chi = D xi in the workspace.  Raises
+        HMCError if a chain's solve stops unconverged."""
         info = (_lib.CGInfo * self.n_chains)()
         sf = (ctypes.c_double * self.n_chains)()
         self._check(self._lib.hmc_fermion_force(self._ctx, _ptr(phi), None, tol, max_iter,
@@ -384,10 +394,8 @@ class Lattice:
         w = _lib.FORCE_SETS[which] if isinstance(which, str) else int(which)
         out = self.new_links() if out is None else out
         info = (_lib.CGInfo * self.n_chains)()
-        rc = self._lib.hmc_hessian_vector(self._ctx, w, _ptr(phi), _ptr(v), _ptr(out), _prec(prec),
-                                          info)
-        if rc != _lib.HMC_E_NOCONV:
-            self._check(rc)
+        self._check_solve(self._lib.hmc_hessian_vector(self._ctx, w, _ptr(phi), _ptr(v), _ptr(out),
+                                                       _prec(prec), info))
         return out, (self._cg_result(info) if w != FORCE_GAUGE else None)
 
     def force_gradient_term(self, which="total", phi=None, prec="fp64",
@@ -397,9 +405,8 @@ class Lattice:
         w = _lib.FORCE_SETS[which] if isinstance(which, str) else int(which)
         out = self.new_links() if out is None else out
         info = (_lib.CGInfo * self.n_chains)()
-        rc = self._lib.hmc_force_gradient_term(self._ctx, w, _ptr(phi), _ptr(out), _prec(prec), info)
-        if rc != _lib.HMC_E_NOCONV:
-            self._check(rc)
+        self._check_solve(self._lib.hmc_force_gradient_term(self._ctx, w, _ptr(phi), _ptr(out),
+                                                            _prec(prec), info))
         return out, (self._cg_result(info) if w != FORCE_GAUGE else None)
 
     # ---------------------------------------------------------------- updates (Sec. 2.1)
@@ -419,10 +426,8 @@ class Lattice:
 
     def trajectory(self, scheme="adapted_nested_fg", tau=1.0, n_outer=8, n_inner=4, prec="fp64"):
         info = (_lib.TrajInfo * self.n_chains)()
-        rc = self._lib.hmc_trajectory(self._ctx, _scheme(scheme), tau, n_outer, n_inner,
-                                      _prec(prec), info)
-        if rc not in (0, _lib.HMC_E_NOCONV, _lib.HMC_E_NAN):
-            self._check(rc)
+        self._check_solve(self._lib.hmc_trajectory(self._ctx, _scheme(scheme), tau, n_outer,
+                                                   n_inner, _prec(prec), info))
         return self._traj_result(info)
 
     def refresh(self):
@@ -432,10 +437,8 @@ class Lattice:
     def integrate(self, scheme="adapted_nested_fg", tau=1.0, n_outer=8, n_inner=4, prec="fp64"):
         """Molecular dynamics only from the current q, p, phi (no refresh, no Metropolis)."""
         info = (_lib.TrajInfo * self.n_chains)()
-        rc = self._lib.hmc_integrate(self._ctx, _scheme(scheme), tau, n_outer, n_inner,
-                                     _prec(prec), info)
-        if rc not in (0, _lib.HMC_E_NOCONV, _lib.HMC_E_NAN):
-            self._check(rc)
+        self._check_solve(self._lib.hmc_integrate(self._ctx, _scheme(scheme), tau, n_outer,
+                                                  n_inner, _prec(prec), info))
         return self._traj_result(info)
 
 
@@ -459,7 +462,10 @@ class _ActionForce(torch.autograd.Function):
         q, phi = ctx.saved_tensors
         lat = ctx.lat
         lat.q.copy_(q.detach())
-        hv, _ = lat.hessian_vector(grad_F.detach().contiguous(), "total", phi)
+        hv, res = lat.hessian_vector(grad_F.detach().contiguous(), "total", phi)
+        if res is not None and not all(res.converged):
+            raise HMCError(_lib.HMC_E_NOCONV, "the Hessian solve of the force's backward did not "
+                                              "converge")
         return hv, None, None, None, None
 
 
@@ -514,6 +520,5 @@ def trajectories_concurrent(lattices, scheme="adapted_nested_fg", tau=1.0, n_out
     if rc == _lib.HMC_E_INVAL and all(r == 0 for r in rcs):
         raise HMCError(rc, "trajectories_concurrent needs distinct bound lattices on distinct streams")
     for lat, r in zip(lats, rcs):
-        if r not in (0, _lib.HMC_E_NOCONV, _lib.HMC_E_NAN):
-            lat._check(r)
+        lat._check_solve(r)
     return [lat._traj_result(i) for lat, i in zip(lats, infos)]

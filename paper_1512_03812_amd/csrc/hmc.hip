@@ -517,7 +517,8 @@ size_t fused_lds(hmc_ctx *c, int vmax, bool mixed) {
 }
 
 // CG on D^dagger D x = phi with the links already materialised (U64, and the FP32 angles if mixed).
-// Per-chain results land in c->cg_host.  Returns HMC_E_NOCONV if a chain did not converge.
+// Per-chain results land in c->cg_host.  Returns HMC_E_NAN if a chain's residual became
+// non-finite, else HMC_E_NOCONV if a chain hit max_iter (the other chains are solved).
 // Every check_every slots the host reads back how many workgroups still belong to
 // unconverged chains and launches only those from then on.
 int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, int prec);
@@ -667,7 +668,8 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
         slot_launch(c, slot,
                     [&](int k, int sample, hipEvent_t e0, hipEvent_t e1) {
                         const int gi = gl[k];
-                        launch_cg_step1(gc[gi], f, mixed, slot, tol, po, pn, false, sample, gs[gi], e0, e1);
+                        launch_cg_step1(gc[gi], f, mixed, slot, tol, max_it, po, pn, false, sample, gs[gi], e0,
+                                        e1);
                         if (c->has_large) launch_finalize_large(big, f.p1, f.fin1, gs[gi]);
                     },
                     [&](int k, hipEvent_t e0, hipEvent_t e1) {
@@ -705,7 +707,8 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     }
     // fold the last slot's residual into the state (decision only), on every large chain
     for (int gi = 0; gi < ng; ++gi) {
-        launch_cg_step1(gfull[gi], f, mixed, slot, tol, pb[slot & 1], pb[(slot + 1) & 1], true, -1, gs[gi]);
+        launch_cg_step1(gfull[gi], f, mixed, slot, tol, max_it, pb[slot & 1], pb[(slot + 1) & 1], true,
+                        -1, gs[gi]);
         if (mixed) launch_cg_finish_mixed(gfull[gi], f, gs[gi]);
     }
     if (ng == 2) {
@@ -718,17 +721,26 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     if ((rc = to_host(c, c->cg_host.data(), c->cg() + (size_t)(slot & 1) * c->nchains,
                       sizeof(CGState) * c->nchains))) return rc;
     if (c->timer.on) timer_flush(c);
-    for (const CGState &s : c->cg_host)
-        if (!s.converged) return fail(c, HMC_E_NOCONV, "CG did not converge in %d iterations", max_iter);
+    int nonfinite = 0, capped = 0;
+    for (const CGState &s : c->cg_host) {
+        nonfinite += s.converged == kStopNonFinite;
+        capped += s.converged != kConverged && s.converged != kStopNonFinite;
+    }
+    if (nonfinite) return fail(c, HMC_E_NAN, "CG: the residual of %d chain(s) became non-finite", nonfinite);
+    if (capped) return fail(c, HMC_E_NOCONV, "CG did not converge in %d iterations (%d chain(s))", max_iter, capped);
     return HMC_OK;
 }
+
+// A solve's failure that concerns single chains (they stopped unconverged; the others have
+// their solutions): the caller goes on and reports it.
+bool chain_failure(int rc) { return rc == HMC_E_NOCONV || rc == HMC_E_NAN; }
 
 void fill_cg_info(hmc_ctx *c, hmc_cg_info *info, const std::vector<double> *true2) {
     if (!info) return;
     for (int k = 0; k < c->nchains; ++k) {
         const CGState &s = c->cg_host[k];
         info[k].iters = s.iters;
-        info[k].converged = s.converged;
+        info[k].converged = s.converged == kConverged;
         info[k].reliable_updates = s.n_updates;
         info[k].pad = 0;
         info[k].rel_resid = s.phi2 > 0 ? sqrt(s.rho / s.phi2) : 0.0;  // last decided residual
@@ -750,18 +762,21 @@ struct MD {
     int hvp_solves = 0;  // Hessian-vector solves of exact force-gradient terms
 };
 
-// Books one solve's iterations and per-chain convergence; returns rc unless it is only
-// HMC_E_NOCONV (recorded in md.status, the trajectory goes on and the chain is rejected).
+// Books one solve's iterations and per-chain convergence; returns rc unless it only says that
+// some chains stopped unconverged (HMC_E_NOCONV, HMC_E_NAN: recorded in md.status and per
+// chain, the trajectory goes on and those chains are rejected).
 int note_solve(MD &md, int rc) {
     hmc_ctx *c = md.c;
     md.solves++;
     if (c->deferring) return rc;  // iterations and convergence are read from the device log
     for (int k = 0; k < c->nchains; ++k) {
         md.iters[k] += c->cg_host[k].iters;
-        if (!c->cg_host[k].converged) md.chain_status[k] = HMC_E_NOCONV;
+        const int code = c->cg_host[k].converged;
+        if (code != kConverged && md.chain_status[k] == HMC_OK)
+            md.chain_status[k] = code == kStopNonFinite ? HMC_E_NAN : HMC_E_NOCONV;
     }
-    if (rc == HMC_E_NOCONV) {
-        md.status = rc;
+    if (chain_failure(rc)) {
+        if (md.status == HMC_OK) md.status = rc;
         return HMC_OK;
     }
     return rc;
@@ -1257,11 +1272,11 @@ int hmc_autotune(hmc_ctx *c, int prec, double tol, hmc_tune_info *out) {
             c->persist_vmax = pv;
             ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, c->q_version);
             rc = solve(c, c->spin(SPHI), c->spin(SXI), tol, c->max_iter, prec);  // warm-up
-            if (rc && rc != HMC_E_NOCONV) return rc;
+            if (rc && !chain_failure(rc)) return rc;
             const auto t0 = std::chrono::steady_clock::now();
             for (int rep = 0; rep < 2; ++rep) {
                 rc = solve(c, c->spin(SPHI), c->spin(SXI), tol, c->max_iter, prec);
-                if (rc && rc != HMC_E_NOCONV) return rc;
+                if (rc && !chain_failure(rc)) return rc;
             }
             const double ms =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / 2;
@@ -1334,7 +1349,7 @@ int hmc_cg_solve(hmc_ctx *c, const void *phi, void *x, double tol, int max_iter,
     if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
     ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, c->q_version);
     int rc = solve(c, (const double2 *)phi, (double2 *)x, tol, max_iter, prec);
-    if (rc && rc != HMC_E_NOCONV) return rc;
+    if (rc && !chain_failure(rc)) return rc;
     std::vector<double> t2(c->nchains);
     double *dev = c->sums() + 12 * c->nchains;
     launch_true_residual64(c->geo(), c->U64(), (const double2 *)phi, (const double2 *)x,
@@ -1362,7 +1377,7 @@ int hmc_fermion_force(hmc_ctx *c, const void *phi, double *f, double tol, int ma
     if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
     ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, c->q_version);
     int rc = solve(c, (const double2 *)phi, c->spin(SXI), tol, max_iter, prec);
-    if (rc && rc != HMC_E_NOCONV) return rc;
+    if (rc && !chain_failure(rc)) return rc;
     launch_dslash64(c->geo(), c->U64(), c->spin(SXI), c->spin(SCHI), false, c->stream);
     if (f) launch_fermion_force(c->geo(), c->U64(), c->spin(SCHI), c->spin(SXI), f, c->stream);
     fill_cg_info(c, info, nullptr);
@@ -1402,10 +1417,11 @@ int hmc_actions(hmc_ctx *c, const void *phi, double tol, double *s_gauge, double
                 double *s_fermion) {
     CHECK_BOUND(c);
     const int C = c->nchains;
+    int solve_rc = HMC_OK;
     if (phi && s_fermion) {
         ensure_links(c, c->link(LQ), false, c->q_version);
-        int rc = solve(c, (const double2 *)phi, c->spin(SXI), tol, c->max_iter, HMC_PREC_FP64);
-        if (rc) return rc;
+        solve_rc = solve(c, (const double2 *)phi, c->spin(SXI), tol, c->max_iter, HMC_PREC_FP64);
+        if (solve_rc && !chain_failure(solve_rc)) return solve_rc;
         c->ff_version = c->xi_version = c->chi_version = -1;
     }
     double *dev = c->sums() + 12 * C;
@@ -1417,9 +1433,11 @@ int hmc_actions(hmc_ctx *c, const void *phi, double tol, double *s_gauge, double
     for (int k = 0; k < C; ++k) {
         if (s_gauge) s_gauge[k] = c->chains[k].beta * h[k];
         if (plaq) plaq[k] = h[C + k] / c->chains[k].V;
-        if (s_fermion && phi) s_fermion[k] = h[2 * C + k];
+        // a chain whose solve stopped unconverged gets NaN rather than an inexact S_F
+        if (s_fermion && phi)
+            s_fermion[k] = c->cg_host[k].converged == kConverged ? h[2 * C + k] : NAN;
     }
-    return HMC_OK;
+    return solve_rc;
 }
 
 int hmc_update_links(hmc_ctx *c, double eps) {
@@ -1619,7 +1637,7 @@ static int trajectory_body(hmc_ctx *c, MD &md, int scheme, double tau, int n_out
     launch_copy(c->link(LQ), c->link(LQ0), sizeof(double) * 2 * c->Vtot, c->stream);
     launch_copy(c->link(LP), c->link(LP0), sizeof(double) * 2 * c->Vtot, c->stream);
     int rc = run_md(md, scheme, tau, n_outer, n_inner);
-    if (rc && rc != HMC_E_NOCONV) return rc;
+    if (rc && !chain_failure(rc)) return rc;
     return finish_traj_device(c, md, true);
 }
 
@@ -1820,7 +1838,7 @@ int hmc_integrate(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, 
         c->xi_version = c->chi_version = -1;
     }
     rc = run_md(md, scheme, tau, n_outer, n_inner);
-    if (rc && rc != HMC_E_NOCONV) return rc;
+    if (rc && !chain_failure(rc)) return rc;
     return finish_traj(c, md, false, info);
 }
 

@@ -488,8 +488,8 @@ __global__ void k_cg_init(Geo g, CGFields f, double delta2) {
 template <bool MIXED, bool NT>
 __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
                            CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f,
-                           double tol2, const void *p_old_v, void *p_new_v, int decide_only,
-                           int sample) {
+                           double tol2, int max_iter, const void *p_old_v, void *p_new_v,
+                           int decide_only, int sample) {
     using R = typename Prec<MIXED>::R;
     using S = typename Prec<MIXED>::S;
     using C = cplx_t<R>;
@@ -550,18 +550,24 @@ __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *
     if (first) {
         n_phi2 = rho; n_target = tol2 * rho; n_rmax2 = rho; n_rho_p = rho;
         n_iters = 0; n_nupd = 0;
-        n_conv = rho <= n_target ? 1 : 0;
+        n_conv = rho <= n_target ? kConverged : 0;
     } else if (p_mode == kModeUpdate) {
         n_nupd = p_nupd + 1;
         n_rmax2 = rho;
-        n_conv = rho <= n_target ? 1 : 0;
+        n_conv = rho <= n_target ? kConverged : 0;
         n_beta = rho / p_rho_p;
     } else {
         n_iters = p_iters + 1;
         n_rho_p = p_rho;
         n_beta = rho / p_rho;
-        if (!MIXED) n_conv = rho <= n_target ? 1 : 0;
+        if (!MIXED) n_conv = rho <= n_target ? kConverged : 0;
         else update = rho <= n_target || rho <= delta2 * n_rmax2;
+    }
+    // an unconverged chain stops on a non-finite residual, or at the iteration cap unless
+    // this slot recomputes its FP64 residual (which decides convergence)
+    if (!n_conv && !update) {
+        if (!isfinite(rho)) n_conv = kStopNonFinite;
+        else if (n_iters >= max_iter) n_conv = kStopMaxIter;
     }
     if (leader) {
         out->rho = n_rho; out->rho_p = n_rho_p; out->target = n_target; out->phi2 = n_phi2;
@@ -786,27 +792,27 @@ static void launch_stamped(K kernel, dim3 grid, dim3 block, size_t lds, hipStrea
 }
 
 template <bool MIXED, bool NT>
-static void launch_step1_inst(const Geo &g, const CGFields &f, int slot, double tol, const void *p_old,
-                              void *p_new, bool decide_only, int sample, hipStream_t s, hipEvent_t ev0,
-                              hipEvent_t ev1) {
+static void launch_step1_inst(const Geo &g, const CGFields &f, int slot, double tol, int max_iter,
+                              const void *p_old, void *p_new, bool decide_only, int sample,
+                              hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     using C = cplx_t<typename Prec<MIXED>::R>;
     launch_stamped(k_cg_step1<MIXED, NT>, dim3(g.nblocks), dim3(g.block), g.block * sizeof(LdsSpinor<C>),
-                   s, ev0, ev1, g.work, g.chains, f.st, slot, g.nchains, g, f, tol * tol, p_old, p_new,
-                   decide_only ? 1 : 0, sample);
+                   s, ev0, ev1, g.work, g.chains, f.st, slot, g.nchains, g, f, tol * tol, max_iter, p_old,
+                   p_new, decide_only ? 1 : 0, sample);
 }
 
 void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
-                     const void *p_old, void *p_new, bool decide_only, int sample, hipStream_t s,
-                     hipEvent_t ev0, hipEvent_t ev1) {
+                     int max_iter, const void *p_old, void *p_new, bool decide_only, int sample,
+                     hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const bool nt = stream_fields(g, mixed);
     if (mixed && nt)
-        launch_step1_inst<true, true>(g, f, slot, tol, p_old, p_new, decide_only, sample, s, ev0, ev1);
+        launch_step1_inst<true, true>(g, f, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
     else if (mixed)
-        launch_step1_inst<true, false>(g, f, slot, tol, p_old, p_new, decide_only, sample, s, ev0, ev1);
+        launch_step1_inst<true, false>(g, f, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
     else if (nt)
-        launch_step1_inst<false, true>(g, f, slot, tol, p_old, p_new, decide_only, sample, s, ev0, ev1);
+        launch_step1_inst<false, true>(g, f, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
     else
-        launch_step1_inst<false, false>(g, f, slot, tol, p_old, p_new, decide_only, sample, s, ev0, ev1);
+        launch_step1_inst<false, false>(g, f, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
 }
 
 // One workgroup per sampled slot: the sum over chains of its byte row, which is then zeroed
@@ -974,7 +980,7 @@ __global__ void k_cg_iter(Geo g, CGIterFields f, int slot, double tol2, int deci
     double alpha = 0.0, beta = 0.0;
     if (first) {  // tb = ||phi||^2 from the initial kernel; p = r
         n_phi2 = tb; n_target = tol2 * tb; n_rmax2 = tb; n_iters = 0; n_nupd = 0;
-        n_conv = tb <= n_target ? 1 : 0;
+        n_conv = tb <= n_target ? kConverged : !isfinite(tb) ? kStopNonFinite : 0;
         n_buf = buf ^ 1;
     } else if (p_mode == kModeUpdate) {
         n_mode = kModeUpdate2;
@@ -985,14 +991,15 @@ __global__ void k_cg_iter(Geo g, CGIterFields f, int slot, double tol2, int deci
             n_rmax2 = tb;
             A = p_t2;
             D2 = p_s2;
-            n_conv = tb <= n_target ? 1 : 0;
+            n_conv = tb <= n_target ? kConverged : 0;
         } else if (!MIXED) {
-            n_conv = tb <= n_target ? 1 : 0;
+            n_conv = tb <= n_target ? kConverged : 0;
         } else if (tb <= n_target || tb <= delta2 * n_rmax2) {
             n_mode = kModeUpdate;
             n_t2 = ta;
             n_s2 = td;
         }
+        if (!n_conv && n_mode == kModeNormal && !isfinite(tb)) n_conv = kStopNonFinite;
         if (!n_conv && n_mode == kModeNormal) {
             alpha = tb / A;
             beta = (tb - 2.0 * alpha * tc + alpha * alpha * D2) / tb;
@@ -1309,9 +1316,10 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
     double rho = v[0], rho_prev = v[0], rmax2 = v[0];
     int iters = 0, nupd = 0;
     bool conv = rho <= target;
+    bool finite = isfinite(rho);
     auto loadP = [&](int q, C &b0, C &b1) { b0 = ps[q - off]; b1 = ps[V + q - off]; };
     auto loadT = [&](int q, C &b0, C &b1) { b0 = ts[q - off]; b1 = ts[V + q - off]; };
-    while (!conv && iters < max_iter) {
+    while (!conv && finite && iters < max_iter) {
         // t = D p
         v[0] = 0.0;
 #pragma unroll
@@ -1346,6 +1354,7 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
         double beta = rho_new / rho;
         rho_prev = rho;
         rho = rho_new;
+        if (!isfinite(rho_new)) { finite = false; break; }
         if (!MIXED) {
             if (rho_new <= target) { conv = true; break; }
         } else if (rho_new <= target || rho_new <= delta2 * rmax2) {
@@ -1375,6 +1384,7 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
             ++nupd;
             rmax2 = v[0];
             if (v[0] <= target) { rho = v[0]; conv = true; break; }
+            if (!isfinite(v[0])) { rho = v[0]; finite = false; break; }
             beta = v[0] / rho_prev;
             rho = v[0];
         }
@@ -1410,7 +1420,7 @@ k_cg_wg(Geo g, CGFields f, const int *__restrict__ chain_list, double tol2, doub
             CGState *o = f.st + (size_t)par * g.nchains + c;
             o->rho = rho; o->rho_p = rho_prev; o->target = target; o->phi2 = phi2; o->rmax2 = rmax2;
             o->beta = 0.0; o->delta2 = delta2; o->alpha = 0.0; o->iters = iters;
-            o->converged = conv ? 1 : 0;
+            o->converged = conv ? kConverged : !finite ? kStopNonFinite : kStopMaxIter;
             o->mode = kModeNormal; o->n_updates = nupd;
         }
     }
@@ -1549,7 +1559,7 @@ void launch_compact(const Geo &full, CGState *st, int max_iter, BlockWork *out, 
 
 __global__ void k_count_converged(const CGState *__restrict__ st, int n, int *out) {
     double v[1] = {0.0};
-    for (int c = threadIdx.x; c < n; c += blockDim.x) v[0] += st[c].converged;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) v[0] += st[c].converged == kConverged;
     block_sum_all<1>(v);
     if (threadIdx.x == 0) out[0] = (int)v[0];
 }
@@ -1839,14 +1849,76 @@ void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
 }
 
 // ================================================================ random numbers
-// Box-Muller pair from Philox words: r = sqrt(-2 log(1 - ua)), (r cos 2 pi ub, r sin 2 pi ub).
+// Box-Muller pair from Philox words: r = sqrt(-2 ln(1 - ua)), (r cos 2 pi ub, r sin 2 pi ub),
+// with ln, sin and cos taken by one written method (Cody and Waite's argument reduction, then
+// truncated series with exact reciprocal coefficients), evaluated with IEEE operations only
+// (+, -, *, / and sqrt rounded to nearest, no contraction into fused multiply-adds), so the
+// momenta and pseudofermions of Sec. 2.1 have the same bits on any host that evaluates the
+// same operations in the same order.
+
+// ln y for 0 < y <= 1: y = m 2^e with m in [1/sqrt 2, sqrt 2); with f = (m-1)/(m+1) and
+// s = f^2, ln m = 2 atanh f = 2 (f + f s A(s)), A(s) = sum_{k=1..11} s^(k-1) / (2k+1)
+// (|f| <= 0.1716); ln y = (e C2 + ln m) + e C1, where C1 = 355/512 is exact in 9 bits
+// and C2 = ln 2 - C1 (rounded).
+__device__ __forceinline__ double bm_log(double y) {
+#pragma clang fp contract(off)
+    int e = 0;
+    double m = frexp(y, &e);
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e -= 1;
+    }
+    const double f = (m - 1.0) / (m + 1.0);
+    const double s = f * f;
+    double a = 1.0 / 23.0;
+#pragma unroll
+    for (int k = 21; k >= 3; k -= 2) a = 1.0 / (double)k + s * a;
+    const double lnm = 2.0 * (f + f * (s * a));
+    const double de = (double)e;
+    return (de * -2.121944400546905827679e-4 + lnm) + de * 0.693359375;
+}
+
+// (sin 2 pi u, cos 2 pi u) for u in [0, 1), u a multiple of 2^-53.  The quadrant
+// n = floor(4u + 1/2) and the offset d = u - n/4 in [-1/8, 1/8] are exact; x = 2 pi d is
+// formed with 2 pi split into its rounded value and the rounded remainder; on |x| <= pi/4
+// sin x = x - x (z S(z)), cos x = 1 - z K(z) with z = x^2 and the alternating series
+// S = 1/3! - z/5! + ... - z^9/21!, K = 1/2! - z/4! + ... + z^10/22!, summed from the
+// highest power down.
+__device__ __forceinline__ void bm_sincos_turn(double u, double &sn, double &cs) {
+#pragma clang fp contract(off)
+    const double n = floor(4.0 * u + 0.5);
+    const double d = u - 0.25 * n;
+    const double x = d * 6.283185307179586 + d * 2.4492935982947064e-16;
+    const double z = x * x;
+    // 1/k! for k = 2..22 (each k! is exact in binary64 up to 22!)
+    double fact[23];
+    fact[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= 22; ++k) fact[k] = fact[k - 1] * (double)k;
+    double S = -1.0 / fact[21];
+#pragma unroll
+    for (int k = 19; k >= 3; k -= 2) S = ((k & 2) ? 1.0 : -1.0) / fact[k] + z * S;
+    double K = 1.0 / fact[22];
+#pragma unroll
+    for (int k = 20; k >= 2; k -= 2) K = ((k & 2) ? 1.0 : -1.0) / fact[k] + z * K;
+    const double sx = x - x * (z * S);
+    const double cx = 1.0 - z * K;
+    switch ((int)n & 3) {
+    case 0: sn = sx; cs = cx; break;
+    case 1: sn = cx; cs = -sx; break;
+    case 2: sn = -sx; cs = -cx; break;
+    default: sn = -cx; cs = sx; break;
+    }
+}
+
 __device__ __forceinline__ void gaussian_pair(const U32x4 &w, double &g0, double &g1) {
 #pragma clang fp contract(off)
     const double ua = u01_from(w.v[0], w.v[1]), ub = u01_from(w.v[2], w.v[3]);
-    const double r = sqrt(-2.0 * log(1.0 - ua));
-    const double a = 6.283185307179586 * ub;
-    g0 = r * cos(a);
-    g1 = r * sin(a);
+    const double r = __builtin_sqrt(-2.0 * bm_log(1.0 - ua));
+    double sn, cs;
+    bm_sincos_turn(ub, sn, cs);
+    g0 = r * cs;
+    g1 = r * sn;
 }
 
 __global__ void k_rng_links(Geo g, uint32_t k0, uint32_t k1, double *__restrict__ q) {
@@ -2029,7 +2101,7 @@ void launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, p, v);
 }
 
-// log[2c] = iterations, log[2c + 1] = converged of chain c's finished solve
+// log[2c] = iterations, log[2c + 1] = stop code (CGState::converged) of chain c's finished solve
 __global__ void k_log_solve(const CGState *__restrict__ st, int nchains, int *__restrict__ log) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nchains) return;
@@ -2043,14 +2115,16 @@ void launch_log_solve(const CGState *st, int nchains, int *log, hipStream_t s) {
                        nchains, log);
 }
 
-// status[c] = -3 (the library's "did not converge") if any of the n logged solves of chain c
-// did not converge, else 0
+// status[c]: -3 (the library's "did not converge") or -5 (non-finite residual) from the first
+// of the n logged solves of chain c that stopped unconverged, else 0
 __global__ void k_chain_status(const int *__restrict__ log, int n, int nchains, int *__restrict__ status) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nchains) return;
     int st = 0;
-    for (int k = 0; k < n; ++k)
-        if (!log[((size_t)k * nchains + c) * 2 + 1]) st = -3;
+    for (int k = 0; k < n && st == 0; ++k) {
+        const int code = log[((size_t)k * nchains + c) * 2 + 1];
+        if (code != kConverged) st = code == kStopNonFinite ? -5 : -3;
+    }
     status[c] = st;
 }
 

@@ -34,7 +34,9 @@ struct CGState {
     double t2;      // fused iteration: ||D p||^2 of the last direction (kept across an update)
     double s2;      // fused iteration: ||D^dagger D p||^2 of the last direction
     int iters;      // CG iterations completed
-    int converged;  // 1 once the stopping test passed
+    int converged;  // 0 while iterating; kConverged once the stopping test passed; a chain
+                    // that stops without converging holds kStopMaxIter (iteration cap) or
+                    // kStopNonFinite (its residual norm is not finite)
     int mode;       // kModeInit, kModeNormal, kModeUpdate (this slot), kModeUpdate2
     int n_updates;  // mixed: FP64 residual recomputations completed
     int buf;        // fused iteration: which of the two buffers holds r, s and p
@@ -43,6 +45,8 @@ struct CGState {
 static_assert(sizeof(CGState) % 16 == 0, "CGState alignment");
 // kModeUpdate2: the second half of a fused-iteration residual recomputation.
 enum { kModeInit = 0, kModeNormal = 1, kModeUpdate = 2, kModeUpdate2 = 3 };
+// CGState::converged: nonzero once a chain has stopped; only kConverged means converged.
+enum { kConverged = 1, kStopMaxIter = 2, kStopNonFinite = 3 };
 
 // Sampled slots per solve whose bytes the timing records (rows of the device byte table).
 constexpr int kMaxSamples = 256;
@@ -111,10 +115,11 @@ void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, h
 // the previous slot, apply the previous slot's x += alpha p_old, then p_new = r + beta p_old
 // and t = D p_new with partial ||t||^2 (or, in a reliable-update slot,
 // t64 = D (x64 + x32 + alpha p_old)).  decide_only: state update and the owed x update only.
-// ev0/ev1 (optional): stamped with the kernel's own start and end (timing).
+// A chain stops unconverged once it has done max_iter iterations or its residual norm is
+// not finite.  ev0/ev1 (optional): stamped with the kernel's own start and end (timing).
 void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
-                     const void *p_old, void *p_new, bool decide_only, int sample, hipStream_t s,
-                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                     int max_iter, const void *p_old, void *p_new, bool decide_only, int sample,
+                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // sums[2 b + k] = sum over chains of samples[b][chain][k], b < n; the rows are zeroed.
 void launch_sample_sums(double *samples, int n, int nchains, double *sums, hipStream_t s);
 // Slot k, second kernel: alpha from the partials of step 1 (kept in the state for the next
@@ -235,9 +240,11 @@ void launch_metropolis(const Geo &g, uint64_t seed, const uint32_t *traj, const 
 void launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s);
 // dst = src, n16 16-byte elements (nontemporal streaming copy)
 void launch_stream_copy(const void *src, void *dst, size_t n16, hipStream_t s);
-// iterations and convergence flag of every chain's finished solve (state st) -> log[2 c + k]
+// iterations and stop code (CGState::converged) of every chain's finished solve (state st)
+// -> log[2 c + k]
 void launch_log_solve(const CGState *st, int nchains, int *log, hipStream_t s);
-// status[c] = -3 if any of the n logged solves (log[k][c][2]) of chain c did not converge
+// status[c] = -3 (iteration cap) or -5 (non-finite residual) from the first of the n logged
+// solves (log[k][c][2]) of chain c that stopped unconverged, else 0
 void launch_chain_status(const int *log, int n, int nchains, int *status, hipStream_t s);
 // q = q0 on the chains whose Metropolis test failed.
 void launch_restore(const Geo &g, const MetroOut *m, const double *q0, double *q, hipStream_t s);

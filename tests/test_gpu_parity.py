@@ -1,7 +1,8 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle, element by
 element on the same seeded inputs.  FP64 tolerances: 1e-12 relative for the
 stencil-level operators, 1e-10 relative for solver-dependent quantities (forces,
-Delta H) with CG tolerances of 1e-14, bit-identity for the Philox uniforms."""
+Delta H) with CG tolerances of 1e-14, bit-identity for the Philox uniforms and the
+Gaussian momenta and pseudofermions."""
 import math
 
 import numpy as np
@@ -20,50 +21,7 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def hmc():
-    import paper_1512_03812_amd as m
-    return m
-
-
-def rel(a, b):
-    a, b = np.asarray(a), np.asarray(b)
-    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
-
-
-class Batch:
-    """A Lattice plus numpy<->native helpers for a list of (Lx, Lt, beta, m0)."""
-
-    def __init__(self, shapes, seed=0, persistent=None):
-        m = hmc()
-        Lx = [s[0] for s in shapes]
-        Lt = [s[1] for s in shapes]
-        beta = [s[2] if len(s) > 2 else 2.0 for s in shapes]
-        m0 = [s[3] if len(s) > 3 else 0.1 for s in shapes]
-        self.lat = m.Lattice.batch(Lx, Lt, beta, m0, seed=seed)
-        if persistent is not None:
-            self.lat.set_persistent_limit(persistent)
-        self.shapes = list(zip(Lx, Lt, beta, m0))
-
-    def links_to_native(self, arrays, out=None):
-        flat = np.concatenate([np.ascontiguousarray(a, dtype=np.float64).ravel() for a in arrays])
-        return self.lat.pack_links(torch.from_numpy(flat), out=out)
-
-    def spinor_to_native(self, arrays, out=None):
-        flat = np.concatenate([np.ascontiguousarray(a, dtype=np.complex128).ravel() for a in arrays])
-        return self.lat.pack_spinor(torch.from_numpy(flat), out=out)
-
-    def links_from_native(self, t):
-        flat = self.lat.unpack_links(t).cpu().numpy()
-        return [flat[2 * o:2 * o + 2 * Lx * Lt].reshape(Lt, Lx, 2)
-                for o, (Lx, Lt, _, _) in zip(self.lat.offsets, self.shapes)]
-
-    def spinor_from_native(self, t):
-        flat = self.lat.unpack_spinor(t).cpu().numpy()
-        return [flat[2 * o:2 * o + 2 * Lx * Lt].reshape(Lt, Lx, 2)
-                for o, (Lx, Lt, _, _) in zip(self.lat.offsets, self.shapes)]
-
-    def set_q(self, arrays):
-        self.links_to_native(arrays, out=self.lat.q)
+from tests.gpu_helpers import Batch, hmc, rel, run_oracle_chain  # noqa: E402
 
 
 SHAPES = [(2, 2), (4, 4), (8, 8), (6, 10), (34, 18), (32, 32)]
@@ -98,24 +56,21 @@ def test_hot_start_uniforms_bit_identical():
         assert np.array_equal(got, want)
 
 
-def test_refresh_streams_match_oracle():
-    seed = 987654321
-    b = Batch([(8, 8), (6, 10)], seed=seed)
-    b.lat.trajectory_counter = 5
+@pytest.mark.parametrize("seed,traj", [(987654321, 5), (1512, 0), (0xDEADBEEF12345, 77)])
+def test_refresh_streams_bit_identical(seed, traj):
+    """Momenta and pseudofermion Gaussians of the refresh (Sec. 2.1) have the oracle's bits:
+    both sides evaluate Box-Muller's ln, sin and cos by the same written method."""
+    b = Batch([(8, 8), (6, 10), (32, 32), (2, 2)], seed=seed)
+    b.lat.trajectory_counter = traj
     b.lat.refresh()
     torch.cuda.synchronize()
     ps = b.links_from_native(b.lat.p)
     zs = b.spinor_from_native(b.lat.zeta)
-    n_exact = n_total = 0
     for c, (Lx, Lt, _, _) in enumerate(b.shapes):
-        p_ref = oracle.random_momenta(Lx, Lt, seed, chain=c, traj=5)
-        z_ref = oracle.random_zeta(Lx, Lt, seed, chain=c, traj=5)
-        # Gaussians: same uniforms, libm vs device log/cos/sin may differ in the last ulps
-        assert np.max(np.abs(ps[c] - p_ref) / np.maximum(np.abs(p_ref), 1e-3)) < 8e-16
-        assert np.max(np.abs(zs[c] - z_ref) / np.maximum(np.abs(z_ref), 1e-3)) < 8e-16
-        n_exact += np.sum(ps[c] == p_ref)
-        n_total += p_ref.size
-    assert n_exact > 0.5 * n_total
+        p_ref = oracle.random_momenta(Lx, Lt, seed, chain=c, traj=traj)
+        z_ref = oracle.random_zeta(Lx, Lt, seed, chain=c, traj=traj)
+        assert np.array_equal(ps[c], p_ref), (c, np.max(np.abs(ps[c] - p_ref)))
+        assert np.array_equal(zs[c], z_ref), (c, np.max(np.abs(zs[c] - z_ref)))
 
 
 # ------------------------------------------------------------------ Dirac operator
@@ -465,17 +420,6 @@ def test_md_parity(scheme):
 
 
 # ------------------------------------------------------------------ HMC trajectories
-def run_oracle_chain(Lx, Lt, beta, m0, seed, chain, n_traj, scheme, tau, n_outer, n_inner, tol,
-                     fg_exact=False, quenched=False):
-    q = oracle.random_links(Lx, Lt, seed, chain)
-    out = []
-    for t in range(n_traj):
-        q, info = oracle.hmc_trajectory(q, beta, m0, seed, chain, t, scheme, tau, n_outer, n_inner,
-                                        tol=tol, fg_exact=fg_exact, quenched=quenched)
-        out.append((q.copy(), info))
-    return out
-
-
 def test_plain_method_8x8_omelyan():
     """The plain FP64 method on 8 x 8: beta 2, m0 0.1, 5-stage scheme, 10 steps, tau 1."""
     seed = 2024

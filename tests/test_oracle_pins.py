@@ -97,6 +97,42 @@ def test_gaussian_moments():
         assert abs(gp[1] - r * math.sin(2 * math.pi * u[1])) < 1e-14 * max(1, r)
 
 
+def test_box_muller_log_against_high_precision():
+    """The written ln of the Box-Muller step against mpmath at 40 digits: within 2 ulp over
+    random 53-bit arguments, exact at powers of two times ln 2's split, 0 at 1."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(3)
+    args = [float(k) * 2.0**-53 for k in rng.integers(1, 2**53, size=4000)]
+    args += [2.0**-53, 0.5, 0.70710678118654752, 0.7071067811865476, 0.999999, 1.0 - 2.0**-53]
+    for y in args:
+        got = oracle.ln_unit(y)
+        want = mpmath.log(mpmath.mpf(y))
+        assert abs(mpmath.mpf(got) - want) <= 2 * 2.0**-52 * abs(want) + 1e-300, y
+    assert oracle.ln_unit(1.0) == 0.0
+    for e in (1, 2, 17, 53):
+        assert abs(oracle.ln_unit(2.0**-e) + e * math.log(2)) <= 2.0**-52 * e * math.log(2)
+
+
+def test_box_muller_sincos_against_high_precision():
+    """The written sin/cos of 2 pi u against mpmath within 1 ulp of 1 over random arguments,
+    and exact on the quadrant points (a wrong quadrant rotation or series sign fails)."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 40
+    rng = np.random.default_rng(4)
+    us = [float(k) * 2.0**-53 for k in rng.integers(0, 2**53, size=4000)]
+    us += [0.125, 0.375, 0.625, 0.875, 1.0 - 2.0**-53, 2.0**-53]
+    for u in us:
+        sn, cs = oracle.sincos_turn(u)
+        x = 2 * mpmath.pi * mpmath.mpf(u)
+        assert abs(mpmath.mpf(sn) - mpmath.sin(x)) <= 2.0**-52, u
+        assert abs(mpmath.mpf(cs) - mpmath.cos(x)) <= 2.0**-52, u
+    assert oracle.sincos_turn(0.0) == (0.0, 1.0)
+    assert oracle.sincos_turn(0.25) == (1.0, 0.0)
+    assert oracle.sincos_turn(0.5) == (0.0, -1.0)
+    assert oracle.sincos_turn(0.75) == (-1.0, 0.0)
+
+
 def test_pseudofermion_and_momentum_normalisation():
     # <zeta^dagger zeta> = 2V for density exp(-zeta^dagger zeta); <p^2/2> = 1/2 per link
     Lx = Lt = 16
@@ -152,6 +188,20 @@ def test_free_field_spectrum():
             w = math.sqrt(math.sin(kx) ** 2 + math.sin(kt) ** 2)
             expect += [M + 1j * w, M - 1j * w]
     assert multiset_distance(ev, np.array(expect)) < 1e-12
+
+
+@pytest.mark.parametrize("Lx,Lt", [(2, 2), (6, 10), (34, 18)])
+def test_dirac_at_listed_sites_is_the_full_operator(Lx, Lt):
+    """The per-site evaluation of D (used for sampled sites of large lattices) gives the bits
+    of the whole-lattice D at every site, in any order and with repeats, so it inherits the
+    pins of D (plane waves, free-field spectrum, adjointness, gauge invariance)."""
+    q = inputs.random_angles(Lx, Lt, 71)
+    psi = inputs.random_spinor(Lx, Lt, 72)
+    full = oracle.dirac(q, psi, 0.13).reshape(Lx * Lt, 2)
+    sites = np.arange(Lx * Lt)
+    assert np.array_equal(oracle.dirac_sites(q, psi, 0.13, sites), full)
+    picks = np.random.default_rng(73).integers(0, Lx * Lt, size=3 * Lx * Lt)
+    assert np.array_equal(oracle.dirac_sites(q, psi, 0.13, picks), full[picks])
 
 
 def test_adjointness_and_gamma5_hermiticity():
@@ -344,6 +394,34 @@ def test_stage_sequences(scheme):
     want = fractions_of(gold["schemes"][scheme])
     assert [k for k, _ in got] == [k for k, _ in want]
     assert np.allclose([e for _, e in got], [e for _, e in want], rtol=0, atol=1e-15)
+
+
+def test_eleven_stage_coefficients_are_fourth_order():
+    """The oracle's 11-stage sequence (Eq. (6)) composed as matrix exponentials of two random
+    non-commuting matrices A, B against exp(h (A + B)): the local error falls as h^5 (a
+    fourth-order scheme), as the published coefficients require; one wrong digit in sigma,
+    eta, lambda or theta leaves h^3."""
+    from scipy.linalg import expm
+    q = inputs.smooth_angles(4, 4, 20)
+    p = inputs.random_momenta(4, 4, 21)
+    phi = inputs.random_spinor(4, 4, 22)
+    _, _, info = oracle.md_integrate(q, p, phi, 2.0, 0.1, "omelyan_11stage", 1.0, 1, 1,
+                                     trace_cap=200)
+    seq = info["trace"]
+    assert [k for k, _ in seq] == ["B", "A"] * 5 + ["B"]
+    g = np.random.default_rng(5)
+    A, B = g.normal(size=(6, 6)), g.normal(size=(6, 6))
+
+    def local_error(h):
+        U = np.eye(6)
+        for kind, c in seq:
+            U = expm(c * h * (A if kind == "A" else B)) @ U
+        return np.linalg.norm(U - expm(h * (A + B)))
+
+    hs = [0.08, 0.04, 0.02]
+    errs = [local_error(h) for h in hs]
+    slopes = [math.log(errs[i] / errs[i + 1]) / math.log(2) for i in range(2)]
+    assert all(abs(s - 5.0) < 0.3 for s in slopes), slopes
 
 
 @pytest.mark.parametrize("scheme", list(oracle.SCHEMES))
