@@ -245,6 +245,23 @@ int hmc_dslash_dagger(hmc_ctx *ctx, const void *in, void *out);
 int hmc_cg_solve(hmc_ctx *ctx, const void *phi, void *x, double tol, int max_iter, int prec,
                  hmc_cg_info *info);
 
+/* hmc_cg_solve in FP64 that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): every chain's CG runs in the one-workgroup persistent solver, and all kernel
+ * scratch (the links U = exp(i q), the CG states, the chain list, the true-residual
+ * intermediate and its partial sums) lives in one static device array of the library
+ * (4.5 MiB, held by each GPU the library runs on until the process ends) instead of the
+ * bound workspace.  The call makes no hipMalloc, hipFree or other allocating call; it reads
+ * q and the chain tables from the bound workspace and writes only x and info.
+ * Limits: V_total <= 65536 sites, n_chains <= 1024, every chain at most 2048 sites
+ * (HMC_E_NOMEM / HMC_E_INVAL with a message otherwise).  Results are those of hmc_cg_solve
+ * with prec = HMC_PREC_FP64 on the same context, bit for bit; return codes as there.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU (from
+ * several streams or threads) race and must be serialised by the caller.  The current device
+ * must be the one the context was bound on. */
+int hmc_cg_solve_noalloc(hmc_ctx *ctx, const void *phi, void *x, double tol, int max_iter,
+                         hmc_cg_info *info);
+
 /* ---------------------------------------------------------------- forces (Sec. 3) */
 
 /* f = dS_F/dq (Eqs. (17), (18)): solves xi = (D^dagger D)^{-1} phi, forms chi = D xi and

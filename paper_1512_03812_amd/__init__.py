@@ -331,6 +331,15 @@ class Lattice:
                                                  _prec(prec), info))
         return out, self._cg_result(info)
 
+    def cg_solve_noalloc(self, phi: torch.Tensor, out: torch.Tensor, tol=1e-12, max_iter=100000):
+        """hmc_cg_solve_noalloc: the FP64 solve of cg_solve with the library's static scratch
+        (no device allocation; every chain within 2048 sites).  out: a caller-owned spinor
+        field.  Returns (out, CGResult)."""
+        info = (_lib.CGInfo * self.n_chains)()
+        self._check_solve(self._lib.hmc_cg_solve_noalloc(self._ctx, _ptr(phi), _ptr(out), tol,
+                                                         max_iter, info))
+        return out, self._cg_result(info)
+
     # ---------------------------------------------------------------- forces (Sec. 3)
     def fermion_force(self, phi: torch.Tensor, tol=1e-12, max_iter=100000, prec="fp64",
                       out: Optional[torch.Tensor] = None):

@@ -80,6 +80,7 @@ SIGNATURES = {
     "hmc_dslash": (_I, [_P, _P, _P]),
     "hmc_dslash_dagger": (_I, [_P, _P, _P]),
     "hmc_cg_solve": (_I, [_P, _P, _P, _D, _I, _I, _P]),
+    "hmc_cg_solve_noalloc": (_I, [_P, _P, _P, _D, _I, _P]),
     "hmc_fermion_force": (_I, [_P, _P, _P, _D, _I, _I, _P, _P]),
     "hmc_fermion_force_chixi": (_I, [_P, _P, _P, _P]),
     "hmc_total_force_chixi": (_I, [_P, _P, _P, _P]),

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <exception>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -142,6 +143,9 @@ struct hmc_ctx {
     std::string err;
     // per-solve bookkeeping of the last CG (host copies)
     std::vector<CGState> cg_host;
+    std::vector<double> resid_host;  // true residual norms of the last allocation-free solve
+    void *static_scratch = nullptr;  // this device's address of the static scratch array
+    std::string static_scratch_err;
     KernelTimer timer;
 
     // ------------------------------------------------------------ accessors
@@ -298,8 +302,59 @@ int make_ctx(hmc_ctx **out, int n, const int *Lx, const int *Lt, const double *b
     build_tables(c);
     layout_workspace(c, (size_t)c->nlog_max);
     c->cg_host.resize(n);
+    c->resid_host.resize(n);
     *out = c;
     return HMC_OK;
+}
+
+// ------------------------------------------------------------------ allocation-free solve
+// Scratch of hmc_cg_solve_noalloc: one array in static device memory, of which every GPU
+// that loads the library holds its own copy until the process ends.  Host code never uses
+// the array's name as an address: each device's address is taken once, with that device
+// current, by hipGetSymbolAddress (scratch_address, called from hmc_bind).  Layout for the
+// largest context the entry point takes: FP64 links U [2][V] and the true-residual
+// intermediate t [2][V] (double2), the CG states [2][C], the chain list [C], partial sums
+// [P] and per-chain sums [C].
+constexpr int kNoAllocMaxSites = 65536;    // V_total
+constexpr int kNoAllocMaxChains = 1024;
+constexpr int kNoAllocMaxPartials = 4096;  // logical workgroups of the context's table
+constexpr size_t kNoAllocOffT = (size_t)2 * kNoAllocMaxSites * sizeof(double2);
+constexpr size_t kNoAllocOffState = 2 * kNoAllocOffT;
+constexpr size_t kNoAllocOffList =
+    kNoAllocOffState + (size_t)2 * kNoAllocMaxChains * sizeof(CGState);
+constexpr size_t kNoAllocOffPartials = kNoAllocOffList + (size_t)kNoAllocMaxChains * sizeof(int);
+constexpr size_t kNoAllocOffSums =
+    kNoAllocOffPartials + (size_t)kNoAllocMaxPartials * sizeof(double);
+constexpr size_t kNoAllocBytes = kNoAllocOffSums + (size_t)kNoAllocMaxChains * sizeof(double);
+static_assert(kNoAllocOffState % 256 == 0 && kNoAllocOffList % 256 == 0 &&
+                  kNoAllocOffPartials % 256 == 0 && kNoAllocOffSums % 256 == 0,
+              "scratch regions are 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (the current device is the context's).
+void scratch_address(hmc_ctx *c) {
+    c->static_scratch = nullptr;
+    if (c->device < 0 || c->device >= kMaxDevices) {
+        c->static_scratch_err = "device index out of range";
+        return;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[c->device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            c->static_scratch_err = std::string("hipGetSymbolAddress failed: ") + hipGetErrorString(e);
+            return;
+        }
+        g_scratch_addr[c->device] = p;
+    }
+    c->static_scratch = g_scratch_addr[c->device];
 }
 
 // ------------------------------------------------------------------ helpers on a bound context
@@ -1074,6 +1129,7 @@ int hmc_bind(hmc_ctx *c, void *ws, size_t bytes, void *stream) {
     c->graph_epoch++;
     c->stream = (hipStream_t)stream;
     HIP_TRY(c, hipGetDevice(&c->device));
+    scratch_address(c);
     if (!c->pinned) {
         c->pinned_bytes = align_up(sizeof(CGState) * c->nchains + sizeof(MetroOut) * c->nchains +
                                    sizeof(double) * 16 * c->nchains + 4096);
@@ -1358,6 +1414,59 @@ int hmc_cg_solve(hmc_ctx *c, const void *phi, void *x, double tol, int max_iter,
     if (rc2) return rc2;
     fill_cg_info(c, info, &t2);
     return rc;
+}
+
+int hmc_cg_solve_noalloc(hmc_ctx *c, const void *phi, void *x, double tol, int max_iter,
+                         hmc_cg_info *info) {
+    CHECK_BOUND(c);
+    if (!phi || !x || phi == x) return fail(c, HMC_E_INVAL, "need distinct phi/x");
+    if (!(tol >= 0) || max_iter < 1) return fail(c, HMC_E_INVAL, "bad tol/max_iter");
+    if (!c->static_scratch)
+        return fail(c, HMC_E_HIP, "no device address of the static scratch: %s", c->static_scratch_err.c_str());
+    int dev = -1;
+    HIP_TRY(c, hipGetDevice(&dev));
+    if (dev != c->device) return fail(c, HMC_E_INVAL, "the current device is not the context's");
+    const Geo g = c->geo();
+    if (c->Vtot > kNoAllocMaxSites || c->nchains > kNoAllocMaxChains || g.nlog > kNoAllocMaxPartials)
+        return fail(c, HMC_E_NOMEM,
+                    "the allocation-free solve takes at most %d sites, %d chains and %d workgroups "
+                    "(context: %d, %d, %d)", kNoAllocMaxSites, kNoAllocMaxChains, kNoAllocMaxPartials,
+                    c->Vtot, c->nchains, g.nlog);
+    int vmax = 0;
+    for (const ChainInfo &ci : c->chains) vmax = std::max(vmax, ci.V);
+    if (vmax > 2048 || cg_wg_lds_bytes(vmax, false) + 1024 > c->lds_max)
+        return fail(c, HMC_E_INVAL, "the allocation-free solve needs every chain within %d sites",
+                    std::min(2048, persistent_limit(c, false)));
+    char *base = (char *)c->static_scratch;
+    double2 *U = (double2 *)base;
+    double2 *t = (double2 *)(base + kNoAllocOffT);
+    CGState *st = (CGState *)(base + kNoAllocOffState);
+    int *list = (int *)(base + kNoAllocOffList);
+    double *partials = (double *)(base + kNoAllocOffPartials);
+    double *sums = (double *)(base + kNoAllocOffSums);
+    launch_make_links(g, c->link(LQ), U, nullptr, c->stream);
+    launch_iota(list, c->nchains, c->stream);
+    CGFields f = {};
+    f.phi = (const double2 *)phi;
+    f.x64 = (double2 *)x;
+    f.U64 = U;
+    f.st = st;
+    if (launch_cg_wg(g, f, false, list, c->nchains, vmax, tol, c->delta, max_iter, c->stream))
+        return fail(c, HMC_E_HIP, "the persistent solver's LDS request was refused");
+    launch_true_residual64(g, U, (const double2 *)phi, (const double2 *)x, t, partials, sums, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    int rc = to_host(c, c->cg_host.data(), st, sizeof(CGState) * c->nchains);
+    if (rc) return rc;
+    if ((rc = to_host(c, c->resid_host.data(), sums, sizeof(double) * c->nchains))) return rc;
+    fill_cg_info(c, info, &c->resid_host);
+    int nonfinite = 0, capped = 0;
+    for (const CGState &s : c->cg_host) {
+        nonfinite += s.converged == kStopNonFinite;
+        capped += s.converged != kConverged && s.converged != kStopNonFinite;
+    }
+    if (nonfinite) return fail(c, HMC_E_NAN, "CG: the residual of %d chain(s) became non-finite", nonfinite);
+    if (capped) return fail(c, HMC_E_NOCONV, "CG did not converge in %d iterations (%d chain(s))", max_iter, capped);
+    return HMC_OK;
 }
 
 int hmc_fermion_force_chixi(hmc_ctx *c, const void *chi, const void *xi, double *f) {

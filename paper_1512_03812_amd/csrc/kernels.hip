@@ -2095,6 +2095,15 @@ void launch_stream_copy(const void *src, void *dst, size_t n16, hipStream_t s) {
                        (f32x4 *)dst, n16);
 }
 
+__global__ void k_iota(int *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
+}
+
+void launch_iota(int *p, int n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_iota, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+}
+
 __global__ void k_set_u32(uint32_t *p, uint32_t v) { *p = v; }
 
 void launch_set_u32(uint32_t *p, uint32_t v, hipStream_t s) {

@@ -246,6 +246,8 @@ void launch_log_solve(const CGState *st, int nchains, int *log, hipStream_t s);
 // status[c] = -3 (iteration cap) or -5 (non-finite residual) from the first of the n logged
 // solves (log[k][c][2]) of chain c that stopped unconverged, else 0
 void launch_chain_status(const int *log, int n, int nchains, int *status, hipStream_t s);
+// p[i] = i for i < n.
+void launch_iota(int *p, int n, hipStream_t s);
 // q = q0 on the chains whose Metropolis test failed.
 void launch_restore(const Geo &g, const MetroOut *m, const double *q0, double *q, hipStream_t s);
 
