@@ -32,3 +32,25 @@ def test_batched_golden_matches_the_workload_recipe_and_the_oracle():
         assert abs(info["dH"] - ref["dH"]) <= 1e-12 * max(1.0, abs(ref["dH"]))
         assert abs(info["H0"] - ref["H0"]) <= 1e-12 * abs(ref["H0"])
         assert info["n_dinv"] == ref["n_dinv"]
+
+
+def test_thermalised_golden_matches_the_workload_recipe_and_the_oracle():
+    import numpy as np
+    from bench import workload
+    g = _load("batched_workload_thermalised.json")
+    L, beta, m0 = workload(g["seed"], g["n_chains"])
+    assert sorted(c["L"] for c in g["chains"]) == [16, 16, 32, 32, 64]
+    for ref in g["chains"]:
+        c = ref["chain"]
+        assert (L[c], beta[c], m0[c]) == (ref["L"], ref["beta"], ref["m0"])
+        assert len(ref["links"]) == 2 * ref["L"] ** 2 and ref["traj"] == g["n_therm"]
+    for ref in g["chains"]:
+        if ref["L"] > 16:
+            continue
+        # the check trajectory from the stored links
+        q = np.array(ref["links"]).reshape(ref["L"], ref["L"], 2)
+        _, info = oracle.hmc_trajectory(q, ref["beta"], ref["m0"], g["seed"], ref["chain"],
+                                        ref["traj"], g["scheme"], g["tau"], g["n_outer"],
+                                        g["n_inner"], tol=g["tol"])
+        assert info["accepted"] == ref["accepted"]
+        assert abs(info["dH"] - ref["dH"]) <= 1e-12 * max(1.0, abs(ref["dH"]))
