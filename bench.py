@@ -579,8 +579,8 @@ def main():
     ap.add_argument("--reliable-delta", type=float, default=1e-4,
                     help="mixed CG: FP64 residual recomputation when the FP32 residual has dropped "
                          "by this factor")
-    ap.add_argument("--cg-groups", type=int, choices=[1, 2], default=1,
-                    help="sets of chains whose CG kernels run concurrently on two streams")
+    ap.add_argument("--cg-groups", type=int, choices=[1, 2, 3, 4], default=1,
+                    help="chain groups advanced concurrently, each on its own stream and host thread")
     ap.add_argument("--cg-kernels", choices=["fused", "two"], default="two",
                     help="one fused kernel per CG iteration where the chains allow it, or two")
     ap.add_argument("--persistent-limit", type=int, default=0,

@@ -185,14 +185,19 @@ int hmc_set_check_interval(hmc_ctx *ctx, int every);
  * handle the larger chains; 0 disables it.  Default and maximum 2048. */
 int hmc_set_persistent_limit(hmc_ctx *ctx, int vmax);
 
-/* The chains that the multi-workgroup CG kernels iterate are split into `groups` (1 or 2)
- * sets of about equal sites; with 2 the second set iterates on a library-owned stream
- * beside the bound one, so that one set's kernels can fill the GPU while the other's ramp
- * up, drain or wait at a kernel boundary.  Each chain's arithmetic is the same either way:
- * results are bit-identical.  A batch with a chain above 2048 workgroups uses one set.
- * The sampled timing then reports, per kernel, both sets' bytes over the span from the
- * first start to the last end.  Default 1: on the batched workload 2 sets gained 0.5-3.7 %,
- * as both sets still wait together at every convergence check. */
+/* Chain groups (Sec. 2.1: the chains are independent HMC updates).  With groups > 1,
+ * hmc_trajectory splits the chains into that many contiguous ranges of about equal sites and
+ * advances each range through the whole trajectory (refresh, molecular dynamics with its own
+ * solves, convergence checks and workgroup compaction, energies, Metropolis) on its own
+ * stream, driven by its own host thread (the first range on the calling thread and the bound
+ * stream; the others on library-owned streams, after the work already on the bound stream,
+ * which waits for all of them before the call returns).  One range's kernels then fill the
+ * GPU while another's host waits at a convergence check or its solve drains.  Each chain's
+ * arithmetic is the same either way: results are bit-identical for any group count.  With
+ * more groups than chains each chain is a group.  Other calls (hmc_cg_solve, hmc_integrate,
+ * captured trajectories of hmc_set_graph) run the chains as one set.  The kernel statistics
+ * of hmc_get_kernel_stats add up the groups' launches (which overlap in time).  groups: 1..4,
+ * default 1. */
 int hmc_set_cg_groups(hmc_ctx *ctx, int groups);
 
 /* CG kernels of the multi-workgroup solver (Sec. 3 calls the solve "D^-1").  With on = 1

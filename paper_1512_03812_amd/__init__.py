@@ -256,7 +256,8 @@ class Lattice:
         self._check(self._lib.hmc_set_persistent_limit(self._ctx, int(vmax)))
 
     def set_cg_groups(self, groups: int):
-        """1 (default) or 2 concurrently iterating sets of the multi-workgroup chains."""
+        """Chain groups (1..4, default 1): trajectories advance the chains as that many
+        contiguous groups, each on its own stream and host thread (bit-identical results)."""
         self._check(self._lib.hmc_set_cg_groups(self._ctx, int(groups)))
 
     def set_fused_cg(self, on: bool):

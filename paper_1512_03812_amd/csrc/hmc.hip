@@ -42,10 +42,9 @@ enum Spin32Buf { FX, FR, FT, FPA, FPB, FR2, FS2, kNumSpin32Bufs };
 // sums to the host, so the bytes of exactly those launches are attributed to the measured
 // durations with no copy inside the iteration loop.
 struct TimedSlot {
-    hipEvent_t ev[2][4];  // per chain group: step 1 start, end; step 2 start, end
-    int ngroups;          // groups launched in this slot (their kernels run concurrently)
-    int sample;           // row of the device byte table (shared by the groups' chains)
-    bool two;             // step 2 was launched (not the fused iteration)
+    hipEvent_t ev[4];  // step 1 start, end; step 2 start, end
+    int sample;        // row of the device byte table
+    bool two;          // step 2 was launched (not the fused iteration)
 };
 
 struct KernelTimer {
@@ -66,6 +65,9 @@ struct KernelTimer {
 // Contexts hmc_trajectories_concurrent advances at once (one host thread each).
 constexpr int kMaxConcurrent = 8;
 
+// Chain groups of one context (hmc_set_cg_groups).
+constexpr int kMaxGroups = 4;
+
 // Solves whose results a captured trajectory can log on the device.
 constexpr int kMaxLoggedSolves = 1024;
 
@@ -82,7 +84,9 @@ struct GraphEntry {
 struct hmc_ctx {
     // ------------------------------------------------------------ geometry (host)
     int nchains = 0;
-    int Vtot = 0;
+    int Vtot = 0;            // sites of the flat site space (field planes are Vtot apart)
+    int site0 = 0;           // the chains' contiguous site range [site0, site0 + nsites)
+    int nsites = 0;          // (a chain group's context covers part of its parent's space)
     int block = 256;
     int nlog_max = 0;  // workgroups of the table at the smallest workgroup size
     bool has_large = false;  // some chain has more than kMaxChainBlocks workgroups
@@ -118,15 +122,18 @@ struct hmc_ctx {
     // ------------------------------------------------------------ solver partition
     hipStream_t side = nullptr;           // second stream for the persistent solver
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-    // Two concurrent groups of multi-workgroup chains: group 1 iterates on `aux` beside
-    // group 0 on the bound stream, so that one group's kernels fill the GPU while the
-    // other's ramp up, drain or wait at a kernel boundary.
-    int cg_groups = 1;                    // 1 or 2 (hmc_set_cg_groups)
     int device = 0;                       // the device current at hmc_bind
-    hipStream_t aux = nullptr;
-    hipEvent_t aux_fork_ev = nullptr, aux_join_ev = nullptr;
-    int grp_nb[2] = {0, 0};               // workgroups of each group in the big list
-    int part_groups = -1;                 // cg_groups the partition was built for
+    // Chain groups (hmc_set_cg_groups): contiguous ranges of the chains, each advanced through
+    // a trajectory as a context of its own (grp[g]: its own tables, stream and host thread;
+    // the fields are this context's), so that one group's kernels run while another's host
+    // waits at a convergence check or its solve drains.
+    int groups = 1;
+    int grp_n = 0;                        // groups built (0: none)
+    int grp_first[kMaxGroups + 1] = {};   // chain ranges [grp_first[g], grp_first[g + 1])
+    hmc_ctx *grp[kMaxGroups] = {};
+    hipEvent_t grp_fork = nullptr, grp_join[kMaxGroups] = {};
+    bool is_group = false;                // a group of another context (owns no workspace)
+    size_t off_groups = 0, groups_bytes = 0;  // the workspace area of the groups' tables
     int part_vmax = -1;                   // vmax the device partition tables were built for
     int n_big_blocks = 0, n_small = 0, small_vmax = 0;
     size_t lds_max = 64 * 1024;           // dynamic LDS a workgroup may opt in to
@@ -167,6 +174,8 @@ struct hmc_ctx {
         g.nchains = nchains;
         g.Vtot = Vtot;
         g.block = block;
+        g.site0 = site0;
+        g.nsites = nsites;
         return g;
     }
     double *partials() const { return at<double>(off_partials); }
@@ -234,10 +243,10 @@ void build_tables(hmc_ctx *c) {
 // Per-workgroup arrays are sized for the smallest workgroup the tuner may choose.
 constexpr int kMinBlock = 128;
 
-void layout_workspace(hmc_ctx *c, size_t N) {
-    size_t o = 0;
+// The per-chain and per-workgroup tables of a context with C chains and N logical workgroups,
+// carved from byte offset o of the workspace; returns the end.
+size_t layout_tables(hmc_ctx *c, size_t o, size_t C, size_t N) {
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
-    const size_t C = c->nchains, V = c->Vtot;
     c->off_chains = take(sizeof(ChainInfo) * C);
     c->off_work = take(sizeof(BlockWork) * N);
     c->off_active = take(sizeof(BlockWork) * N);
@@ -254,6 +263,22 @@ void layout_workspace(hmc_ctx *c, size_t N) {
     c->off_metro = take(sizeof(MetroOut) * C);
     c->off_status = take(sizeof(int) * C);
     c->off_count = take(sizeof(int) * 4);
+    return o;
+}
+
+// Bytes of layout_tables beyond its proportional part: each of its 16 tables rounds up to
+// 256 bytes, and the sample sums, counter and counts do not scale with C or N.
+constexpr size_t kTablesFixed = 16 * kAlign + sizeof(double) * 2 * kMaxSamples + 2 * kAlign;
+
+void layout_workspace(hmc_ctx *c, size_t N) {
+    const size_t C = c->nchains, V = c->Vtot;
+    size_t o = layout_tables(c, 0, C, N);
+    // the tables of up to kMaxGroups chain groups: they partition the chains and workgroups,
+    // so together they take at most these tables' bytes plus the fixed part of each
+    c->off_groups = o;
+    c->groups_bytes = o + kMaxGroups * kTablesFixed;
+    o = align_up(c->off_groups + c->groups_bytes);
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
     for (int b = 0; b < kNumLinkBufs; ++b) c->off_links[b] = take(sizeof(double) * 2 * V);
     for (int b = 0; b < kNumSpinBufs; ++b) c->off_spin[b] = take(sizeof(double2) * 2 * V);
     c->off_U64 = take(sizeof(double2) * 2 * V);
@@ -295,6 +320,7 @@ int make_ctx(hmc_ctx **out, int n, const int *Lx, const int *Lt, const double *b
         off += ci.V;
     }
     c->Vtot = off;
+    c->nsites = off;
     c->block = kMinBlock;
     build_tables(c);
     c->nlog_max = (int)c->work.size();
@@ -376,6 +402,17 @@ int to_host(hmc_ctx *c, void *dst, const void *src_dev, size_t bytes) {
     return HMC_OK;
 }
 
+// dst = src on the context's sites of both planes of a real link field.
+void copy_links(hmc_ctx *c, const double *src, double *dst) {
+    if (c->site0 == 0 && c->nsites == c->Vtot) {
+        launch_copy(src, dst, sizeof(double) * 2 * c->Vtot, c->stream);
+        return;
+    }
+    (void)hipMemcpy2DAsync(dst + c->site0, sizeof(double) * c->Vtot, src + c->site0,
+                           sizeof(double) * c->Vtot, sizeof(double) * c->nsites, 2,
+                           hipMemcpyDeviceToDevice, c->stream);
+}
+
 void ensure_links(hmc_ctx *c, const double *q, bool need32, long version) {
     // version >= 0 identifies q == LQ at that version; -1 forces a rebuild
     const bool have64 = version >= 0 && c->links_version == version;
@@ -432,25 +469,10 @@ void timer_reduce(hmc_ctx *c) {
 // event and byte sum is complete.
 void timer_flush(hmc_ctx *c) {
     KernelTimer &T = c->timer;
-    // With two groups, a kernel's duration is the span from the earlier group's start to
-    // the later group's end, and its bytes are both groups' (the kernels run concurrently).
-    auto span = [&](const TimedSlot &ts, int k, float *ms) {
-        float lo = 0.f, hi = 0.f;
-        for (int g = 0; g < ts.ngroups; ++g) {
-            float s0 = 0.f, s1 = 0.f;
-            if (hipEventElapsedTime(&s0, ts.ev[0][2 * k], ts.ev[g][2 * k]) != hipSuccess ||
-                hipEventElapsedTime(&s1, ts.ev[0][2 * k], ts.ev[g][2 * k + 1]) != hipSuccess)
-                return false;
-            lo = g ? std::min(lo, s0) : s0;
-            hi = g ? std::max(hi, s1) : s1;
-        }
-        *ms = hi - lo;
-        return true;
-    };
     for (const TimedSlot &ts : T.pending) {
         float a = 0.f, b = 0.f;
-        if (!span(ts, 0, &a)) continue;
-        if (ts.two && !span(ts, 1, &b)) continue;
+        if (hipEventElapsedTime(&a, ts.ev[0], ts.ev[1]) != hipSuccess) continue;
+        if (ts.two && hipEventElapsedTime(&b, ts.ev[2], ts.ev[3]) != hipSuccess) continue;
         T.ms[0] += a;
         T.bytes[0] += T.sums_host[2 * ts.sample];
         T.timed[0]++;
@@ -468,7 +490,7 @@ void timer_flush(hmc_ctx *c) {
 // each kernel gets its start and end events and step 1 records the bytes of both steps in
 // the row given to it (-1: not sampled).
 template <typename L1, typename L2>
-void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2, bool two = true, int ngroups = 1) {
+void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2, bool two = true) {
     KernelTimer &T = c->timer;
     if (T.on) T.launches++;
     // Sampled slots sit mid-way between the convergence checks, a few slots after the host
@@ -477,22 +499,16 @@ void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2, bool two = true, int 
     const int since = T.since_sync++;
     if (!T.on || slot % T.sample_every != T.sample_every / 2 || since < 2 ||
         (int)T.pending.size() == kMaxSamples || !T.sums_host) {
-        for (int g = 0; g < ngroups; ++g) {
-            step1(g, -1, nullptr, nullptr);
-            if (two) step2(g, nullptr, nullptr);
-        }
+        step1(-1, nullptr, nullptr);
+        if (two) step2(nullptr, nullptr);
         return;
     }
     TimedSlot ts;
-    for (int g = 0; g < ngroups; ++g)
-        for (int k = 0; k < 4; ++k) ts.ev[g][k] = timer_event(c);
-    ts.ngroups = ngroups;
+    for (int k = 0; k < 4; ++k) ts.ev[k] = timer_event(c);
     ts.sample = (int)T.pending.size();
     ts.two = two;
-    for (int g = 0; g < ngroups; ++g) {
-        step1(g, ts.sample, ts.ev[g][0], ts.ev[g][1]);
-        if (two) step2(g, ts.ev[g][2], ts.ev[g][3]);
-    }
+    step1(ts.sample, ts.ev[0], ts.ev[1]);
+    if (two) step2(ts.ev[2], ts.ev[3]);
     T.pending.push_back(ts);
 }
 
@@ -500,7 +516,7 @@ void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2, bool two = true, int 
 // multi-workgroup slot kernels, and uploads the workgroup list of the latter and the chain
 // list of the former.
 int build_partition(hmc_ctx *c, int vmax) {
-    if (c->part_vmax == vmax && c->part_groups == c->cg_groups) return HMC_OK;
+    if (c->part_vmax == vmax) return HMC_OK;
     std::vector<BlockWork> big;
     std::vector<int> small;
     int svmax = 0, rc = HMC_OK;
@@ -510,27 +526,8 @@ int build_partition(hmc_ctx *c, int vmax) {
             svmax = std::max(svmax, c->chains[k].V);
         }
     }
-    // the large chains, split into groups of about equal sites (largest first, each to the
-    // lighter group); the big list holds group 0's workgroups, then group 1's
-    std::vector<int> grp(c->nchains, 0), order;
-    for (int k = 0; k < c->nchains; ++k)
-        if (c->chains[k].V > vmax) order.push_back(k);
-    if (c->cg_groups == 2) {
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int a, int b) { return c->chains[a].V > c->chains[b].V; });
-        long long load[2] = {0, 0};
-        for (int k : order) {
-            grp[k] = load[1] < load[0] ? 1 : 0;
-            load[grp[k]] += c->chains[k].V;
-        }
-    }
-    c->grp_nb[0] = c->grp_nb[1] = 0;
-    for (int g = 0; g < 2; ++g)
-        for (const BlockWork &w : c->work)
-            if (c->chains[w.chain].V > vmax && grp[w.chain] == g) {
-                big.push_back(w);
-                c->grp_nb[g]++;
-            }
+    for (const BlockWork &w : c->work)
+        if (c->chains[w.chain].V > vmax) big.push_back(w);
     if (!big.empty())
         HIP_TRY(c, hipMemcpyAsync(c->at<BlockWork>(c->off_big), big.data(), sizeof(BlockWork) * big.size(),
                                   hipMemcpyHostToDevice, c->stream));
@@ -542,7 +539,6 @@ int build_partition(hmc_ctx *c, int vmax) {
     c->n_small = (int)small.size();
     c->small_vmax = svmax;
     c->part_vmax = vmax;
-    c->part_groups = c->cg_groups;
     return HMC_OK;
 }
 
@@ -667,11 +663,11 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
         int interval = c->check_every, next_check = interval, last_active = big.nblocks;
         for (; slot < max_slots; ++slot) {
             slot_launch(c, slot,
-                        [&](int, int sample, hipEvent_t e0, hipEvent_t e1) {
+                        [&](int sample, hipEvent_t e0, hipEvent_t e1) {
                             launch_cg_iter(g, fi, mixed, slot, tol, false, sample, lds_iter, c->stream,
                                            e0, e1);
                         },
-                        [](int, hipEvent_t, hipEvent_t) {}, false);
+                        [](hipEvent_t, hipEvent_t) {}, false);
             if (slot + 1 == next_check) {
                 int active = 0, live = 0;
                 if ((rc = check_convergence(c, big, max_iter, &active, &live))) return rc;
@@ -688,88 +684,45 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
         launch_cg_iter(big, fi, mixed, slot, tol, true, -1, lds_iter, c->stream);
         if (mixed) launch_cg_finish_mixed(big, f, c->stream);
     } else if (big.nblocks > 0) {
-    // Two groups of chains iterate concurrently, group 1 on the aux stream, unless a chain
-    // needs the finalize kernel (it reads every chain's partials) or a group is empty.
-    const int ng = c->cg_groups == 2 && !c->has_large && c->grp_nb[0] > 0 && c->grp_nb[1] > 0 ? 2 : 1;
-    hipStream_t gs[2] = {c->stream, c->aux};
-    Geo gfull[2] = {big, big};
-    if (ng == 2) {
-        gfull[0].nblocks = c->grp_nb[0];
-        gfull[1].work = big.work + c->grp_nb[0];
-        gfull[1].nblocks = c->grp_nb[1];
-    }
-    Geo gc[2] = {gfull[0], gfull[1]};
-    BlockWork *act[2] = {c->at<BlockWork>(c->off_active),
-                         c->at<BlockWork>(c->off_active) + (ng == 2 ? c->grp_nb[0] : 0)};
-    int *counts = c->at<int>(c->off_count);  // [active, live] per group
-    bool done[2] = {false, ng < 2};
-    launch_cg_init(big, f, mixed, c->delta, c->stream);
-    if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
-    if (ng == 2) {
-        HIP_TRY(c, hipEventRecord(c->aux_fork_ev, c->stream));
-        HIP_TRY(c, hipStreamWaitEvent(c->aux, c->aux_fork_ev, 0));
-    }
-    // iteration slots: CG iterations plus, in mixed precision, FP64 residual recomputations
-    const int max_slots = mixed ? max_iter + max_iter / 2 + 64 : max_iter;
-    const int max_it = mixed ? max_iter : max_slots;
-    // Convergence checks: the first after check_every slots; the interval doubles (up to
-    // 4x) while no chain converges and falls back when the active set shrinks.
-    int interval = c->check_every, next_check = interval, last_active = big.nblocks;
-    for (; slot < max_slots; ++slot) {
-        void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
-        int gl[2], n = 0;  // groups still iterating
-        for (int gi = 0; gi < 2; ++gi)
-            if (!done[gi]) gl[n++] = gi;
-        slot_launch(c, slot,
-                    [&](int k, int sample, hipEvent_t e0, hipEvent_t e1) {
-                        const int gi = gl[k];
-                        launch_cg_step1(gc[gi], f, mixed, slot, tol, max_it, po, pn, false, sample, gs[gi], e0,
-                                        e1);
-                        if (c->has_large) launch_finalize_large(big, f.p1, f.fin1, gs[gi]);
-                    },
-                    [&](int k, hipEvent_t e0, hipEvent_t e1) {
-                        const int gi = gl[k];
-                        launch_cg_step2(gc[gi], f, mixed, slot, pn, gs[gi], e0, e1);
-                        if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, gs[gi]);
-                    },
-                    true, n);
-        if (slot + 1 == next_check) {
-            for (int gi = 0; gi < 2; ++gi)
-                if (!done[gi]) launch_compact(gfull[gi], c->cg(), max_it, act[gi], counts + 2 * gi, gs[gi]);
-            if (!done[1] && ng == 2) {
-                HIP_TRY(c, hipEventRecord(c->aux_join_ev, c->aux));
-                HIP_TRY(c, hipStreamWaitEvent(c->stream, c->aux_join_ev, 0));
+        Geo gc = big;
+        BlockWork *act = c->at<BlockWork>(c->off_active);
+        int *counts = c->at<int>(c->off_count);  // [active workgroups, live chains]
+        launch_cg_init(big, f, mixed, c->delta, c->stream);
+        if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
+        // iteration slots: CG iterations plus, in mixed precision, FP64 residual recomputations
+        const int max_slots = mixed ? max_iter + max_iter / 2 + 64 : max_iter;
+        // Convergence checks: the first after check_every slots; the interval doubles (up to
+        // 4x) while no chain converges and falls back when the active set shrinks.
+        int interval = c->check_every, next_check = interval, last_active = big.nblocks;
+        for (; slot < max_slots; ++slot) {
+            void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
+            slot_launch(c, slot,
+                        [&](int sample, hipEvent_t e0, hipEvent_t e1) {
+                            launch_cg_step1(gc, f, mixed, slot, tol, max_iter, po, pn, false, sample,
+                                            c->stream, e0, e1);
+                            if (c->has_large) launch_finalize_large(big, f.p1, f.fin1, c->stream);
+                        },
+                        [&](hipEvent_t e0, hipEvent_t e1) {
+                            launch_cg_step2(gc, f, mixed, slot, pn, c->stream, e0, e1);
+                            if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
+                        });
+            if (slot + 1 == next_check) {
+                launch_compact(big, c->cg(), max_iter, act, counts, c->stream);
+                int nh[2] = {0, 0};
+                if ((rc = to_host(c, nh, counts, sizeof(nh)))) return rc;
+                if (nh[0] == 0 || (mixed && nh[1] == 0)) { ++slot; break; }
+                gc.work = act;
+                gc.nblocks = nh[0];
+                interval = nh[0] == last_active ? std::min(2 * interval, 4 * c->check_every)
+                                                : c->check_every;
+                last_active = nh[0];
+                next_check = slot + 1 + interval;
             }
-            int nh[4] = {0, 0, 0, 0};
-            if ((rc = to_host(c, nh, counts, sizeof(nh)))) return rc;
-            int active = 0;
-            for (int gi = 0; gi < 2; ++gi) {
-                if (done[gi]) continue;
-                if (nh[2 * gi] == 0 || (mixed && nh[2 * gi + 1] == 0)) {
-                    done[gi] = true;
-                } else {
-                    gc[gi].work = act[gi];
-                    gc[gi].nblocks = nh[2 * gi];
-                    active += nh[2 * gi];
-                }
-            }
-            if (done[0] && done[1]) { ++slot; break; }
-            interval = active == last_active ? std::min(2 * interval, 4 * c->check_every)
-                                             : c->check_every;
-            last_active = active;
-            next_check = slot + 1 + interval;
         }
-    }
-    // fold the last slot's residual into the state (decision only), on every large chain
-    for (int gi = 0; gi < ng; ++gi) {
-        launch_cg_step1(gfull[gi], f, mixed, slot, tol, max_it, pb[slot & 1], pb[(slot + 1) & 1], true,
-                        -1, gs[gi]);
-        if (mixed) launch_cg_finish_mixed(gfull[gi], f, gs[gi]);
-    }
-    if (ng == 2) {
-        HIP_TRY(c, hipEventRecord(c->aux_join_ev, c->aux));
-        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->aux_join_ev, 0));
-    }
+        // fold the last slot's residual into the state (decision only), on every large chain
+        launch_cg_step1(big, f, mixed, slot, tol, max_iter, pb[slot & 1], pb[(slot + 1) & 1], true, -1,
+                        c->stream);
+        if (mixed) launch_cg_finish_mixed(big, f, c->stream);
     }
     if (c->n_small > 0) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->join_ev, 0));
     if (c->timer.on) timer_reduce(c);
@@ -843,7 +796,7 @@ int fermion_force_at(MD &md, const double *q, long version, double *out) {
     md.force_evals++;
     if (version >= 0 && c->ff_version == version) {
         if (out != c->link(LFF))
-            launch_copy(c->link(LFF), out, sizeof(double) * 2 * c->Vtot, c->stream);
+            copy_links(c, c->link(LFF), out);
         return HMC_OK;
     }
     ensure_links(c, q, md.prec == HMC_PREC_MIXED, version);
@@ -854,7 +807,7 @@ int fermion_force_at(MD &md, const double *q, long version, double *out) {
     c->xi_version = c->chi_version = version;
     if (version >= 0) {
         if (out != c->link(LFF))
-            launch_copy(out, c->link(LFF), sizeof(double) * 2 * c->Vtot, c->stream);
+            copy_links(c, out, c->link(LFF));
         c->ff_version = version;
     }
     return HMC_OK;
@@ -1097,6 +1050,134 @@ int set_block(hmc_ctx *c, int block) {
     return sync(c);
 }
 
+// ------------------------------------------------------------------ chain groups
+void drop_groups(hmc_ctx *c) {
+    for (int g = 0; g < c->grp_n; ++g) {
+        hmc_ctx *k = c->grp[g];
+        if (!k) continue;
+        if (k->stream) (void)hipStreamSynchronize(k->stream);
+        if (g > 0 && k->stream) (void)hipStreamDestroy(k->stream);
+        if (k->side) (void)hipStreamDestroy(k->side);
+        if (k->fork_ev) (void)hipEventDestroy(k->fork_ev);
+        if (k->join_ev) (void)hipEventDestroy(k->join_ev);
+        for (hipEvent_t e : k->timer.pool) (void)hipEventDestroy(e);
+        if (k->timer.sums_host) (void)hipHostFree(k->timer.sums_host);
+        if (k->pinned) (void)hipHostFree(k->pinned);
+        delete k;
+        c->grp[g] = nullptr;
+    }
+    c->grp_n = 0;
+}
+
+// The settings of the parent that a group's trajectory reads.
+int sync_group(hmc_ctx *c, hmc_ctx *k) {
+    k->tol = c->tol;
+    k->max_iter = c->max_iter;
+    k->delta = c->delta;
+    k->check_every = c->check_every;
+    k->quenched = c->quenched;
+    k->fg_mode = c->fg_mode;
+    k->fused_on = c->fused_on;
+    if (k->persist_vmax != c->persist_vmax) {
+        k->persist_vmax = c->persist_vmax;
+        k->part_vmax = -1;
+    }
+    k->lds_max = c->lds_max;
+    k->traj = c->traj;
+    if (k->block != c->block) return set_block(k, c->block);
+    return HMC_OK;
+}
+
+// Splits the chains into min(groups, n_chains) contiguous ranges of about equal sites and
+// builds a context for each: its own chain and workgroup tables (in this context's group
+// area of the workspace), CG state, stream, host bookkeeping; the fields are this context's.
+int build_groups(hmc_ctx *c) {
+    const int G = std::min(c->groups, c->nchains);
+    if (c->grp_n == G) {
+        c->grp[0]->stream = c->stream;
+        for (int g = 0; g < G; ++g) {
+            int rc = sync_group(c, c->grp[g]);
+            if (rc) return fail(c, rc, "chain group %d: %s", g, c->grp[g]->err.c_str());
+        }
+        return HMC_OK;
+    }
+    int rc = sync(c);
+    if (rc) return rc;
+    drop_groups(c);
+    // boundaries: group g starts at the first chain whose preceding sites reach g/G of the total
+    std::vector<int> first(G + 1, c->nchains);
+    first[0] = 0;
+    long long acc = 0;
+    int g = 1;
+    for (int k = 0; k < c->nchains && g < G; ++k) {
+        acc += c->chains[k].V;
+        while (g < G && acc * G >= (long long)g * c->Vtot && k + 1 < c->nchains) first[g++] = k + 1;
+    }
+    // no empty range (G <= n_chains): at most n - (G - h) chains before group h, at least h
+    for (int h = G - 1; h >= 1; --h) first[h] = std::min(first[h], first[h + 1] - 1);
+    for (int h = 1; h < G; ++h) first[h] = std::max(first[h], first[h - 1] + 1);
+    if (!c->grp_fork) {
+        HIP_TRY(c, hipEventCreateWithFlags(&c->grp_fork, hipEventDisableTiming));
+        for (int h = 0; h < kMaxGroups; ++h)
+            HIP_TRY(c, hipEventCreateWithFlags(&c->grp_join[h], hipEventDisableTiming));
+    }
+    size_t off = c->off_groups;
+    for (int h = 0; h < G; ++h) {
+        hmc_ctx *k = new hmc_ctx();
+        c->grp[h] = k;
+        c->grp_n = h + 1;
+        c->grp_first[h] = first[h];
+        k->is_group = true;
+        k->nchains = first[h + 1] - first[h];
+        k->chains.assign(c->chains.begin() + first[h], c->chains.begin() + first[h + 1]);
+        k->Vtot = c->Vtot;
+        k->site0 = k->chains[0].off;
+        k->nsites = 0;
+        for (const ChainInfo &ci : k->chains) k->nsites += ci.V;
+        k->seed = c->seed;
+        k->block = kMinBlock;
+        build_tables(k);
+        const size_t nlog_min = k->work.size();
+        k->block = c->block;
+        build_tables(k);
+        off = align_up(layout_tables(k, off, k->nchains, nlog_min));
+        if (off > c->off_groups + c->groups_bytes)
+            return fail(c, HMC_E_NOMEM, "chain group tables exceed their workspace area");
+        for (int b = 0; b < kNumLinkBufs; ++b) k->off_links[b] = c->off_links[b];
+        for (int b = 0; b < kNumSpinBufs; ++b) k->off_spin[b] = c->off_spin[b];
+        for (int b = 0; b < kNumSpin32Bufs; ++b) k->off_spin32[b] = c->off_spin32[b];
+        k->off_U64 = c->off_U64;
+        k->off_A32 = c->off_A32;
+        k->off_Uw = c->off_Uw;
+        k->ws = c->ws;
+        k->ws_bytes = c->ws_bytes;
+        k->device = c->device;
+        k->lds_max = c->lds_max;
+        k->static_scratch = c->static_scratch;
+        k->cg_host.resize(k->nchains);
+        k->resid_host.resize(k->nchains);
+        if (h == 0) k->stream = c->stream;
+        else HIP_TRY(c, hipStreamCreateWithFlags(&k->stream, hipStreamNonBlocking));
+        HIP_TRY(c, hipStreamCreateWithFlags(&k->side, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&k->fork_ev, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&k->join_ev, hipEventDisableTiming));
+        k->pinned_bytes = align_up(sizeof(CGState) * k->nchains + sizeof(MetroOut) * k->nchains +
+                                   sizeof(double) * 16 * k->nchains + 4096);
+        HIP_TRY(c, hipHostMalloc(&k->pinned, k->pinned_bytes, hipHostMallocDefault));
+        HIP_TRY(c, hipMemcpyAsync(k->at<ChainInfo>(k->off_chains), k->chains.data(),
+                                  sizeof(ChainInfo) * k->nchains, hipMemcpyHostToDevice, k->stream));
+        HIP_TRY(c, hipMemcpyAsync(k->at<BlockWork>(k->off_work), k->work.data(),
+                                  sizeof(BlockWork) * k->work.size(), hipMemcpyHostToDevice, k->stream));
+        HIP_TRY(c, hipStreamSynchronize(k->stream));
+        if (c->timer.on) {
+            if ((rc = hmc_set_timing(k, 1))) return fail(c, rc, "chain group timing: %s", k->err.c_str());
+        }
+        if ((rc = sync_group(c, k))) return fail(c, rc, "chain group %d: %s", h, k->err.c_str());
+    }
+    c->grp_first[G] = c->nchains;
+    return HMC_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1125,6 +1206,8 @@ int hmc_bind(hmc_ctx *c, void *ws, size_t bytes, void *stream) {
     if ((uintptr_t)ws % kAlign) return fail(c, HMC_E_INVAL, "workspace must be 256-byte aligned");
     if (bytes < c->ws_bytes)
         return fail(c, HMC_E_NOMEM, "workspace has %zu bytes, needs %zu", bytes, c->ws_bytes);
+    if (c->is_group) return fail(c, HMC_E_INVAL, "a chain group is bound through its parent");
+    drop_groups(c);
     c->ws = (char *)ws;
     c->graph_epoch++;
     c->stream = (hipStream_t)stream;
@@ -1149,11 +1232,6 @@ int hmc_bind(hmc_ctx *c, void *ws, size_t bytes, void *stream) {
         HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
-    }
-    if (!c->aux) {
-        HIP_TRY(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->aux_fork_ev, hipEventDisableTiming));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->aux_join_ev, hipEventDisableTiming));
     }
     c->part_vmax = -1;
     HIP_TRY(c, hipMemcpyAsync(c->at<ChainInfo>(c->off_chains), c->chains.data(),
@@ -1280,9 +1358,16 @@ int hmc_set_persistent_limit(hmc_ctx *c, int vmax) {
 }
 
 int hmc_set_cg_groups(hmc_ctx *c, int groups) {
-    if (!c || groups < 1 || groups > 2) return HMC_E_INVAL;
-    c->cg_groups = groups;
-    c->graph_epoch++;
+    if (!c || groups < 1 || groups > kMaxGroups) return HMC_E_INVAL;
+    if (c->is_group) return fail(c, HMC_E_INVAL, "a chain group cannot be split again");
+    if (groups != c->groups) {
+        if (c->ws) {
+            int rc = sync(c);
+            if (rc) return rc;
+        }
+        drop_groups(c);
+    }
+    c->groups = groups;
     return HMC_OK;
 }
 
@@ -1743,8 +1828,8 @@ int hmc_refresh(hmc_ctx *c) {
 // molecular dynamics and the device part of the Metropolis step.
 static int trajectory_body(hmc_ctx *c, MD &md, int scheme, double tau, int n_outer, int n_inner) {
     refresh(c);
-    launch_copy(c->link(LQ), c->link(LQ0), sizeof(double) * 2 * c->Vtot, c->stream);
-    launch_copy(c->link(LP), c->link(LP0), sizeof(double) * 2 * c->Vtot, c->stream);
+    copy_links(c, c->link(LQ), c->link(LQ0));
+    copy_links(c, c->link(LP), c->link(LP0));
     int rc = run_md(md, scheme, tau, n_outer, n_inner);
     if (rc && !chain_failure(rc)) return rc;
     return finish_traj_device(c, md, true);
@@ -1854,12 +1939,65 @@ static int graph_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, int
     return rc;
 }
 
+// One trajectory with the chains split into groups: each group runs hmc_trajectory as a
+// context of its own, on its own stream and host thread (group 0 on the calling thread and
+// the bound stream), after the work already on the bound stream; the bound stream then waits
+// for every group.
+static int grouped_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner,
+                              int prec, hmc_traj_info *info) {
+    int rc = build_groups(c);
+    if (rc) return rc;
+    const int G = c->grp_n;
+    HIP_TRY(c, hipEventRecord(c->grp_fork, c->stream));
+    for (int g = 1; g < G; ++g) HIP_TRY(c, hipStreamWaitEvent(c->grp[g]->stream, c->grp_fork, 0));
+    int rcs[kMaxGroups] = {};
+    auto run = [&](int g) {
+        hmc_ctx *k = c->grp[g];
+        if (hipSetDevice(k->device) != hipSuccess) {
+            rcs[g] = fail(k, HMC_E_HIP, "hipSetDevice failed in a chain group");
+            return;
+        }
+        rcs[g] = hmc_trajectory(k, scheme, tau, n_outer, n_inner, prec,
+                                info ? info + c->grp_first[g] : nullptr);
+    };
+    int caller_dev = 0;
+    HIP_TRY(c, hipGetDevice(&caller_dev));
+    std::thread th[kMaxGroups];
+    bool started[kMaxGroups] = {};
+    for (int g = 1; g < G; ++g) {
+        try {
+            th[g] = std::thread(run, g);
+            started[g] = true;
+        } catch (const std::exception &) {
+            run(g);  // no thread: this group runs after the others on the calling thread
+        }
+    }
+    run(0);
+    for (int g = 1; g < G; ++g)
+        if (started[g]) th[g].join();
+    (void)hipSetDevice(caller_dev);
+    for (int g = 1; g < G; ++g) {
+        HIP_TRY(c, hipEventRecord(c->grp_join[g], c->grp[g]->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->grp_join[g], 0));
+    }
+    forget_all(c);
+    c->traj++;
+    for (int g = 0; g < G; ++g)
+        if (rcs[g]) {
+            c->err = c->grp[g]->err;
+            return rcs[g];
+        }
+    return HMC_OK;
+}
+
 int hmc_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, int prec,
                    hmc_traj_info *info) {
     CHECK_BOUND(c);
     int rc = check_md_args(c, scheme, tau, n_outer, n_inner, prec);
     if (rc) return rc;
     if (c->graph_on) return graph_trajectory(c, scheme, tau, n_outer, n_inner, prec, info);
+    if (c->groups > 1 && c->nchains > 1)
+        return grouped_trajectory(c, scheme, tau, n_outer, n_inner, prec, info);
     MD md;
     init_md(md, c, prec);
     launch_set_u32(c->at<uint32_t>(c->off_trajc), c->traj, c->stream);
@@ -1926,8 +2064,8 @@ int hmc_integrate(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, 
     // initial S_F is solved for (stored in the refresh slot)
     const Geo g = c->geo();
     const int C = c->nchains;
-    launch_copy(c->link(LQ), c->link(LQ0), sizeof(double) * 2 * c->Vtot, c->stream);
-    launch_copy(c->link(LP), c->link(LP0), sizeof(double) * 2 * c->Vtot, c->stream);
+    copy_links(c, c->link(LQ), c->link(LQ0));
+    copy_links(c, c->link(LP), c->link(LP0));
     double *rs = c->sums() + 7 * C;
     {
         // 1/2 sum p^2 and S_F(q0) = Re phi^dagger xi(q0)
@@ -1973,6 +2111,10 @@ int hmc_set_timing(hmc_ctx *c, int on) {
     T.bytes[0] = T.bytes[1] = 0.0;
     T.timed[0] = T.timed[1] = 0;
     T.launches = 0;
+    for (int g = 0; g < c->grp_n; ++g) {
+        int rc = hmc_set_timing(c->grp[g], on);
+        if (rc) return fail(c, rc, "chain group timing: %s", c->grp[g]->err.c_str());
+    }
     return HMC_OK;
 }
 
@@ -1985,18 +2127,27 @@ int hmc_get_kernel_stats(hmc_ctx *c, int which, hmc_kernel_stat *out) {
     out->timed_bytes = T.bytes[which];
     out->sample_every = T.sample_every;
     out->fused = T.fused ? 1 : 0;
+    for (int g = 0; g < c->grp_n; ++g) {  // the chain groups' launches add up
+        const KernelTimer &K = c->grp[g]->timer;
+        out->launches += K.launches;
+        out->timed_launches += K.timed[which];
+        out->timed_ms += K.ms[which];
+        out->timed_bytes += K.bytes[which];
+        out->fused |= K.fused ? 1 : 0;
+    }
     return HMC_OK;
 }
 
 int hmc_destroy(hmc_ctx *c) {
     if (!c) return HMC_E_INVAL;
+    drop_groups(c);
+    if (c->grp_fork) (void)hipEventDestroy(c->grp_fork);
+    for (hipEvent_t e : c->grp_join)
+        if (e) (void)hipEventDestroy(e);
     for (GraphEntry &g : c->graphs) drop_graph(g);
     for (hipEvent_t e : c->timer.pool) (void)hipEventDestroy(e);
     if (c->timer.sums_host) (void)hipHostFree(c->timer.sums_host);
     if (c->side) (void)hipStreamDestroy(c->side);
-    if (c->aux) (void)hipStreamDestroy(c->aux);
-    if (c->aux_fork_ev) (void)hipEventDestroy(c->aux_fork_ev);
-    if (c->aux_join_ev) (void)hipEventDestroy(c->aux_join_ev);
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     if (c->pinned) (void)hipHostFree(c->pinned);

@@ -1828,20 +1828,24 @@ void launch_hessian_vector(const Geo &g, const double2 *U, const double *v, cons
 }
 
 // ================================================================ updates
+// blockIdx.y selects the plane (mu); the sites [site0, site0 + n) of both planes
 __global__ void k_axpy(const double *__restrict__ a, double c, const double *__restrict__ b,
-                       double *__restrict__ out, size_t n) {
+                       double *__restrict__ out, size_t site0, size_t n, size_t plane) {
+    const size_t base = blockIdx.y * plane + site0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
-        out[i] = a[i] + c * b[i];
+        out[base + i] = a[base + i] + c * b[base + i];
 }
 
 void launch_axpy_links(const Geo &g, const double *a, double c, const double *b, double *out,
                        hipStream_t s) {
-    const size_t n = 2 * (size_t)g.Vtot;
+    const size_t n = (size_t)g.nsites;
     const int block = 256;
     size_t grid = (n + block - 1) / block;
-    if (grid > 65536) grid = 65536;
-    hipLaunchKernelGGL(k_axpy, dim3((unsigned)grid), dim3(block), 0, s, a, c, b, out, n);
+    if (grid > 32768) grid = 32768;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)grid, 2), dim3(block), 0, s, a, c, b, out,
+                       (size_t)g.site0, n, (size_t)g.Vtot);
 }
 
 void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {

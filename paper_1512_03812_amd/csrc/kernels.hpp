@@ -14,8 +14,9 @@ struct Geo {
     int nblocks;              // workgroups launched
     int nlog;                 // logical workgroups of the whole batch (size of a partials row)
     int nchains;
-    int Vtot;
+    int Vtot;                 // sites of the flat site space (the stride between field planes)
     int block;                // threads per workgroup
+    int site0, nsites;        // the contiguous flat-site range of these chains
 };
 
 // Per-chain CG state.  Double-buffered by the parity of the iteration slot: the first
@@ -205,8 +206,9 @@ void launch_hessian_vector(const Geo &g, const double2 *U, const double *v, cons
                            const double *q, bool gauge, double scale, double *out, hipStream_t s);
 
 // ---------------------------------------------------------------- updates
+// out = a + c b over the real link fields, on the sites [site0, site0 + nsites) of g
 void launch_axpy_links(const Geo &g, const double *a, double c, const double *b, double *out,
-                       hipStream_t s);  // out = a + c b over the real link fields
+                       hipStream_t s);
 void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- random numbers

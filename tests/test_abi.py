@@ -89,7 +89,8 @@ def test_unbound_context_is_rejected_without_touching_the_gpu(lib):
     assert lib.hmc_force_gradient_term(ctx, 2, buf, buf, 0, None) == -1
     assert lib.hmc_hessian_vector(ctx, 0, None, buf, buf, 0, None) == -1
     assert lib.hmc_stream_copy(ctx, buf, buf, 16) == -1
-    assert lib.hmc_set_cg_groups(ctx, 0) == -1 and lib.hmc_set_cg_groups(ctx, 3) == -1
+    assert lib.hmc_set_cg_groups(ctx, 0) == -1 and lib.hmc_set_cg_groups(ctx, 5) == -1
+    assert lib.hmc_set_cg_groups(ctx, 3) == 0 and lib.hmc_set_cg_groups(ctx, 1) == 0
     assert lib.hmc_set_cg_groups(ctx, 2) == 0 and lib.hmc_set_cg_groups(ctx, 1) == 0
     assert lib.hmc_set_fused_cg(ctx, 1) == 0 and lib.hmc_set_fused_cg(ctx, 0) == 0
     ctxs = (ctypes.c_void_p * 9)(*([ctx.value] * 9))

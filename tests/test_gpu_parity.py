@@ -225,24 +225,43 @@ def test_solution_does_not_depend_on_the_check_interval(prec, fused):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_two_chain_groups_match_one_bitwise(prec):
-    """The multi-workgroup chains split into two concurrently iterating sets give the same
-    bits as one set: trajectories of a batch of uneven chains."""
+def test_chain_groups_match_one_bitwise(prec):
+    """Trajectories of a batch of uneven chains with the chains split into 2, 3 or 4 groups
+    (each advanced on its own stream and host thread) give the bits of one group; with the
+    persistent solver on and off."""
     shapes = [(16, 16, 2.0, 0.1), (32, 32, 1.5, 0.05), (64, 16, 3.0, 0.2), (8, 8, 1.0, 0.3),
               (32, 16, 2.0, 0.15), (16, 32, 2.5, 0.08), (64, 64, 2.0, 0.1)]
-    res = []
-    for groups in (1, 2):
-        b = Batch(shapes, seed=31, persistent=0)
-        b.lat.set_cg_groups(groups)
-        b.lat.hot_start()
-        b.lat.set_solver(tol=1e-12 if prec == "fp64" else 1e-10)
-        out = []
-        for _ in range(2):
-            r = b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2, prec=prec)
-            out.append((list(r.dH), list(r.accepted), list(r.n_cg_iters)))
-        res.append((out, b.lat.q.cpu().numpy().copy()))
-    assert res[0][0] == res[1][0]
-    assert np.array_equal(res[0][1], res[1][1])
+    for persistent in (0, 2048):
+        res = []
+        for groups in (1, 2, 3, 4):
+            b = Batch(shapes, seed=31, persistent=persistent)
+            b.lat.set_cg_groups(groups)
+            b.lat.hot_start()
+            b.lat.set_solver(tol=1e-12 if prec == "fp64" else 1e-10)
+            out = []
+            for _ in range(2):
+                r = b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2, prec=prec)
+                out.append((list(r.dH), list(r.accepted), list(r.n_cg_iters), list(r.status),
+                            r.n_solves, list(r.plaquette)))
+            torch.cuda.synchronize()
+            res.append((out, b.lat.q.cpu().numpy().copy(), b.lat.p.cpu().numpy().copy()))
+        for k in range(1, 4):
+            assert res[0][0] == res[k][0], (persistent, k)
+            assert np.array_equal(res[0][1], res[k][1])
+            assert np.array_equal(res[0][2], res[k][2])
+
+
+def test_more_groups_than_chains_and_a_single_chain():
+    for shapes in ([(16, 16, 2.0, 0.1), (8, 8, 1.0, 0.3)], [(32, 32, 2.0, 0.1)]):
+        res = []
+        for groups in (1, 4):
+            b = Batch(shapes, seed=5, persistent=0)
+            b.lat.set_cg_groups(groups)
+            b.lat.hot_start()
+            r = b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2)
+            res.append((list(r.dH), b.lat.q.cpu().numpy().copy()))
+        assert res[0][0] == res[1][0]
+        assert np.array_equal(res[0][1], res[1][1])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
