@@ -8,14 +8,20 @@ Metropolis) for every chain of the batched workload:
   beta ~ U[1, 4], m0 ~ U[0.02, 0.2] (seeded), tau = 1, n_outer = 8, n_inner = 4,
   CG in FP32 with FP64 reliable updates to a true relative residual of 1e-10,
   Delta H / Metropolis / energies in FP64.
-value = chain-trajectories per second over the timed steps (inputs resident in HBM).  The
-workgroup size is autotuned; the persistent small-chain solver is off unless asked for
-(--persistent-limit -1 keeps the tuned limit), so that every CG kernel in the timed region
-runs alone and its event-timed bandwidth is its own.
-Beside it: the dominant kernel's roofline figure (event-timed inside the timed region),
-the plain FP64 single-chain 32 x 32 path on the same GPU, mixed against FP64 precision on
-a 256 x 256 lattice (beta 4, m0 0.05), and the CPU oracle timed on a bounded sample of the
-same workload.
+The chains are thermalised from the hot start first (untimed), then the autotuner picks the
+launch settings (workgroup size, step-kernel variant, check interval, reliable-update factor,
+chain groups) and its pick is used as is.  value = chain-trajectories per second over the
+timed steps (inputs resident in HBM), one hmc_trajectory call per step.
+Beside it:
+  - the dominant CG kernel's roofline figure, event-timed in a pass of the same workload run
+    as one chain group right after the timed steps (with several groups the kernels of
+    different groups overlap in time, so a kernel's duration would not be its own);
+  - the Delta H error against the FP64 oracle: sampled chains are loaded with oracle-made
+    thermalised links and run one trajectory of the whole batch at the timed tolerance and at
+    1e-12, against the oracle's trajectory from the same links and random numbers;
+  - the same workload timed at CG tolerance 1e-12 (the setting that meets the 1e-8 target);
+  - the plain FP64 single-chain 32 x 32 path, mixed against FP64 precision on 256 x 256;
+  - the CPU oracle on all available host cores (sampled workload, per-unit timings).
 """
 import argparse
 import hashlib
@@ -32,22 +38,23 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 METRIC = "HMC trajectories/sec at fixed acceptance; Dslash+CG achieved HBM GB/s"
 
 # The library attributes algorithmic bytes to its sampled, event-timed CG launches (bytes
-# per site: mixed FP32 slot 112 / 64 for step 1 / step 2, FP64 residual-recomputation slot
+# per site: mixed FP32 slot 104 / 56 for step 1 / step 2, FP64 residual-recomputation slot
 # 144 / 224, FP64 solver 224 / 128; times the sites of the chains not yet converged).
 KERNELS = {0: ("k_cg_step1<true, false>", "mixed-precision CG step 1: x update, direction, t = D p"),
            1: ("k_cg_step2<true, false>", "mixed-precision CG step 2: r -= alpha D^dagger t")}
 
 
 def hbm_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter record, or None
-    if the kernels have changed since the counters were taken."""
+    """The committed rocprofv3 record of `kernel` (HBM bytes per launch from the FETCH_SIZE and
+    WRITE_SIZE runs, and the kernel-trace mean duration of the same command), or None if the
+    kernels have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_batched512.json")
     src = os.path.join(ROOT, "paper_1512_03812_amd", "csrc", "kernels.hip")
     try:
         rec = json.load(open(path))
         if rec["kernel_source_sha256"] != hashlib.sha256(open(src, "rb").read()).hexdigest():
             return None
-        return rec["kernels"][kernel]["hbm_bytes_per_launch"]
+        return rec["kernels"][kernel]
     except (OSError, KeyError, ValueError):
         return None
 
@@ -61,8 +68,10 @@ def workload(seed=1512, n_chains=512):
     return L, beta, m0
 
 
-def run_batched(args):
-    import torch
+SCHEDULE = ("adapted_nested_fg", 1.0, 8, 4)
+
+
+def make_batch(args):
     import paper_1512_03812_amd as hmc
     L, beta, m0 = workload(args.seed, args.chains)
     if args.uniform_L:
@@ -72,38 +81,113 @@ def run_batched(args):
     lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
     lat.set_check_interval(args.check_interval)
     lat.set_fused_cg(args.cg_kernels == "fused")
-    lat.set_cg_groups(args.cg_groups)
     if args.block:
         lat.set_block_size(args.block)
-    tune = None
-    for w in range(args.warmup):
-        lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
-        if w == 0 and not args.no_tune:
-            tune = lat.autotune("mixed", 1e-10)
-        if w == 0 and args.persistent_limit >= 0:
-            # the persistent solver runs beside the slot kernels on a second stream; with it
-            # off every CG kernel has the GPU to itself and its event timing is its own
-            lat.set_persistent_limit(args.persistent_limit)
-            if tune is not None:
-                tune["persistent_limit"] = args.persistent_limit
-    torch.cuda.synchronize()
-    lat.set_timing(not args.no_timing)
+    return lat, L, beta, m0
+
+
+def timed_steps(lat, steps, prec="mixed"):
+    import torch
     acc, status, iters, force_evals, solves = [], [], 0, 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+    for _ in range(steps):
+        r = lat.trajectory(*SCHEDULE, prec=prec)
         acc += r.accepted
         status += r.status
         iters += sum(r.n_cg_iters)
         force_evals, solves = r.n_force_evals, r.n_solves
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    s1, s2 = lat.kernel_stats(0), lat.kernel_stats(1)
+    return dict(dt=time.perf_counter() - t0, acc=acc, status=status, force_evals=force_evals,
+                solves=solves, cg_iters_per_traj=iters / max(1, steps))
+
+
+def run_batched(args):
+    """Thermalisation, autotuning, warm-up, the timed steps, then the single-group roofline
+    pass (every 32nd CG slot event-timed)."""
+    lat, L, beta, m0 = make_batch(args)
+    for _ in range(args.therm):
+        lat.trajectory(*SCHEDULE, prec="mixed")
+    tune = None
+    if not args.no_tune:
+        tune = lat.autotune("mixed", 1e-10, schedule=SCHEDULE)
+    used = {"groups": args.groups or (tune["groups"] if tune else 1),
+            "persistent_limit": (args.persistent_limit if args.persistent_limit >= 0 else
+                                 (tune["persistent_limit"] if tune else 2048))}
+    lat.set_cg_groups(used["groups"])
+    lat.set_persistent_limit(used["persistent_limit"])
+    for _ in range(args.warmup):
+        lat.trajectory(*SCHEDULE, prec="mixed")
+    first_timed = lat.trajectory_counter
+    res = timed_steps(lat, args.steps)
+    res.update(L=L, sites=lat.V_total, n_chains=lat.n_chains, tune=tune, used=used,
+               timed_trajectories=[first_timed, lat.trajectory_counter])
+    # roofline pass: one group, the persistent solver off (every CG kernel runs alone)
+    lat.set_cg_groups(1)
+    lat.set_persistent_limit(0)
+    lat.set_timing(not args.no_timing)
+    rp = timed_steps(lat, args.roofline_steps)
+    res["s1"], res["s2"] = lat.kernel_stats(0), lat.kernel_stats(1)
     lat.set_timing(False)
-    return dict(L=L, dt=dt, acc=acc, status=status, s1=s1, s2=s2, sites=lat.V_total, tune=tune,
-                n_chains=lat.n_chains, force_evals=force_evals, solves=solves,
-                cg_iters_per_traj=iters / max(1, args.steps))
+    res["roofline_pass"] = {"trajectories": args.roofline_steps, "groups": 1, "persistent_limit": 0,
+                            "ms_per_step": round(1e3 * rp["dt"] / max(1, args.roofline_steps), 3)}
+    lat.set_cg_groups(used["groups"])
+    lat.set_persistent_limit(used["persistent_limit"])
+    res["lat"] = lat
+    return res
+
+
+def dH_error_vs_oracle(lat, tols):
+    """Sampled chains get the oracle's thermalised links (tests/golden, written by the oracle
+    alone); one trajectory of the whole batch per tolerance, with the trajectory counter of the
+    oracle's record, is compared chain by chain with the oracle's FP64 trajectory (CG 1e-14)."""
+    import numpy as np
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", "batched_workload_thermalised.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    q_saved = lat.q.clone()
+    ctr_saved = lat.trajectory_counter
+    lex = lat.unpack_links(lat.q)
+    for ref in gold["chains"]:
+        c = ref["chain"]
+        o = 2 * lat.offsets[c]
+        lex[o:o + 2 * ref["L"] ** 2] = torch.tensor(ref["links"], dtype=torch.float64,
+                                                     device=lex.device)
+    q_check = lat.pack_links(lex)
+    out = {}
+    for tol in tols:
+        lat.q.copy_(q_check)
+        lat.mark_links_changed()
+        lat.trajectory_counter = gold["n_therm"]
+        lat.set_solver(tol=tol, max_iter=20000)
+        r = lat.trajectory(gold["scheme"], gold["tau"], gold["n_outer"], gold["n_inner"], prec="mixed")
+        errs = [abs(r.dH[ref["chain"]] - ref["dH"]) for ref in gold["chains"]]
+        same = all(bool(r.accepted[ref["chain"]]) == ref["accepted"] for ref in gold["chains"])
+        out[f"{tol:g}"] = {"max_abs_dH_error": float(np.max(errs)), "dH_errors": [float(e) for e in errs],
+                           "same_decisions": same}
+    lat.set_solver(tol=1e-10, max_iter=20000)
+    lat.q.copy_(q_saved)
+    lat.mark_links_changed()
+    lat.trajectory_counter = ctr_saved
+    return {"chains": [ref["chain"] for ref in gold["chains"]],
+            "L": [ref["L"] for ref in gold["chains"]],
+            "reference": (f"FP64 oracle trajectory (CG 1e-14) from links after {gold['n_therm']} oracle "
+                          "trajectories (tests/golden/batched_workload_thermalised.json)"),
+            "by_cg_tolerance": out}
+
+
+def run_tight(lat, steps):
+    """The workload at CG tolerance 1e-12, the setting whose Delta H meets the 1e-8 target."""
+    lat.set_solver(tol=1e-12, max_iter=20000)
+    lat.trajectory(*SCHEDULE, prec="mixed")
+    r = timed_steps(lat, steps)
+    lat.set_solver(tol=1e-10, max_iter=20000)
+    n = lat.n_chains * steps
+    return {"value": round(n / r["dt"], 3), "unit": "chain-trajectories/s", "steps": steps,
+            "ms_per_step": round(1e3 * r["dt"] / steps, 3), "cg_tolerance": 1e-12,
+            "acceptance": round(sum(r["acc"]) / len(r["acc"]), 4),
+            "cg_iters_per_step": r["cg_iters_per_traj"]}
 
 
 def run_concurrent(args, n_ctx=2):
@@ -233,20 +317,40 @@ def run_precision(args, sizes, n_traj, n_therm):
     return out
 
 
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)), "model": model}
+
+
 def cpu_baseline(args):
-    """The oracle (plain FP64 C) on a bounded, stratified sample of the workload: full oracle
-    trajectories (adapted nested FG, tau 1, 8 x 4, CG to 1e-10) from the hot start of the
-    first 6 chains with L = 16, the first 4 with L = 32 and the first 3 with L = 64; for
-    L = 128 one fermion-force solve at its hot start, scaled by the trajectory/solve time
-    ratio measured on the L = 64 chains.  Per-size mean times are weighted by the workload's
-    count of chains of each size.  The sample runs twice: on one core, then as concurrent
-    threads on the host's cores (the oracle keeps no global state and its ctypes calls
-    release the interpreter lock), where each core advances its own chains; `value` is that
-    all-cores figure, with the per-task times taken under the full load."""
-    import os
+    """The oracle (plain FP64 C, -O2, no fast-math) on a bounded, stratified sample of the
+    workload, plus its per-unit costs on the small configurations.
+
+    Workload rate: full oracle trajectories (adapted nested FG, tau 1, 8 x 4, CG to 1e-10)
+    from the hot start of the first `cores` chains with L = 16, 32 and 64, and one
+    fermion-force solve of the first `cores` chains with L = 64 and 128 (an L = 128
+    trajectory is taken as its solve time times the trajectory/solve ratio of the L = 64
+    chains); per-size mean times, weighted by the workload's count of chains of each size,
+    give the time of one trajectory of all 512 chains on one core; the tasks run as `cores`
+    concurrent threads (the oracle keeps no global state and its calls release the
+    interpreter lock), so value = cores x 512 / that time, with each task timed under the
+    full load.  `cores` is the number of CPUs this process may use, at most 16.  The same
+    sample with one task per size, run alone on one core, gives single_core_value."""
     from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
     import oracle
+    from tests import inputs
     L, beta, m0 = workload(args.seed, args.chains)
+    info = cpu_info()
+    cores = max(1, min(16, info["usable_cpus"]))
 
     def first(Ls, k):
         return [i for i, l in enumerate(L) if l == Ls][:k]
@@ -254,8 +358,7 @@ def cpu_baseline(args):
     def traj_task(c):
         q = oracle.random_links(L[c], L[c], args.seed, c)
         t0 = time.perf_counter()
-        oracle.hmc_trajectory(q, beta[c], m0[c], args.seed, c, 0, "adapted_nested_fg", 1.0, 8, 4,
-                              tol=1e-10)
+        oracle.hmc_trajectory(q, beta[c], m0[c], args.seed, c, 0, *SCHEDULE, tol=1e-10)
         return ("traj", L[c], time.perf_counter() - t0)
 
     def solve_task(c):
@@ -265,9 +368,6 @@ def cpu_baseline(args):
         oracle.fermion_force(q, phi, m0[c], tol=1e-10)
         return ("solve", L[c], time.perf_counter() - t0)
 
-    tasks = [(traj_task, c) for Ls, k in ((16, 6), (32, 4), (64, 3)) for c in first(Ls, k)]
-    tasks += [(solve_task, c) for Ls in (64, 128) for c in first(Ls, 1)]
-
     def estimate(results):
         per_L = {}
         for Ls in (16, 32, 64):
@@ -276,32 +376,74 @@ def cpu_baseline(args):
                 per_L[Ls] = sum(ts) / len(ts)
         s64 = [t for kind, l, t in results if kind == "solve" and l == 64]
         s128 = [t for kind, l, t in results if kind == "solve" and l == 128]
-        ratio = per_L[64] / s64[0] if (64 in per_L and s64) else 33.0
-        if s128:
-            per_L[128] = ratio * s128[0]
+        ratio = per_L[64] / (sum(s64) / len(s64))
+        per_L[128] = ratio * sum(s128) / len(s128)
         return per_L, ratio, sum(per_L[Ls] * L.count(Ls) for Ls in per_L)
 
-    t_begin = time.perf_counter()
-    one = [fn(c) for fn, c in tasks]
-    per_L1, ratio1, total1 = estimate(one)
-    t_one = time.perf_counter() - t_begin
-    cores = max(1, min(16, os.cpu_count() or 1, len(tasks)))
+    def sample(k):
+        tasks = [(traj_task, c) for Ls in (16, 32, 64) for c in first(Ls, k)]
+        return tasks + [(solve_task, c) for Ls in (64, 128) for c in first(Ls, k)]
+
     t_begin = time.perf_counter()
     with ThreadPoolExecutor(max_workers=cores) as ex:
-        many = list(ex.map(lambda fc: fc[0](fc[1]), tasks))
+        many = list(ex.map(lambda fc: fc[0](fc[1]), sample(cores)))
     per_L, ratio, total = estimate(many)
     t_many = time.perf_counter() - t_begin
+    t_begin = time.perf_counter()
+    one = [fn(c) for fn, c in sample(1)]
+    per_L1, ratio1, total1 = estimate(one)
+    t_one = time.perf_counter() - t_begin
+
+    # per-unit costs on one core: C1 (8 x 8), C2 (32 x 32, five schemes), C4 (256 x 256)
+    units = {}
+    q8 = oracle.random_links(8, 8, args.seed, 0)
+    t0 = time.perf_counter()
+    for t in range(10):
+        oracle.hmc_trajectory(q8, 2.0, 0.1, args.seed, 0, t, "omelyan", 1.0, 10, 1, tol=1e-12)
+    units["c1_trajectory_s"] = (time.perf_counter() - t0) / 10
+    q32 = oracle.random_links(32, 32, args.seed, 0)
+    units["c2_trajectory_s"] = {}
+    for scheme, n_outer, n_inner in (("leapfrog", 16, 1), ("omelyan", 8, 1), ("force_gradient", 4, 1),
+                                     ("nested_fg", 4, 2), ("adapted_nested_fg", 4, 4)):
+        t0 = time.perf_counter()
+        oracle.hmc_trajectory(q32, 2.0, 0.1, args.seed, 0, 0, scheme, 1.0, n_outer, n_inner, tol=1e-12)
+        units["c2_trajectory_s"][f"{scheme} {n_outer}x{n_inner}"] = round(time.perf_counter() - t0, 4)
+    phi32 = oracle.dirac_dagger(q32, oracle.random_zeta(32, 32, args.seed, 0, 0), 0.1)
+    t0 = time.perf_counter()
+    _, it32, _ = oracle.cg(q32, phi32, 0.1, tol=1e-12)
+    t32 = time.perf_counter() - t0
+    units["c2_solve_ms"] = round(1e3 * t32, 3)
+    units["c2_cg_iteration_ns_per_site"] = round(1e9 * t32 / max(1, it32) / 1024, 2)
+    q256 = inputs.smooth_angles(256, 256, args.seed, 0.5)
+    psi = inputs.random_spinor(256, 256, args.seed)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        oracle.dirac(q256, psi, 0.05)
+    units["dslash_ns_per_site"] = round(1e9 * (time.perf_counter() - t0) / 5 / 65536, 2)
+    phi256 = oracle.dirac_dagger(q256, psi, 0.05)
+    t0 = time.perf_counter()
+    _, it256, _ = oracle.cg(q256, phi256, 0.05, tol=1e-10)
+    t256 = time.perf_counter() - t0
+    units["c4_solve_ms"] = round(1e3 * t256, 1)
+    units["c4_cg_iteration_ns_per_site"] = round(1e9 * t256 / max(1, it256) / 65536, 2)
+    units["c4_trajectory_s_extrapolated"] = round(33 * t256, 1)
+    units["how"] = ("one core; C1: 8x8 beta 2 m0 0.1, 5-stage 10 steps, tol 1e-12, mean of 10 trajectories; "
+                    "C2: 32x32 beta 2 m0 0.1 hot start, one trajectory per scheme at its "
+                    ">=90%-acceptance step setting, tol 1e-12, and one CG solve of phi = D^dagger zeta; "
+                    "Dslash: 256x256; C4: 256x256 m0 0.05, smooth links, CG to 1e-10, trajectory = 33 "
+                    "solves (4 n_outer + 1 of the adapted scheme at 8 x 4) x the solve time")
     return {"value": round(cores * len(L) / total, 4), "unit": "chain-trajectories/s",
-            "cores": cores, "kind": "oracle",
-            "sample": (f"{len(tasks)} oracle tasks: full trajectories from the hot start of the "
-                       "first 6 L=16, 4 L=32 and 3 L=64 chains, and one solve each of the first L=64 "
-                       f"and L=128 chain (L=128 trajectory = solve x the L=64 trajectory/solve ratio, "
-                       f"{ratio:.1f}); weighted by the workload's L counts; run once on 1 core "
-                       f"({t_one:.1f} s) and once as {cores} concurrent threads ({t_many:.1f} s wall), "
-                       f"whose per-task times give value = {cores} x chains / weighted time"),
+            "cores": cores, "kind": "oracle", "cpu": info,
+            "sample": (f"{len(many)} oracle tasks on {cores} concurrent threads ({t_many:.1f} s wall): full "
+                       f"trajectories from the hot start of the first {cores} chains with L=16, 32, 64 and "
+                       f"one solve each of the first {cores} chains with L=64 and 128 (L=128 trajectory = "
+                       f"solve x the L=64 trajectory/solve ratio, {ratio:.1f}); weighted by the workload's "
+                       f"L counts; value = cores x chains / weighted time per chain-trajectory set"),
             "single_core_value": round(len(L) / total1, 4),
+            "single_core_sample": f"one task per size, alone on one core ({t_one:.1f} s)",
             "seconds_per_chain_traj_by_L": {str(k): round(v, 3) for k, v in per_L.items()},
-            "seconds_per_chain_traj_by_L_single_core": {str(k): round(v, 3) for k, v in per_L1.items()}}
+            "seconds_per_chain_traj_by_L_single_core": {str(k): round(v, 3) for k, v in per_L1.items()},
+            "per_unit": units}
 
 
 def run_sweep(args):
@@ -568,8 +710,18 @@ def main():
     ap.add_argument("--single-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true")
-    ap.add_argument("--no-concurrent", action="store_true",
-                    help="skip the two-context concurrent run of the workload")
+    ap.add_argument("--concurrent", action="store_true",
+                    help="also time the workload as two contexts advanced by hmc_trajectories_concurrent")
+    ap.add_argument("--therm", type=int, default=30,
+                    help="untimed trajectories from the hot start before tuning and warm-up")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="chain groups of the timed steps (0: the autotuner's pick)")
+    ap.add_argument("--roofline-steps", type=int, default=3,
+                    help="trajectories of the single-group, event-timed roofline pass")
+    ap.add_argument("--tight-steps", type=int, default=4,
+                    help="timed trajectories of the workload at CG tolerance 1e-12 (0: skip)")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the Delta H comparison with the oracle's thermalised trajectories")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--block", type=int, default=0, help="fixed workgroup size (with --no-tune)")
     ap.add_argument("--uniform-L", type=int, default=0,
@@ -579,13 +731,10 @@ def main():
     ap.add_argument("--reliable-delta", type=float, default=1e-4,
                     help="mixed CG: FP64 residual recomputation when the FP32 residual has dropped "
                          "by this factor")
-    ap.add_argument("--cg-groups", type=int, choices=[1, 2, 3, 4], default=1,
-                    help="chain groups advanced concurrently, each on its own stream and host thread")
     ap.add_argument("--cg-kernels", choices=["fused", "two"], default="two",
                     help="one fused kernel per CG iteration where the chains allow it, or two")
-    ap.add_argument("--persistent-limit", type=int, default=0,
-                    help="persistent-solver limit in sites after tuning (default 0: off, so that "
-                         "the timed CG kernels run alone; -1 keeps the tuned value)")
+    ap.add_argument("--persistent-limit", type=int, default=-1,
+                    help="persistent-solver limit in sites for the timed steps (-1: the autotuner's pick)")
     ap.add_argument("--sweep", action="store_true",
                     help="roofline sweep on single large lattices instead of the HMC benchmark")
     ap.add_argument("--sweep-sizes", type=int, nargs="+", default=[256, 512, 1024, 2048, 4096, 8192])
@@ -648,6 +797,7 @@ def main():
         del src, dst, small
 
     b = run_batched(args)
+    lat = b.pop("lat")
     n_traj = b["n_chains"] * args.steps
     value = n_traj / b["dt"]
     s1, s2 = b["s1"], b["s2"]
@@ -657,9 +807,10 @@ def main():
     kname, kdesc = KERNELS[which]
     ach = sd["timed_bytes"] / (sd["timed_ms"] * 1e-3) / 1e9 if sd["timed_ms"] > 0 else 0.0
     t12 = (s1["timed_ms"] + s2["timed_ms"]) * 1e-3
-    avg_s = sd["timed_ms"] * 1e-3 / max(1, sd["timed_launches"])
-    tb = hbm_traffic(kname)
-    traffic = round(tb / avg_s / 1e9, 1) if (tb and avg_s > 0) else None
+    rec = hbm_traffic(kname)
+    traffic = None
+    if rec and rec.get("kernel_trace_mean_us"):
+        traffic = round(rec["hbm_bytes_per_launch"] / (rec["kernel_trace_mean_us"] * 1e-6) / 1e9, 1)
     cg_gbs = (s1["timed_bytes"] + s2["timed_bytes"]) / t12 / 1e9 if t12 > 0 else 0.0
     out = {
         "metric": METRIC,
@@ -680,8 +831,14 @@ def main():
                          "mixed CG (FP32 + FP64 reliable updates) to true residual 1e-10"),
             "n_chains": b["n_chains"], "sites": b["sites"], "scheme": "adapted_nested_fg",
             "parallelism": "single GPU, chains batched in every launch",
+            "thermalisation_trajectories": args.therm,
+            "timed_trajectory_counters": b["timed_trajectories"],
         },
-        "autotune": b["tune"],
+        "autotune": {"pick": b["tune"], "used": b["used"],
+                     "searched": {"block": [128, 256, 512, 1024], "persistent_limit": [0, 1024, 2048],
+                                  "step_variant": ["plain", "two_sites", "resident", "waves8"],
+                                  "check_interval": [16, 32, 64], "reliable_delta": [1e-3, 1e-4, 1e-5],
+                                  "groups": [1, 2, 3, 4]}},
         "acceptance": round(sum(b["acc"]) / len(b["acc"]), 4),
         "chain_failures": sum(1 for s in b["status"] if s != 0),
         "cg_iters_per_step": b["cg_iters_per_traj"],
@@ -691,12 +848,13 @@ def main():
             "bound": "hbm", "kernel": f"{kname} ({kdesc})",
             "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "traffic_bytes_per_launch": tb,
+            "traffic_record": rec,
             "avg_launch_us": round(1e3 * sd["timed_ms"] / max(1, sd["timed_launches"]), 3),
             "avg_bytes_per_launch": round(sd["timed_bytes"] / max(1, sd["timed_launches"])),
             "timed_launches": sd["timed_launches"], "launches": sd["launches"],
             "sample_every": sd["sample_every"],
             "share_of_cg_step_time": round(sd["timed_ms"] / max(1e-30, s1["timed_ms"] + s2["timed_ms"]), 3),
+            "measured_in": b["roofline_pass"],
         },
         "cg_step1_step2_gbs": round(cg_gbs, 1),
         "cg_steps": {KERNELS[k][0]: {"avg_launch_us": round(1e3 * st["timed_ms"] / max(1, st["timed_launches"]), 3),
@@ -704,7 +862,12 @@ def main():
                                      "timed_launches": st["timed_launches"]}
                      for k, st in ((0, s1), (1, s2))},
     }
-    if not args.no_concurrent:
+    if not args.no_oracle_check:
+        out["dH_error_vs_oracle"] = dH_error_vs_oracle(lat, (1e-10, 1e-12))
+    if args.tight_steps > 0:
+        out["cg_tol_1e-12"] = run_tight(lat, args.tight_steps)
+    del lat
+    if args.concurrent:
         out["concurrent_contexts"] = run_concurrent(args)
     if not args.no_single:
         out["fp64_single_chain"] = run_single_fp64(args)

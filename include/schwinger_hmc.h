@@ -216,17 +216,48 @@ int hmc_set_fused_cg(hmc_ctx *ctx, int on);
 /* Threads per workgroup of the site kernels (128..1024, multiple of 64; default 256). */
 int hmc_set_block_size(hmc_ctx *ctx, int block);
 
-/* Autotuner: times CG solves of this context's own chains at its current links (with a
- * fresh pseudofermion; p and phi are overwritten) for workgroup sizes {128, 256, 512, 1024} and
- * each applicable persistent-solver limit {0, 1024, 2048}, and keeps the fastest. */
+/* Variants of the two CG step kernels (compile-time instantiations):
+ * HMC_STEP_PLAIN     one lattice site per thread (default);
+ * HMC_STEP_TWO_SITES two sites per thread (a workgroup's strip of each parity plane is twice
+ *                    as long, so fewer of its stencil neighbours lie outside it);
+ * HMC_STEP_RESIDENT  a grid of at most the workgroups resident on the GPU at once walks the
+ *                    workgroup list (no partly filled last round, fewer workgroup starts);
+ * HMC_STEP_WAVES8    at most 64 VGPRs per thread, so 8 waves per SIMD fit.
+ * All give the same iterates.  The tables are rebuilt for the variant's sites per thread. */
+enum { HMC_STEP_PLAIN = 0, HMC_STEP_TWO_SITES = 1, HMC_STEP_RESIDENT = 2, HMC_STEP_WAVES8 = 3 };
+int hmc_set_step_variant(hmc_ctx *ctx, int variant);
+
+/* A trajectory schedule for the autotuner's chain-group search. */
 typedef struct {
-    int block;             /* chosen workgroup size */
-    int persistent_limit;  /* chosen persistent-solver limit (sites) */
-    double solve_ms;       /* mean time of one solve with that choice */
+    int scheme, n_outer, n_inner, pad;
+    double tau;
+} hmc_tune_schedule;
+
+/* The autotuner's pick (and what it cost to find). */
+typedef struct {
+    int block;             /* workgroup size of the site kernels */
+    int persistent_limit;  /* persistent-solver limit (sites) */
+    int step_variant;      /* HMC_STEP_* */
+    int check_interval;    /* CG slots between convergence checks */
+    int groups;            /* chain groups (hmc_set_cg_groups) */
     int candidates;        /* configurations timed */
-    int pad;
+    double reliable_delta; /* mixed precision: reliable-update factor */
+    double solve_ms;       /* mean wall time of one solve with the pick */
+    double traj_ms;        /* wall time of one trajectory with the pick (0: groups not searched) */
 } hmc_tune_info;
-int hmc_autotune(hmc_ctx *ctx, int prec, double tol, hmc_tune_info *out);
+
+/* Autotuner: times CG solves of this context's own chains at its current links (with a
+ * fresh pseudofermion: p and phi are overwritten; q is kept) and keeps the fastest setting,
+ * one dimension after the other: workgroup size {128, 256, 512, 1024} x persistent-solver
+ * limit {0, 1024, 2048 where chains fit}; step-kernel variant (sites per thread 1 or 2,
+ * resident grid, 64-VGPR bound); convergence-check interval {16, 32, 64}; in mixed
+ * precision the reliable-update factor {1e-3, 1e-4, 1e-5} (which changes the iterates within
+ * the tolerance).  If traj is not NULL and the context has several chains, it then times one
+ * trajectories of that schedule (the mean of two, after a warm-up one) for 1..4 chain groups and keeps
+ * the fastest; q and the trajectory counter are restored afterwards.  tol: the solver
+ * tolerance of the timed solves and trajectories. */
+int hmc_autotune(hmc_ctx *ctx, int prec, double tol, const hmc_tune_schedule *traj,
+                 hmc_tune_info *out);
 
 /* ---------------------------------------------------------------- operators (Sec. 3) */
 

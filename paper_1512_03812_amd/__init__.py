@@ -267,13 +267,29 @@ class Lattice:
     def set_block_size(self, block: int):
         self._check(self._lib.hmc_set_block_size(self._ctx, int(block)))
 
-    def autotune(self, prec="fp64", tol=1e-10) -> dict:
-        """Times solves over workgroup sizes and persistent-solver limits; keeps the fastest.
-        Overwrites p and phi (not q)."""
+    def autotune(self, prec="fp64", tol=1e-10, schedule=None) -> dict:
+        """hmc_autotune: workgroup size x persistent limit, step-kernel variant, check interval,
+        reliable-update factor (mixed), and, given schedule = (scheme, tau, n_outer, n_inner),
+        the chain-group count by whole trajectories.  Overwrites p and phi (q is kept)."""
         t = _lib.TuneInfo()
-        self._check(self._lib.hmc_autotune(self._ctx, _prec(prec), tol, ctypes.byref(t)))
-        return {"block": t.block, "persistent_limit": t.persistent_limit, "solve_ms": t.solve_ms,
+        sched = None
+        if schedule is not None:
+            scheme, tau, n_outer, n_inner = schedule
+            sched = _lib.TuneSchedule(_scheme(scheme), int(n_outer), int(n_inner), 0, float(tau))
+        self._check(self._lib.hmc_autotune(self._ctx, _prec(prec), tol,
+                                           ctypes.byref(sched) if sched is not None else None,
+                                           ctypes.byref(t)))
+        names = {v: k for k, v in _lib.STEP_VARIANTS.items()}
+        return {"block": t.block, "persistent_limit": t.persistent_limit,
+                "step_variant": names.get(t.step_variant, t.step_variant),
+                "check_interval": t.check_interval, "groups": t.groups,
+                "reliable_delta": t.reliable_delta, "solve_ms": t.solve_ms, "traj_ms": t.traj_ms,
                 "candidates": t.candidates}
+
+    def set_step_variant(self, variant):
+        """CG step-kernel variant: "plain", "two_sites", "resident" or "waves8"."""
+        v = _lib.STEP_VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        self._check(self._lib.hmc_set_step_variant(self._ctx, v))
 
     def set_check_interval(self, every: int):
         self._check(self._lib.hmc_set_check_interval(self._ctx, int(every)))

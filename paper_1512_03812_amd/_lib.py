@@ -38,9 +38,20 @@ class TrajInfo(ctypes.Structure):
                 ("n_cg_iters", ctypes.c_longlong)]
 
 
+class TuneSchedule(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int), ("n_outer", ctypes.c_int), ("n_inner", ctypes.c_int),
+                ("pad", ctypes.c_int), ("tau", ctypes.c_double)]
+
+
 class TuneInfo(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("persistent_limit", ctypes.c_int),
-                ("solve_ms", ctypes.c_double), ("candidates", ctypes.c_int), ("pad", ctypes.c_int)]
+                ("step_variant", ctypes.c_int), ("check_interval", ctypes.c_int),
+                ("groups", ctypes.c_int), ("candidates", ctypes.c_int),
+                ("reliable_delta", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("traj_ms", ctypes.c_double)]
+
+
+STEP_VARIANTS = {"plain": 0, "two_sites": 1, "resident": 2, "waves8": 3}
 
 
 class KernelStat(ctypes.Structure):
@@ -76,7 +87,8 @@ SIGNATURES = {
     "hmc_set_fused_cg": (_I, [_P, _I]),
     "hmc_set_cg_groups": (_I, [_P, _I]),
     "hmc_set_block_size": (_I, [_P, _I]),
-    "hmc_autotune": (_I, [_P, _I, _D, _P]),
+    "hmc_autotune": (_I, [_P, _I, _D, _P, _P]),
+    "hmc_set_step_variant": (_I, [_P, _I]),
     "hmc_dslash": (_I, [_P, _P, _P]),
     "hmc_dslash_dagger": (_I, [_P, _P, _P]),
     "hmc_cg_solve": (_I, [_P, _P, _P, _D, _I, _I, _P]),

@@ -84,6 +84,7 @@ struct GraphEntry {
 struct hmc_ctx {
     // ------------------------------------------------------------ geometry (host)
     int nchains = 0;
+    int step_variant = kStepPlain;  // CG step-kernel variant (sites per thread of the tables)
     int Vtot = 0;            // sites of the flat site space (field planes are Vtot apart)
     int site0 = 0;           // the chains' contiguous site range [site0, site0 + nsites)
     int nsites = 0;          // (a chain group's context covers part of its parent's space)
@@ -219,7 +220,7 @@ void build_tables(hmc_ctx *c) {
     c->has_large = false;
     for (int ch = 0; ch < c->nchains; ++ch) {
         ChainInfo &ci = c->chains[ch];
-        const int spt = 1;
+        const int spt = step_variant_spt(c->step_variant);
         ci.block0 = (int)logical.size();
         const int half = c->block / 2;
         ci.nblocks = (ci.Vh + half * spt - 1) / (half * spt);
@@ -554,7 +555,7 @@ int persistent_limit(hmc_ctx *c, bool mixed) {
 // LDS bytes of the fused iteration over the chains above vmax at the current workgroup
 // size, or 0 if one of them cannot use it (or the fused iteration is switched off).
 size_t fused_lds(hmc_ctx *c, int vmax, bool mixed) {
-    if (!c->fused_on) return 0;
+    if (!c->fused_on || step_variant_spt(c->step_variant) != 1) return 0;
     int entries = 0;
     for (const ChainInfo &ci : c->chains) {
         if (ci.V <= vmax) continue;
@@ -698,12 +699,13 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
             void *po = pb[slot & 1], *pn = pb[(slot + 1) & 1];
             slot_launch(c, slot,
                         [&](int sample, hipEvent_t e0, hipEvent_t e1) {
-                            launch_cg_step1(gc, f, mixed, slot, tol, max_iter, po, pn, false, sample,
+                            launch_cg_step1(gc, f, mixed, c->step_variant, slot, tol, max_iter, po, pn,
+                                            false, sample,
                                             c->stream, e0, e1);
                             if (c->has_large) launch_finalize_large(big, f.p1, f.fin1, c->stream);
                         },
                         [&](hipEvent_t e0, hipEvent_t e1) {
-                            launch_cg_step2(gc, f, mixed, slot, pn, c->stream, e0, e1);
+                            launch_cg_step2(gc, f, mixed, c->step_variant, slot, pn, c->stream, e0, e1);
                             if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
                         });
             if (slot + 1 == next_check) {
@@ -720,7 +722,8 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
             }
         }
         // fold the last slot's residual into the state (decision only), on every large chain
-        launch_cg_step1(big, f, mixed, slot, tol, max_iter, pb[slot & 1], pb[(slot + 1) & 1], true, -1,
+        launch_cg_step1(big, f, mixed, c->step_variant, slot, tol, max_iter, pb[slot & 1],
+                        pb[(slot + 1) & 1], true, -1,
                         c->stream);
         if (mixed) launch_cg_finish_mixed(big, f, c->stream);
     }
@@ -1033,13 +1036,16 @@ void init_md(MD &md, hmc_ctx *c, int prec) {
     forget_links(c);
 }
 
-// Rebuilds the workgroup tables for another workgroup size and uploads them.
-int set_block(hmc_ctx *c, int block) {
+// Rebuilds the workgroup tables for another workgroup size or step-kernel variant (its
+// sites per thread) and uploads them.
+int set_tables(hmc_ctx *c, int block, int variant) {
     if (block < kMinBlock || block > 1024 || block % 64) return fail(c, HMC_E_INVAL, "bad workgroup size");
-    if (block == c->block) return HMC_OK;
+    if (variant < 0 || variant >= kNumStepVariants) return fail(c, HMC_E_INVAL, "bad step-kernel variant");
+    if (block == c->block && variant == c->step_variant) return HMC_OK;
     int rc = sync(c);
     if (rc) return rc;
     c->block = block;
+    c->step_variant = variant;
     c->graph_epoch++;
     build_tables(c);
     HIP_TRY(c, hipMemcpyAsync(c->at<ChainInfo>(c->off_chains), c->chains.data(),
@@ -1084,8 +1090,7 @@ int sync_group(hmc_ctx *c, hmc_ctx *k) {
     }
     k->lds_max = c->lds_max;
     k->traj = c->traj;
-    if (k->block != c->block) return set_block(k, c->block);
-    return HMC_OK;
+    return set_tables(k, c->block, c->step_variant);
 }
 
 // Splits the chains into min(groups, n_chains) contiguous ranges of about equal sites and
@@ -1386,64 +1391,148 @@ int hmc_mark_links_changed(hmc_ctx *c) {
 
 int hmc_set_block_size(hmc_ctx *c, int block) {
     CHECK_BOUND(c);
-    return set_block(c, block);
+    return set_tables(c, block, c->step_variant);
 }
 
-int hmc_autotune(hmc_ctx *c, int prec, double tol, hmc_tune_info *out) {
+// Mean wall time of `reps` solves of the current right-hand side (after one warm-up solve).
+static int time_solves(hmc_ctx *c, int prec, double tol, int reps, double *ms) {
+    ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, c->q_version);
+    int rc = solve(c, c->spin(SPHI), c->spin(SXI), tol, c->max_iter, prec);
+    if (rc && !chain_failure(rc)) return rc;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int rep = 0; rep < reps; ++rep) {
+        rc = solve(c, c->spin(SPHI), c->spin(SXI), tol, c->max_iter, prec);
+        if (rc && !chain_failure(rc)) return rc;
+    }
+    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
+    return HMC_OK;
+}
+
+int hmc_autotune(hmc_ctx *c, int prec, double tol, const hmc_tune_schedule *traj, hmc_tune_info *out) {
     CHECK_BOUND(c);
+    if (c->is_group) return fail(c, HMC_E_INVAL, "tune the parent context, not a chain group");
     if (prec != HMC_PREC_FP64 && prec != HMC_PREC_MIXED) return fail(c, HMC_E_INVAL, "bad precision");
     if (!(tol > 0)) return fail(c, HMC_E_INVAL, "bad tolerance");
+    if (traj) {
+        int rc = check_md_args(c, traj->scheme, traj->tau, traj->n_outer, traj->n_inner, prec);
+        if (rc) return rc;
+    }
     // a realistic right-hand side at the current links: phi = D^dagger zeta
     forget_all(c);
     refresh(c);
+    int n = 0, rc = HMC_OK;
+    double best = 1e300, ms = 0.0;
+    // 1. workgroup size x persistent-solver limit
     std::vector<int> persist = {0};
     int vmin = 1 << 30;
     for (const ChainInfo &ci : c->chains) vmin = std::min(vmin, ci.V);
     if (vmin <= 1024) persist.push_back(1024);
     for (const ChainInfo &ci : c->chains)
         if (ci.V > 1024 && ci.V <= 2048) { persist.push_back(2048); break; }
-    const int blocks[4] = {128, 256, 512, 1024};
-    const int saved_block = c->block, saved_persist = c->persist_vmax;
-    double best = 1e300;
-    int best_block = saved_block, best_persist = saved_persist, n = 0;
-    for (int b : blocks) {
-        int rc = set_block(c, b);
-        if (rc) return rc;
+    int best_block = c->block, best_persist = c->persist_vmax;
+    for (int b : {128, 256, 512, 1024}) {
+        if ((rc = set_tables(c, b, kStepPlain))) return rc;
         for (int pv : persist) {
             c->persist_vmax = pv;
-            ensure_links(c, c->link(LQ), prec == HMC_PREC_MIXED, c->q_version);
-            rc = solve(c, c->spin(SPHI), c->spin(SXI), tol, c->max_iter, prec);  // warm-up
-            if (rc && !chain_failure(rc)) return rc;
-            const auto t0 = std::chrono::steady_clock::now();
-            for (int rep = 0; rep < 2; ++rep) {
-                rc = solve(c, c->spin(SPHI), c->spin(SXI), tol, c->max_iter, prec);
-                if (rc && !chain_failure(rc)) return rc;
-            }
-            const double ms =
-                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / 2;
+            if ((rc = time_solves(c, prec, tol, 2, &ms))) return rc;
             ++n;
-            if (ms < best) {
-                best = ms;
-                best_block = b;
-                best_persist = pv;
-            }
+            if (ms < best) { best = ms; best_block = b; best_persist = pv; }
         }
     }
-    int rc = set_block(c, best_block);
-    if (rc) return rc;
     c->persist_vmax = best_persist;
+    // 2. step-kernel variant (sites per thread, resident grid, register bound)
+    //    (the plain variant at this size was timed in step 1)
+    int best_variant = kStepPlain;
+    for (int v = kStepPlain + 1; v < kNumStepVariants; ++v) {
+        if ((rc = set_tables(c, best_block, v))) return rc;
+        if ((rc = time_solves(c, prec, tol, 2, &ms))) return rc;
+        ++n;
+        if (ms < best) { best = ms; best_variant = v; }
+    }
+    if ((rc = set_tables(c, best_block, best_variant))) return rc;
+    // 3. convergence-check interval
+    int best_every = c->check_every;
+    for (int every : {16, 32, 64}) {
+        c->check_every = every;
+        if ((rc = time_solves(c, prec, tol, 2, &ms))) return rc;
+        ++n;
+        if (ms < best) { best = ms; best_every = every; }
+    }
+    c->check_every = best_every;
+    // 4. mixed precision: the reliable-update factor (it changes the iterates within the
+    //    tolerance, not only the speed)
+    double best_delta = c->delta;
+    if (prec == HMC_PREC_MIXED) {
+        for (double d : {1e-3, 1e-4, 1e-5}) {
+            c->delta = d;
+            if ((rc = time_solves(c, prec, tol, 2, &ms))) return rc;
+            ++n;
+            if (ms < best) { best = ms; best_delta = d; }
+        }
+        c->delta = best_delta;
+    }
+    // 5. chain groups, by whole trajectories of the given schedule from the current links
+    //    (links, trajectory counter and tolerance restored afterwards)
+    int best_groups = c->groups;
+    double best_traj = 0.0;
+    if (traj && c->nchains > 1) {
+        std::vector<double> q(2 * (size_t)c->Vtot);
+        HIP_TRY(c, hipMemcpyAsync(q.data(), c->link(LQ), sizeof(double) * q.size(), hipMemcpyDeviceToHost,
+                                  c->stream));
+        if ((rc = sync(c))) return rc;
+        const uint32_t traj0 = c->traj;
+        const double tol0 = c->tol;
+        c->tol = tol;
+        best_traj = 1e300;
+        for (int gr = 1; gr <= std::min(kMaxGroups, c->nchains); ++gr) {
+            if ((rc = hmc_set_cg_groups(c, gr))) return rc;
+            // a warm-up trajectory, then the mean of two timed ones (each from the links the
+            // previous one left, so every candidate sees a different but equally thermalised
+            // configuration; the links are restored below)
+            double t_ms = 0.0;
+            for (int rep = 0; rep < 3; ++rep) {
+                if ((rc = sync(c))) return rc;
+                const auto t0 = std::chrono::steady_clock::now();
+                rc = hmc_trajectory(c, traj->scheme, traj->tau, traj->n_outer, traj->n_inner, prec, nullptr);
+                if (rc && !chain_failure(rc)) return rc;
+                if ((rc = sync(c))) return rc;
+                if (rep > 0)
+                    t_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / 2;
+            }
+            ++n;
+            if (t_ms < best_traj) { best_traj = t_ms; best_groups = gr; }
+        }
+        if ((rc = hmc_set_cg_groups(c, best_groups))) return rc;
+        HIP_TRY(c, hipMemcpyAsync(c->link(LQ), q.data(), sizeof(double) * q.size(), hipMemcpyHostToDevice,
+                                  c->stream));
+        if ((rc = sync(c))) return rc;
+        c->traj = traj0;
+        c->tol = tol0;
+    }
     c->part_vmax = -1;
     c->graph_epoch++;
     forget_all(c);
     if (out) {
+        memset(out, 0, sizeof *out);
         out->block = best_block;
         out->persistent_limit = best_persist;
-        out->solve_ms = best;
+        out->step_variant = best_variant;
+        out->check_interval = best_every;
+        out->groups = best_groups;
         out->candidates = n;
-        out->pad = 0;
+        out->reliable_delta = best_delta;
+        out->solve_ms = best;
+        out->traj_ms = best_traj;
     }
-    (void)saved_block;
-    (void)saved_persist;
+    return HMC_OK;
+}
+
+int hmc_set_step_variant(hmc_ctx *c, int variant) {
+    CHECK_BOUND(c);
+    int rc = set_tables(c, c->block, variant);
+    if (rc) return rc;
+    c->part_vmax = -1;
+    c->graph_epoch++;
     return HMC_OK;
 }
 

@@ -12,8 +12,10 @@
 // the host needs go through a one-workgroup-per-chain finalize kernel.
 #include <math.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -485,15 +487,22 @@ __global__ void k_cg_init(Geo g, CGFields f, double delta2) {
 // the CG states) and the slot as leading scalar arguments: the library is built with kernarg
 // preloading, so these arrive in SGPRs at wave launch and the first table load does not wait
 // for a kernarg load.  (Geo and CGFields still carry the same pointers for the rest.)
-template <bool MIXED, bool NT>
-__global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
-                           CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f,
-                           double tol2, int max_iter, const void *p_old_v, void *p_new_v,
-                           int decide_only, int sample) {
+//
+// Each kernel handles one work entry per workgroup, or, in the resident variant, a grid of at
+// most the workgroups that fit on the GPU at once walks the list (entry b, b + grid, ...).
+// SPT sites per thread: a workgroup of B threads owns the half-site range
+// [start, start + SPT B/2) of both parity planes; thread t takes plane t >= B/2 and the
+// half-sites start + (t mod B/2) + j B/2, j < SPT, whose LDS slot is
+// plane * SPT B/2 + (t mod B/2) + j B/2.
+template <bool MIXED, bool NT, int SPT>
+__device__ __forceinline__ void step1_entry(const BlockWork w, const ChainInfo *__restrict__ chains,
+                                            CGState *__restrict__ states, int slot, int nchains,
+                                            const Geo &g, const CGFields &f, double tol2, int max_iter,
+                                            const void *p_old_v, void *p_new_v, int decide_only,
+                                            int sample) {
     using R = typename Prec<MIXED>::R;
     using S = typename Prec<MIXED>::S;
     using C = cplx_t<R>;
-    const BlockWork w = work[blockIdx.x];
     CGState *out = states + (size_t)(slot & 1) * nchains + w.chain;
     const CGState *prev = states + (size_t)((slot + 1) & 1) * nchains + w.chain;
     // The state is read field by field in scalars (a whole-struct copy per thread would be
@@ -513,7 +522,7 @@ __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *
     }
     // x update still owed by the previous slot (none after the initial or an update slot)
     const double pend = p_mode == kModeNormal ? p_alpha : 0.0;
-    // The operands of a normal slot on the own site are loaded before the chain total, so
+    // The operands of a normal slot on the own sites are loaded before the chain total, so
     // their latency overlaps its partial loads (they go unused in the other modes).
     const S *__restrict__ p_old = (const S *)p_old_v;
     S *__restrict__ p_new = (S *)p_new_v;
@@ -524,23 +533,33 @@ __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *
     else { r = f.r64; t = f.t64; x = f.x64; }
     const LinkSrc<MIXED> U = link_source<MIXED>(f);
     const int half = (int)blockDim.x >> 1;
+    const int span = half * SPT;
     const int par = (int)threadIdx.x >= half ? 1 : 0;
-    const int i = w.start + (int)threadIdx.x - par * half;
-    const bool own = i < ci.Vh;
+    const int i0 = w.start + (int)threadIdx.x - par * half;
     const bool first = p_mode == kModeInit;
-    Site s = {};
-    Nbr nb = {};
-    SiteLinks<C> lk = {};
-    C a0 = {}, a1 = {}, q0 = {}, q1 = {}, x0 = {}, x1 = {};
-    if (own) {
-        s = decode_site(ci, par * ci.Vh + i);
-        nb = neighbours(ci, s);
-        sp_load(r, Vtot, s.flat, a0, a1);
-        if (!first) {
-            sp_load(p_old, Vtot, s.flat, q0, q1);
-            sp_load(x, Vtot, s.flat, x0, x1);
+    bool own[SPT];
+    Site s[SPT];
+    Nbr nb[SPT];
+    SiteLinks<C> lk[SPT];
+    C a0[SPT], a1[SPT], q0[SPT], q1[SPT], x0[SPT], x1[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int i = i0 + j * half;
+        own[j] = i < ci.Vh;
+        s[j] = Site{};
+        nb[j] = Nbr{};
+        lk[j] = SiteLinks<C>{};
+        a0[j] = a1[j] = q0[j] = q1[j] = x0[j] = x1[j] = C{};
+        if (own[j]) {
+            s[j] = decode_site(ci, par * ci.Vh + i);
+            nb[j] = neighbours(ci, s[j]);
+            sp_load(r, Vtot, s[j].flat, a0[j], a1[j]);
+            if (!first) {
+                sp_load(p_old, Vtot, s[j].flat, q0[j], q1[j]);
+                sp_load(x, Vtot, s[j].flat, x0[j], x1[j]);
+            }
+            lk[j] = site_links(U, nb[j], s[j].flat, Vtot);
         }
-        lk = site_links(U, nb, s.flat, Vtot);
     }
     const double rho = chain_total(f.p2, f.fin2, ci, w.chain);
     double n_rho = rho, n_rho_p = p_rho_p, n_target = p_target, n_phi2 = p_phi2, n_rmax2 = p_rmax2;
@@ -626,9 +645,8 @@ __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *
         return;
     }
     const R beta = (R)n_beta;
-    // Own site: x += pend p_old (deferred from the previous slot), p_new = r + beta p_old,
-    // staged in LDS for the neighbours inside the workgroup; t = D p_new (one site per
-    // thread: the tables use w.spt == 1).
+    // Own sites: x += pend p_old (deferred from the previous slot), p_new = r + beta p_old,
+    // staged in LDS for the neighbours inside the workgroup; t = D p_new.
     LdsSpinor<C> *lds = (LdsSpinor<C> *)smem_d;
     auto direction = [&](int fl, C &b0, C &b1) {
         sp_load(r, Vtot, fl, b0, b1);
@@ -639,42 +657,46 @@ __global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *
             b1 = cmake<C>(b1.x + beta * c1.x, b1.y + beta * c1.y);
         }
     };
-    if (own) {
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        if (!own[j]) continue;
         if (!first) {
-            x0.x += a_pend * q0.x; x0.y += a_pend * q0.y;
-            x1.x += a_pend * q1.x; x1.y += a_pend * q1.y;
-            sp_store_wt<NT>(x, Vtot, s.flat, x0, x1);
-            a0 = cmake<C>(a0.x + beta * q0.x, a0.y + beta * q0.y);
-            a1 = cmake<C>(a1.x + beta * q1.x, a1.y + beta * q1.y);
+            x0[j].x += a_pend * q0[j].x; x0[j].y += a_pend * q0[j].y;
+            x1[j].x += a_pend * q1[j].x; x1[j].y += a_pend * q1[j].y;
+            sp_store_wt<NT>(x, Vtot, s[j].flat, x0[j], x1[j]);
+            a0[j] = cmake<C>(a0[j].x + beta * q0[j].x, a0[j].y + beta * q0[j].y);
+            a1[j] = cmake<C>(a1[j].x + beta * q1[j].x, a1[j].y + beta * q1[j].y);
         }
-        sp_store_wt<NT>(p_new, Vtot, s.flat, a0, a1);
-        lds[threadIdx.x].a = a0;
-        lds[threadIdx.x].b = a1;
+        sp_store_wt<NT>(p_new, Vtot, s[j].flat, a0[j], a1[j]);
+        const int k = par * span + (int)threadIdx.x - par * half + j * half;
+        lds[k].a = a0[j];
+        lds[k].b = a1[j];
     }
     __syncthreads();
     double v[1] = {0.0};
-    if (own) {
-        auto load = [&](int fl, C &b0, C &b1) {
-            const int k = lds_slot(ci, w, half, fl);
-            if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
-            else direction(fl, b0, b1);
-        };
+    auto load = [&](int fl, C &b0, C &b1) {
+        const int k = lds_slot(ci, w, span, fl);
+        if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
+        else direction(fl, b0, b1);
+    };
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        if (!own[j]) continue;
         C o0, o1;
-        dslash_site_links<R, false>(nb, lk, a0, a1, (R)(2.0 + ci.m0), load, o0, o1);
-        sp_store_wt<NT>(t, Vtot, s.flat, o0, o1);
-        v[0] = norm2(o0) + norm2(o1);
+        dslash_site_links<R, false>(nb[j], lk[j], a0[j], a1[j], (R)(2.0 + ci.m0), load, o0, o1);
+        sp_store_wt<NT>(t, Vtot, s[j].flat, o0, o1);
+        v[0] += norm2(o0) + norm2(o1);
     }
     write_partials<1>(v, f.p1, g.nlog, w.logical);
 }
 
-template <bool MIXED, bool NT>
-__global__ void k_cg_step2(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
-                           CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f,
-                           const void *p_new_v) {
+template <bool MIXED, bool NT, int SPT>
+__device__ __forceinline__ void step2_entry(const BlockWork w, const ChainInfo *__restrict__ chains,
+                                            CGState *__restrict__ states, int slot, int nchains,
+                                            const Geo &g, const CGFields &f, const void *p_new_v) {
     using R = typename Prec<MIXED>::R;
     using S = typename Prec<MIXED>::S;
     using C = cplx_t<R>;
-    const BlockWork w = work[blockIdx.x];
     CGState *st = states + (size_t)(slot & 1) * nchains + w.chain;
     // the state's fields before the chain's table entry, so that both loads are in flight
     // together
@@ -723,46 +745,110 @@ __global__ void k_cg_step2(const BlockWork *__restrict__ work, const ChainInfo *
     if constexpr (MIXED) { t = f.t32; r = f.r32; }
     else { t = f.t64; r = f.r64; }
     const LinkSrc<MIXED> U = link_source<MIXED>(f);
-    // The own site's t, r and links are loaded before the chain total, so their latency
+    // The own sites' t, r and links are loaded before the chain total, so their latency
     // overlaps its partial loads.  t is staged in LDS for the neighbours inside the
-    // workgroup (one site per thread: the tables use w.spt == 1).
+    // workgroup.
     LdsSpinor<C> *lds = (LdsSpinor<C> *)smem_d;
     const int half = (int)blockDim.x >> 1;
+    const int span = half * SPT;
     const int par = (int)threadIdx.x >= half ? 1 : 0;
-    const int i = w.start + (int)threadIdx.x - par * half;
-    const bool own = i < ci.Vh;
-    Site s = {};
-    Nbr nb = {};
-    SiteLinks<C> lk = {};
-    C t0 = {}, t1 = {}, r0 = {}, r1 = {};
-    if (own) {
-        s = decode_site(ci, par * ci.Vh + i);
-        nb = neighbours(ci, s);
-        sp_load(t, Vtot, s.flat, t0, t1);
-        sp_load(r, Vtot, s.flat, r0, r1);
-        lk = site_links(U, nb, s.flat, Vtot);
-        lds[threadIdx.x].a = t0;
-        lds[threadIdx.x].b = t1;
+    const int i0 = w.start + (int)threadIdx.x - par * half;
+    bool own[SPT];
+    Site s[SPT];
+    Nbr nb[SPT];
+    SiteLinks<C> lk[SPT];
+    C t0[SPT], t1[SPT], r0[SPT], r1[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int i = i0 + j * half;
+        own[j] = i < ci.Vh;
+        s[j] = Site{};
+        nb[j] = Nbr{};
+        lk[j] = SiteLinks<C>{};
+        t0[j] = t1[j] = r0[j] = r1[j] = C{};
+        if (own[j]) {
+            s[j] = decode_site(ci, par * ci.Vh + i);
+            nb[j] = neighbours(ci, s[j]);
+            sp_load(t, Vtot, s[j].flat, t0[j], t1[j]);
+            sp_load(r, Vtot, s[j].flat, r0[j], r1[j]);
+            lk[j] = site_links(U, nb[j], s[j].flat, Vtot);
+            const int k = par * span + (int)threadIdx.x - par * half + j * half;
+            lds[k].a = t0[j];
+            lds[k].b = t1[j];
+        }
     }
     const double pAp = chain_total(f.p1, f.fin1, ci, w.chain);
     const double alpha_d = s_rho / pAp;
     if (w.logical == ci.block0 && threadIdx.x == 0) st->alpha = alpha_d;  // owed to x (next slot)
     const R alpha = (R)alpha_d;
     __syncthreads();
-    if (own) {
-        auto load = [&](int fl, C &b0, C &b1) {
-            const int k = lds_slot(ci, w, half, fl);
-            if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
-            else sp_load(t, Vtot, fl, b0, b1);
-        };
+    auto load = [&](int fl, C &b0, C &b1) {
+        const int k = lds_slot(ci, w, span, fl);
+        if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
+        else sp_load(t, Vtot, fl, b0, b1);
+    };
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        if (!own[j]) continue;
         C a0, a1;
-        dslash_site_links<R, true>(nb, lk, t0, t1, (R)(2.0 + ci.m0), load, a0, a1);
-        r0.x -= alpha * a0.x; r0.y -= alpha * a0.y;
-        r1.x -= alpha * a1.x; r1.y -= alpha * a1.y;
-        sp_store_wt<NT>(r, Vtot, s.flat, r0, r1);
-        v[0] = norm2(r0) + norm2(r1);
+        dslash_site_links<R, true>(nb[j], lk[j], t0[j], t1[j], (R)(2.0 + ci.m0), load, a0, a1);
+        r0[j].x -= alpha * a0.x; r0[j].y -= alpha * a0.y;
+        r1[j].x -= alpha * a1.x; r1[j].y -= alpha * a1.y;
+        sp_store_wt<NT>(r, Vtot, s[j].flat, r0[j], r1[j]);
+        v[0] += norm2(r0[j]) + norm2(r1[j]);
     }
     write_partials<1>(v, f.p2, g.nlog, w.logical);
+}
+
+// The entry loop of the resident variant: a barrier between entries, so that no thread
+// rewrites LDS (the staged spinors, the partial sums) while another still reads the previous
+// entry's.
+#define STEP_ENTRIES(RES, BODY)                                                          \
+    if constexpr (RES) {                                                                 \
+        for (int b = blockIdx.x; b < g.nblocks; b += gridDim.x) {                        \
+            if (b != (int)blockIdx.x) __syncthreads();                                   \
+            BODY(work[b]);                                                               \
+        }                                                                                \
+    } else {                                                                             \
+        BODY(work[blockIdx.x]);                                                          \
+    }
+
+template <bool MIXED, bool NT, int SPT, bool RES>
+__global__ void k_cg_step1(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
+                           CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f,
+                           double tol2, int max_iter, const void *p_old_v, void *p_new_v,
+                           int decide_only, int sample) {
+#define BODY1(W) step1_entry<MIXED, NT, SPT>(W, chains, states, slot, nchains, g, f, tol2, max_iter, \
+                                             p_old_v, p_new_v, decide_only, sample)
+    STEP_ENTRIES(RES, BODY1)
+#undef BODY1
+}
+
+// The same with at most 64 VGPRs (8 waves per SIMD): the occupancy variant.
+template <bool MIXED, bool NT>
+__global__ void __attribute__((amdgpu_waves_per_eu(8)))
+k_cg_step1_w8(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
+              CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f, double tol2,
+              int max_iter, const void *p_old_v, void *p_new_v, int decide_only, int sample) {
+    step1_entry<MIXED, NT, 1>(work[blockIdx.x], chains, states, slot, nchains, g, f, tol2, max_iter,
+                              p_old_v, p_new_v, decide_only, sample);
+}
+
+template <bool MIXED, bool NT, int SPT, bool RES>
+__global__ void k_cg_step2(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
+                           CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f,
+                           const void *p_new_v) {
+#define BODY2(W) step2_entry<MIXED, NT, SPT>(W, chains, states, slot, nchains, g, f, p_new_v)
+    STEP_ENTRIES(RES, BODY2)
+#undef BODY2
+}
+
+template <bool MIXED, bool NT>
+__global__ void __attribute__((amdgpu_waves_per_eu(8)))
+k_cg_step2_w8(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
+              CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f,
+              const void *p_new_v) {
+    step2_entry<MIXED, NT, 1>(work[blockIdx.x], chains, states, slot, nchains, g, f, p_new_v);
 }
 
 __global__ void k_cg_finish_mixed(Geo g, CGFields f) {
@@ -791,28 +877,74 @@ static void launch_stamped(K kernel, dim3 grid, dim3 block, size_t lds, hipStrea
     else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
 }
 
-template <bool MIXED, bool NT>
-static void launch_step1_inst(const Geo &g, const CGFields &f, int slot, double tol, int max_iter,
-                              const void *p_old, void *p_new, bool decide_only, int sample,
-                              hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    using C = cplx_t<typename Prec<MIXED>::R>;
-    launch_stamped(k_cg_step1<MIXED, NT>, dim3(g.nblocks), dim3(g.block), g.block * sizeof(LdsSpinor<C>),
-                   s, ev0, ev1, g.work, g.chains, f.st, slot, g.nchains, g, f, tol * tol, max_iter, p_old,
-                   p_new, decide_only ? 1 : 0, sample);
+int step_variant_spt(int variant) { return variant == kStepTwoSites ? 2 : 1; }
+
+// Workgroups of `kernel` resident on the whole GPU at once with `block` threads and `lds`
+// bytes of dynamic LDS (cached per kernel, size and device).
+static int resident_workgroups(const void *kernel, int block, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, size_t, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1 << 30;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(kernel, block, lds, dev);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        per_cu < 1 || cus < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+        cus = 256;
+    }
+    return cache[key] = per_cu * cus;
 }
 
-void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
+template <bool MIXED, bool NT>
+static void launch_step1_inst(const Geo &g, const CGFields &f, int variant, int slot, double tol,
+                              int max_iter, const void *p_old, void *p_new, bool decide_only,
+                              int sample, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    using C = cplx_t<typename Prec<MIXED>::R>;
+    const size_t lds = (size_t)g.block * step_variant_spt(variant) * sizeof(LdsSpinor<C>);
+    const int dec = decide_only ? 1 : 0;
+#define ARGS1 s, ev0, ev1, g.work, g.chains, f.st, slot, g.nchains, g, f, tol * tol, max_iter, p_old, \
+              p_new, dec, sample
+    switch (variant) {
+    case kStepTwoSites:
+        launch_stamped(k_cg_step1<MIXED, NT, 2, false>, dim3(g.nblocks), dim3(g.block), lds, ARGS1);
+        break;
+    case kStepResident: {
+        const void *k = (const void *)k_cg_step1<MIXED, NT, 1, true>;
+        const int grid = std::min(g.nblocks, resident_workgroups(k, g.block, lds));
+        launch_stamped(k_cg_step1<MIXED, NT, 1, true>, dim3(grid), dim3(g.block), lds, ARGS1);
+        break;
+    }
+    case kStepWaves8:
+        launch_stamped(k_cg_step1_w8<MIXED, NT>, dim3(g.nblocks), dim3(g.block), lds, ARGS1);
+        break;
+    default:
+        launch_stamped(k_cg_step1<MIXED, NT, 1, false>, dim3(g.nblocks), dim3(g.block), lds, ARGS1);
+    }
+#undef ARGS1
+}
+
+void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int variant, int slot, double tol,
                      int max_iter, const void *p_old, void *p_new, bool decide_only, int sample,
                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (g.nblocks <= 0) return;
     const bool nt = stream_fields(g, mixed);
     if (mixed && nt)
-        launch_step1_inst<true, true>(g, f, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
+        launch_step1_inst<true, true>(g, f, variant, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
     else if (mixed)
-        launch_step1_inst<true, false>(g, f, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
+        launch_step1_inst<true, false>(g, f, variant, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
     else if (nt)
-        launch_step1_inst<false, true>(g, f, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
+        launch_step1_inst<false, true>(g, f, variant, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
     else
-        launch_step1_inst<false, false>(g, f, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
+        launch_step1_inst<false, false>(g, f, variant, slot, tol, max_iter, p_old, p_new, decide_only, sample, s, ev0, ev1);
 }
 
 // One workgroup per sampled slot: the sum over chains of its byte row, which is then zeroed
@@ -838,20 +970,38 @@ void launch_sample_sums(double *samples, int n, int nchains, double *sums, hipSt
 }
 
 template <bool MIXED, bool NT>
-static void launch_step2_inst(const Geo &g, const CGFields &f, int slot, const void *p_new, hipStream_t s,
-                              hipEvent_t ev0, hipEvent_t ev1) {
+static void launch_step2_inst(const Geo &g, const CGFields &f, int variant, int slot, const void *p_new,
+                              hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     using C = cplx_t<typename Prec<MIXED>::R>;
-    launch_stamped(k_cg_step2<MIXED, NT>, dim3(g.nblocks), dim3(g.block), g.block * sizeof(LdsSpinor<C>),
-                   s, ev0, ev1, g.work, g.chains, f.st, slot, g.nchains, g, f, p_new);
+    const size_t lds = (size_t)g.block * step_variant_spt(variant) * sizeof(LdsSpinor<C>);
+#define ARGS2 s, ev0, ev1, g.work, g.chains, f.st, slot, g.nchains, g, f, p_new
+    switch (variant) {
+    case kStepTwoSites:
+        launch_stamped(k_cg_step2<MIXED, NT, 2, false>, dim3(g.nblocks), dim3(g.block), lds, ARGS2);
+        break;
+    case kStepResident: {
+        const void *k = (const void *)k_cg_step2<MIXED, NT, 1, true>;
+        const int grid = std::min(g.nblocks, resident_workgroups(k, g.block, lds));
+        launch_stamped(k_cg_step2<MIXED, NT, 1, true>, dim3(grid), dim3(g.block), lds, ARGS2);
+        break;
+    }
+    case kStepWaves8:
+        launch_stamped(k_cg_step2_w8<MIXED, NT>, dim3(g.nblocks), dim3(g.block), lds, ARGS2);
+        break;
+    default:
+        launch_stamped(k_cg_step2<MIXED, NT, 1, false>, dim3(g.nblocks), dim3(g.block), lds, ARGS2);
+    }
+#undef ARGS2
 }
 
-void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
-                     hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int variant, int slot,
+                     const void *p_new, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (g.nblocks <= 0) return;
     const bool nt = stream_fields(g, mixed);
-    if (mixed && nt) launch_step2_inst<true, true>(g, f, slot, p_new, s, ev0, ev1);
-    else if (mixed) launch_step2_inst<true, false>(g, f, slot, p_new, s, ev0, ev1);
-    else if (nt) launch_step2_inst<false, true>(g, f, slot, p_new, s, ev0, ev1);
-    else launch_step2_inst<false, false>(g, f, slot, p_new, s, ev0, ev1);
+    if (mixed && nt) launch_step2_inst<true, true>(g, f, variant, slot, p_new, s, ev0, ev1);
+    else if (mixed) launch_step2_inst<true, false>(g, f, variant, slot, p_new, s, ev0, ev1);
+    else if (nt) launch_step2_inst<false, true>(g, f, variant, slot, p_new, s, ev0, ev1);
+    else launch_step2_inst<false, false>(g, f, variant, slot, p_new, s, ev0, ev1);
 }
 
 void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s) {

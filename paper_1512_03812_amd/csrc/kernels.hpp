@@ -110,6 +110,13 @@ struct CGFields {
     CGState *st;              // [2][nchains]
     double *samples;          // timing: [kMaxSamples][nchains][2] bytes of sampled slots
 };
+// Variants of the two CG step kernels (compile-time instantiations the autotuner chooses
+// among): one site per thread (plain), two sites per thread (the workgroup tables must then
+// be built with spt = 2), a resident grid that walks the workgroup list, and at most 64
+// VGPRs (8 waves per SIMD).
+enum { kStepPlain = 0, kStepTwoSites = 1, kStepResident = 2, kStepWaves8 = 3, kNumStepVariants = 4 };
+int step_variant_spt(int variant);
+
 // x = 0, r = phi, partial ||phi||^2 -> p2, state[1] = initial.
 void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, hipStream_t s);
 // Slot k, first kernel: decide (converged / beta / reliable update) from the partials of
@@ -118,7 +125,7 @@ void launch_cg_init(const Geo &g, const CGFields &f, bool mixed, double delta, h
 // t64 = D (x64 + x32 + alpha p_old)).  decide_only: state update and the owed x update only.
 // A chain stops unconverged once it has done max_iter iterations or its residual norm is
 // not finite.  ev0/ev1 (optional): stamped with the kernel's own start and end (timing).
-void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int slot, double tol,
+void launch_cg_step1(const Geo &g, const CGFields &f, bool mixed, int variant, int slot, double tol,
                      int max_iter, const void *p_old, void *p_new, bool decide_only, int sample,
                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // sums[2 b + k] = sum over chains of samples[b][chain][k], b < n; the rows are zeroed.
@@ -126,8 +133,9 @@ void launch_sample_sums(double *samples, int n, int nchains, double *sums, hipSt
 // Slot k, second kernel: alpha from the partials of step 1 (kept in the state for the next
 // slot's x update), r -= alpha D^dagger t with partial ||r||^2 (or the FP64 residual
 // recomputation, which also folds x32 and the owed alpha p into x64).
-void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int slot, const void *p_new,
-                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_cg_step2(const Geo &g, const CGFields &f, bool mixed, int variant, int slot,
+                     const void *p_new, hipStream_t s, hipEvent_t ev0 = nullptr,
+                     hipEvent_t ev1 = nullptr);
 // Fused CG iteration: one kernel per iteration for chains whose workgroups own whole
 // lattice rows (see cg_iter_eligible).  Slot k applies the previous iteration's step
 // (r -= alpha s, x += alpha p, with the squared norm of the new residual predicted from the

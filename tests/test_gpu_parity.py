@@ -523,11 +523,74 @@ def test_other_workgroup_sizes_keep_parity(block):
 def test_autotune_picks_a_valid_configuration():
     b = Batch([(16, 16, 2.0, 0.1), (32, 32, 3.0, 0.05), (64, 64, 2.0, 0.1)], seed=3)
     b.lat.hot_start()
-    t = b.lat.autotune("mixed", 1e-10)
+    q0 = b.lat.q.clone()
+    t = b.lat.autotune("mixed", 1e-10, schedule=("adapted_nested_fg", 1.0, 4, 2))
     assert t["block"] in (128, 256, 512, 1024) and t["persistent_limit"] in (0, 1024, 2048)
-    assert t["candidates"] >= 3 and t["solve_ms"] > 0
+    assert t["step_variant"] in ("plain", "two_sites", "resident", "waves8")
+    assert t["check_interval"] in (16, 32, 64) and t["reliable_delta"] in (1e-3, 1e-4, 1e-5)
+    assert t["groups"] in (1, 2, 3) and t["traj_ms"] > 0
+    assert t["candidates"] >= 4 * 2 + 3 + 3 + 3 + 3 and t["solve_ms"] > 0
+    assert torch.equal(b.lat.q, q0) and b.lat.trajectory_counter == 0
     r = b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2, prec="mixed")
     assert all(s == 0 for s in r.status)
+
+
+STEP_VARIANTS = ["plain", "two_sites", "resident", "waves8"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("variant", STEP_VARIANTS)
+def test_every_step_variant_keeps_parity(variant, prec):
+    """Each step-kernel variant the autotuner may pick: solves of a batch of uneven chains
+    (several workgroups per chain, a ragged last strip, whole-chain workgroups) against the
+    oracle, at two workgroup sizes."""
+    shapes = [(8, 8, 2.0, 0.1), (34, 18, 1.5, 0.2), (64, 64, 2.0, 0.1), (30, 46, 2.5, 0.05)]
+    q = [inputs.random_angles(s_[0], s_[1], 300 + i) for i, s_ in enumerate(shapes)]
+    phi = [inputs.random_spinor(s_[0], s_[1], 310 + i) for i, s_ in enumerate(shapes)]
+    refs = [oracle.cg(q[i], phi[i], s_[3], tol=1e-14)[0] for i, s_ in enumerate(shapes)]
+    for block in (128, 512):
+        b = Batch(shapes, persistent=0)
+        b.lat.set_block_size(block)
+        b.lat.set_step_variant(variant)
+        b.set_q(q)
+        x, res = b.lat.cg_solve(b.spinor_to_native(phi), tol=1e-14, prec=prec)
+        assert all(res.converged)
+        got = b.spinor_from_native(x)
+        for i in range(len(shapes)):
+            assert rel(got[i], refs[i]) < 1e-10, (block, i)
+
+
+@pytest.mark.parametrize("variant", ["resident", "waves8"])
+def test_resident_and_register_bound_variants_give_the_plain_bits(variant):
+    """The resident grid and the 64-VGPR bound run the plain variant's arithmetic: trajectories
+    of a batch are bit-identical to it."""
+    shapes = [(16, 16, 2.0, 0.1), (32, 32, 1.5, 0.05), (64, 16, 3.0, 0.2), (8, 8, 1.0, 0.3)]
+    res = []
+    for v in ("plain", variant):
+        b = Batch(shapes, seed=17, persistent=0)
+        b.lat.set_step_variant(v)
+        b.lat.hot_start()
+        b.lat.set_solver(tol=1e-10)
+        out = [list(b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2, prec="mixed").dH) for _ in range(2)]
+        res.append((out, b.lat.q.cpu().numpy().copy()))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("delta", [1e-3, 1e-4, 1e-5])
+def test_every_reliable_update_factor_reaches_the_fp64_residual(delta):
+    shapes = [(32, 32, 2.0, 0.05), (64, 64, 3.0, 0.02)]
+    b = Batch(shapes, persistent=0)
+    q = [inputs.smooth_angles(s_[0], s_[1], 320 + i, 0.5) for i, s_ in enumerate(shapes)]
+    phi = [inputs.random_spinor(s_[0], s_[1], 330 + i) for i, s_ in enumerate(shapes)]
+    b.set_q(q)
+    b.lat.set_solver(tol=1e-10, reliable_delta=delta)
+    x, res = b.lat.cg_solve(b.spinor_to_native(phi), tol=1e-10, prec="mixed")
+    assert all(res.converged) and max(res.rel_resid_true) <= 1.05e-10
+    got = b.spinor_from_native(x)
+    for i, s_ in enumerate(shapes):
+        xr = oracle.cg(q[i], phi[i], s_[3], tol=1e-13)[0]
+        assert rel(got[i], xr) < 2e-5
 
 
 def test_trajectory_is_bitwise_reproducible():
