@@ -133,6 +133,9 @@ struct hmc_ctx {
     int grp_first[kMaxGroups + 1] = {};   // chain ranges [grp_first[g], grp_first[g + 1])
     hmc_ctx *grp[kMaxGroups] = {};
     hipEvent_t grp_fork = nullptr, grp_join[kMaxGroups] = {};
+    // The groups' streams beyond the bound one, created once and kept for the context's life
+    // (re-creating streams re-deals the process's few hardware queues).
+    hipStream_t grp_stream[kMaxGroups] = {};
     bool is_group = false;                // a group of another context (owns no workspace)
     size_t off_groups = 0, groups_bytes = 0;  // the workspace area of the groups' tables
     int part_vmax = -1;                   // vmax the device partition tables were built for
@@ -414,6 +417,17 @@ void copy_links(hmc_ctx *c, const double *src, double *dst) {
                            hipMemcpyDeviceToDevice, c->stream);
 }
 
+// The library's second stream (persistent solver, graph capture), created on first use: an
+// idle stream still takes one of the process's few hardware queues, which concurrent chain
+// groups need.
+int ensure_side(hmc_ctx *c) {
+    if (c->side) return HMC_OK;
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    return HMC_OK;
+}
+
 void ensure_links(hmc_ctx *c, const double *q, bool need32, long version) {
     // version >= 0 identifies q == LQ at that version; -1 forces a rebuild
     const bool have64 = version >= 0 && c->links_version == version;
@@ -615,6 +629,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     }
     // small chains: one persistent workgroup each, on the side stream
     if (c->n_small > 0) {
+        if ((rc = ensure_side(c))) return rc;
         HIP_TRY(c, hipEventRecord(c->fork_ev, c->stream));
         HIP_TRY(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
         if (launch_cg_wg(full, f, mixed, c->at<int>(c->off_small), c->n_small, c->small_vmax, tol,
@@ -1062,7 +1077,6 @@ void drop_groups(hmc_ctx *c) {
         hmc_ctx *k = c->grp[g];
         if (!k) continue;
         if (k->stream) (void)hipStreamSynchronize(k->stream);
-        if (g > 0 && k->stream) (void)hipStreamDestroy(k->stream);
         if (k->side) (void)hipStreamDestroy(k->side);
         if (k->fork_ev) (void)hipEventDestroy(k->fork_ev);
         if (k->join_ev) (void)hipEventDestroy(k->join_ev);
@@ -1161,11 +1175,9 @@ int build_groups(hmc_ctx *c) {
         k->static_scratch = c->static_scratch;
         k->cg_host.resize(k->nchains);
         k->resid_host.resize(k->nchains);
-        if (h == 0) k->stream = c->stream;
-        else HIP_TRY(c, hipStreamCreateWithFlags(&k->stream, hipStreamNonBlocking));
-        HIP_TRY(c, hipStreamCreateWithFlags(&k->side, hipStreamNonBlocking));
-        HIP_TRY(c, hipEventCreateWithFlags(&k->fork_ev, hipEventDisableTiming));
-        HIP_TRY(c, hipEventCreateWithFlags(&k->join_ev, hipEventDisableTiming));
+        if (h > 0 && !c->grp_stream[h])
+            HIP_TRY(c, hipStreamCreateWithFlags(&c->grp_stream[h], hipStreamNonBlocking));
+        k->stream = h == 0 ? c->stream : c->grp_stream[h];
         k->pinned_bytes = align_up(sizeof(CGState) * k->nchains + sizeof(MetroOut) * k->nchains +
                                    sizeof(double) * 16 * k->nchains + 4096);
         HIP_TRY(c, hipHostMalloc(&k->pinned, k->pinned_bytes, hipHostMallocDefault));
@@ -1232,11 +1244,6 @@ int hmc_bind(hmc_ctx *c, void *ws, size_t bytes, void *stream) {
             plain = 0;
         (void)hipGetLastError();
         c->lds_max = (size_t)std::max(std::max(optin, plain), 0);
-    }
-    if (!c->side) {
-        HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
     }
     c->part_vmax = -1;
     HIP_TRY(c, hipMemcpyAsync(c->at<ChainInfo>(c->off_chains), c->chains.data(),
@@ -1935,6 +1942,7 @@ static int graph_capture(hmc_ctx *c, GraphEntry &e) {
                                     "solver's limit (%d sites)", persistent_limit(c, mixed));
     if (prepare_cg_wg(c->small_vmax, mixed))
         return fail(c, HMC_E_INVAL, "the persistent solver's LDS request was refused");
+    if ((rc = ensure_side(c))) return rc;
     MD md;
     init_md(md, c, e.prec);
     c->deferring = true;
@@ -2230,6 +2238,8 @@ int hmc_get_kernel_stats(hmc_ctx *c, int which, hmc_kernel_stat *out) {
 int hmc_destroy(hmc_ctx *c) {
     if (!c) return HMC_E_INVAL;
     drop_groups(c);
+    for (hipStream_t st : c->grp_stream)
+        if (st) (void)hipStreamDestroy(st);
     if (c->grp_fork) (void)hipEventDestroy(c->grp_fork);
     for (hipEvent_t e : c->grp_join)
         if (e) (void)hipEventDestroy(e);
