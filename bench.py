@@ -177,6 +177,20 @@ def dH_error_vs_oracle(lat, tols):
             "by_cg_tolerance": out}
 
 
+def run_graph(lat, steps):
+    """The timed steps again with captured CG iteration chunks (hmc_set_graph): each solve's
+    slots replay a recorded chunk of check-interval slots; the host reads the active count
+    once per chunk.  Same chains, settings and results as the eager steps."""
+    lat.set_graph(True)
+    lat.trajectory(*SCHEDULE, prec="mixed")  # records the chunks
+    r = timed_steps(lat, steps)
+    lat.set_graph(False)
+    n = lat.n_chains * steps
+    return {"value": round(n / r["dt"], 3), "unit": "chain-trajectories/s", "steps": steps,
+            "ms_per_step": round(1e3 * r["dt"] / steps, 3),
+            "how": "captured chunks of CG iteration slots, the rest of each trajectory eager"}
+
+
 def run_tight(lat, steps):
     """The workload at CG tolerance 1e-12, the setting whose Delta H meets the 1e-8 target."""
     lat.set_solver(tol=1e-12, max_iter=20000)
@@ -718,6 +732,8 @@ def main():
                     help="chain groups of the timed steps (0: the autotuner's pick)")
     ap.add_argument("--roofline-steps", type=int, default=3,
                     help="trajectories of the single-group, event-timed roofline pass")
+    ap.add_argument("--graph-steps", type=int, default=4,
+                    help="timed trajectories with captured CG iteration chunks (0: skip)")
     ap.add_argument("--tight-steps", type=int, default=4,
                     help="timed trajectories of the workload at CG tolerance 1e-12 (0: skip)")
     ap.add_argument("--no-oracle-check", action="store_true",
@@ -864,6 +880,8 @@ def main():
     }
     if not args.no_oracle_check:
         out["dH_error_vs_oracle"] = dH_error_vs_oracle(lat, (1e-10, 1e-12))
+    if args.graph_steps > 0:
+        out["captured"] = run_graph(lat, args.graph_steps)
     if args.tight_steps > 0:
         out["cg_tol_1e-12"] = run_tight(lat, args.tight_steps)
     del lat

@@ -195,7 +195,7 @@ int hmc_set_persistent_limit(hmc_ctx *ctx, int vmax);
  * GPU while another's host waits at a convergence check or its solve drains.  Each chain's
  * arithmetic is the same either way: results are bit-identical for any group count.  With
  * more groups than chains each chain is a group.  Other calls (hmc_cg_solve, hmc_integrate,
- * captured trajectories of hmc_set_graph) run the chains as one set.  The kernel statistics
+ * whole-trajectory graphs of hmc_set_graph) run the chains as one set.  The kernel statistics
  * of hmc_get_kernel_stats add up the groups' launches (which overlap in time).  groups: 1..4,
  * default 1. */
 int hmc_set_cg_groups(hmc_ctx *ctx, int groups);
@@ -390,13 +390,18 @@ int hmc_trajectory(hmc_ctx *ctx, int scheme, double tau, int n_outer, int n_inne
 int hmc_trajectories_concurrent(hmc_ctx **ctxs, int n, int scheme, double tau, int n_outer,
                                 int n_inner, int prec, hmc_traj_info **infos, int *rcs);
 
-/* Captured trajectories.  With on != 0, hmc_trajectory records its whole device work (refresh,
- * molecular dynamics with every solve, energies, Metropolis) as one HIP graph on first use of
- * a (scheme, tau, n_outer, n_inner, prec) schedule and replays that graph afterwards: one launch
- * per trajectory and no host round trip until its results are read.  The results are those of
- * the eager path, bit for bit.  Needs every chain within the persistent solver's limit (its
- * solves have no host-driven loop); hmc_trajectory returns HMC_E_INVAL otherwise.  Any setter
- * (solver, quenched, force-gradient mode, persistent limit, workgroup size) and a new binding
+/* Captured trajectories.  With on != 0, hmc_trajectory runs from HIP graphs:
+ *  - when every chain is within the persistent solver's limit, its whole device work (refresh,
+ *    molecular dynamics with every solve, energies, Metropolis) is recorded as one graph on
+ *    first use of a (scheme, tau, n_outer, n_inner, prec) schedule and replayed afterwards: one
+ *    launch per trajectory and no host round trip until its results are read;
+ *  - otherwise the iteration slots of every solve run as a captured chunk of check-interval
+ *    slots (both CG step kernels per slot over the active workgroup list, whose length the
+ *    kernels read from the device, then the compaction), replayed until the host, reading
+ *    the active count once per chunk, finds every chain stopped; the rest of the trajectory
+ *    is launched as usual.  This also holds inside chain groups (hmc_set_cg_groups).
+ * The results are those of the eager path, bit for bit.  Any setter (solver, quenched,
+ * force-gradient mode, persistent limit, workgroup size, step variant) and a new binding
  * discard the captured graphs.  Default off. */
 int hmc_set_graph(hmc_ctx *ctx, int on);
 

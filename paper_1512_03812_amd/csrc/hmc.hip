@@ -81,6 +81,20 @@ struct GraphEntry {
     int solves = 0, force_evals = 0, hvp_solves = 0, logged = 0;
 };
 
+// A captured chunk of CG iteration slots (graph mode with chains above the persistent
+// solver's limit): `slots` slots of both step kernels over the active workgroup list, whose
+// length the kernels read from the device, then the compaction that shortens the list.  The
+// slots only select state and direction buffers by their parity, so one chunk (an even number
+// of slots) serves every chunk of every solve with the same fields and settings.
+struct ChunkGraph {
+    long epoch;
+    const void *phi, *x;
+    int mixed, slots, nblocks, block, variant, max_iter, vmax;
+    double tol, delta;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct hmc_ctx {
     // ------------------------------------------------------------ geometry (host)
     int nchains = 0;
@@ -106,6 +120,7 @@ struct hmc_ctx {
     bool graph_on = false;
     long graph_epoch = 0;          // bumped by every setting a captured graph bakes in
     std::vector<GraphEntry> graphs;
+    std::vector<ChunkGraph> chunks;  // captured CG iteration chunks
     bool deferring = false;        // capturing: solves log their results on the device
     int log_count = 0;             // solves logged by the trajectory being captured
     bool log_overflow = false;
@@ -582,6 +597,76 @@ size_t fused_lds(hmc_ctx *c, int vmax, bool mixed) {
     return lds;
 }
 
+// The captured iteration chunk for these fields and settings (recorded on first use on the
+// library's second stream, so that the bound stream may be the default one).
+int chunk_graph(hmc_ctx *c, const CGFields &f0, const Geo &big, void *const pb[2], bool mixed,
+                int chunk, double tol, int max_iter, ChunkGraph **out) {
+    for (ChunkGraph &e : c->chunks)
+        if (e.epoch == c->graph_epoch && e.phi == f0.phi && e.x == f0.x64 && e.mixed == mixed &&
+            e.slots == chunk && e.nblocks == big.nblocks && e.block == c->block &&
+            e.variant == c->step_variant && e.max_iter == max_iter && e.vmax == c->part_vmax &&
+            e.tol == tol && e.delta == c->delta) {
+            *out = &e;
+            return HMC_OK;
+        }
+    // graphs of older settings go
+    for (ChunkGraph &e : c->chunks)
+        if (e.epoch != c->graph_epoch) {
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+            if (e.graph) (void)hipGraphDestroy(e.graph);
+            e.exec = nullptr;
+        }
+    c->chunks.erase(std::remove_if(c->chunks.begin(), c->chunks.end(),
+                                   [](const ChunkGraph &e) { return e.exec == nullptr; }),
+                    c->chunks.end());
+    int rc = ensure_side(c);
+    if (rc) return rc;
+    int *counts = c->at<int>(c->off_count);
+    CGFields f = f0;
+    f.active = counts;
+    Geo g = big;
+    g.work = c->at<BlockWork>(c->off_active);
+    hipError_t e = hipStreamBeginCapture(c->side, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, HMC_E_HIP, "chunk capture could not start: %s", hipGetErrorString(e));
+    }
+    for (int k = 0; k < chunk; ++k) {
+        launch_cg_step1(g, f, mixed, c->step_variant, k, tol, max_iter, pb[k & 1], pb[(k + 1) & 1], false,
+                        -1, c->side);
+        if (c->has_large) launch_finalize_large(big, f.p1, f.fin1, c->side);
+        launch_cg_step2(g, f, mixed, c->step_variant, k, pb[(k + 1) & 1], c->side);
+        if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->side);
+    }
+    launch_compact(big, c->cg(), max_iter, c->at<BlockWork>(c->off_active), counts, c->side);
+    ChunkGraph cg;
+    e = hipStreamEndCapture(c->side, &cg.graph);
+    if (e != hipSuccess || !cg.graph) {
+        (void)hipGetLastError();
+        return fail(c, HMC_E_HIP, "chunk capture failed: %s", hipGetErrorString(e));
+    }
+    if (hipGraphInstantiate(&cg.exec, cg.graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(cg.graph);
+        (void)hipGetLastError();
+        return fail(c, HMC_E_HIP, "chunk graph instantiation failed");
+    }
+    cg.epoch = c->graph_epoch;
+    cg.phi = f0.phi;
+    cg.x = f0.x64;
+    cg.mixed = mixed;
+    cg.slots = chunk;
+    cg.nblocks = big.nblocks;
+    cg.block = c->block;
+    cg.variant = c->step_variant;
+    cg.max_iter = max_iter;
+    cg.vmax = c->part_vmax;
+    cg.tol = tol;
+    cg.delta = c->delta;
+    c->chunks.push_back(cg);
+    *out = &c->chunks.back();
+    return HMC_OK;
+}
+
 // CG on D^dagger D x = phi with the links already materialised (U64, and the FP32 angles if mixed).
 // Per-chain results land in c->cg_host.  Returns HMC_E_NAN if a chain's residual became
 // non-finite, else HMC_E_NOCONV if a chain hit max_iter (the other chains are solved).
@@ -592,7 +677,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     const bool mixed = prec == HMC_PREC_MIXED;
     const Geo full = c->geo();
     Geo g = full;
-    CGFields f;
+    CGFields f = {};
     f.phi = phi;
     f.x64 = x;
     f.r64 = c->spin(SR);
@@ -698,6 +783,29 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
         }
         // the last slot's residual decides the final state of every large chain
         launch_cg_iter(big, fi, mixed, slot, tol, true, -1, lds_iter, c->stream);
+        if (mixed) launch_cg_finish_mixed(big, f, c->stream);
+    } else if (big.nblocks > 0 && c->graph_on) {
+        // captured chunks of iteration slots; the host reads the active count once per chunk
+        BlockWork *act = c->at<BlockWork>(c->off_active);
+        int *counts = c->at<int>(c->off_count);  // [active workgroups, live chains]
+        const int chunk = std::max(2, (c->check_every + 1) / 2 * 2);
+        ChunkGraph *cg = nullptr;
+        if ((rc = chunk_graph(c, f, big, pb, mixed, chunk, tol, max_iter, &cg))) return rc;
+        // the first chunk iterates the whole list
+        launch_copy(big.work, act, sizeof(BlockWork) * big.nblocks, c->stream);
+        launch_set_u32((uint32_t *)counts, (uint32_t)big.nblocks, c->stream);
+        launch_cg_init(big, f, mixed, c->delta, c->stream);
+        if (c->has_large) launch_finalize_large(big, f.p2, f.fin2, c->stream);
+        const int max_slots = mixed ? max_iter + max_iter / 2 + 64 : max_iter;
+        while (slot < max_slots) {
+            HIP_TRY(c, hipGraphLaunch(cg->exec, c->stream));
+            slot += chunk;
+            int nh[2] = {0, 0};
+            if ((rc = to_host(c, nh, counts, sizeof(nh)))) return rc;
+            if (nh[0] == 0 || (mixed && nh[1] == 0)) break;
+        }
+        launch_cg_step1(big, f, mixed, c->step_variant, slot, tol, max_iter, pb[slot & 1],
+                        pb[(slot + 1) & 1], true, -1, c->stream);
         if (mixed) launch_cg_finish_mixed(big, f, c->stream);
     } else if (big.nblocks > 0) {
         Geo gc = big;
@@ -1071,12 +1179,21 @@ int set_tables(hmc_ctx *c, int block, int variant) {
     return sync(c);
 }
 
+void drop_chunks(hmc_ctx *c) {
+    for (ChunkGraph &e : c->chunks) {
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        if (e.graph) (void)hipGraphDestroy(e.graph);
+    }
+    c->chunks.clear();
+}
+
 // ------------------------------------------------------------------ chain groups
 void drop_groups(hmc_ctx *c) {
     for (int g = 0; g < c->grp_n; ++g) {
         hmc_ctx *k = c->grp[g];
         if (!k) continue;
         if (k->stream) (void)hipStreamSynchronize(k->stream);
+        drop_chunks(k);
         if (k->side) (void)hipStreamDestroy(k->side);
         if (k->fork_ev) (void)hipEventDestroy(k->fork_ev);
         if (k->join_ev) (void)hipEventDestroy(k->join_ev);
@@ -1098,6 +1215,7 @@ int sync_group(hmc_ctx *c, hmc_ctx *k) {
     k->quenched = c->quenched;
     k->fg_mode = c->fg_mode;
     k->fused_on = c->fused_on;
+    k->graph_on = c->graph_on;
     if (k->persist_vmax != c->persist_vmax) {
         k->persist_vmax = c->persist_vmax;
         k->part_vmax = -1;
@@ -2092,7 +2210,14 @@ int hmc_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner,
     CHECK_BOUND(c);
     int rc = check_md_args(c, scheme, tau, n_outer, n_inner, prec);
     if (rc) return rc;
-    if (c->graph_on) return graph_trajectory(c, scheme, tau, n_outer, n_inner, prec, info);
+    if (c->graph_on && !c->is_group) {
+        // the whole trajectory as one graph when every solve is one persistent-solver kernel;
+        // otherwise the solves' iteration slots run as captured chunks (solve)
+        int vmax = 0;
+        for (const ChainInfo &ci : c->chains) vmax = std::max(vmax, ci.V);
+        if (vmax <= persistent_limit(c, prec == HMC_PREC_MIXED))
+            return graph_trajectory(c, scheme, tau, n_outer, n_inner, prec, info);
+    }
     if (c->groups > 1 && c->nchains > 1)
         return grouped_trajectory(c, scheme, tau, n_outer, n_inner, prec, info);
     MD md;
@@ -2238,6 +2363,7 @@ int hmc_get_kernel_stats(hmc_ctx *c, int which, hmc_kernel_stat *out) {
 int hmc_destroy(hmc_ctx *c) {
     if (!c) return HMC_E_INVAL;
     drop_groups(c);
+    drop_chunks(c);
     for (hipStream_t st : c->grp_stream)
         if (st) (void)hipStreamDestroy(st);
     if (c->grp_fork) (void)hipEventDestroy(c->grp_fork);

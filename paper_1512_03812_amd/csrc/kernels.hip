@@ -803,13 +803,15 @@ __device__ __forceinline__ void step2_entry(const BlockWork w, const ChainInfo *
 // The entry loop of the resident variant: a barrier between entries, so that no thread
 // rewrites LDS (the staged spinors, the partial sums) while another still reads the previous
 // entry's.
+// With f.active set (captured iteration chunks), the entry count comes from the device.
 #define STEP_ENTRIES(RES, BODY)                                                          \
+    const int n_entries = f.active ? *f.active : g.nblocks;                              \
     if constexpr (RES) {                                                                 \
-        for (int b = blockIdx.x; b < g.nblocks; b += gridDim.x) {                        \
+        for (int b = blockIdx.x; b < n_entries; b += gridDim.x) {                        \
             if (b != (int)blockIdx.x) __syncthreads();                                   \
             BODY(work[b]);                                                               \
         }                                                                                \
-    } else {                                                                             \
+    } else if ((int)blockIdx.x < n_entries) {                                            \
         BODY(work[blockIdx.x]);                                                          \
     }
 
@@ -830,8 +832,10 @@ __global__ void __attribute__((amdgpu_waves_per_eu(8)))
 k_cg_step1_w8(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
               CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f, double tol2,
               int max_iter, const void *p_old_v, void *p_new_v, int decide_only, int sample) {
-    step1_entry<MIXED, NT, 1>(work[blockIdx.x], chains, states, slot, nchains, g, f, tol2, max_iter,
-                              p_old_v, p_new_v, decide_only, sample);
+#define BODY1(W) step1_entry<MIXED, NT, 1>(W, chains, states, slot, nchains, g, f, tol2, max_iter, \
+                                           p_old_v, p_new_v, decide_only, sample)
+    STEP_ENTRIES(false, BODY1)
+#undef BODY1
 }
 
 template <bool MIXED, bool NT, int SPT, bool RES>
@@ -848,7 +852,9 @@ __global__ void __attribute__((amdgpu_waves_per_eu(8)))
 k_cg_step2_w8(const BlockWork *__restrict__ work, const ChainInfo *__restrict__ chains,
               CGState *__restrict__ states, int slot, int nchains, Geo g, CGFields f,
               const void *p_new_v) {
-    step2_entry<MIXED, NT, 1>(work[blockIdx.x], chains, states, slot, nchains, g, f, p_new_v);
+#define BODY2(W) step2_entry<MIXED, NT, 1>(W, chains, states, slot, nchains, g, f, p_new_v)
+    STEP_ENTRIES(false, BODY2)
+#undef BODY2
 }
 
 __global__ void k_cg_finish_mixed(Geo g, CGFields f) {

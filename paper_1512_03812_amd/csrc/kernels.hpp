@@ -109,6 +109,8 @@ struct CGFields {
     double *fin1, *fin2;      // per-chain totals of p1, p2 for chains above kMaxChainBlocks
     CGState *st;              // [2][nchains]
     double *samples;          // timing: [kMaxSamples][nchains][2] bytes of sampled slots
+    const int *active;        // step kernels: if set, the number of work entries is *active (the
+                              // grid may be larger; the workgroups beyond it exit at once)
 };
 // Variants of the two CG step kernels (compile-time instantiations the autotuner chooses
 // among): one site per thread (plain), two sites per thread (the workgroup tables must then

@@ -820,16 +820,36 @@ def test_graph_trajectories_match_eager_bitwise(scheme, n_outer, n_inner, prec, 
     assert runs[0][1] == runs[1][1]
 
 
-def test_graph_mode_needs_every_chain_in_the_persistent_solver():
-    m = hmc()
-    b = Batch([(8, 8), (64, 64)], seed=3)
-    b.lat.hot_start()
-    b.lat.set_graph(True)
-    with pytest.raises(m.HMCError):
-        b.lat.trajectory("adapted_nested_fg", 1.0, 2, 2)
-    b.lat.set_graph(False)
-    r = b.lat.trajectory("adapted_nested_fg", 1.0, 2, 2)
-    assert all(s == 0 for s in r.status)
+@pytest.mark.parametrize("persistent,groups,variant", [(0, 1, "plain"), (2048, 1, "plain"), (0, 2, "plain"),
+                                                    (0, 1, "resident"), (1024, 3, "two_sites")])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_chunks_of_large_chains_match_eager_bitwise(prec, persistent, groups, variant):
+    """Chains above the persistent solver's limit (64 x 64, 128 x 32, 70 x 62): in graph mode
+    their solves run as captured chunks of iteration slots.  Trajectories, with eager work between
+    them and a recapture after a setting changes, give the eager path's bits; also with the
+    persistent solver beside the chunks, with chain groups and with other step variants."""
+    shapes = [(8, 8, 2.0, 0.1), (64, 64, 1.5, 0.05), (16, 16, 3.0, 0.2), (128, 32, 2.0, 0.1),
+              (70, 62, 2.5, 0.08)]
+    runs = []
+    for graph in (False, True):
+        b = Batch(shapes, seed=21, persistent=persistent)
+        b.lat.set_cg_groups(groups)
+        b.lat.set_step_variant(variant)
+        b.lat.hot_start()
+        b.lat.set_solver(tol=1e-11 if prec == "fp64" else 1e-10)
+        b.lat.set_check_interval(16)
+        b.lat.set_graph(graph)
+        res = []
+        for t in range(3):
+            if t == 2:
+                b.lat.set_check_interval(8)   # discards the captured chunks: recaptured at 8 slots
+            r = b.lat.trajectory("adapted_nested_fg", 1.0, 3, 2, prec=prec)
+            res.append((list(r.dH), list(r.accepted), list(r.n_cg_iters), list(r.status), r.n_solves))
+            b.lat.actions()
+            torch.cuda.synchronize()
+        runs.append((b.lat.q.cpu().numpy().copy(), res))
+    assert runs[0][1] == runs[1][1]
+    assert np.array_equal(runs[0][0], runs[1][0])
 
 
 # ------------------------------------------------------------------ mixed precision
