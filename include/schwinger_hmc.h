@@ -84,7 +84,8 @@ enum {
     HMC_FIELD_PHI = 2,  /* pseudofermion phi of the current trajectory, spinor field */
     HMC_FIELD_CHI = 3,  /* chi = D xi after the last fermion force, spinor field (Eq. (18)) */
     HMC_FIELD_XI = 4,   /* xi = (D^dagger D)^{-1} phi after the last fermion force, spinor field */
-    HMC_FIELD_F = 5,    /* last force written by a trajectory, real link field */
+    HMC_FIELD_F = 5,    /* last force field a trajectory stored, real link field (kicks that
+                           involve the gauge force apply it directly and store none) */
     HMC_FIELD_ZETA = 6  /* Gaussian zeta of the last refresh (phi = D^dagger zeta), spinor field */
 };
 

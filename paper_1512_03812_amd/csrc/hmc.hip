@@ -961,11 +961,24 @@ void stage_A(MD &md, double eps) {
     c->q_version++;
 }
 
+// e^{eps B}: p -= eps F.  Kicks with the gauge force (alone, or added to the fermion force)
+// apply it in the kernel that computes it; the fermion-only kick goes through the F field.
 int stage_B(MD &md, int which, double eps) {
     hmc_ctx *c = md.c;
+    const Geo g = c->geo();
+    if (which == 0 || (which == 2 && c->quenched)) {
+        launch_gauge_kick(g, c->link(LQ), nullptr, -eps, c->link(LP), c->stream);
+        return HMC_OK;
+    }
+    if (which == 2) {
+        int rc = fermion_force_at(md, c->link(LQ), c->q_version, c->link(LFT));
+        if (rc) return rc;
+        launch_gauge_kick(g, c->link(LQ), c->link(LFT), -eps, c->link(LP), c->stream);
+        return HMC_OK;
+    }
     int rc = force_at(md, which, c->link(LQ), c->q_version, c->link(LF));
     if (rc) return rc;
-    launch_axpy_links(c->geo(), c->link(LP), -eps, c->link(LF), c->link(LP), c->stream);
+    launch_axpy_links(g, c->link(LP), -eps, c->link(LF), c->link(LP), c->stream);
     return HMC_OK;
 }
 

@@ -422,25 +422,55 @@ void launch_make_links(const Geo &g, const double *q, double2 *U64, float *A32, 
 }
 
 // ================================================================ Dirac operator
-template <bool DAG>
+// Each thread stages its own sites' input spinor in LDS; the stencil reads the neighbours
+// from there when the workgroup owns them (the other parity plane at nearby half-site
+// indices) and from global memory otherwise.  Outputs are stored write-through (no other
+// thread of the kernel reads them), non-temporal as well when the fields are far larger than
+// the Infinity Cache.
+template <bool DAG, bool NT>
 __global__ void k_dslash64(Geo g, const double2 *__restrict__ U, const double2 *__restrict__ in,
                            double2 *__restrict__ out) {
-    SITES_BEGIN
-    const Site s = decode_site(ci, local);
-    const Nbr nb = neighbours(ci, s);
-    auto load = [&](int f, double2 &b0, double2 &b1) { b0 = in[f]; b1 = in[(size_t)Vtot + f]; };
-    double2 o0, o1;
-    dslash_site<double, DAG>(nb, s.flat, Vtot, U, in[s.flat], in[(size_t)Vtot + s.flat],
-                             2.0 + ci.m0, load, o0, o1);
-    out[s.flat] = o0;
-    out[(size_t)Vtot + s.flat] = o1;
-    SITES_END
+    LdsSpinor<double2> *lds = (LdsSpinor<double2> *)smem_d;
+    const BlockWork w = g.work[blockIdx.x];
+    const ChainInfo ci = g.chains[w.chain];
+    const int Vtot = g.Vtot;
+    const int half = (int)blockDim.x >> 1;
+    const int span = half * w.spt;
+    const int par = (int)threadIdx.x >= half ? 1 : 0;
+    const int i0 = w.start + (int)threadIdx.x - par * half;
+    for (int j = 0; j < w.spt; ++j) {
+        const int i = i0 + j * half;
+        if (i >= ci.Vh) break;
+        const int fl = ci.off + par * ci.Vh + i;
+        lds[par * span + i - w.start].a = in[fl];
+        lds[par * span + i - w.start].b = in[(size_t)Vtot + fl];
+    }
+    __syncthreads();
+    auto load = [&](int f, double2 &b0, double2 &b1) {
+        const int k = lds_slot(ci, w, span, f);
+        if (k >= 0) { b0 = lds[k].a; b1 = lds[k].b; }
+        else { b0 = in[f]; b1 = in[(size_t)Vtot + f]; }
+    };
+    for (int j = 0; j < w.spt; ++j) {
+        const int i = i0 + j * half;
+        if (i >= ci.Vh) break;
+        const Site s = decode_site(ci, par * ci.Vh + i);
+        const Nbr nb = neighbours(ci, s);
+        const LdsSpinor<double2> own = lds[par * span + i - w.start];
+        double2 o0, o1;
+        dslash_site<double, DAG>(nb, s.flat, Vtot, U, own.a, own.b, 2.0 + ci.m0, load, o0, o1);
+        sp_store_wt<NT>(out, Vtot, s.flat, o0, o1);
+    }
 }
 
 void launch_dslash64(const Geo &g, const double2 *U, const double2 *in, double2 *out, bool dagger,
                      hipStream_t s) {
-    if (dagger) hipLaunchKernelGGL(k_dslash64<true>, dim3(g.nblocks), dim3(g.block), 0, s, g, U, in, out);
-    else hipLaunchKernelGGL(k_dslash64<false>, dim3(g.nblocks), dim3(g.block), 0, s, g, U, in, out);
+    const size_t lds = (size_t)2 * g.block * sizeof(LdsSpinor<double2>);  // up to 2 sites per thread
+    const bool nt = (double)g.Vtot * 96.0 > 512.0 * 1024 * 1024;
+    if (dagger && nt) hipLaunchKernelGGL((k_dslash64<true, true>), dim3(g.nblocks), dim3(g.block), lds, s, g, U, in, out);
+    else if (dagger) hipLaunchKernelGGL((k_dslash64<true, false>), dim3(g.nblocks), dim3(g.block), lds, s, g, U, in, out);
+    else if (nt) hipLaunchKernelGGL((k_dslash64<false, true>), dim3(g.nblocks), dim3(g.block), lds, s, g, U, in, out);
+    else hipLaunchKernelGGL((k_dslash64<false, false>), dim3(g.nblocks), dim3(g.block), lds, s, g, U, in, out);
 }
 
 // ================================================================ CG on D^dagger D
@@ -1801,27 +1831,60 @@ __device__ __forceinline__ double plaq_angle(const ChainInfo &ci, const double *
 
 // dS_G/dq: F_x(n) = beta [sin theta(n) - sin theta(n - t)], F_t(n) = beta [sin theta(n - x)
 // - sin theta(n)] -- Eq. (16) with P read as P_{mu nu}(n), whose angle is -theta for mu = t.
-__global__ void k_gauge_force(Geo g, const double *__restrict__ q, const double *add,
+// Each thread takes sin theta of its own sites' plaquettes and stages them in LDS; the
+// neighbours' plaquettes (n - x, n - t) come from there when the workgroup owns them and are
+// recomputed (the same operations) otherwise.  KICK: p += c (F + add) instead of F = F + add.
+template <bool KICK>
+__global__ void k_gauge_force(Geo g, const double *__restrict__ q, const double *add, double c,
                               double *F) {
-    SITES_BEGIN
-    const Site s = decode_site(ci, local);
-    const double th = plaq_angle(ci, q, Vtot, s.x, s.t);
-    const double th_mt = plaq_angle(ci, q, Vtot, s.x, wrap_dec(s.t, ci.Lt));
-    const double th_mx = plaq_angle(ci, q, Vtot, wrap_dec(s.x, ci.Lx), s.t);
-    const double sn = sin(th);
-    double fx = ci.beta * (sn - sin(th_mt));
-    double ft = ci.beta * (sin(th_mx) - sn);
-    if (add) {
-        fx += add[s.flat];
-        ft += add[(size_t)Vtot + s.flat];
+    double *sin_lds = smem_d;
+    const BlockWork w = g.work[blockIdx.x];
+    const ChainInfo ci = g.chains[w.chain];
+    const int Vtot = g.Vtot;
+    const int half = (int)blockDim.x >> 1;
+    const int span = half * w.spt;
+    const int par = (int)threadIdx.x >= half ? 1 : 0;
+    for (int j = 0; j < w.spt; ++j) {
+        const int i = w.start + (int)threadIdx.x - par * half + j * half;
+        if (i >= ci.Vh) break;
+        const Site s = decode_site(ci, par * ci.Vh + i);
+        sin_lds[par * span + i - w.start] = sin(plaq_angle(ci, q, Vtot, s.x, s.t));
     }
-    F[s.flat] = fx;
-    F[(size_t)Vtot + s.flat] = ft;
-    SITES_END
+    __syncthreads();
+    auto sin_at = [&](int x, int t) {
+        const int k = lds_slot(ci, w, span, flat_of(ci, x, t));
+        return k >= 0 ? sin_lds[k] : sin(plaq_angle(ci, q, Vtot, x, t));
+    };
+    for (int j = 0; j < w.spt; ++j) {
+        const int i = w.start + (int)threadIdx.x - par * half + j * half;
+        if (i >= ci.Vh) break;
+        const Site s = decode_site(ci, par * ci.Vh + i);
+        const double sn = sin_lds[par * span + i - w.start];
+        double fx = ci.beta * (sn - sin_at(s.x, wrap_dec(s.t, ci.Lt)));
+        double ft = ci.beta * (sin_at(wrap_dec(s.x, ci.Lx), s.t) - sn);
+        if (add) {
+            fx += add[s.flat];
+            ft += add[(size_t)Vtot + s.flat];
+        }
+        if (KICK) {
+            F[s.flat] = F[s.flat] + c * fx;
+            F[(size_t)Vtot + s.flat] = F[(size_t)Vtot + s.flat] + c * ft;
+        } else {
+            F[s.flat] = fx;
+            F[(size_t)Vtot + s.flat] = ft;
+        }
+    }
 }
 
 void launch_gauge_force(const Geo &g, const double *q, const double *add, double *F, hipStream_t s) {
-    hipLaunchKernelGGL(k_gauge_force, dim3(g.nblocks), dim3(g.block), 0, s, g, q, add, F);
+    hipLaunchKernelGGL(k_gauge_force<false>, dim3(g.nblocks), dim3(g.block), (size_t)2 * g.block * sizeof(double),
+                       s, g, q, add, 0.0, F);
+}
+
+void launch_gauge_kick(const Geo &g, const double *q, const double *add, double c, double *p,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_gauge_force<true>, dim3(g.nblocks), dim3(g.block), (size_t)2 * g.block * sizeof(double),
+                       s, g, q, add, c, p);
 }
 
 // ================================================================ Hessian-vector products

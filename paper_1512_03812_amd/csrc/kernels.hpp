@@ -199,6 +199,9 @@ void launch_fermion_force(const Geo &g, const double2 *U, const double2 *chi, co
                           double *f, hipStream_t s);
 // F = dS_G/dq (Eq. (16)), plus add[] if add != null (add may alias F).
 void launch_gauge_force(const Geo &g, const double *q, const double *add, double *F, hipStream_t s);
+// The kick with the gauge force in one kernel: p += c (dS_G/dq + add) (add may be null).
+void launch_gauge_kick(const Geo &g, const double *q, const double *add, double c, double *p,
+                       hipStream_t s);
 
 // ---------------------------------------------------------------- Hessian-vector products
 // W = i v U per link (the links of dD[v], the derivative of D along v).
