@@ -110,7 +110,8 @@ def run_batched(args):
         lat.trajectory(*SCHEDULE, prec="mixed")
     tune = None
     if not args.no_tune:
-        tune = lat.autotune("mixed", 1e-10, schedule=SCHEDULE)
+        # with a fixed group count (--groups) the tuner leaves the groups alone
+        tune = lat.autotune("mixed", 1e-10, schedule=None if args.groups else SCHEDULE)
     used = {"groups": args.groups or (tune["groups"] if tune else 1),
             "persistent_limit": (args.persistent_limit if args.persistent_limit >= 0 else
                                  (tune["persistent_limit"] if tune else 2048))}
@@ -729,7 +730,8 @@ def main():
     ap.add_argument("--therm", type=int, default=30,
                     help="untimed trajectories from the hot start before tuning and warm-up")
     ap.add_argument("--groups", type=int, default=0,
-                    help="chain groups of the timed steps (0: the autotuner's pick)")
+                    help="chain groups of the timed steps (0: the autotuner's pick; otherwise the "
+                         "tuner does not search them)")
     ap.add_argument("--roofline-steps", type=int, default=3,
                     help="trajectories of the single-group, event-timed roofline pass")
     ap.add_argument("--graph-steps", type=int, default=4,

@@ -278,7 +278,7 @@ size_t layout_tables(hmc_ctx *c, size_t o, size_t C, size_t N) {
     c->off_log = take(sizeof(int) * 2 * kMaxLoggedSolves * C);
     c->off_sample_sums = take(sizeof(double) * 2 * kMaxSamples);
     c->off_sums = take(sizeof(double) * 16 * C);
-    c->off_fin = take(sizeof(double) * 2 * C);
+    c->off_fin = take(sizeof(double) * 2 * kFinSlices * C);
     c->off_metro = take(sizeof(MetroOut) * C);
     c->off_status = take(sizeof(int) * C);
     c->off_count = take(sizeof(int) * 4);
@@ -690,7 +690,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     f.p1 = c->partials();
     f.p2 = c->partials() + full.nlog;
     f.fin1 = c->at<double>(c->off_fin);
-    f.fin2 = f.fin1 + c->nchains;
+    f.fin2 = f.fin1 + (size_t)kFinSlices * c->nchains;
     f.st = c->cg();
     f.samples = c->at<double>(c->off_samples);
     void *pb[2];

@@ -125,28 +125,43 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *partials
 // The chain's total of one partial row, identical in every wavefront of the chain: each
 // wavefront re-adds the partials of chains of at most kMaxChainBlocks workgroups itself (lane
 // l takes partials l, l + 64, ... in order, then the fixed DPP tree of wave_sum), with no LDS
-// and no barrier, so the site loads issued before it stay in flight; larger chains read fin
-// (written by k_finalize_large after the producer).
+// and no barrier, so the site loads issued before it stay in flight; larger chains re-add the
+// kFinSlices slice sums that k_finalize_large wrote after the producer.
 __device__ __forceinline__ double chain_total(const double *__restrict__ row,
                                               const double *__restrict__ fin, const ChainInfo &ci,
                                               int chain) {
-    if (ci.nblocks > kMaxChainBlocks) return fin[chain];
     double a = 0.0;
+    if (ci.nblocks > kMaxChainBlocks) {
+        const int l = (int)(threadIdx.x & 63);
+        if (l < kFinSlices) a = fin[(size_t)chain * kFinSlices + l];
+        return wave_sum(a);
+    }
     for (int j = (int)(threadIdx.x & 63); j < ci.nblocks; j += 64) a += row[ci.block0 + j];
     return wave_sum(a);
 }
 
+// Slice sums of the partials of chains above kMaxChainBlocks workgroups: workgroup (c, y)
+// adds the partials of slice y of chain c (each thread four consecutive ones per pass into
+// independent accumulators), in a fixed order, into fin[c][y].
 __global__ void k_finalize_large(Geo g, const double *__restrict__ row, double *fin) {
     const ChainInfo ci = g.chains[blockIdx.x];
     if (ci.nblocks <= kMaxChainBlocks) return;
-    double v[1] = {0.0};
-    for (int j = threadIdx.x; j < ci.nblocks; j += blockDim.x) v[0] += row[ci.block0 + j];
+    const int len = (ci.nblocks + kFinSlices - 1) / kFinSlices;
+    const int lo = (int)blockIdx.y * len, hi = min(ci.nblocks, lo + len);
+    const double *__restrict__ r = row + ci.block0;
+    double acc[4] = {0, 0, 0, 0};
+    for (int base = lo + 4 * (int)threadIdx.x; base < hi; base += 4 * (int)blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (base + k < hi) acc[k] += r[base + k];
+    }
+    double v[1] = {(acc[0] + acc[1]) + (acc[2] + acc[3])};
     block_sum_all<1>(v);
-    if (threadIdx.x == 0) fin[blockIdx.x] = v[0];
+    if (threadIdx.x == 0) fin[(size_t)blockIdx.x * kFinSlices + blockIdx.y] = v[0];
 }
 
 void launch_finalize_large(const Geo &g, const double *row, double *fin, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_large, dim3(g.nchains), dim3(1024), 0, s, g, row, fin);
+    hipLaunchKernelGGL(k_finalize_large, dim3(g.nchains, kFinSlices), dim3(256), 0, s, g, row, fin);
 }
 
 template <int NV> __global__ void k_finalize(Geo g, const double *__restrict__ partials, double *out) {

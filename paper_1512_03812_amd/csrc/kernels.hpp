@@ -82,6 +82,9 @@ constexpr int kMaxReduce = 8;
 // A consumer workgroup re-adds its chain's partials itself when the chain has at most this
 // many workgroups; larger chains get their totals from a finalize kernel instead.
 constexpr int kMaxChainBlocks = 2048;
+// Slices of such a chain's partials that k_finalize_large sums separately (one workgroup
+// each); the consumers re-add the slice sums.
+constexpr int kFinSlices = 64;
 
 // ---------------------------------------------------------------- layout
 // to_native: nat <- lex, else lex <- nat
@@ -106,7 +109,8 @@ struct CGFields {
     const double2 *U64;
     const float *A32;  // FP32 link angles [2][Vtot] (boundary sign folded in as +pi)
     double *p1, *p2;          // partial rows: ||D p||^2 (step 1) and ||r||^2 (step 2)
-    double *fin1, *fin2;      // per-chain totals of p1, p2 for chains above kMaxChainBlocks
+    double *fin1, *fin2;      // per-chain slice sums [nchains][kFinSlices] of p1, p2 for chains
+                              // above kMaxChainBlocks
     CGState *st;              // [2][nchains]
     double *samples;          // timing: [kMaxSamples][nchains][2] bytes of sampled slots
     const int *active;        // step kernels: if set, the number of work entries is *active (the
@@ -169,7 +173,8 @@ void launch_cg_iter(const Geo &g, const CGIterFields &f, bool mixed, int slot, d
 // Lets both instantiations use lds_bytes of dynamic LDS; -1 if the device refuses.
 int grant_cg_iter_lds(size_t lds_bytes);
 
-// fin[c] = sum of row's partials of chain c, for the chains above kMaxChainBlocks.
+// fin[c][y] = sum of slice y of row's partials of chain c, for the chains above
+// kMaxChainBlocks.
 void launch_finalize_large(const Geo &g, const double *row, double *fin, hipStream_t s);
 // x64 += x32 (end of a mixed solve).
 void launch_cg_finish_mixed(const Geo &g, const CGFields &f, hipStream_t s);
