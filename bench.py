@@ -828,6 +828,7 @@ def main():
     rec = hbm_traffic(kname)
     traffic = None
     if rec and rec.get("kernel_trace_mean_us"):
+        # counter bytes per dispatch over the kernel-trace mean duration of the same dispatches
         traffic = round(rec["hbm_bytes_per_launch"] / (rec["kernel_trace_mean_us"] * 1e-6) / 1e9, 1)
     cg_gbs = (s1["timed_bytes"] + s2["timed_bytes"]) / t12 / 1e9 if t12 > 0 else 0.0
     out = {
@@ -869,6 +870,7 @@ def main():
             "traffic_record": rec,
             "avg_launch_us": round(1e3 * sd["timed_ms"] / max(1, sd["timed_launches"]), 3),
             "avg_bytes_per_launch": round(sd["timed_bytes"] / max(1, sd["timed_launches"])),
+            "avg_bytes_per_launch_all_slots": round(sd["all_bytes"] / max(1, sd["launches"])),
             "timed_launches": sd["timed_launches"], "launches": sd["launches"],
             "sample_every": sd["sample_every"],
             "share_of_cg_step_time": round(sd["timed_ms"] / max(1e-30, s1["timed_ms"] + s2["timed_ms"]), 3),
@@ -877,7 +879,8 @@ def main():
         "cg_step1_step2_gbs": round(cg_gbs, 1),
         "cg_steps": {KERNELS[k][0]: {"avg_launch_us": round(1e3 * st["timed_ms"] / max(1, st["timed_launches"]), 3),
                                      "achieved_gbs": round(st["timed_bytes"] / max(1e-30, st["timed_ms"] * 1e-3) / 1e9, 1),
-                                     "timed_launches": st["timed_launches"]}
+                                     "timed_launches": st["timed_launches"],
+                                     "avg_bytes_per_launch_all_slots": round(st["all_bytes"] / max(1, st["launches"]))}
                      for k, st in ((0, s1), (1, s2))},
     }
     if not args.no_oracle_check:

@@ -432,6 +432,8 @@ typedef struct {
     int sample_every;         /* sampling period in slots */
     int fused;                /* 1: the solves ran the fused iteration, whose kernel is
                                  index 0 (index 1 then holds nothing) */
+    double all_bytes;         /* algorithmic bytes of this kernel over every slot launched while
+                                 timing was on (two-kernel iteration), timed or not */
 } hmc_kernel_stat;
 
 int hmc_set_timing(hmc_ctx *ctx, int on);

@@ -57,7 +57,8 @@ STEP_VARIANTS = {"plain": 0, "two_sites": 1, "resident": 2, "waves8": 3}
 class KernelStat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_longlong), ("timed_launches", ctypes.c_longlong),
                 ("timed_ms", ctypes.c_double), ("timed_bytes", ctypes.c_double),
-                ("sample_every", ctypes.c_int), ("fused", ctypes.c_int)]
+                ("sample_every", ctypes.c_int), ("fused", ctypes.c_int),
+                ("all_bytes", ctypes.c_double)]
 
 
 # name -> (restype, argtypes)

@@ -53,9 +53,11 @@ struct KernelTimer {
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     std::vector<TimedSlot> pending;
-    double *sums_host = nullptr;  // pinned: [kMaxSamples][2] byte sums of the pending samples
+    double *sums_host = nullptr;  // pinned: [kMaxSamples + 1][2] byte sums of the pending samples
+                                  // and (last row) of every slot since the last flush
     double ms[2] = {0.0, 0.0};
     double bytes[2] = {0.0, 0.0};
+    double all_bytes[2] = {0.0, 0.0};  // algorithmic bytes of every slot launched while on
     long long timed[2] = {0, 0};
     long long launches = 0;  // all slots launched while timing was on
     int since_sync = 0;      // slots launched since the host last waited for the stream
@@ -273,10 +275,10 @@ size_t layout_tables(hmc_ctx *c, size_t o, size_t C, size_t N) {
     c->off_small = take(sizeof(int) * C);
     c->off_cg = take(sizeof(CGState) * 2 * C);
     c->off_partials = take(sizeof(double) * kMaxReduce * N);
-    c->off_samples = take(sizeof(double) * 2 * kMaxSamples * C);
+    c->off_samples = take(sizeof(double) * 2 * (kMaxSamples + 1) * C);
     c->off_trajc = take(sizeof(uint32_t));
     c->off_log = take(sizeof(int) * 2 * kMaxLoggedSolves * C);
-    c->off_sample_sums = take(sizeof(double) * 2 * kMaxSamples);
+    c->off_sample_sums = take(sizeof(double) * 2 * (kMaxSamples + 1));
     c->off_sums = take(sizeof(double) * 16 * C);
     c->off_fin = take(sizeof(double) * 2 * kFinSlices * C);
     c->off_metro = take(sizeof(MetroOut) * C);
@@ -488,17 +490,23 @@ hipEvent_t timer_event(hmc_ctx *c) {
 // wait); the caller synchronises before timer_flush.
 void timer_reduce(hmc_ctx *c) {
     KernelTimer &T = c->timer;
-    if (T.pending.empty()) return;
     const int n = (int)T.pending.size();
     double *sums = c->at<double>(c->off_sample_sums);
-    launch_sample_sums(c->at<double>(c->off_samples), n, c->nchains, sums, c->stream);
+    double *rows = c->at<double>(c->off_samples);
+    if (n > 0) launch_sample_sums(rows, n, c->nchains, sums, c->stream);
+    launch_sample_sums(rows + (size_t)2 * kMaxSamples * c->nchains, 1, c->nchains, sums + 2 * kMaxSamples,
+                       c->stream);
     (void)hipMemcpyAsync(T.sums_host, sums, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, c->stream);
+    (void)hipMemcpyAsync(T.sums_host + 2 * kMaxSamples, sums + 2 * kMaxSamples, sizeof(double) * 2,
+                         hipMemcpyDeviceToHost, c->stream);
 }
 
 // Called only after the stream was synchronised (following timer_reduce): every recorded
 // event and byte sum is complete.
 void timer_flush(hmc_ctx *c) {
     KernelTimer &T = c->timer;
+    T.all_bytes[0] += T.sums_host[2 * kMaxSamples];
+    T.all_bytes[1] += T.sums_host[2 * kMaxSamples + 1];
     for (const TimedSlot &ts : T.pending) {
         float a = 0.f, b = 0.f;
         if (hipEventElapsedTime(&a, ts.ev[0], ts.ev[1]) != hipSuccess) continue;
@@ -693,6 +701,8 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     f.fin2 = f.fin1 + (size_t)kFinSlices * c->nchains;
     f.st = c->cg();
     f.samples = c->at<double>(c->off_samples);
+    if (c->timer.on && c->timer.sums_host)
+        f.all_bytes = f.samples + (size_t)2 * kMaxSamples * c->nchains;
     void *pb[2];
     if (mixed) { pb[0] = c->spin32(FPA); pb[1] = c->spin32(FPB); }
     else { pb[0] = c->spin(SPA); pb[1] = c->spin(SPB); }
@@ -2334,16 +2344,18 @@ int hmc_set_timing(hmc_ctx *c, int on) {
     }
     KernelTimer &T = c->timer;
     if (on && !T.sums_host)
-        HIP_TRY(c, hipHostMalloc((void **)&T.sums_host, sizeof(double) * 2 * kMaxSamples,
+        HIP_TRY(c, hipHostMalloc((void **)&T.sums_host, sizeof(double) * 2 * (kMaxSamples + 1),
                                  hipHostMallocDefault));
     if (c->ws)  // rows of samples abandoned by an earlier error start from zero again
         HIP_TRY(c, hipMemsetAsync(c->at<double>(c->off_samples), 0,
-                                  sizeof(double) * 2 * kMaxSamples * c->nchains, c->stream));
+                                  sizeof(double) * 2 * (kMaxSamples + 1) * c->nchains, c->stream));
     T.on = on != 0;
+    c->graph_epoch++;  // captured chunks bake in whether slots record their bytes
     T.pending.clear();
     T.pool_used = 0;
     T.ms[0] = T.ms[1] = 0.0;
     T.bytes[0] = T.bytes[1] = 0.0;
+    T.all_bytes[0] = T.all_bytes[1] = 0.0;
     T.timed[0] = T.timed[1] = 0;
     T.launches = 0;
     for (int g = 0; g < c->grp_n; ++g) {
@@ -2362,12 +2374,14 @@ int hmc_get_kernel_stats(hmc_ctx *c, int which, hmc_kernel_stat *out) {
     out->timed_bytes = T.bytes[which];
     out->sample_every = T.sample_every;
     out->fused = T.fused ? 1 : 0;
+    out->all_bytes = T.all_bytes[which];
     for (int g = 0; g < c->grp_n; ++g) {  // the chain groups' launches add up
         const KernelTimer &K = c->grp[g]->timer;
         out->launches += K.launches;
         out->timed_launches += K.timed[which];
         out->timed_ms += K.ms[which];
         out->timed_bytes += K.bytes[which];
+        out->all_bytes += K.all_bytes[which];
         out->fused |= K.fused ? 1 : 0;
     }
     return HMC_OK;

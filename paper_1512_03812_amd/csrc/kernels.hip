@@ -639,11 +639,20 @@ __device__ __forceinline__ void step1_entry(const BlockWork w, const ChainInfo *
         out->converged = n_conv; out->mode = update ? kModeUpdate : kModeNormal;
         out->n_updates = n_nupd;
         out->alpha = update ? pend : 0.0;
-        if (sample >= 0 && !n_conv && !decide_only) {
-            // timing: the algorithmic bytes of both steps of this slot for this chain
-            double* row = f.samples + ((size_t)sample * g.nchains + w.chain) * 2;
-            row[0] = ci.V * (!MIXED ? kBytesFp64Step1 : update ? kBytesUpdateStep1 : kBytesFp32Step1);
-            row[1] = ci.V * (!MIXED ? kBytesFp64Step2 : update ? kBytesUpdateStep2 : kBytesFp32Step2);
+        if (!n_conv && !decide_only) {
+            // timing: the algorithmic bytes of both steps of this slot for this chain, in the
+            // sampled slot's row and in the running sums over every slot
+            const double b1 = ci.V * (!MIXED ? kBytesFp64Step1 : update ? kBytesUpdateStep1 : kBytesFp32Step1);
+            const double b2 = ci.V * (!MIXED ? kBytesFp64Step2 : update ? kBytesUpdateStep2 : kBytesFp32Step2);
+            if (sample >= 0) {
+                double *row = f.samples + ((size_t)sample * g.nchains + w.chain) * 2;
+                row[0] = b1;
+                row[1] = b2;
+            }
+            if (f.all_bytes) {
+                f.all_bytes[2 * w.chain] += b1;
+                f.all_bytes[2 * w.chain + 1] += b2;
+            }
         }
     }
     const R a_pend = (R)pend;

@@ -113,6 +113,7 @@ struct CGFields {
                               // above kMaxChainBlocks
     CGState *st;              // [2][nchains]
     double *samples;          // timing: [kMaxSamples][nchains][2] bytes of sampled slots
+    double *all_bytes;        // timing: [nchains][2] running sums of the bytes of every slot
     const int *active;        // step kernels: if set, the number of work entries is *active (the
                               // grid may be larger; the workgroups beyond it exit at once)
 };
