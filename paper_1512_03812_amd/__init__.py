@@ -247,8 +247,10 @@ class Lattice:
         self._check(self._lib.hmc_set_fg_mode(self._ctx, _lib.FG_MODES[mode]))
 
     def set_graph(self, on: bool):
-        """Capture each trajectory schedule as one HIP graph and replay it (every chain must
-        fit the persistent solver)."""
+        """Run trajectories from HIP graphs: one graph per trajectory schedule when every chain
+        fits the persistent solver, otherwise each solve's CG iteration slots as replays of
+        captured chunks (the rest of the trajectory eager).  Results are bit-identical to the
+        eager path."""
         self._check(self._lib.hmc_set_graph(self._ctx, int(bool(on))))
 
     def set_persistent_limit(self, vmax: int):
