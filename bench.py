@@ -131,7 +131,8 @@ def run_batched(args):
     res["s1"], res["s2"] = lat.kernel_stats(0), lat.kernel_stats(1)
     lat.set_timing(False)
     res["roofline_pass"] = {"trajectories": args.roofline_steps, "groups": 1, "persistent_limit": 0,
-                            "ms_per_step": round(1e3 * rp["dt"] / max(1, args.roofline_steps), 3)}
+                            "ms_per_step": round(1e3 * rp["dt"] / max(1, args.roofline_steps), 3),
+                            "cg_iters_per_traj": rp["cg_iters_per_traj"]}
     lat.set_cg_groups(used["groups"])
     lat.set_persistent_limit(used["persistent_limit"])
     res["lat"] = lat
@@ -221,7 +222,7 @@ def run_concurrent(args, n_ctx=2):
             lat.hot_start()
             lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
             lat.set_check_interval(args.check_interval)
-            lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+                    lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
             if not args.no_tune:
                 lat.autotune("mixed", 1e-10)
             lat.set_persistent_limit(args.persistent_limit if args.persistent_limit >= 0 else 0)
@@ -463,9 +464,10 @@ def cpu_baseline(args):
 
 def run_sweep(args):
     """Roofline sweep on single large lattices, and on one batch of equal chains (beta 2,
-    m0 0.1, hot start): FP64 dslash, and CG iterations in FP64 and in mixed precision (512
-    iteration slots, every 32nd event-timed), beside the library's streaming copy of 1 GiB (and
-    torch's copy) as the measured bandwidth ceiling."""
+    m0 0.1, hot start), at each workgroup size of --sweep-blocks: FP64 dslash (the median of
+    three runs of 20 launches), and CG iterations in FP64 and in mixed precision (512 iteration
+    slots, every 32nd event-timed), beside the library's streaming copy of 1 GiB (and torch's
+    copy) as the measured bandwidth ceiling."""
     import torch
     import paper_1512_03812_amd as hmc
     out = {"metric": "Dslash and CG iteration achieved HBM GB/s (single large lattices)",
@@ -501,39 +503,41 @@ def run_sweep(args):
                hmc.Lattice.batch([L] * nb, [L] * nb, 2.0, 0.1, seed=args.seed))
         lat.hot_start()
         lat.set_fused_cg(args.cg_kernels == "fused")
-        if args.block:
-            lat.set_block_size(args.block)
         V = lat.V_total
         psi = torch.randn(2, V, dtype=torch.complex128, device="cuda")
         dst = lat.new_spinor()
-        for _ in range(3):
-            lat.dslash(psi, out=dst)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        reps = 20
-        torch.cuda.synchronize()
-        ev[0].record(lat.stream)
-        for _ in range(reps):
-            lat.dslash(psi, out=dst)
-        ev[1].record(lat.stream)
-        torch.cuda.synchronize()
-        us = 1e3 * ev[0].elapsed_time(ev[1]) / reps
-        row = {"L": L, "chains": nb, "sites": V, "dslash64_us": round(us, 2),
-               "dslash64_gbs": round(96 * V / (us * 1e-6) / 1e9, 1)}
-        for prec in ("fp64", "mixed"):
-            lat.set_persistent_limit(0)
-            lat.set_timing(True)
-            lat.cg_solve(psi, tol=1e-30, max_iter=512, prec=prec)
-            s1, s2 = lat.kernel_stats(0), lat.kernel_stats(1)
-            lat.set_timing(False)
-            t1, t2 = s1["timed_ms"] * 1e-3, s2["timed_ms"] * 1e-3
-            row[f"cg_{prec}_step1_gbs"] = round(s1["timed_bytes"] / t1 / 1e9, 1)
-            row[f"cg_{prec}_step1_us"] = round(1e6 * t1 / max(1, s1["timed_launches"]), 2)
-            row[f"cg_{prec}_step2_us"] = round(1e6 * t2 / max(1, s2["timed_launches"]), 2)
-            row[f"cg_{prec}_step2_gbs"] = round(s2["timed_bytes"] / t2 / 1e9, 1)
-            row[f"cg_{prec}_iter_us"] = round(1e6 * (t1 + t2) / max(1, s2["timed_launches"]), 2)
-            row[f"cg_{prec}_iter_gbs"] = round((s1["timed_bytes"] + s2["timed_bytes"]) / (t1 + t2) / 1e9, 1)
-        out["sizes"].append(row)
-        print(json.dumps(row), file=sys.stderr, flush=True)
+        for block in ([args.block] if args.block else args.sweep_blocks):
+            lat.set_block_size(block)
+            for _ in range(3):
+                lat.dslash(psi, out=dst)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            reps, runs = 20, []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                ev[0].record(lat.stream)
+                for _ in range(reps):
+                    lat.dslash(psi, out=dst)
+                ev[1].record(lat.stream)
+                torch.cuda.synchronize()
+                runs.append(1e3 * ev[0].elapsed_time(ev[1]) / reps)
+            us = sorted(runs)[1]  # the median of three runs of 20 launches
+            row = {"L": L, "chains": nb, "sites": V, "block": block, "dslash64_us": round(us, 2),
+                   "dslash64_gbs": round(96 * V / (us * 1e-6) / 1e9, 1)}
+            for prec in ("fp64", "mixed"):
+                lat.set_persistent_limit(0)
+                lat.set_timing(True)
+                lat.cg_solve(psi, tol=1e-30, max_iter=512, prec=prec)
+                s1, s2 = lat.kernel_stats(0), lat.kernel_stats(1)
+                lat.set_timing(False)
+                t1, t2 = s1["timed_ms"] * 1e-3, s2["timed_ms"] * 1e-3
+                row[f"cg_{prec}_step1_gbs"] = round(s1["timed_bytes"] / t1 / 1e9, 1)
+                row[f"cg_{prec}_step1_us"] = round(1e6 * t1 / max(1, s1["timed_launches"]), 2)
+                row[f"cg_{prec}_step2_us"] = round(1e6 * t2 / max(1, s2["timed_launches"]), 2)
+                row[f"cg_{prec}_step2_gbs"] = round(s2["timed_bytes"] / t2 / 1e9, 1)
+                row[f"cg_{prec}_iter_us"] = round(1e6 * (t1 + t2) / max(1, s2["timed_launches"]), 2)
+                row[f"cg_{prec}_iter_gbs"] = round((s1["timed_bytes"] + s2["timed_bytes"]) / (t1 + t2) / 1e9, 1)
+            out["sizes"].append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
         del lat, psi, dst
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
@@ -571,7 +575,9 @@ def run_acceptance_table(args):
     step-count pair, the acceptance over 100 chains (one batched trajectory each, from
     configurations thermalised by 200 5-stage trajectories), and the single-chain FP64 rate;
     the smallest setting with acceptance >= 0.9 is the scheme's point.  Batched workload: the
-    same scan of (n_outer, n_inner) for the adapted nested scheme in mixed precision."""
+    same scan of (n_outer, n_inner) for the adapted nested scheme in mixed precision, after
+    the benchmark's thermalisation and autotuning, each setting from the same links over
+    --table-steps trajectories; its point is the fastest setting with acceptance >= 0.9."""
     import math
     import torch
     import paper_1512_03812_amd as hmc
@@ -616,9 +622,12 @@ def run_acceptance_table(args):
     lat = hmc.Lattice.batch(L, L, beta, m0, seed=args.seed)
     lat.hot_start()
     lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
-    lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+    # the benchmark's preparation: thermalisation, then the autotuner with the benchmark's
+    # schedule (chain groups included)
+    for _ in range(max(1, args.therm)):
+        lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
     if not args.no_tune:
-        lat.autotune("mixed", 1e-10)
+        lat.autotune("mixed", 1e-10, schedule=("adapted_nested_fg", 1.0, 8, 4))
     if args.persistent_limit >= 0:
         lat.set_persistent_limit(args.persistent_limit)
     for _ in range(2):
@@ -756,6 +765,8 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="roofline sweep on single large lattices instead of the HMC benchmark")
     ap.add_argument("--sweep-sizes", type=int, nargs="+", default=[256, 512, 1024, 2048, 4096, 8192])
+    ap.add_argument("--sweep-blocks", type=int, nargs="+", default=[256, 512],
+                    help="workgroup sizes of the sweep (each lattice is measured at every one)")
     ap.add_argument("--sweep-batch", type=int, nargs=2, default=[1024, 128], metavar=("CHAINS", "L"),
                     help="also sweep a batch of CHAINS chains of L x L (0 0: none)")
     ap.add_argument("--acceptance-table", action="store_true",
@@ -763,7 +774,7 @@ def main():
     ap.add_argument("--table-chains", type=int, default=100)
     ap.add_argument("--table-therm", type=int, default=200)
     ap.add_argument("--table-single", type=int, default=3)
-    ap.add_argument("--table-steps", type=int, default=3)
+    ap.add_argument("--table-steps", type=int, default=5)
     ap.add_argument("--paper-study", action="store_true",
                     help="the paper's integrator study (Sec. 4) instead of the HMC benchmark")
     ap.add_argument("--study-sets", type=int, default=200)
@@ -831,6 +842,21 @@ def main():
         # counter bytes per dispatch over the kernel-trace mean duration of the same dispatches
         traffic = round(rec["hbm_bytes_per_launch"] / (rec["kernel_trace_mean_us"] * 1e-6) / 1e9, 1)
     cg_gbs = (s1["timed_bytes"] + s2["timed_bytes"]) / t12 / 1e9 if t12 > 0 else 0.0
+    # CG bytes per trajectory against the wall time of the timed steps: the bandwidth the whole
+    # job draws for its solves, with the tuned chain groups overlapping one another's launches
+    rpass = b["roofline_pass"]
+    wall = None
+    if s1["launches"] and rpass["cg_iters_per_traj"]:
+        per_traj = (s1["all_bytes"] + s2["all_bytes"]) / max(1, args.roofline_steps)
+        per_traj *= b["cg_iters_per_traj"] / rpass["cg_iters_per_traj"]
+        ms = 1e3 * b["dt"] / max(1, args.steps)
+        wall = {"gbs": round(per_traj / (ms * 1e-3) / 1e9, 1),
+                "frac": round(per_traj / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "bytes_per_traj": round(per_traj), "ms_per_traj": round(ms, 3),
+                "how": ("algorithmic bytes of every CG step-kernel launch per trajectory (counted "
+                        "in the roofline pass, scaled by the timed steps' CG iterations per "
+                        "trajectory) over the timed steps' wall time per trajectory, which "
+                        "includes every other kernel and every host wait")}
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -877,6 +903,7 @@ def main():
             "measured_in": b["roofline_pass"],
         },
         "cg_step1_step2_gbs": round(cg_gbs, 1),
+        "cg_bytes_over_wall_time": wall,
         "cg_steps": {KERNELS[k][0]: {"avg_launch_us": round(1e3 * st["timed_ms"] / max(1, st["timed_launches"]), 3),
                                      "achieved_gbs": round(st["timed_bytes"] / max(1e-30, st["timed_ms"] * 1e-3) / 1e9, 1),
                                      "timed_launches": st["timed_launches"],
