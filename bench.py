@@ -222,7 +222,7 @@ def run_concurrent(args, n_ctx=2):
             lat.hot_start()
             lat.set_solver(tol=1e-10, max_iter=20000, reliable_delta=args.reliable_delta)
             lat.set_check_interval(args.check_interval)
-                    lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
+            lat.trajectory("adapted_nested_fg", 1.0, 8, 4, prec="mixed")
             if not args.no_tune:
                 lat.autotune("mixed", 1e-10)
             lat.set_persistent_limit(args.persistent_limit if args.persistent_limit >= 0 else 0)
