@@ -2,7 +2,8 @@
 
 - 32 x 32 trajectories (beta 2, m0 0.1, CG tolerance 1e-12) of the five schemes of the
   scheme comparison over its step grid (n_outer in {4, 8, 16}, n_inner in {2, 4} for the
-  nested schemes), on both solver paths, against the FP64 oracle (Sec. 2.1, 2.2);
+  nested schemes), on both solver paths, against the FP64 oracle (Sec. 2.1, 2.2), and one
+  trajectory each of 100 chains of that configuration in one batch;
 - the action S = S_G + S_F as a torch.autograd.Function at 128 x 128 for m0 in {0.1, 0.05}:
   its gradient against central finite differences (eps = 1e-6, 64 seeded links) and the
   oracle force (Sec. 3, Eqs. (13)-(17));
@@ -76,6 +77,39 @@ def test_scheme_comparison_32x32_matches_oracle(scheme, n_outer, n_inner, persis
         assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - qr)) < 1e-9, t
 
 
+# One trajectory each of 100 chains of the same configuration from independent hot starts
+# (Philox chain index), in one batch, against 100 oracle trajectories.
+C2_BATCH, C2_BATCH_SEED = 100, 3233
+
+
+def _oracle_c2_chain(args):
+    scheme, n_outer, n_inner, c = args
+    q = oracle.random_links(C2_L, C2_L, C2_BATCH_SEED, c)
+    _, info = oracle.hmc_trajectory(q, C2_BETA, C2_M0, C2_BATCH_SEED, c, 0, scheme, 1.0, n_outer,
+                                    n_inner, tol=C2_TOL)
+    return info
+
+
+@lru_cache(maxsize=None)
+def c2_batch_reference(scheme, n_outer, n_inner):
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        return list(ex.map(_oracle_c2_chain, [(scheme, n_outer, n_inner, c) for c in range(C2_BATCH)]))
+
+
+@pytest.mark.parametrize("persistent", SOLVERS)
+@pytest.mark.parametrize("scheme,n_outer,n_inner", [("omelyan", 8, 1), ("adapted_nested_fg", 4, 2)])
+def test_scheme_comparison_100_chains_match_oracle(scheme, n_outer, n_inner, persistent):
+    refs = c2_batch_reference(scheme, n_outer, n_inner)
+    b = Batch([(C2_L, C2_L, C2_BETA, C2_M0)] * C2_BATCH, seed=C2_BATCH_SEED, persistent=persistent)
+    b.lat.hot_start()
+    b.lat.set_solver(tol=C2_TOL)
+    r = b.lat.trajectory(scheme, 1.0, n_outer, n_inner)
+    for c, ir in enumerate(refs):
+        assert ir["rc"] == 0 and r.status[c] == 0, c
+        assert r.accepted[c] == ir["accepted"], c
+        assert abs(r.dH[c] - ir["dH"]) <= 1e-10 * max(1.0, abs(ir["dH"])), (c, r.dH[c], ir["dH"])
+
+
 # ------------------------------------------------------------------ differentiation at 128 x 128
 @pytest.mark.parametrize("m0", [0.1, 0.05])
 def test_autograd_action_128_against_finite_differences_and_oracle(m0):
@@ -93,7 +127,7 @@ def test_autograd_action_128_against_finite_differences_and_oracle(m0):
     ref = oracle.gauge_force(q, beta) + fr
     assert rel(grad, ref) < 1e-10
     S_ref = oracle.gauge_action(q, beta) + sfr
-    assert abs(float(S[0]) - S_ref) < 1e-11 * S_ref
+    assert abs(float(S[0].detach()) - S_ref) < 1e-11 * S_ref
     g = np.random.default_rng(1283 + int(m0 * 100))
     eps, worst = 1e-6, 0.0
     for _ in range(64):
