@@ -2220,12 +2220,17 @@ static int grouped_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, i
     }
     forget_all(c);
     c->traj++;
-    for (int g = 0; g < G; ++g)
-        if (rcs[g]) {
-            c->err = c->grp[g]->err;
-            return rcs[g];
-        }
-    return HMC_OK;
+    // a failure of the call itself first; then per-chain failures, a non-finite one before an
+    // iteration cap (as a single context reports them)
+    int worst = -1;
+    for (int g = 0; g < G; ++g) {
+        if (!rcs[g]) continue;
+        const auto rank = [](int r) { return !chain_failure(r) ? 2 : r == HMC_E_NAN ? 1 : 0; };
+        if (worst < 0 || rank(rcs[g]) > rank(rcs[worst])) worst = g;
+    }
+    if (worst < 0) return HMC_OK;
+    c->err = c->grp[worst]->err;
+    return rcs[worst];
 }
 
 int hmc_trajectory(hmc_ctx *c, int scheme, double tau, int n_outer, int n_inner, int prec,

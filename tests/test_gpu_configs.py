@@ -9,7 +9,8 @@
   oracle force (Sec. 3, Eqs. (13)-(17));
 - the C ABI's per-chain failure convention inside a batched trajectory: a chain whose solve
   hits the iteration cap, or whose links hold a NaN, reports its status, is rejected and gets
-  its links back, and every other chain is bit-identical to the run without it.
+  its links back, and every other chain is bit-identical to the run without it (also with
+  the chains split into two groups).
 """
 import math
 from concurrent.futures import ThreadPoolExecutor
@@ -149,8 +150,9 @@ FAIL_SHAPES = [(16, 16, 2.0, 0.5), (16, 16, 1.5, 0.5), (16, 16, 2.0, -0.4), (16,
 LIGHT = 2
 
 
-def _run(shapes, prec, persistent, max_iter, plant_nan=None, n_traj=2):
+def _run(shapes, prec, persistent, max_iter, plant_nan=None, n_traj=2, groups=1):
     b = Batch(shapes, seed=4242, persistent=persistent)
+    b.lat.set_cg_groups(groups)
     b.lat.hot_start()
     b.lat.set_solver(tol=1e-12, max_iter=max_iter)
     if plant_nan is not None:
@@ -165,10 +167,11 @@ def _run(shapes, prec, persistent, max_iter, plant_nan=None, n_traj=2):
     return out
 
 
+@pytest.mark.parametrize("groups", [1, 2])
 @pytest.mark.parametrize("persistent", SOLVERS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_chain_at_the_iteration_cap_is_rejected_alone(prec, persistent):
-    capped = _run(FAIL_SHAPES, prec, persistent, 200)
+def test_chain_at_the_iteration_cap_is_rejected_alone(prec, persistent, groups):
+    capped = _run(FAIL_SHAPES, prec, persistent, 200, groups=groups)
     free = _run(FAIL_SHAPES, prec, persistent, 100000)
     for (before, r, after), (_, rf, after_f) in zip(capped, free):
         assert r.status[LIGHT] == -3 and not r.accepted[LIGHT]
@@ -183,12 +186,13 @@ def test_chain_at_the_iteration_cap_is_rejected_alone(prec, persistent):
             assert np.array_equal(after[c], after_f[c]), c
 
 
+@pytest.mark.parametrize("groups", [1, 2])
 @pytest.mark.parametrize("persistent", SOLVERS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_chain_with_a_nan_link_is_rejected_alone(prec, persistent):
+def test_chain_with_a_nan_link_is_rejected_alone(prec, persistent, groups):
     bad = 1
     shapes = [(16, 16, 2.0, 0.2), (16, 16, 1.5, 0.2), (8, 8, 2.0, 0.1), (16, 16, 3.0, 0.15)]
-    poisoned = _run(shapes, prec, persistent, 100000, plant_nan=bad)
+    poisoned = _run(shapes, prec, persistent, 100000, plant_nan=bad, groups=groups)
     clean = _run(shapes, prec, persistent, 100000)
     for (before, r, after), (_, rc, after_c) in zip(poisoned, clean):
         assert r.status[bad] == -5 and not r.accepted[bad]
