@@ -157,6 +157,11 @@ struct hmc_ctx {
     size_t off_groups = 0, groups_bytes = 0;  // the workspace area of the groups' tables
     int part_vmax = -1;                   // vmax the device partition tables were built for
     int n_big_blocks = 0, n_small = 0, small_vmax = 0;
+    // the persistent-solver chains in size classes (at most 1024 and 2048 sites: one and two
+    // sites per thread), each launched with its own workgroup size and LDS: class k holds
+    // n_cls[k] chains from entry cls_first[k] of the small-chain list, the largest with
+    // vmax_cls[k] sites
+    int n_cls[2] = {}, cls_first[2] = {}, vmax_cls[2] = {};
     size_t lds_max = 64 * 1024;           // dynamic LDS a workgroup may opt in to
     // ------------------------------------------------------------ pinned host staging
     void *pinned = nullptr;
@@ -553,16 +558,26 @@ void slot_launch(hmc_ctx *c, int slot, L1 step1, L2 step2, bool two = true) {
 // Splits the chains between the persistent one-workgroup solver (V <= vmax) and the
 // multi-workgroup slot kernels, and uploads the workgroup list of the latter and the chain
 // list of the former.
+// Size class of a persistent-solver chain: one or two sites per thread of its workgroup.
+static int size_class(int V) { return V <= 1024 ? 0 : 1; }
+
 int build_partition(hmc_ctx *c, int vmax) {
     if (c->part_vmax == vmax) return HMC_OK;
     std::vector<BlockWork> big;
     std::vector<int> small;
     int svmax = 0, rc = HMC_OK;
-    for (int k = 0; k < c->nchains; ++k) {
-        if (c->chains[k].V <= vmax) {
-            small.push_back(k);
-            svmax = std::max(svmax, c->chains[k].V);
+    for (int cls = 0; cls < 2; ++cls) {
+        c->cls_first[cls] = (int)small.size();
+        c->vmax_cls[cls] = 0;
+        for (int k = 0; k < c->nchains; ++k) {
+            const int V = c->chains[k].V;
+            if (V <= vmax && size_class(V) == cls) {
+                small.push_back(k);
+                c->vmax_cls[cls] = std::max(c->vmax_cls[cls], V);
+                svmax = std::max(svmax, V);
+            }
         }
+        c->n_cls[cls] = (int)small.size() - c->cls_first[cls];
     }
     for (const BlockWork &w : c->work)
         if (c->chains[w.chain].V > vmax) big.push_back(w);
@@ -587,6 +602,25 @@ int persistent_limit(hmc_ctx *c, bool mixed) {
     int v = std::min(c->persist_vmax, 2048);
     while (v > 0 && cg_wg_lds_bytes(v, mixed) + 1024 > c->lds_max) v /= 2;
     return v;
+}
+
+// Raises the LDS grant of every size class of the persistent solver; nonzero if the device
+// refuses one (then nothing has been launched).
+static int prepare_small(hmc_ctx *c, bool mixed) {
+    for (int cls = 0; cls < 2; ++cls)
+        if (c->n_cls[cls] > 0 && prepare_cg_wg(c->vmax_cls[cls], mixed)) return -1;
+    return 0;
+}
+
+// The persistent solver over every size class on stream s (after prepare_small).
+static int launch_small(hmc_ctx *c, const Geo &g, const CGFields &f, bool mixed, double tol, int max_iter,
+                        hipStream_t s) {
+    for (int cls = 0; cls < 2; ++cls)
+        if (c->n_cls[cls] > 0 &&
+            launch_cg_wg(g, f, mixed, c->at<int>(c->off_small) + c->cls_first[cls], c->n_cls[cls],
+                         c->vmax_cls[cls], tol, c->delta, max_iter, s))
+            return -1;
+    return 0;
 }
 
 // LDS bytes of the fused iteration over the chains above vmax at the current workgroup
@@ -711,8 +745,7 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     if (c->deferring) {
         // inside a captured trajectory: every chain is a persistent-solver chain; the solve
         // runs on the bound stream and logs its per-chain results on the device
-        if (c->n_small != c->nchains || launch_cg_wg(full, f, mixed, c->at<int>(c->off_small), c->n_small,
-                                                      c->small_vmax, tol, c->delta, max_iter, c->stream))
+        if (c->n_small != c->nchains || launch_small(c, full, f, mixed, tol, max_iter, c->stream))
             return fail(c, HMC_E_INVAL, "a captured trajectory needs every chain in the persistent solver");
         if (c->log_count < kMaxLoggedSolves)
             launch_log_solve(c->cg(), c->nchains, c->at<int>(c->off_log) + (size_t)2 * c->log_count * c->nchains,
@@ -724,16 +757,17 @@ int solve(hmc_ctx *c, const double2 *phi, double2 *x, double tol, int max_iter, 
     }
     // small chains: one persistent workgroup each, on the side stream
     if (c->n_small > 0) {
+        if (prepare_small(c, mixed)) {
+            // the device refused an LDS request: lower the limit below the largest class and
+            // solve again (nothing has been launched)
+            c->lds_max = cg_wg_lds_bytes(c->small_vmax, mixed) - 1;
+            return solve(c, phi, x, tol, max_iter, prec);
+        }
         if ((rc = ensure_side(c))) return rc;
         HIP_TRY(c, hipEventRecord(c->fork_ev, c->stream));
         HIP_TRY(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
-        if (launch_cg_wg(full, f, mixed, c->at<int>(c->off_small), c->n_small, c->small_vmax, tol,
-                         c->delta, max_iter, c->side)) {
-            // the device refused the LDS request: solve every chain with the slot kernels
-            c->lds_max = cg_wg_lds_bytes(c->small_vmax, mixed) - 1;
-            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->fork_ev, 0));
-            return solve(c, phi, x, tol, max_iter, prec);
-        }
+        if (launch_small(c, full, f, mixed, tol, max_iter, c->side))
+            return fail(c, HMC_E_HIP, "the persistent solver could not be launched");
         HIP_TRY(c, hipEventRecord(c->join_ev, c->side));
     }
     // large chains: multi-workgroup slot kernels on the bound stream
@@ -2081,7 +2115,7 @@ static int graph_capture(hmc_ctx *c, GraphEntry &e) {
     if (c->n_small != c->nchains)
         return fail(c, HMC_E_INVAL, "a captured trajectory needs every chain within the persistent "
                                     "solver's limit (%d sites)", persistent_limit(c, mixed));
-    if (prepare_cg_wg(c->small_vmax, mixed))
+    if (prepare_small(c, mixed))
         return fail(c, HMC_E_INVAL, "the persistent solver's LDS request was refused");
     if ((rc = ensure_side(c))) return rc;
     MD md;

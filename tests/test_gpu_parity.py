@@ -3,7 +3,9 @@ element on the same seeded inputs.  FP64 tolerances: 1e-12 relative for the
 stencil-level operators, 1e-10 relative for solver-dependent quantities (forces,
 Delta H) with CG tolerances of 1e-14, bit-identity for the Philox uniforms and the
 Gaussian momenta and pseudofermions."""
+import functools
 import math
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -864,6 +866,61 @@ def test_mixed_cg_reaches_fp64_residual(Lx, m0, persistent):
     assert res.converged[0] and res.rel_resid_true[0] < 1e-10 and res.reliable_updates[0] > 0
     x64, res64 = b.lat.cg_solve(b.spinor_to_native([phi]), tol=1e-13)
     assert rel(b.spinor_from_native(x)[0], b.spinor_from_native(x64)[0]) < 1e-7
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_persistent_size_classes_match_the_slot_kernels(prec):
+    """The persistent solver runs its chains as two launches, one per size class (one and two
+    sites per thread); with chains of both classes and larger ones in the batch, every chain
+    gets the slot kernels' solution to the tolerance and the oracle's."""
+    shapes = [(32, 32, 4.0, 0.05), (64, 32, 2.0, 0.1), (16, 16, 3.0, 0.08), (48, 40, 1.5, 0.2),
+              (8, 6, 2.0, 0.1), (64, 64, 2.5, 0.1)]
+    q = [inputs.smooth_angles(s[0], s[1], 300 + k, 0.3) for k, s in enumerate(shapes)]
+    phi = [inputs.random_spinor(s[0], s[1], 310 + k) for k, s in enumerate(shapes)]
+    tol = 1e-12 if prec == "fp64" else 1e-10
+    out = {}
+    for persistent in (0, 2048):
+        b = Batch(shapes, persistent=persistent)
+        b.set_q(q)
+        x, res = b.lat.cg_solve(b.spinor_to_native(phi), tol=tol, prec=prec)
+        assert all(res.converged) and max(res.rel_resid_true) < tol
+        out[persistent] = b.spinor_from_native(x)
+    for k, (Lx, Lt, _, m0) in enumerate(shapes):
+        xr, _, _ = oracle.cg(q[k], phi[k], m0, tol=1e-14)
+        assert rel(out[2048][k], xr) < (1e-10 if prec == "fp64" else 1e-8), k
+        assert rel(out[2048][k], out[0][k]) < (1e-10 if prec == "fp64" else 1e-8), k
+
+
+PERSIST_SHAPES, PERSIST_SEED = [(64, 64, 4.0, 0.1), (16, 16, 2.0, 0.1), (64, 48, 3.0, 0.15)], 4097
+
+
+@functools.lru_cache(maxsize=None)
+def _persist_refs():
+    with ThreadPoolExecutor(max_workers=len(PERSIST_SHAPES)) as ex:
+        return list(ex.map(lambda cs: run_oracle_chain(cs[1][0], cs[1][1], cs[1][2], cs[1][3], PERSIST_SEED,
+                                                       cs[0], 2, "adapted_nested_fg", 1.0, 4, 2, 1e-12),
+                           enumerate(PERSIST_SHAPES)))
+
+
+@pytest.mark.parametrize("persistent", [0, 2048])
+def test_mixed_batched_trajectories_with_64x64_chains(persistent):
+    """Mixed-precision trajectories of a batch with 64 x 64 and 64 x 48 chains (slot kernels)
+    and a 16 x 16 chain (slot kernels or the persistent solver): the same accept decisions as
+    the FP64 oracle, Delta H and the links within the tolerance's reach."""
+    shapes = PERSIST_SHAPES
+    b = Batch(shapes, seed=PERSIST_SEED, persistent=persistent)
+    b.lat.hot_start()
+    b.lat.set_solver(tol=1e-12)
+    refs = _persist_refs()
+    for t in range(2):
+        r = b.lat.trajectory("adapted_nested_fg", 1.0, 4, 2, prec="mixed")
+        qs = b.links_from_native(b.lat.q)
+        for c in range(len(shapes)):
+            qr, ir = refs[c][t]
+            assert r.status[c] == 0
+            assert r.accepted[c] == ir["accepted"], (t, c)
+            assert abs(r.dH[c] - ir["dH"]) < 1e-8 * max(1.0, abs(ir["dH"])), (t, c, r.dH[c], ir["dH"])
+            assert np.max(np.abs(qs[c] - qr)) < 1e-7
 
 
 @pytest.mark.parametrize("persistent", SOLVERS)
