@@ -9,13 +9,16 @@ Metropolis) for every chain of the batched workload:
   CG in FP32 with FP64 reliable updates to a true relative residual of 1e-10,
   Delta H / Metropolis / energies in FP64.
 The chains are thermalised from the hot start first (untimed), then the autotuner picks the
-launch settings (workgroup size, step-kernel variant, check interval, reliable-update factor,
-chain groups) and its pick is used as is.  value = chain-trajectories per second over the
+launch settings (workgroup size, persistent-solver limit, step-kernel variant, check interval,
+reliable-update factor, chain groups) and its pick is used as is.  value = chain-trajectories per second over the
 timed steps (inputs resident in HBM), one hmc_trajectory call per step.
 Beside it:
   - the dominant CG kernel's roofline figure, event-timed in a pass of the same workload run
     as one chain group right after the timed steps (with several groups the kernels of
     different groups overlap in time, so a kernel's duration would not be its own);
+  - the CG step kernels' algorithmic bytes per trajectory over the timed wall time per
+    trajectory (the bandwidth the whole job draws, the groups overlapping);
+  - the same workload with its CG iteration slots replayed as captured graph chunks;
   - the Delta H error against the FP64 oracle: sampled chains are loaded with oracle-made
     thermalised links and run one trajectory of the whole batch at the timed tolerance and at
     1e-12, against the oracle's trajectory from the same links and random numbers;
