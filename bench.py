@@ -465,6 +465,38 @@ def cpu_baseline(args):
             "per_unit": units}
 
 
+def copy_ceilings(seed, mib=1024, reps=10):
+    """Measured bandwidth ceilings of this GPU: torch's copy and the library's streaming copy
+    (16-byte nontemporal accesses, on its own stream) of `mib` MiB, in GB/s of bytes read plus
+    written."""
+    import torch
+    import paper_1512_03812_amd as hmc
+    n = mib << 20
+    a = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    torch_gbs = round(2 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    small = hmc.Lattice(8, 2.0, 0.1, seed=seed)
+    small.stream_copy(a, b)
+    torch.cuda.synchronize()
+    e0.record(small.stream)
+    for _ in range(reps):
+        small.stream_copy(a, b)
+    e1.record(small.stream)
+    torch.cuda.synchronize()
+    lib_gbs = round(2 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b, small
+    torch.cuda.empty_cache()
+    return torch_gbs, lib_gbs
+
+
 def run_sweep(args):
     """Roofline sweep on single large lattices, and on one batch of equal chains (beta 2,
     m0 0.1, hot start), at each workgroup size of --sweep-blocks: FP64 dslash (the median of
@@ -475,29 +507,7 @@ def run_sweep(args):
     import paper_1512_03812_amd as hmc
     out = {"metric": "Dslash and CG iteration achieved HBM GB/s (single large lattices)",
            "unit": "GB/s", "peak": HBM_PEAK_GBS, "sizes": []}
-    n = 1 << 30
-    a = torch.ones(n // 8, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(10):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    out["torch_copy_gbs"] = round(2 * n * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
-    # the library's streaming copy (16-byte nontemporal accesses) on its own stream
-    small = hmc.Lattice(8, 2.0, 0.1, seed=args.seed)
-    small.stream_copy(a, b)
-    torch.cuda.synchronize()
-    e0.record(small.stream)
-    for _ in range(10):
-        small.stream_copy(a, b)
-    e1.record(small.stream)
-    torch.cuda.synchronize()
-    out["copy_ceiling_gbs"] = round(2 * n * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
-    del a, b, small
+    out["torch_copy_gbs"], out["copy_ceiling_gbs"] = copy_ceilings(args.seed)
     cases = [(L, 1) for L in args.sweep_sizes]
     if args.sweep_batch and args.sweep_batch[0] > 0:
         cases.append((args.sweep_batch[1], args.sweep_batch[0]))
@@ -907,12 +917,25 @@ def main():
         },
         "cg_step1_step2_gbs": round(cg_gbs, 1),
         "cg_bytes_over_wall_time": wall,
+        "site_trajectories_per_s": round(value * b["sites"] / b["n_chains"], 1),
         "cg_steps": {KERNELS[k][0]: {"avg_launch_us": round(1e3 * st["timed_ms"] / max(1, st["timed_launches"]), 3),
                                      "achieved_gbs": round(st["timed_bytes"] / max(1e-30, st["timed_ms"] * 1e-3) / 1e9, 1),
                                      "timed_launches": st["timed_launches"],
                                      "avg_bytes_per_launch_all_slots": round(st["all_bytes"] / max(1, st["launches"]))}
                      for k, st in ((0, s1), (1, s2))},
     }
+    # the measured copy ceiling of this GPU beside the peak (a 1 GiB copy, beyond the
+    # Infinity Cache)
+    # (not in the counter runs, whose only streaming copy is the calibration one)
+    if not args.copy_calibration:
+        torch_gbs, lib_gbs = copy_ceilings(args.seed)
+        out["roofline"]["copy_ceiling_gbs"] = lib_gbs
+        out["roofline"]["torch_copy_gbs"] = torch_gbs
+        out["roofline"]["frac_of_copy_ceiling"] = round(ach / lib_gbs, 4)
+        if traffic:
+            out["roofline"]["traffic_frac_of_copy_ceiling"] = round(traffic / lib_gbs, 4)
+        if wall:
+            wall["frac_of_copy_ceiling"] = round(wall["gbs"] / lib_gbs, 4)
     if not args.no_oracle_check:
         out["dH_error_vs_oracle"] = dH_error_vs_oracle(lat, (1e-10, 1e-12))
     if args.graph_steps > 0:
