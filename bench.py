@@ -947,6 +947,9 @@ def main():
         out["concurrent_contexts"] = run_concurrent(args)
     if not args.no_single:
         out["fp64_single_chain"] = run_single_fp64(args)
+        # the batch's chain-trajectories per second against the plain FP64 single chain's
+        # trajectories per second on the same GPU
+        out["fp64_single_chain"]["batched_over_single"] = round(value / out["fp64_single_chain"]["value"], 1)
         out["precision"] = run_precision(args, [256], 3, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
