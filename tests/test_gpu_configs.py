@@ -143,6 +143,44 @@ def test_autograd_action_128_against_finite_differences_and_oracle(m0):
     assert worst < 1e-6 * np.max(np.abs(grad)), worst
 
 
+@pytest.mark.parametrize("m0", [0.1, 0.05])
+def test_autograd_action_on_thermalised_16x16_links(m0):
+    """The differentiation check on thermalised links: the 16 x 16 links the oracle reached
+    after 20 trajectories (stored with the batched workload's check states), at beta 2 and
+    m0 in {0.1, 0.05}: the gradient against the oracle force and against central finite
+    differences (eps = 1e-6) on 64 seeded links."""
+    import json
+    import os
+    m = hmc()
+    path = os.path.join(os.path.dirname(__file__), "golden", "batched_workload_thermalised.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    ref = [c for c in gold["chains"] if c["L"] == 16][0]
+    L, beta = 16, 2.0
+    q = np.array(ref["links"]).reshape(L, L, 2)
+    b = Batch([(L, L, beta, m0)])
+    phi = inputs.random_spinor(L, L, 1601)
+    phin = b.spinor_to_native([phi])
+    qn = b.links_to_native([q]).clone().requires_grad_(True)
+    S = m.SchwingerAction.apply(qn, b.lat, phin, 1e-14)
+    S.sum().backward()
+    grad = b.links_from_native(qn.grad)[0]
+    want = oracle.gauge_force(q, beta) + oracle.fermion_force(q, phi, m0, tol=1e-14)[0]
+    assert rel(grad, want) < 1e-10
+    g = np.random.default_rng(1602)
+    eps, worst = 1e-6, 0.0
+    for _ in range(64):
+        t, x, mu = int(g.integers(L)), int(g.integers(L)), int(g.integers(2))
+        qp, qm = q.copy(), q.copy()
+        qp[t, x, mu] += eps
+        qm[t, x, mu] -= eps
+        with torch.no_grad():
+            sp = float(m.SchwingerAction.apply(b.links_to_native([qp]), b.lat, phin, 1e-14)[0])
+            sm = float(m.SchwingerAction.apply(b.links_to_native([qm]), b.lat, phin, 1e-14)[0])
+        worst = max(worst, abs((sp - sm) / (2 * eps) - grad[t, x, mu]))
+    assert worst < 1e-6 * np.max(np.abs(grad)), worst
+
+
 # ------------------------------------------------------------------ per-chain failures
 # Four 16 x 16 chains from a hot start: three heavy (m0 0.5, about 70 CG iterations per solve)
 # and one light (m0 -0.4, more than 300), so an iteration cap of 200 stops only the light one.
