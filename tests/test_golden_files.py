@@ -54,3 +54,17 @@ def test_thermalised_golden_matches_the_workload_recipe_and_the_oracle():
                                         g["n_inner"], tol=g["tol"])
         assert info["accepted"] == ref["accepted"]
         assert abs(info["dH"] - ref["dH"]) <= 1e-12 * max(1.0, abs(ref["dH"]))
+
+
+def test_thermalised_scheme_comparison_state():
+    """The stored thermalised 32 x 32 state: written by the oracle alone for the stated
+    couplings; its plaquette is that of its links, and it sits near equilibrium (the 5-stage
+    scheme accepts most of the last 100 thermalisation trajectories)."""
+    g = _load("scheme_comparison_thermalised.json")
+    assert (g["L"], g["beta"], g["m0"], g["n_therm"]) == (32, 2.0, 0.1, 200)
+    assert len(g["links"]) == 2 * 32 * 32
+    import numpy as np
+    q = np.array(g["links"]).reshape(32, 32, 2)
+    assert abs(oracle.mean_plaquette(q) - g["plaquette"]) < 1e-12
+    assert g["acceptance_last_100"] >= 0.8
+    assert 0.6 < g["plaquette"] < 0.9

@@ -111,6 +111,48 @@ def test_scheme_comparison_100_chains_match_oracle(scheme, n_outer, n_inner, per
         assert abs(r.dH[c] - ir["dH"]) <= 1e-10 * max(1.0, abs(ir["dH"])), (c, r.dH[c], ir["dH"])
 
 
+# From the thermalised configuration of the comparison (200 5-stage oracle trajectories from
+# the hot start, stored by tests/golden/make_c2_golden.py): the next trajectory of each scheme
+# at its acceptance-matched step setting, against the oracle's from the same links.
+C2T_CASES = [("leapfrog", 32, 1), ("omelyan", 8, 1), ("force_gradient", 4, 1), ("nested_fg", 4, 2),
+             ("adapted_nested_fg", 4, 2), ("adapted_nested_fg", 8, 4)]
+
+
+@lru_cache(maxsize=None)
+def c2_thermalised():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "scheme_comparison_thermalised.json")) as fh:
+        g = json.load(fh)
+    q = np.array(g["links"]).reshape(g["L"], g["L"], 2)
+
+    def run(case):
+        scheme, n_outer, n_inner = case
+        return oracle.hmc_trajectory(q, g["beta"], g["m0"], g["seed"], g["chain"], g["n_therm"],
+                                     scheme, 1.0, n_outer, n_inner, tol=C2_TOL)
+
+    with ThreadPoolExecutor(max_workers=len(C2T_CASES)) as ex:
+        return g, q, dict(zip(C2T_CASES, ex.map(run, C2T_CASES)))
+
+
+@pytest.mark.parametrize("persistent", SOLVERS)
+@pytest.mark.parametrize("scheme,n_outer,n_inner", C2T_CASES)
+def test_scheme_comparison_from_the_thermalised_32x32_configuration(scheme, n_outer, n_inner, persistent):
+    g, q, refs = c2_thermalised()
+    q_ref, info = refs[(scheme, n_outer, n_inner)]
+    assert info["rc"] == 0
+    b = Batch([(g["L"], g["L"], g["beta"], g["m0"])], seed=g["seed"], persistent=persistent)
+    b.set_q([q])
+    b.lat.trajectory_counter = g["n_therm"]
+    b.lat.set_solver(tol=C2_TOL)
+    r = b.lat.trajectory(scheme, 1.0, n_outer, n_inner)
+    assert r.status[0] == 0
+    assert r.accepted[0] == info["accepted"]
+    assert abs(r.dH[0] - info["dH"]) <= 1e-10 * max(1.0, abs(info["dH"])), (r.dH[0], info["dH"])
+    assert abs(r.plaquette[0] - info["plaquette"]) < 1e-11
+    assert np.max(np.abs(b.links_from_native(b.lat.q)[0] - q_ref)) < 1e-9
+
+
 # ------------------------------------------------------------------ differentiation at 128 x 128
 @pytest.mark.parametrize("m0", [0.1, 0.05])
 def test_autograd_action_128_against_finite_differences_and_oracle(m0):
