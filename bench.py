@@ -23,7 +23,8 @@ Beside it:
     thermalised links and run one trajectory of the whole batch at the timed tolerance and at
     1e-12, against the oracle's trajectory from the same links and random numbers;
   - the same workload timed at CG tolerance 1e-12 (the setting that meets the 1e-8 target);
-  - the plain FP64 single-chain 32 x 32 path, mixed against FP64 precision on 256 x 256;
+  - the plain FP64 single-chain 32 x 32 path, mixed against FP64 precision on 256 x 256, and
+    the mixed-precision Delta H error against stored oracle trajectories at 128^2 and 256^2;
   - the CPU oracle on all available host cores (sampled workload, per-unit timings).
 """
 import argparse
@@ -333,6 +334,35 @@ def run_precision(args, sizes, n_traj, n_therm):
             "acceptance": round(sum(acc["mixed"]) / n_traj, 3),
             "mean_abs_dH": round(float(np.mean(np.abs(ref))), 5),
         })
+    return out
+
+
+def precision_dH_error_vs_oracle(tols):
+    """The Delta H error against the FP64 oracle on the precision lattices (128 x 128 and
+    256 x 256, beta 4, m0 0.05, adapted nested FG 8 x 4): the oracle's trajectories from the
+    seeded hot start stored in tests/golden/precision_trajectories.json (written by the oracle
+    alone, CG 1e-12) are replayed in mixed precision at each tolerance."""
+    import paper_1512_03812_amd as hmc
+    with open(os.path.join(ROOT, "tests", "golden", "precision_trajectories.json")) as fh:
+        gold = json.load(fh)
+    out = {}
+    for key in sorted(gold, key=int):
+        rec = gold[key]
+        L = int(key)
+        out[key] = {"trajectories": len(rec["trajectories"]), "reference": f"FP64 oracle, CG {rec['tol']:g}",
+                    "by_cg_tolerance": {}}
+        for tol in tols:
+            lat = hmc.Lattice(L, rec["beta"], rec["m0"], seed=rec["seed"])
+            lat.hot_start()
+            lat.set_solver(tol=tol)
+            errs, same = [], True
+            for ref in rec["trajectories"]:
+                r = lat.trajectory(rec["scheme"], rec["tau"], rec["n_outer"], rec["n_inner"], prec="mixed")
+                errs.append(abs(r.dH[0] - ref["dH"]))
+                same = same and r.accepted[0] == ref["accepted"]
+            out[key]["by_cg_tolerance"][f"{tol:g}"] = {"max_abs_dH_error": max(errs),
+                                                       "dH_errors": errs, "same_decisions": same}
+            del lat
     return out
 
 
@@ -951,6 +981,8 @@ def main():
         # trajectories per second on the same GPU
         out["fp64_single_chain"]["batched_over_single"] = round(value / out["fp64_single_chain"]["value"], 1)
         out["precision"] = run_precision(args, [256], 3, 2)
+        if not args.no_oracle_check:
+            out["precision_dH_error_vs_oracle"] = precision_dH_error_vs_oracle((1e-10, 1e-12))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
